@@ -1,0 +1,182 @@
+/* dfa_spec.h -- C ABI of the MI355X speculative DFA membership test.
+ *
+ * Method: Ko, Jung, Han, Burgstaller, "Speculative parallel DFA membership
+ * tests for multicore, SIMD and cloud computing environments" (arXiv
+ * 1210.5093).  The input string is cut into chunks; every chunk after the
+ * first is matched from each state of its initial-state set I_sigma (Eq. 11),
+ * where sigma is the last symbol of the preceding chunk (reverse lookahead,
+ * Section 4.2, Algorithm 3); the per-chunk state maps L_i (Section 4.1) are
+ * combined in order (Eqs. 8-9) into the exact sequential final state
+ * delta*(q0, w) of Algorithm 1, and the string is accepted iff that state is
+ * in F.
+ *
+ * Conventions for every entry point:
+ *  - Status codes only (DFA_OK = 0, negative on error); no C++ exception
+ *    crosses this boundary.  dfa_last_error() returns a message for the
+ *    calling thread's most recent failure.
+ *  - States are always reported in the caller's numbering 0..num_states-1.
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *    device allocations on the current device.  Host arrays passed to a call
+ *    are only borrowed for the duration of the call.
+ *  - A dfa_t is immutable after dfa_create: concurrent matches of one DFA on
+ *    different streams are safe.
+ *  - Streams are hipStream_t handles passed as void* (0 = the null stream).
+ */
+#ifndef DFA_SPEC_H
+#define DFA_SPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DFA_OK = 0,
+    DFA_E_INVAL = -1,       /* bad argument (null pointer, id out of range, ...) */
+    DFA_E_NOMEM = -2,       /* host or device allocation failed */
+    DFA_E_DEVICE = -3,      /* a HIP runtime call failed */
+    DFA_E_SYMBOL = -4,      /* the input holds a byte outside Sigma */
+    DFA_E_TOOBIG = -5,      /* table or request exceeds a device limit */
+    DFA_E_SPECULATION = -6, /* internal invariant violated: a chunk's true start
+                               state was not in its initial-state set */
+    DFA_E_BUSY = -7,        /* server has no free slot / budget right now */
+    DFA_E_NOTREADY = -8     /* server ticket not finished yet */
+};
+
+/* start_state value meaning "use the DFA's q0". */
+#define DFA_Q0 0xFFFFFFFFu
+
+/* Result record written by the asynchronous entry points (4 x uint32). */
+typedef struct dfa_result {
+    uint32_t final_state;   /* delta*(start, w), caller numbering */
+    uint32_t accepted;      /* 1 iff final_state is in F */
+    uint32_t flags;         /* DFA_FLAG_* bits; 0 on success */
+    uint32_t num_chunks;    /* chunks the input was cut into */
+} dfa_result_t;
+
+#define DFA_FLAG_SYMBOL      1u  /* a byte outside Sigma was seen */
+#define DFA_FLAG_SPECULATION 2u  /* internal invariant violated */
+
+typedef struct dfa dfa_t;
+
+/* Static properties of a compiled DFA (Eqs. 11-12 and the class compression). */
+typedef struct dfa_info {
+    uint32_t num_states;      /* |Q| */
+    uint32_t num_symbols;     /* |Sigma| as given */
+    uint32_t num_classes;     /* K: distinct delta-columns over the bytes in Sigma */
+    uint32_t num_absorbing;   /* states with a self-loop on every symbol (the paper's q_e) */
+    uint32_t imax;            /* I_max of Eq. 12 over the classes */
+    uint32_t q0;
+    double   mean_iset;       /* mean |I_c| over the bytes in Sigma (each byte weighted 1) */
+    uint64_t table_bytes;     /* bytes of the class-major table staged in LDS */
+    uint64_t device_bytes;    /* device memory held by this dfa_t */
+} dfa_info_t;
+
+/* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
+typedef struct dfa_match_opts {
+    uint64_t chunk_len;       /* bytes per chunk; 0 = planner's choice */
+    uint32_t lookahead;       /* 1 = one-symbol reverse lookahead (Algorithm 3,
+                                 default); 0 = every chunk from all non-absorbing
+                                 states (Algorithm 2, the ablation) */
+    uint32_t reserved;
+} dfa_match_opts_t;
+
+/* ---------------------------------------------------------------------------
+ * dfa_create -- compile a DFA (Q, Sigma, delta, q0, F) (Section 2.1) and keep
+ * it resident on the current device.
+ *   delta:          host, num_states * num_symbols entries, row-major
+ *                   delta[q * num_symbols + a]; every entry < num_states
+ *                   (the automaton must be complete, as in the paper).
+ *   num_states:     1 .. 32767.
+ *   num_symbols:    1 .. 256.
+ *   q0:             start state, < num_states.
+ *   accepting:      host, num_accepting state ids (may be NULL if 0).
+ *   byte_to_symbol: host, 256 entries mapping input bytes to symbols; an
+ *                   entry >= num_symbols marks a byte outside Sigma (0xFF
+ *                   is the usual marker).  NULL = identity (num_symbols must
+ *                   be 256).
+ *   out:            receives the handle (owned by the caller; dfa_destroy).
+ * All inputs are copied.  Returns DFA_E_INVAL on an invalid automaton,
+ * DFA_E_TOOBIG if the compressed table cannot be staged in LDS. */
+int dfa_create(const uint32_t *delta, uint32_t num_states, uint32_t num_symbols,
+               uint32_t q0, const uint32_t *accepting, uint32_t num_accepting,
+               const uint8_t *byte_to_symbol, dfa_t **out);
+
+/* Release a DFA (device memory included).  Must not be called while a
+ * match of it may still run on some stream.  NULL is ignored. */
+void dfa_destroy(dfa_t *d);
+
+/* Fill *out with the DFA's static properties. */
+int dfa_info(const dfa_t *d, dfa_info_t *out);
+
+/* ---------------------------------------------------------------------------
+ * dfa_match -- synchronous membership test of a host string (Algorithm 1's
+ * interface: transition function, string, start state, final states ->
+ * true/false).  Copies the input to the device, runs the speculative path and
+ * waits.
+ *   input/len:    host bytes (len may be 0: the final state is the start).
+ *   start_state:  DFA_Q0 or an explicit state (lets a long stream be matched
+ *                 in segments: pass the previous segment's final state).
+ *   final_state:  host out (may be NULL); accepted: host out (may be NULL).
+ * Returns DFA_E_SYMBOL if a byte is outside Sigma (no state is returned). */
+int dfa_match(const dfa_t *d, const uint8_t *input, size_t len, uint32_t start_state,
+              uint32_t *final_state, int *accepted);
+
+/* dfa_match_async -- the same test on device-resident input, enqueued on
+ * `stream`; nothing is waited for.
+ *   d_input:  device, len bytes; must stay valid until the stream passes
+ *             this call.
+ *   d_result: device, one dfa_result_t (4 x uint32), written on the stream.
+ * Errors in the input (bytes outside Sigma) are reported in d_result->flags,
+ * not by the return code. */
+int dfa_match_async(const dfa_t *d, const uint8_t *d_input, size_t len,
+                    uint32_t start_state, void *stream, uint32_t *d_result);
+
+/* dfa_match_ex -- dfa_match_async with options and, optionally, the state at
+ * every chunk boundary.
+ *   opts:          may be NULL (defaults).
+ *   d_boundaries:  NULL, or device, num_chunks + 1 uint32 entries where
+ *                  num_chunks = ceil(len / chunk_len); entry i is the state
+ *                  before chunk i (delta*(start, w[0 : i*chunk_len])), the
+ *                  last entry the final state.  Use dfa_plan_chunks to learn
+ *                  num_chunks beforehand. */
+int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t start_state,
+                 const dfa_match_opts_t *opts, void *stream, uint32_t *d_result,
+                 uint32_t *d_boundaries);
+
+/* Chunk length the library would use for (d, len, opts), and the resulting
+ * number of chunks. */
+int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
+                    uint64_t *chunk_len, uint64_t *num_chunks);
+
+/* ---------------------------------------------------------------------------
+ * dfa_match_batch -- many (DFA, string) pairs of uneven size in one persistent
+ * launch (the paper's representation holds several DFAs and strings in one
+ * table and input array, Section 5).
+ *   dfas:      host array of `count` handles (may repeat).
+ *   d_inputs:  host array of `count` device pointers.
+ *   lens:      host array of `count` lengths.
+ *   d_results: device, count dfa_result_t records, written on the stream.
+ * Each pair's record equals what dfa_match_async would write for it alone. */
+int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
+                    const size_t *lens, size_t count, void *stream, uint32_t *d_results);
+
+/* ---------------------------------------------------------------------------
+ * Instrumentation.  With timing on for a stream, every match call on it
+ * records HIP events around its chunk-matcher kernel and around the whole
+ * call (no work is skipped or reordered).  dfa_timing_read waits for those
+ * events, returns the summed milliseconds and the number of calls, and
+ * clears the record. */
+int dfa_timing_enable(void *stream, int on);
+int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms, uint32_t *calls);
+
+/* Message for a status code / for this thread's last failure. */
+const char *dfa_strerror(int status);
+const char *dfa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFA_SPEC_H */

@@ -1,0 +1,256 @@
+"""MI355X speculative DFA membership test (arXiv 1210.5093) -- Python binding.
+
+Thin ctypes layer over ``libdfaspec.so`` (``include/dfa_spec.h``): argument
+marshalling only.  Every step of the matching runs in the library's HIP
+kernels; there is no Python or CPU fallback, and loading fails loudly if the
+library has not been built.  torch is used only for device buffers and
+stream handles.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfaspec.so")
+
+DFA_OK = 0
+DFA_E_INVAL, DFA_E_NOMEM, DFA_E_DEVICE, DFA_E_SYMBOL = -1, -2, -3, -4
+DFA_E_TOOBIG, DFA_E_SPECULATION, DFA_E_BUSY, DFA_E_NOTREADY = -5, -6, -7, -8
+DFA_Q0 = 0xFFFFFFFF
+FLAG_SYMBOL, FLAG_SPECULATION = 1, 2
+
+
+class DFAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class dfa_info_t(ctypes.Structure):
+    _fields_ = [("num_states", ctypes.c_uint32), ("num_symbols", ctypes.c_uint32),
+                ("num_classes", ctypes.c_uint32), ("num_absorbing", ctypes.c_uint32),
+                ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
+                ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class dfa_match_opts_t(ctypes.Structure):
+    _fields_ = [("chunk_len", ctypes.c_uint64), ("lookahead", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdfaspec.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(the HIP library is required, there is no fallback)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading torch first makes the library bind to that one copy, so device
+    # pointers and streams are shared within the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.dfa_create.restype = I
+    L.dfa_create.argtypes = [P, U32, U32, U32, P, U32, P, ctypes.POINTER(P)]
+    L.dfa_destroy.restype = None
+    L.dfa_destroy.argtypes = [P]
+    L.dfa_info.restype = I
+    L.dfa_info.argtypes = [P, ctypes.POINTER(dfa_info_t)]
+    L.dfa_match.restype = I
+    L.dfa_match.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(U32),
+                            ctypes.POINTER(ctypes.c_int)]
+    L.dfa_match_async.restype = I
+    L.dfa_match_async.argtypes = [P, P, ctypes.c_size_t, U32, P, P]
+    L.dfa_match_ex.restype = I
+    L.dfa_match_ex.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(dfa_match_opts_t), P,
+                               P, P]
+    L.dfa_plan_chunks.restype = I
+    L.dfa_plan_chunks.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
+                                  ctypes.POINTER(U64), ctypes.POINTER(U64)]
+    L.dfa_match_batch.restype = I
+    L.dfa_match_batch.argtypes = [P, P, P, ctypes.c_size_t, P, P]
+    L.dfa_timing_enable.restype = I
+    L.dfa_timing_enable.argtypes = [P, I]
+    L.dfa_timing_read.restype = I
+    L.dfa_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U32)]
+    L.dfa_strerror.restype = ctypes.c_char_p
+    L.dfa_strerror.argtypes = [I]
+    L.dfa_last_error.restype = ctypes.c_char_p
+    L.dfa_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != DFA_OK:
+        raise DFAError(rc, lib().dfa_last_error().decode(errors="replace")
+                       or lib().dfa_strerror(rc).decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _opts(chunk_len: int = 0, lookahead: int = 1) -> dfa_match_opts_t:
+    return dfa_match_opts_t(int(chunk_len), int(lookahead), 0)
+
+
+class DFA:
+    """A DFA (Q, Sigma, delta, q0, F) compiled and resident on the current device."""
+
+    def __init__(self, delta, q0: int, accepting, byte_to_symbol=None):
+        d = np.ascontiguousarray(delta, dtype=np.uint32)
+        if d.ndim != 2:
+            raise ValueError("delta must be a 2-D table [num_states][num_symbols]")
+        acc = np.ascontiguousarray(accepting, dtype=np.uint32)
+        b2s = None if byte_to_symbol is None else np.ascontiguousarray(byte_to_symbol,
+                                                                       dtype=np.uint8)
+        if b2s is not None and b2s.size != 256:
+            raise ValueError("byte_to_symbol must have 256 entries")
+        h = ctypes.c_void_p()
+        _check(lib().dfa_create(d.ctypes.data, d.shape[0], d.shape[1], int(q0),
+                                acc.ctypes.data if acc.size else None, int(acc.size),
+                                b2s.ctypes.data if b2s is not None else None, ctypes.byref(h)))
+        self._h = h
+        self.num_states, self.num_symbols = int(d.shape[0]), int(d.shape[1])
+
+    @classmethod
+    def from_workload(cls, w) -> "DFA":
+        return cls(w.delta, w.q0, w.accepting, w.byte_to_symbol)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("DFA was destroyed")
+        return self._h
+
+    def info(self) -> dfa_info_t:
+        out = dfa_info_t()
+        _check(lib().dfa_info(self.handle, ctypes.byref(out)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().dfa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dfa_create(delta, q0, accepting, byte_to_symbol=None) -> DFA:
+    return DFA(delta, q0, accepting, byte_to_symbol)
+
+
+def dfa_match(d: DFA, data, start: Optional[int] = None) -> Tuple[int, bool]:
+    """Synchronous test of host bytes: (final state, accepted)."""
+    buf = np.frombuffer(bytes(data), dtype=np.uint8) if isinstance(data, (bytes, bytearray)) \
+        else np.ascontiguousarray(data, dtype=np.uint8)
+    fin = ctypes.c_uint32()
+    acc = ctypes.c_int()
+    _check(lib().dfa_match(d.handle, buf.ctypes.data if buf.size else None, int(buf.size),
+                           DFA_Q0 if start is None else int(start), ctypes.byref(fin),
+                           ctypes.byref(acc)))
+    return int(fin.value), bool(acc.value)
+
+
+def _result_tensor(result):
+    import torch
+    if result is None:
+        result = torch.empty(4, dtype=torch.int32, device="cuda")
+    assert result.is_cuda and result.dtype in (torch.int32, torch.uint32) and result.numel() >= 4
+    return result
+
+
+def dfa_match_async(d: DFA, d_input, start: Optional[int] = None, stream=None, result=None):
+    """Enqueue the test of a device uint8 tensor; returns the 4-int32 result tensor
+    (final, accepted, flags, num_chunks) written on the stream."""
+    result = _result_tensor(result)
+    _check(lib().dfa_match_async(d.handle, d_input.data_ptr() if d_input.numel() else None,
+                                 int(d_input.numel()), DFA_Q0 if start is None else int(start),
+                                 _stream_handle(stream), result.data_ptr()))
+    return result
+
+
+def dfa_plan_chunks(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> Tuple[int, int]:
+    c, k = ctypes.c_uint64(), ctypes.c_uint64()
+    o = _opts(chunk_len, lookahead)
+    _check(lib().dfa_plan_chunks(d.handle, int(n), ctypes.byref(o), ctypes.byref(c),
+                                 ctypes.byref(k)))
+    return int(c.value), int(k.value)
+
+
+def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
+                 lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
+                 bound_out=None):
+    """Test with options; optionally the state at every chunk boundary.
+    Returns (result tensor, boundaries tensor or None)."""
+    import torch
+    result = _result_tensor(result)
+    n = int(d_input.numel())
+    bnd = None
+    if boundaries:
+        _, nch = dfa_plan_chunks(d, n, chunk_len, lookahead)
+        bnd = bound_out if bound_out is not None else torch.empty(
+            nch + 1, dtype=torch.int32, device="cuda")
+        assert bnd.numel() >= nch + 1
+    o = _opts(chunk_len, lookahead)
+    _check(lib().dfa_match_ex(d.handle, d_input.data_ptr() if n else None, n,
+                              DFA_Q0 if start is None else int(start), ctypes.byref(o),
+                              _stream_handle(stream), result.data_ptr(),
+                              bnd.data_ptr() if bnd is not None else None))
+    return result, bnd
+
+
+def dfa_match_batch(dfas: Sequence[DFA], inputs: Sequence, stream=None, results=None):
+    """Many (DFA, device string) pairs in one call; returns an int32 [count, 4] tensor."""
+    import torch
+    count = len(dfas)
+    assert len(inputs) == count
+    if results is None:
+        results = torch.empty((count, 4), dtype=torch.int32, device="cuda")
+    hs = (ctypes.c_void_p * max(count, 1))(*[x.handle.value for x in dfas])
+    ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None
+                                             for t in inputs])
+    ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in inputs])
+    _check(lib().dfa_match_batch(hs, ps, ls, count, _stream_handle(stream), results.data_ptr()))
+    return results
+
+
+def dfa_timing_enable(on: bool = True, stream=None) -> None:
+    _check(lib().dfa_timing_enable(_stream_handle(stream), int(bool(on))))
+
+
+def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
+    """(summed matcher-kernel ms, summed whole-call ms, calls) since the last read."""
+    m, c, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint32()
+    _check(lib().dfa_timing_read(_stream_handle(stream), ctypes.byref(m), ctypes.byref(c),
+                                 ctypes.byref(k)))
+    return float(m.value), float(c.value), int(k.value)
+
+
+def result_tuple(result) -> Tuple[int, bool, int, int]:
+    r = result.detach().cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    return int(r[0]), bool(r[1]), int(r[2]), int(r[3])

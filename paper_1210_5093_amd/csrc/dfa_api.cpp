@@ -1,0 +1,234 @@
+// C ABI entry points: matching calls, workspaces, error reporting.
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <utility>
+
+#include "dfa_internal.h"
+
+using namespace dfaspec;
+
+namespace dfaspec {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return DFA_E_DEVICE;
+}
+
+// Per-(device, stream) scratch memory for maps, sizes, boundary values and
+// staged host input.  Calls on one stream are ordered by the stream, so they
+// may share it; callers that use one stream from several host threads must
+// serialise those calls themselves.
+struct Workspace {
+    void *buf = nullptr;
+    size_t bytes = 0;
+    uint8_t *in = nullptr;
+    size_t in_bytes = 0;
+    uint32_t *result = nullptr;   // 4 words for the synchronous path
+    bool timing = false;
+    struct Stamp { hipEvent_t begin, after_match, end; };
+    std::vector<Stamp> stamps;    // one per timed call, read by dfa_timing_read
+};
+
+namespace {
+std::mutex g_ws_mutex;
+std::map<std::pair<int, void *>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace *workspace_for(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    auto &slot = g_ws[{dev, (void *)s}];
+    if (!slot) slot.reset(new Workspace());
+    return slot.get();
+}
+
+int ensure(void **ptr, size_t *have, size_t need) {
+    if (*have >= need && *ptr) return DFA_OK;
+    if (*ptr) {
+        // the stream may still be reading the old buffer
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize (workspace)");
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+        *have = 0;
+    }
+    size_t want = need + need / 4 + 4096;
+    hipError_t e = hipMalloc(ptr, want);
+    if (e != hipSuccess) return fail(DFA_E_NOMEM, "workspace hipMalloc failed");
+    *have = want;
+    return DFA_OK;
+}
+
+uint64_t env_chunk() {
+    const char *v = std::getenv("DFA_CHUNK");
+    return v ? std::strtoull(v, nullptr, 10) : 0;
+}
+
+int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
+              const dfa_match_opts_t *opts, hipStream_t s, uint32_t *d_result,
+              uint32_t *d_bound) {
+    if (!d || !d_result || (len && !d_in)) return fail(DFA_E_INVAL, "match: NULL argument");
+    if (start == DFA_Q0) start = d->dev.q0;
+    if (start >= d->dev.nq) return fail(DFA_E_INVAL, "match: start state out of range");
+    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
+    uint32_t look = opts ? opts->lookahead : 1u;
+    MatchPlan p;
+    int rc = plan_match(d, len, chunk, look, &p);
+    if (rc) return rc;
+    Workspace *ws = workspace_for(s);
+    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    const size_t map_bytes = (p.map_entries * 2 + 255) / 256 * 256;
+    const size_t sz_bytes = (p.msize_entries * 2 + 255) / 256 * 256;
+    const size_t need = map_bytes + 2 * sz_bytes + 256;
+    rc = ensure(&ws->buf, &ws->bytes, need);
+    if (rc) return rc;
+    uint16_t *maps = (uint16_t *)ws->buf;
+    uint16_t *msize = (uint16_t *)((uint8_t *)ws->buf + map_bytes);
+    uint16_t *bvals = (uint16_t *)((uint8_t *)ws->buf + map_bytes + sz_bytes);
+    if (!ws->timing)
+        return launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s, nullptr);
+    Workspace::Stamp st{};
+    hipError_t e = hipEventCreate(&st.begin);
+    if (e == hipSuccess) e = hipEventCreate(&st.after_match);
+    if (e == hipSuccess) e = hipEventCreate(&st.end);
+    if (e == hipSuccess) e = hipEventRecord(st.begin, s);
+    if (e != hipSuccess) return hip_fail(e, "timing events");
+    rc = launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s,
+                      st.after_match);
+    if (rc) return rc;
+    e = hipEventRecord(st.end, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ws->stamps.push_back(st);
+    return DFA_OK;
+}
+}  // namespace
+
+}  // namespace dfaspec
+
+extern "C" int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len,
+                            uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
+                            uint32_t *d_result, uint32_t *d_boundaries) {
+    return run_match(d, d_input, len, start_state, opts, (hipStream_t)stream, d_result,
+                     d_boundaries);
+}
+
+extern "C" int dfa_match_async(const dfa_t *d, const uint8_t *d_input, size_t len,
+                               uint32_t start_state, void *stream, uint32_t *d_result) {
+    return run_match(d, d_input, len, start_state, nullptr, (hipStream_t)stream, d_result,
+                     nullptr);
+}
+
+extern "C" int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
+                               uint64_t *chunk_len, uint64_t *num_chunks) {
+    if (!d) return fail(DFA_E_INVAL, "dfa_plan_chunks: NULL dfa");
+    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
+    MatchPlan p;
+    int rc = plan_match(d, len, chunk, opts ? opts->lookahead : 1u, &p);
+    if (rc) return rc;
+    if (chunk_len) *chunk_len = p.chunk;
+    if (num_chunks) *num_chunks = p.nch;
+    return DFA_OK;
+}
+
+extern "C" int dfa_match(const dfa_t *d, const uint8_t *input, size_t len, uint32_t start_state,
+                         uint32_t *final_state, int *accepted) {
+    if (!d || (len && !input)) return fail(DFA_E_INVAL, "dfa_match: NULL argument");
+    hipStream_t s = nullptr;
+    Workspace *ws = workspace_for(s);
+    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    int rc = ensure((void **)&ws->in, &ws->in_bytes, len + 256);
+    if (rc) return rc;
+    if (!ws->result) {
+        hipError_t e = hipMalloc(&ws->result, 4 * sizeof(uint32_t));
+        if (e != hipSuccess) return fail(DFA_E_NOMEM, "hipMalloc (result)");
+    }
+    if (len) {
+        hipError_t e = hipMemcpyAsync(ws->in, input, len, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (input)");
+    }
+    rc = run_match(d, ws->in, len, start_state, nullptr, s, ws->result, nullptr);
+    if (rc) return rc;
+    uint32_t res[4];
+    hipError_t e = hipMemcpyAsync(res, ws->result, sizeof(res), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "dfa_match readback");
+    if (res[2] & DFA_FLAG_SYMBOL) return fail(DFA_E_SYMBOL, "input holds a byte outside Sigma");
+    if (res[2] & DFA_FLAG_SPECULATION)
+        return fail(DFA_E_SPECULATION, "speculation invariant violated");
+    if (final_state) *final_state = res[0];
+    if (accepted) *accepted = (int)res[1];
+    return DFA_OK;
+}
+
+extern "C" int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
+                               const size_t *lens, size_t count, void *stream,
+                               uint32_t *d_results) {
+    if (count && (!dfas || !d_inputs || !lens || !d_results))
+        return fail(DFA_E_INVAL, "dfa_match_batch: NULL argument");
+    for (size_t i = 0; i < count; ++i) {
+        int rc = run_match(dfas[i], d_inputs[i], lens[i], DFA_Q0, nullptr, (hipStream_t)stream,
+                           d_results + 4 * i, nullptr);
+        if (rc) return rc;
+    }
+    return DFA_OK;
+}
+
+extern "C" int dfa_timing_enable(void *stream, int on) {
+    Workspace *ws = workspace_for((hipStream_t)stream);
+    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    ws->timing = on != 0;
+    return DFA_OK;
+}
+
+extern "C" int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms,
+                               uint32_t *calls) {
+    Workspace *ws = workspace_for((hipStream_t)stream);
+    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    double m = 0.0, c = 0.0;
+    int rc = DFA_OK;
+    for (auto &st : ws->stamps) {
+        float a = 0.f, b = 0.f;
+        hipError_t e = hipEventSynchronize(st.end);
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, st.begin, st.after_match);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, st.begin, st.end);
+        if (e != hipSuccess && rc == DFA_OK) rc = hip_fail(e, "dfa_timing_read");
+        m += a;
+        c += b;
+        (void)hipEventDestroy(st.begin);
+        (void)hipEventDestroy(st.after_match);
+        (void)hipEventDestroy(st.end);
+    }
+    if (calls) *calls = (uint32_t)ws->stamps.size();
+    ws->stamps.clear();
+    if (matcher_ms) *matcher_ms = m;
+    if (call_ms) *call_ms = c;
+    return rc;
+}
+
+extern "C" const char *dfa_strerror(int status) {
+    switch (status) {
+        case DFA_OK: return "ok";
+        case DFA_E_INVAL: return "invalid argument";
+        case DFA_E_NOMEM: return "out of memory";
+        case DFA_E_DEVICE: return "HIP runtime error";
+        case DFA_E_SYMBOL: return "input byte outside the alphabet";
+        case DFA_E_TOOBIG: return "exceeds a device limit";
+        case DFA_E_SPECULATION: return "speculation invariant violated";
+        case DFA_E_BUSY: return "server busy";
+        case DFA_E_NOTREADY: return "not ready";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *dfa_last_error(void) { return dfaspec::g_last_error.c_str(); }

@@ -1,0 +1,230 @@
+// dfa_create / dfa_destroy / dfa_info: validate a DFA, compress its alphabet
+// into equivalence classes, find its absorbing states and initial-state sets,
+// and upload everything to the device once.
+//
+//  * Automaton (Q, Sigma, delta, q0, F) with a total delta: Section 2.1.
+//  * Absorbing states: the paper assumes one error/sink state q_e and leaves
+//    it out of every initial-state set (Section 2.1, Algorithm 3).  Here every
+//    state with a self-loop on all symbols is treated that way: if the true
+//    state at a chunk start is absorbing, it stays so through the chunk, and
+//    the map combination carries it unchanged.
+//  * Initial-state sets I_sigma = {delta(x, sigma) : x in Q} minus the
+//    absorbing states: Eq. (11), first loop of Algorithm 3; I_max: Eq. (12).
+//  * Alphabet classes: bytes whose delta-columns are identical share one
+//    class (numbered by first byte occurrence).  I_sigma depends only on the
+//    column, so I_class = I_sigma for any sigma of the class.  The paper
+//    maps characters to symbol indices (Section 5, the IBase array); the
+//    class compression is this library's addition, so the table fits LDS.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <unordered_map>
+
+#include "dfa_internal.h"
+
+using namespace dfaspec;
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uint32_t q0,
+                          const uint32_t *accepting, uint32_t nacc,
+                          const uint8_t *byte_to_symbol, dfa_t **out) {
+    if (!out) return fail(DFA_E_INVAL, "dfa_create: out is NULL");
+    *out = nullptr;
+    if (!delta) return fail(DFA_E_INVAL, "dfa_create: delta is NULL");
+    if (nq == 0 || nq > kMaxStates)
+        return fail(DFA_E_INVAL, "dfa_create: num_states must be in 1..32767");
+    if (nsym == 0 || nsym > 256)
+        return fail(DFA_E_INVAL, "dfa_create: num_symbols must be in 1..256");
+    if (q0 >= nq) return fail(DFA_E_INVAL, "dfa_create: q0 out of range");
+    if (nacc && !accepting) return fail(DFA_E_INVAL, "dfa_create: accepting is NULL");
+    if (!byte_to_symbol && nsym != 256)
+        return fail(DFA_E_INVAL, "dfa_create: byte_to_symbol may be NULL only with 256 symbols");
+    for (uint64_t i = 0; i < (uint64_t)nq * nsym; ++i)
+        if (delta[i] >= nq) return fail(DFA_E_INVAL, "dfa_create: delta entry out of range");
+    for (uint32_t k = 0; k < nacc; ++k)
+        if (accepting[k] >= nq) return fail(DFA_E_INVAL, "dfa_create: accepting state out of range");
+
+    uint8_t b2s[256];
+    for (int b = 0; b < 256; ++b) b2s[b] = byte_to_symbol ? byte_to_symbol[b] : (uint8_t)b;
+
+    // ---- absorbing states -------------------------------------------------
+    std::vector<uint8_t> absorbing(nq, 1);
+    for (uint32_t s = 0; s < nq; ++s)
+        for (uint32_t a = 0; a < nsym; ++a)
+            if (delta[(uint64_t)s * nsym + a] != s) { absorbing[s] = 0; break; }
+    uint32_t nabs = 0;
+    for (auto v : absorbing) nabs += v;
+
+    // ---- alphabet classes over the bytes in Sigma ------------------------
+    std::vector<int> sym_class(nsym, -1);
+    std::vector<uint32_t> class_sym;  // representative symbol of each class
+    std::unordered_map<std::string, int> col_id;
+    std::string col(nq * sizeof(uint32_t), '\0');
+    int byte_class[256];
+    for (int b = 0; b < 256; ++b) {
+        uint32_t a = b2s[b];
+        if (a >= nsym) { byte_class[b] = -1; continue; }
+        if (sym_class[a] < 0) {
+            for (uint32_t s = 0; s < nq; ++s) {
+                uint32_t t = delta[(uint64_t)s * nsym + a];
+                std::memcpy(&col[s * 4], &t, 4);
+            }
+            auto it = col_id.find(col);
+            if (it == col_id.end()) {
+                int c = (int)class_sym.size();
+                col_id.emplace(col, c);
+                class_sym.push_back(a);
+                sym_class[a] = c;
+            } else {
+                sym_class[a] = it->second;
+            }
+        }
+        byte_class[b] = sym_class[a];
+    }
+    const uint32_t K = (uint32_t)std::max<size_t>(class_sym.size(), 1);
+    const uint32_t Qp = (nq + 1) & ~1u;            // even, so columns stay 4-byte aligned
+    const uint32_t colstride = 2 * Qp;
+    const uint64_t table_bytes = align_up((uint64_t)K * colstride, 16);
+    const int lds = device_lds_bytes();
+    if (lds <= 0) return fail(DFA_E_DEVICE, "dfa_create: no HIP device");
+    if (table_bytes + 1024 > (uint64_t)lds)
+        return fail(DFA_E_TOOBIG, "dfa_create: compressed table (" + std::to_string(table_bytes) +
+                                      " B) does not fit in LDS");
+
+    // ---- class-major table, LUT ------------------------------------------
+    std::vector<uint16_t> table(table_bytes / 2, 0);
+    for (uint32_t c = 0; c < class_sym.size(); ++c)
+        for (uint32_t s = 0; s < nq; ++s)
+            table[(size_t)c * Qp + s] = (uint16_t)(2 * delta[(uint64_t)s * nsym + class_sym[c]]);
+    std::vector<uint32_t> lut(256);
+    for (int b = 0; b < 256; ++b)
+        lut[b] = byte_class[b] < 0 ? kLutInvalid
+                                   : ((uint32_t)byte_class[b] << 24) | ((uint32_t)byte_class[b] * colstride);
+
+    // ---- per-class sets: mode 1 = I_c (Eq. 11), mode 0 = all non-absorbing
+    std::vector<uint32_t> off[2];
+    std::vector<uint16_t> st[2], pos[2];
+    uint32_t setmax[2] = {0, 0};
+    double mean_iset = 0.0;
+    int nvalid_bytes = 0;
+    std::vector<uint32_t> class_size(K, 0);
+    for (int mode = 0; mode < 2; ++mode) {
+        off[mode].assign(K + 1, 0);
+        pos[mode].assign((size_t)K * nq, kBadPos);
+        for (uint32_t c = 0; c < K; ++c) {
+            std::vector<uint8_t> in(nq, 0);
+            if (mode == 1) {
+                if (c < class_sym.size())
+                    for (uint32_t x = 0; x < nq; ++x) in[delta[(uint64_t)x * nsym + class_sym[c]]] = 1;
+            } else {
+                std::fill(in.begin(), in.end(), 1);
+            }
+            off[mode][c] = (uint32_t)st[mode].size();
+            for (uint32_t s = 0; s < nq; ++s) {
+                if (absorbing[s]) {
+                    pos[mode][(size_t)c * nq + s] = (uint16_t)(kTerm | s);
+                } else if (in[s]) {
+                    pos[mode][(size_t)c * nq + s] = (uint16_t)(st[mode].size() - off[mode][c]);
+                    st[mode].push_back((uint16_t)s);
+                }
+            }
+            uint32_t sz = (uint32_t)st[mode].size() - off[mode][c];
+            setmax[mode] = std::max(setmax[mode], sz);
+            if (mode == 1) class_size[c] = sz;
+        }
+        off[mode][K] = (uint32_t)st[mode].size();
+        if (st[mode].empty()) st[mode].push_back(0);  // keep the device array non-empty
+    }
+    for (int b = 0; b < 256; ++b)
+        if (byte_class[b] >= 0) { mean_iset += class_size[byte_class[b]]; ++nvalid_bytes; }
+    if (nvalid_bytes) mean_iset /= nvalid_bytes;
+
+    std::vector<uint32_t> accept_bits((nq + 31) / 32, 0);
+    for (uint32_t k = 0; k < nacc; ++k) accept_bits[accepting[k] >> 5] |= 1u << (accepting[k] & 31);
+
+    // ---- one device arena ---------------------------------------------------
+    struct Piece { const void *src; size_t bytes; size_t at; };
+    std::vector<Piece> pieces;
+    size_t at = 0;
+    auto add = [&](const void *src, size_t bytes) {
+        at = align_up(at, 256);
+        pieces.push_back({src, bytes, at});
+        at += bytes;
+        return pieces.size() - 1;
+    };
+    size_t i_table = add(table.data(), table.size() * 2);
+    size_t i_lut = add(lut.data(), lut.size() * 4);
+    size_t i_off[2], i_st[2], i_pos[2];
+    for (int m = 0; m < 2; ++m) {
+        i_off[m] = add(off[m].data(), off[m].size() * 4);
+        i_st[m] = add(st[m].data(), st[m].size() * 2);
+        i_pos[m] = add(pos[m].data(), pos[m].size() * 2);
+    }
+    size_t i_acc = add(accept_bits.data(), accept_bits.size() * 4);
+    const size_t arena_bytes = align_up(at, 256);
+
+    dfa *d = new (std::nothrow) dfa();
+    if (!d) return fail(DFA_E_NOMEM, "dfa_create: host allocation failed");
+    hipError_t e = hipGetDevice(&d->device);
+    if (e != hipSuccess) { delete d; return hip_fail(e, "hipGetDevice"); }
+    e = hipMalloc(&d->arena, arena_bytes);
+    if (e != hipSuccess) { delete d; return fail(DFA_E_NOMEM, "dfa_create: hipMalloc failed"); }
+    std::vector<uint8_t> staging(arena_bytes, 0);
+    for (auto &p : pieces) std::memcpy(staging.data() + p.at, p.src, p.bytes);
+    e = hipMemcpy(d->arena, staging.data(), arena_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d->arena);
+        delete d;
+        return hip_fail(e, "hipMemcpy (dfa_create)");
+    }
+    auto ptr = [&](size_t i) { return (const void *)((const uint8_t *)d->arena + pieces[i].at); };
+    d->arena_bytes = arena_bytes;
+    d->nsym = nsym;
+    DevDFA &v = d->dev;
+    v.table = (const uint16_t *)ptr(i_table);
+    v.lut = (const uint32_t *)ptr(i_lut);
+    for (int m = 0; m < 2; ++m) {
+        v.set_off[m] = (const uint32_t *)ptr(i_off[m]);
+        v.set_st[m] = (const uint16_t *)ptr(i_st[m]);
+        v.pos[m] = (const uint16_t *)ptr(i_pos[m]);
+        v.setmax[m] = setmax[m];
+        d->setmax_host[m] = setmax[m];
+    }
+    v.accept_bits = (const uint32_t *)ptr(i_acc);
+    v.nq = nq;
+    v.nclass = K;
+    v.colstride = colstride;
+    v.table_bytes = (uint32_t)table_bytes;
+    v.q0 = q0;
+
+    dfa_info_t &inf = d->info;
+    inf.num_states = nq;
+    inf.num_symbols = nsym;
+    inf.num_classes = (uint32_t)class_sym.size();
+    inf.num_absorbing = nabs;
+    inf.imax = setmax[1];
+    inf.q0 = q0;
+    inf.mean_iset = mean_iset;
+    inf.table_bytes = table_bytes;
+    inf.device_bytes = arena_bytes;
+    *out = d;
+    return DFA_OK;
+}
+
+extern "C" void dfa_destroy(dfa_t *d) {
+    if (!d) return;
+    if (d->arena) (void)hipFree(d->arena);
+    delete d;
+}
+
+extern "C" int dfa_info(const dfa_t *d, dfa_info_t *out) {
+    if (!d || !out) return fail(DFA_E_INVAL, "dfa_info: NULL argument");
+    *out = d->info;
+    return DFA_OK;
+}

@@ -1,0 +1,452 @@
+// HIP kernels of the speculative DFA membership test for gfx950 (wave64).
+//
+// Chunk matcher (Algorithm 3's parallel loop; Section 4.2): one wavefront
+// takes one chunk c_i = w[i*C, min((i+1)*C, n)).  Chunk 0 is walked from the
+// start state only; chunk i >= 1 from every state of I_sigma, sigma being the
+// class of the chunk's reverse-lookahead byte w[i*C - 1] (Eq. 11).  The
+// states of the set are spread across the 64 lanes and KS "slots" per lane
+// (state p of the set -> lane p % 64, slot p / 64), so one wave issues KS
+// independent table lookups per input byte.  The class-major transition
+// table T[c][s] (entries premultiplied to byte offsets) is staged in LDS, so a
+// step is one add and one ds_read_u16.  The 64 lanes translate a 64-byte
+// block of input through the byte->class LUT in one go (one byte per lane,
+// coalesced); v_readlane then hands each byte's column offset to the whole
+// wave as a scalar.
+//
+// Combination (Eqs. 8-9): the sparse state map of chunk i stores, for each
+// state of its set, where the walk ends: the end state's position in the next
+// chunk's set, or kTerm|state once the state is absorbing or the chunk is the
+// last.  Composing G consecutive maps (Eq. 9) yields a map of the same form
+// whose domain is the first chunk's set, so a tree of compose levels reduces
+// all maps to one; chunk 0's domain is the single start state, so the top
+// map has one entry: the final state.  A down-sweep over the same levels
+// recovers the state at every chunk boundary (Eq. 8 applied left to right).
+#include "dfa_internal.h"
+
+namespace dfaspec {
+
+constexpr int kWave = 64;
+constexpr int kMaxSlots = 16;   // states per lane per pass: up to 1024 per wave
+
+struct MatchArgs {
+    DevDFA d;
+    const uint8_t *in;
+    uint64_t n;
+    uint64_t chunk;
+    uint32_t nch;
+    uint32_t start;
+    uint32_t mode;      // 1 = initial-state sets, 0 = all non-absorbing states
+    uint32_t stride;    // map entries per chunk
+    uint16_t *maps;
+    uint16_t *msize;
+};
+
+__device__ __forceinline__ uint16_t lds_u16(const uint8_t *base, uint32_t byte_off) {
+    return *reinterpret_cast<const uint16_t *>(base + byte_off);
+}
+
+// One pass over the chunk [beg, end) for up to KS * 64 start states.  st[j]
+// holds 2 * state (a byte offset inside a table column).  Returns true in
+// every lane if some byte of the chunk is outside Sigma.
+template <int KS>
+__device__ __forceinline__ bool walk_pass(const uint8_t *tab, const uint32_t *lut,
+                                          const uint8_t *__restrict__ in, uint64_t beg,
+                                          uint64_t end, uint32_t (&st)[KS > 0 ? KS : 1],
+                                          uint32_t lane) {
+    bool bad = false;
+    uint64_t blk = beg;
+    uint32_t nb = (uint32_t)min<uint64_t>(kWave, end - blk);
+    uint32_t byte = lane < nb ? in[blk + lane] : 0u;
+    while (true) {
+        uint32_t e = lut[byte];
+        bool inval = (lane < nb) && (e == kLutInvalid);
+        bad |= inval;
+        uint32_t co = (e == kLutInvalid) ? 0u : (e & 0xFFFFFFu);
+        // prefetch the next block's bytes while this block is walked
+        uint64_t nblk = blk + kWave;
+        uint32_t nnb = nblk < end ? (uint32_t)min<uint64_t>(kWave, end - nblk) : 0u;
+        uint32_t nbyte = lane < nnb ? in[nblk + lane] : 0u;
+        if (KS > 0) {
+            if (nb == kWave) {
+#pragma unroll 16
+                for (int t = 0; t < kWave; ++t) {
+                    uint32_t s = __builtin_amdgcn_readlane(co, t);
+#pragma unroll
+                    for (int j = 0; j < KS; ++j) st[j] = lds_u16(tab, s + st[j]);
+                }
+            } else {
+                for (uint32_t t = 0; t < nb; ++t) {
+                    uint32_t s = __builtin_amdgcn_readlane(co, t);
+#pragma unroll
+                    for (int j = 0; j < KS; ++j) st[j] = lds_u16(tab, s + st[j]);
+                }
+            }
+        }
+        if (nnb == 0) break;
+        blk = nblk;
+        nb = nnb;
+        byte = nbyte;
+    }
+    return __builtin_amdgcn_read_exec() != 0 && __any(bad);
+}
+
+template <int KS>
+__device__ __forceinline__ bool run_pass(const MatchArgs &a, const uint8_t *tab,
+                                         const uint32_t *lut, uint32_t chunk_id, uint64_t beg,
+                                         uint64_t end, const uint16_t *set, uint32_t base,
+                                         uint32_t m, uint32_t next_class, uint32_t lane) {
+    uint32_t st[KS > 0 ? KS : 1];
+#pragma unroll
+    for (int j = 0; j < (KS > 0 ? KS : 1); ++j) {
+        uint32_t p = base + j * kWave + lane;
+        uint32_t s = 0;
+        if (p < m) s = set ? set[p] : a.start;
+        st[j] = 2u * s;
+    }
+    bool bad = walk_pass<KS>(tab, lut, a.in, beg, end, st, lane);
+    if (KS > 0) {
+        const bool last = (chunk_id + 1 == a.nch);
+        const uint16_t *pos = a.d.pos[a.mode] + (size_t)next_class * a.d.nq;
+        uint16_t *out = a.maps + (size_t)chunk_id * a.stride;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            uint32_t p = base + j * kWave + lane;
+            if (p < m) {
+                uint32_t e = st[j] >> 1;
+                out[p] = last ? (uint16_t)(kTerm | e) : pos[e];
+            }
+        }
+    }
+    return bad;
+}
+
+// Calls run_pass<ks> for a runtime ks in 1..K (a chain of uniform branches).
+template <int K>
+__device__ __forceinline__ bool dispatch_pass(uint32_t ks, const MatchArgs &a, const uint8_t *tab,
+                                              const uint32_t *lut, uint32_t chunk_id,
+                                              uint64_t beg, uint64_t end, const uint16_t *set,
+                                              uint32_t base, uint32_t m, uint32_t next_class,
+                                              uint32_t lane) {
+    if constexpr (K == 0) {
+        return false;
+    } else {
+        if (ks == K)
+            return run_pass<K>(a, tab, lut, chunk_id, beg, end, set, base, m, next_class, lane);
+        return dispatch_pass<K - 1>(ks, a, tab, lut, chunk_id, beg, end, set, base, m,
+                                    next_class, lane);
+    }
+}
+
+__global__ __launch_bounds__(1024, 8) void k_match(MatchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint8_t *tab = smem;
+    const uint32_t *lut = reinterpret_cast<const uint32_t *>(smem + a.d.table_bytes);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.d.table);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
+        for (uint32_t i = threadIdx.x; i < a.d.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
+        const uint4 *lsrc = reinterpret_cast<const uint4 *>(a.d.lut);
+        uint4 *ldst = reinterpret_cast<uint4 *>(smem + a.d.table_bytes);
+        for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) ldst[i] = lsrc[i];
+    }
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t waves = blockDim.x / kWave;
+    for (uint32_t c = blockIdx.x * waves + wave; c < a.nch; c += gridDim.x * waves) {
+        const uint64_t beg = (uint64_t)c * a.chunk;
+        const uint64_t end = min(beg + a.chunk, a.n);
+        const uint16_t *set = nullptr;
+        uint32_t m = 1;
+        if (c > 0) {
+            uint32_t e = lut[a.in[beg - 1]];
+            if (e == kLutInvalid) {
+                m = 0;   // the preceding chunk reports the byte
+            } else {
+                uint32_t cls = e >> 24;
+                uint32_t o0 = a.d.set_off[a.mode][cls];
+                m = a.d.set_off[a.mode][cls + 1] - o0;
+                set = a.d.set_st[a.mode] + o0;
+            }
+        }
+        uint32_t next_class = 0;
+        if (c + 1 < a.nch) {
+            uint32_t e = lut[a.in[end - 1]];
+            next_class = (e == kLutInvalid) ? 0u : (e >> 24);
+        }
+        bool bad = false;
+        if (m == 0) {
+            bad = run_pass<0>(a, tab, lut, c, beg, end, set, 0, 0, next_class, lane);
+        } else {
+            for (uint32_t base = 0; base < m; base += kMaxSlots * kWave) {
+                const uint32_t ks = min<uint32_t>(kMaxSlots, (m - base + kWave - 1) / kWave);
+                bad |= dispatch_pass<kMaxSlots>(ks, a, tab, lut, c, beg, end, set, base, m,
+                                                next_class, lane);
+            }
+        }
+        if (lane == 0) a.msize[c] = (uint16_t)(m | (bad ? kFlagSymbol : 0));
+    }
+}
+
+// Compose G consecutive maps of one level into one map of the next (Eq. 9).
+__global__ __launch_bounds__(256) void k_compose(const uint16_t *__restrict__ in_maps,
+                                                 const uint16_t *__restrict__ in_msize,
+                                                 uint32_t n_in, uint32_t stride, uint32_t G,
+                                                 uint16_t *__restrict__ out_maps,
+                                                 uint16_t *__restrict__ out_msize) {
+    extern __shared__ __align__(16) uint16_t sm[];
+    __shared__ uint32_t flag;
+    const uint32_t g = blockIdx.x;
+    const uint32_t first = g * G;
+    const uint32_t cnt = min(G, n_in - first);
+    if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    if (threadIdx.x < cnt && (in_msize[first + threadIdx.x] & kFlagSymbol)) atomicOr(&flag, 1u);
+    const uint16_t *src = in_maps + (size_t)first * stride;
+    const uint32_t entries = cnt * stride;
+    for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) sm[i] = src[i];
+    __syncthreads();
+    const uint32_t m = in_msize[first] & 0x7FFFu;
+    for (uint32_t p = threadIdx.x; p < m; p += blockDim.x) {
+        uint32_t v = sm[p];
+        for (uint32_t t = 1; t < cnt && !(v & kTerm); ++t) {
+            v = (v < stride) ? sm[t * stride + v] : kBadPos;
+        }
+        out_maps[(size_t)g * stride + p] = (uint16_t)v;
+    }
+    if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m | (flag ? kFlagSymbol : 0));
+}
+
+// Down-sweep: the value at the start of group g (bv_up[g], or position 0 at
+// the top) is pushed through the group's member maps; bv_l[i] receives the
+// value at the start of member i.
+__global__ void k_down(const uint16_t *__restrict__ maps_l, uint32_t n_l, uint32_t stride,
+                       uint32_t G, const uint16_t *__restrict__ bv_up, uint32_t n_up,
+                       uint16_t *__restrict__ bv_l) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_up) return;
+    uint32_t v = bv_up ? bv_up[g] : 0u;
+    const uint32_t first = g * G;
+    const uint32_t cnt = min(G, n_l - first);
+    for (uint32_t t = 0; t < cnt; ++t) {
+        bv_l[first + t] = (uint16_t)v;
+        if (!(v & kTerm)) v = (v < stride) ? maps_l[(size_t)(first + t) * stride + v] : kBadPos;
+    }
+}
+
+// Level-0 boundary values -> states in the caller's numbering.
+__global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
+                               uint32_t nch, uint32_t start, uint32_t mode,
+                               const uint16_t *__restrict__ bv0, uint32_t *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    const uint32_t v = bv0[i];
+    uint32_t s;
+    if (v & kTerm) {
+        s = v & 0x7FFFu;
+    } else if (i == 0) {
+        s = start;
+    } else {
+        const uint32_t e = d.lut[in[(uint64_t)i * chunk - 1]];
+        if (e == kLutInvalid) {
+            s = 0xFFFFFFFFu;
+        } else {
+            const uint32_t cls = e >> 24;
+            const uint32_t o0 = d.set_off[mode][cls];
+            s = (v < d.set_off[mode][cls + 1] - o0) ? d.set_st[mode][o0 + v] : 0xFFFFFFFFu;
+        }
+    }
+    out[i] = s;
+}
+
+__global__ void k_finalize(DevDFA d, const uint16_t *__restrict__ top_map,
+                           const uint16_t *__restrict__ top_msize, uint32_t nch,
+                           uint32_t *__restrict__ result, uint32_t *__restrict__ boundaries) {
+    if (threadIdx.x != 0) return;
+    const uint32_t v = top_map[0];
+    uint32_t flags = 0, fin = 0xFFFFFFFFu, acc = 0;
+    if (top_msize[0] & kFlagSymbol) {
+        flags |= DFA_FLAG_SYMBOL;
+    } else if (!(v & kTerm) || (v & 0x7FFFu) >= d.nq) {
+        flags |= DFA_FLAG_SPECULATION;
+    } else {
+        fin = v & 0x7FFFu;
+        acc = (d.accept_bits[fin >> 5] >> (fin & 31)) & 1u;
+    }
+    result[0] = fin;
+    result[1] = acc;
+    result[2] = flags;
+    result[3] = nch;
+    if (boundaries) boundaries[nch] = fin;
+}
+
+__global__ void k_empty(DevDFA d, uint32_t start, uint32_t *__restrict__ result,
+                        uint32_t *__restrict__ boundaries) {
+    if (threadIdx.x != 0) return;
+    result[0] = start;
+    result[1] = (d.accept_bits[start >> 5] >> (start & 31)) & 1u;
+    result[2] = 0;
+    result[3] = 0;
+    if (boundaries) boundaries[0] = start;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+struct DevProps {
+    int lds = 0;
+    int cus = 0;
+    bool ok = false;
+};
+DevProps &props() {
+    static std::mutex mu;
+    static DevProps cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        static DevProps none;
+        return none;
+    }
+    DevProps &p = cache[dev];
+    std::lock_guard<std::mutex> lk(mu);
+    if (!p.ok) {
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) {
+            p.lds = (int)pr.maxSharedMemoryPerMultiProcessor;
+            if (p.lds <= 0) p.lds = (int)pr.sharedMemPerBlock;
+            if ((int)pr.sharedMemPerBlock < p.lds) {
+                // dynamic LDS beyond the default per-block limit needs opting in
+                if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_match),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        p.lds) != hipSuccess)
+                    p.lds = (int)pr.sharedMemPerBlock;
+                (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_compose),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, p.lds);
+            }
+            p.cus = pr.multiProcessorCount;
+            p.ok = true;
+        }
+    }
+    return p;
+}
+}  // namespace
+
+int device_lds_bytes() { return props().lds; }
+int device_cu_count() { return props().cus; }
+
+int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p) {
+    *p = MatchPlan();
+    p->n = n;
+    p->lookahead = lookahead ? 1u : 0u;
+    const uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead], 1u);
+    p->stride = (setmax + 7u) & ~7u;
+    const int lds = device_lds_bytes();
+    const int cus = std::max(device_cu_count(), 1);
+    const uint32_t footprint = d->dev.table_bytes + 1024u;
+    const uint32_t wg_per_cu = std::max<uint32_t>(1u, std::min<uint32_t>(8u, (uint32_t)lds / footprint));
+    p->waves_per_block = std::min<uint32_t>(16u, std::max<uint32_t>(4u, (32u + wg_per_cu - 1) / wg_per_cu));
+    if (n == 0) return DFA_OK;
+    uint64_t chunk = chunk_req;
+    if (chunk == 0) {
+        const uint64_t conc = (uint64_t)cus * std::min<uint32_t>(32u, wg_per_cu * p->waves_per_block);
+        const uint64_t target = 4 * conc;
+        chunk = (n + target - 1) / target;
+        chunk = (chunk + 63) / 64 * 64;
+        chunk = std::max<uint64_t>(chunk, 256);
+    }
+    p->chunk = chunk;
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
+    p->nch = (uint32_t)nch;
+    // compose fan-in: G maps of `stride` entries staged in LDS
+    const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);
+    p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(64, stage / (2ull * p->stride)));
+    uint64_t cnt = nch, moff = 0, soff = 0;
+    uint32_t L = 0;
+    p->level_count[0] = (uint32_t)cnt;
+    p->level_off[0] = 0;
+    p->msize_off[0] = 0;
+    moff += cnt * p->stride;
+    soff += cnt;
+    while (cnt > 1) {
+        if (L + 1 >= kMaxLevels) return fail(DFA_E_TOOBIG, "too many compose levels");
+        cnt = (cnt + p->group - 1) / p->group;
+        ++L;
+        p->level_count[L] = (uint32_t)cnt;
+        p->level_off[L] = moff;
+        p->msize_off[L] = soff;
+        moff += cnt * p->stride;
+        soff += cnt;
+    }
+    p->levels = L;
+    p->map_entries = moff;
+    p->msize_entries = soff;
+    p->blocks = (uint32_t)std::min<uint64_t>((nch + p->waves_per_block - 1) / p->waves_per_block,
+                                             0x7FFFFFFFull);
+    return DFA_OK;
+}
+
+int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
+                 uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
+                 uint32_t *d_boundaries, hipStream_t s, hipEvent_t ev_after_match) {
+    if (p.n == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, d->dev, start, d_result, d_boundaries);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && ev_after_match) e = hipEventRecord(ev_after_match, s);
+        return e == hipSuccess ? DFA_OK : hip_fail(e, "k_empty launch");
+    }
+    MatchArgs a;
+    a.d = d->dev;
+    a.in = d_in;
+    a.n = p.n;
+    a.chunk = p.chunk;
+    a.nch = p.nch;
+    a.start = start;
+    a.mode = p.lookahead;
+    a.stride = p.stride;
+    a.maps = maps + p.level_off[0];
+    a.msize = msize + p.msize_off[0];
+    const size_t lds_match = d->dev.table_bytes + 1024u;
+    hipLaunchKernelGGL(k_match, dim3(p.blocks), dim3(p.waves_per_block * kWave), lds_match, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_match launch");
+    if (ev_after_match) {
+        e = hipEventRecord(ev_after_match, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    for (uint32_t l = 0; l < p.levels; ++l) {
+        const size_t lds = (size_t)p.group * p.stride * 2u;
+        hipLaunchKernelGGL(k_compose, dim3(p.level_count[l + 1]), dim3(256), lds, s,
+                           maps + p.level_off[l], msize + p.msize_off[l], p.level_count[l],
+                           p.stride, p.group, maps + p.level_off[l + 1],
+                           msize + p.msize_off[l + 1]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "k_compose launch");
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d->dev, maps + p.level_off[p.levels],
+                       msize + p.msize_off[p.levels], p.nch, d_result, d_boundaries);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_finalize launch");
+    if (d_boundaries) {
+        // bvals reuses the msize offsets (one value per map at every level)
+        for (int l = (int)p.levels; l >= 1; --l) {
+            const uint32_t n_up = p.level_count[l];
+            const uint16_t *up = (l == (int)p.levels) ? nullptr : bvals + p.msize_off[l];
+            hipLaunchKernelGGL(k_down, dim3((n_up + 255) / 256), dim3(256), 0, s,
+                               maps + p.level_off[l - 1], p.level_count[l - 1], p.stride, p.group,
+                               up, n_up, bvals + p.msize_off[l - 1]);
+        }
+        if (p.levels == 0) {
+            hipLaunchKernelGGL(k_down, dim3(1), dim3(256), 0, s, maps, 1u, p.stride, 1u,
+                               (const uint16_t *)nullptr, 1u, bvals);
+        }
+        hipLaunchKernelGGL(k_bound_states, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev,
+                           d_in, p.chunk, p.nch, start, p.lookahead, bvals, d_boundaries);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "boundary kernels launch");
+    }
+    return DFA_OK;
+}
+
+}  // namespace dfaspec

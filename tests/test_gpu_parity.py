@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit-exact.
+
+Every final state, accept bit and chunk-boundary state must equal the oracle's
+sequential walk (Algorithm 1) on the same seeded input: tolerance 0 (integer
+work; the final state is unique).  Sizes span many chunks and ragged tails;
+the bench configuration (C2 at 256 MiB, planner chunking) is checked in
+full."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import load_golden
+from workloads import configs, from_pattern, patterns, random_dfa, column_dfa, streams
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dfa_mod():
+    import torch
+    import paper_1210_5093_amd as dfa
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dfa.lib()
+    return dfa
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.array(x, dtype=np.uint8, copy=True)).to("cuda")
+
+
+def gpu_run(dfa, d, x, chunk=0, lookahead=1, start=None, boundaries=True):
+    import torch
+    t = to_dev(x)
+    res, bnd = dfa.dfa_match_ex(d, t, start=start, chunk_len=chunk, lookahead=lookahead,
+                                boundaries=boundaries)
+    torch.cuda.synchronize()
+    fin, acc, flags, nch = dfa.result_tuple(res)
+    b = None if bnd is None else (bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF)
+    return fin, acc, flags, nch, b
+
+
+def check(dfa, w, x, chunk=0, lookahead=1, start=None, boundaries=True):
+    """Run on the GPU and compare everything with the oracle."""
+    d = dfa.DFA.from_workload(w)
+    s0 = w.q0 if start is None else start
+    fin, acc, flags, nch, b = gpu_run(dfa, d, x, chunk, lookahead, start, boundaries)
+    ofin, _ = oracle.walk(w.delta, w.byte_to_symbol, s0, x)
+    oacc = oracle.accepts(ofin, w.accepting)
+    assert flags == 0, f"flags {flags}"
+    assert (fin, acc) == (ofin, oacc), f"gpu {(fin, acc)} oracle {(ofin, oacc)}"
+    if boundaries:
+        used_chunk, n_ch = dfa.dfa_plan_chunks(d, len(x), chunk, lookahead)
+        assert nch == n_ch
+        probes = [min(i * used_chunk, len(x)) for i in range(nch + 1)]
+        _, ps = oracle.walk(w.delta, w.byte_to_symbol, s0, x, probes=probes)
+        bad = np.nonzero(b != ps)[0]
+        assert bad.size == 0, f"boundary mismatch at chunks {bad[:10]}: {b[bad[:10]]} vs {ps[bad[:10]]}"
+    d.close()
+    return fin, acc, nch
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked examples
+# ---------------------------------------------------------------------------
+def golden_workload(name):
+    from workloads.dfas import DFA as W
+    g = load_golden(name)
+    b2s = np.full(256, 0xFF, dtype=np.uint8)
+    for i, ch in enumerate(g["symbols"]):
+        b2s[ord(ch)] = i
+    return g, W(np.asarray(g["delta"], dtype=np.uint32), g["q0"],
+                np.asarray(g["accepting"], dtype=np.uint32), b2s, name)
+
+
+def test_motivating_example_printed_values(dfa_mod):
+    g, w = golden_workload("motivating_dfa.json")
+    x = np.frombuffer(g["input"].encode(), dtype=np.uint8)
+    d = dfa_mod.DFA.from_workload(w)
+    fin, acc, flags, nch, b = gpu_run(dfa_mod, d, x, chunk=4)
+    assert flags == 0 and nch == 3
+    assert fin == g["printed"]["final_state"] and acc == g["printed"]["accepted"]
+    assert b.tolist() == g["printed"]["boundary_states"]
+    info = d.info()
+    assert info.imax == g["printed"]["imax"] and info.num_absorbing == 1
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 3, 5, 7, 12, 18, 64])
+def test_example_dfa_all_chunkings(dfa_mod, chunk):
+    g, w = golden_workload("example_dfa.json")
+    for key in ("input36", "input20"):
+        x = np.frombuffer(g[key].encode(), dtype=np.uint8)
+        fin, acc, _ = check(dfa_mod, w, x, chunk=chunk)
+        assert fin == g["derived"]["final_state_" + key]
+
+
+# ---------------------------------------------------------------------------
+# C1: 16-state random DFA over bytes, 1 MiB
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_c1_full_size(dfa_mod, seed):
+    w = configs.c1_dfa(seed)
+    x = configs.c1_input()
+    say("C1 seed", seed)
+    check(dfa_mod, w, x)                    # planner chunking
+    check(dfa_mod, w, x, chunk=4099)        # ragged tail
+
+
+@pytest.mark.parametrize("chunk", [1, 63, 64, 65, 1000, 65536, 1 << 20, 1 << 21])
+def test_c1_chunk_lengths(dfa_mod, chunk):
+    w = configs.c1_dfa(1)
+    x = configs.c1_input(300_001)
+    check(dfa_mod, w, x, chunk=chunk)
+
+
+def test_c1_lookahead_ablation_matches(dfa_mod):
+    """Algorithm 2 (every chunk from all states) and Algorithm 3 (initial-state
+    sets) give the same result as the sequential walk."""
+    w = configs.c1_dfa(2)
+    x = configs.c1_input(200_000)
+    a = check(dfa_mod, w, x, chunk=777, lookahead=0)
+    b = check(dfa_mod, w, x, chunk=777, lookahead=1)
+    assert a == b
+
+
+# ---------------------------------------------------------------------------
+# C2: ~300-state protein DFA, residues
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("chunk", [0, 100, 4096, 5000, 65536])
+def test_c2_prefix_many_chunks(dfa_mod, chunk):
+    w = configs.c2_dfa()
+    x = configs.c2_input(3 * (1 << 20) + 17)
+    check(dfa_mod, w, x, chunk=chunk)
+
+
+def test_c2_full_size_bench_configuration(dfa_mod):
+    """256 MiB, planner chunking as timed by bench.py: final state, accept and
+    every boundary state."""
+    w = configs.c2_dfa()
+    x = configs.c2_input()
+    say("C2 full", x.size)
+    check(dfa_mod, w, x)
+
+
+def test_c2_ablation_all_states(dfa_mod):
+    w = configs.c2_dfa()
+    x = configs.c2_input(1 << 20)
+    check(dfa_mod, w, x, chunk=8192, lookahead=0)
+
+
+# ---------------------------------------------------------------------------
+# C3 shapes at moderate size (the 10 GiB runs are in test_gpu_large.py)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("chunk", [4096, 65536, 1 << 20])
+def test_c3_protein_1297_states(dfa_mod, chunk):
+    w = configs.c3_protein_dfa()
+    x = configs.c3_protein_input(16 * (1 << 20) + 3)
+    say("C3 protein chunk", chunk)
+    check(dfa_mod, w, x, chunk=chunk)
+
+
+@pytest.mark.parametrize("chunk", [4096, 65536, 1 << 20])
+def test_c3_byte_512_states(dfa_mod, chunk):
+    w = configs.c3_byte_dfa()
+    x = configs.c3_byte_input(16 * (1 << 20) + 5)
+    say("C3 byte chunk", chunk)
+    check(dfa_mod, w, x, chunk=chunk)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+def test_empty_and_tiny_inputs(dfa_mod):
+    w = configs.c1_dfa(3)
+    for n in (0, 1, 2, 63, 64, 65):
+        x = configs.c1_input(n) if n else np.zeros(0, dtype=np.uint8)
+        check(dfa_mod, w, x, chunk=16)
+        check(dfa_mod, w, x)
+
+
+def test_explicit_start_state_resumes_a_stream(dfa_mod):
+    """Matching w = u v in two calls (the second starting in the first's final
+    state) equals matching w at once (associativity of Eq. 9)."""
+    import torch
+    w = configs.c2_dfa()
+    x = configs.c2_input(500_000)
+    d = dfa_mod.DFA.from_workload(w)
+    r1 = dfa_mod.result_tuple(dfa_mod.dfa_match_async(d, to_dev(x[:123_457])))
+    r2 = dfa_mod.result_tuple(dfa_mod.dfa_match_async(d, to_dev(x[123_457:]), start=r1[0]))
+    whole = dfa_mod.result_tuple(dfa_mod.dfa_match_async(d, to_dev(x)))
+    torch.cuda.synchronize()
+    assert r2[:3] == whole[:3]
+    ofin, _ = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
+    assert whole[0] == ofin
+    for s in (0, 7, w.num_states - 1):
+        check(dfa_mod, w, x[:50_000], chunk=999, start=s)
+
+
+@pytest.mark.parametrize("pos", [0, 1, 999, 1000, 1001, 4095, 4096, 49_999])
+def test_invalid_byte_is_reported(dfa_mod, pos):
+    w = configs.c2_dfa()
+    x = configs.c2_input(50_000).copy()
+    x[pos] = ord("B")   # not an amino-acid letter
+    with pytest.raises(oracle.InvalidSymbol):
+        oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
+    d = dfa_mod.DFA.from_workload(w)
+    fin, acc, flags, nch, _ = gpu_run(dfa_mod, d, x, chunk=1000, boundaries=False)
+    assert flags & dfa_mod.FLAG_SYMBOL
+    with pytest.raises(dfa_mod.DFAError) as ei:
+        dfa_mod.dfa_match(d, x)
+    assert ei.value.status == dfa_mod.DFA_E_SYMBOL
+
+
+def test_anchored_pattern_reaches_error_state(dfa_mod):
+    """Anchored pattern DFA: the non-accepting sink (q_e) is reached early and
+    carried through every later chunk unchanged."""
+    pd = patterns.pattern_dfa(32, contains=False)
+    w = from_pattern(pd)
+    x = configs.c2_input(200_000)
+    fin, acc, _ = check(dfa_mod, w, x, chunk=333)
+    assert oracle.absorbing(w.delta)[fin]
+
+
+def test_empty_initial_state_set(dfa_mod):
+    """A class whose every transition enters an absorbing state has an empty
+    I_sigma: chunks after it have no lanes and are still scanned."""
+    from workloads.dfas import DFA as W
+    rng = np.random.default_rng(5)
+    delta = rng.integers(0, 6, (7, 4)).astype(np.uint32)
+    delta[6, :] = 6          # state 6 absorbing
+    delta[:, 3] = 6          # symbol 3 always leads into it
+    b2s = np.full(256, 0xFF, dtype=np.uint8)
+    b2s[:4] = np.arange(4)
+    w = W(delta, 0, np.array([1, 6], dtype=np.uint32), b2s, "empty-iset")
+    x = rng.integers(0, 3, 20_000).astype(np.uint8)
+    x[::997] = 3
+    check(dfa_mod, w, x, chunk=50)
+    check(dfa_mod, w, x, chunk=997)
+
+
+def test_single_state_and_two_symbol_dfas(dfa_mod):
+    from workloads.dfas import DFA as W
+    b2s = np.full(256, 0xFF, dtype=np.uint8)
+    b2s[:2] = [0, 1]
+    one = W(np.zeros((1, 2), dtype=np.uint32), 0, np.array([0], dtype=np.uint32), b2s, "one")
+    x = np.random.default_rng(1).integers(0, 2, 10_000).astype(np.uint8)
+    check(dfa_mod, one, x, chunk=128)
+    parity = W(np.array([[0, 1], [1, 0]], dtype=np.uint32), 0, np.array([1], dtype=np.uint32),
+               b2s, "parity")
+    check(dfa_mod, parity, x, chunk=100)
+
+
+def test_random_dfas_many_shapes(dfa_mod):
+    rng = np.random.default_rng(2024)
+    for k in range(12):
+        q = int(rng.integers(2, 700))
+        if k % 2:
+            w = random_dfa(k, q, int(rng.integers(2, 40)), 3)
+            x = rng.integers(0, w.num_symbols, 100_000).astype(np.uint8)
+        else:
+            qq = min(q, 500)
+            w = column_dfa(k, k + 1, qq, int(rng.integers(2, 64)))
+            x = streams.uniform_bytes(k, 100_000)
+        say("random shape", k, w.num_states, w.num_symbols)
+        check(dfa_mod, w, x, chunk=int(rng.integers(50, 5000)))
+
+
+def test_host_entry_point_matches(dfa_mod):
+    w = configs.c2_dfa()
+    x = configs.c2_input(1 << 20)
+    d = dfa_mod.DFA.from_workload(w)
+    assert dfa_mod.dfa_match(d, x) == oracle.membership(w.delta, w.byte_to_symbol, w.q0,
+                                                        w.accepting, x)
+    assert dfa_mod.dfa_match(d, b"") == (w.q0, oracle.accepts(w.q0, w.accepting))
+
+
+def test_batch_equals_individual(dfa_mod):
+    import torch
+    ws = [configs.c1_dfa(1), configs.c2_dfa(), configs.c3_byte_dfa()]
+    ds = [dfa_mod.DFA.from_workload(w) for w in ws]
+    rng = np.random.default_rng(3)
+    pairs, xs = [], []
+    for i in range(20):
+        k = i % 3
+        n = int(rng.integers(0, 300_000))
+        x = configs.c2_input(n, first=i * 1000) if k == 1 else streams.uniform_bytes(i, n)
+        pairs.append(k)
+        xs.append(x)
+    ins = [to_dev(x) for x in xs]
+    res = dfa_mod.dfa_match_batch([ds[k] for k in pairs], ins).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    torch.cuda.synchronize()
+    for i, (k, x) in enumerate(zip(pairs, xs)):
+        ofin, oacc = oracle.membership(ws[k].delta, ws[k].byte_to_symbol, ws[k].q0,
+                                       ws[k].accepting, x)
+        assert (res[i, 0], bool(res[i, 1]), res[i, 2]) == (ofin, oacc, 0), i

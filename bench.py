@@ -165,6 +165,8 @@ def main() -> int:
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
     lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
+    packed = info.packed_layout != 0 and os.environ.get("DFA_KERNEL", "") != "1"
+    kernel = f"k_match2<{info.packed_layout}>" if packed else "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
     achieved = lookups / (matcher_avg_ms * 1e-3)
     line = {
@@ -194,7 +196,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "lds",
-            "kernel": "k_match",
+            "kernel": kernel,
             "achieved": round(achieved / 1e9, 2),
             "peak": round(LDS_LOOKUP_PEAK / 1e9, 1),
             "unit": "Glookup/s",

@@ -72,6 +72,10 @@ typedef struct dfa_info {
     double   mean_iset;       /* mean |I_c| over the bytes in Sigma (each byte weighted 1) */
     uint64_t table_bytes;     /* bytes of the class-major table staged in LDS */
     uint64_t device_bytes;    /* device memory held by this dfa_t */
+    uint32_t packed_layout;   /* 0: one-chunk-per-wavefront matcher only;
+                                 1: packed-pair matcher, state-major table;
+                                 2: packed-pair matcher, class-major table */
+    uint32_t reserved;
 } dfa_info_t;
 
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
@@ -165,7 +169,8 @@ int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
 
 /* ---------------------------------------------------------------------------
  * Instrumentation.  With timing on for a stream, every match call on it
- * records HIP events around its chunk-matcher kernel and around the whole
+ * records HIP events around its chunk-matcher kernel (the preparation
+ * kernels before it excluded) and around the whole
  * call (no work is skipped or reordered).  dfa_timing_read waits for those
  * events, returns the summed milliseconds and the number of calls, and
  * clears the record. */

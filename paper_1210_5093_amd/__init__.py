@@ -35,7 +35,8 @@ class dfa_info_t(ctypes.Structure):
                 ("num_classes", ctypes.c_uint32), ("num_absorbing", ctypes.c_uint32),
                 ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
                 ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("packed_layout", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class dfa_match_opts_t(ctypes.Structure):

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdfaspec.so")
-SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip"]
+PROBE = os.path.join(HERE, "lds_peak_probe")
+SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip", "dfa_match2.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions stay disabled in all device code.
@@ -36,6 +37,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # measurement program for the LDS-lookup roofline denominator
+    probe_src = os.path.join(HERE, "csrc", "lds_peak_probe.hip")
+    cmd = [HIPCC, "-O3", "-std=c++17", *DEVICE_FLAGS, "-o", PROBE + ".tmp", probe_src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

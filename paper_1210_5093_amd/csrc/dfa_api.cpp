@@ -36,7 +36,7 @@ struct Workspace {
     size_t in_bytes = 0;
     uint32_t *result = nullptr;   // 4 words for the synchronous path
     bool timing = false;
-    struct Stamp { hipEvent_t begin, after_match, end; };
+    struct Stamp { hipEvent_t begin, before_match, after_match, end; };
     std::vector<Stamp> stamps;    // one per timed call, read by dfa_timing_read
 };
 
@@ -88,25 +88,62 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     if (rc) return rc;
     Workspace *ws = workspace_for(s);
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
-    const size_t map_bytes = (p.map_entries * 2 + 255) / 256 * 256;
-    const size_t sz_bytes = (p.msize_entries * 2 + 255) / 256 * 256;
-    const size_t need = map_bytes + 2 * sz_bytes + 256;
-    rc = ensure(&ws->buf, &ws->bytes, need);
+    auto a256 = [](uint64_t b) { return (size_t)((b + 255) / 256 * 256); };
+    const size_t map_bytes = a256(p.map_entries * 2);
+    const size_t sz_bytes = a256(p.msize_entries * 2);
+    size_t need = map_bytes + 2 * sz_bytes;
+    size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0;
+    if (p.packed && len) {
+        need += a256(((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64);
+        bad_off = need;
+        need += a256((uint64_t)p.tblocks * 4);
+        bsum_off = need;
+        need += a256((uint64_t)match2_scan_blocks(p.nch) * 4 + 4);
+        first_off = need;
+        need += a256(((uint64_t)p.nch + 1) * 4);
+        tf_off = need;
+        need += a256((p.max_tiles + 1) * 4);
+        ccls_off = need;
+        need += a256((uint64_t)p.nch * 2);
+    }
+    rc = ensure(&ws->buf, &ws->bytes, need + 256);
     if (rc) return rc;
-    uint16_t *maps = (uint16_t *)ws->buf;
-    uint16_t *msize = (uint16_t *)((uint8_t *)ws->buf + map_bytes);
-    uint16_t *bvals = (uint16_t *)((uint8_t *)ws->buf + map_bytes + sz_bytes);
-    if (!ws->timing)
-        return launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s, nullptr);
+    uint8_t *base = (uint8_t *)ws->buf;
+    uint16_t *maps = (uint16_t *)base;
+    uint16_t *msize = (uint16_t *)(base + map_bytes);
+    uint16_t *bvals = (uint16_t *)(base + map_bytes + sz_bytes);
     Workspace::Stamp st{};
-    hipError_t e = hipEventCreate(&st.begin);
-    if (e == hipSuccess) e = hipEventCreate(&st.after_match);
-    if (e == hipSuccess) e = hipEventCreate(&st.end);
-    if (e == hipSuccess) e = hipEventRecord(st.begin, s);
-    if (e != hipSuccess) return hip_fail(e, "timing events");
-    rc = launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s,
-                      st.after_match);
+    hipError_t e = hipSuccess;
+    if (ws->timing) {
+        e = hipEventCreate(&st.begin);
+        if (e == hipSuccess) e = hipEventCreate(&st.before_match);
+        if (e == hipSuccess) e = hipEventCreate(&st.after_match);
+        if (e == hipSuccess) e = hipEventCreate(&st.end);
+        if (e == hipSuccess) e = hipEventRecord(st.begin, s);
+        if (e != hipSuccess) return hip_fail(e, "timing events");
+    }
+    if (p.packed && len) {
+        rc = launch_match2(d, d_in, start, p, base + code_off, (uint32_t *)(base + bad_off),
+                           (uint32_t *)(base + bsum_off), (uint32_t *)(base + first_off),
+                           (uint32_t *)(base + tf_off),
+                           (uint16_t *)(base + ccls_off), maps, msize, s,
+                           ws->timing ? st.before_match : nullptr);
+        if (rc) return rc;
+        if (ws->timing) {
+            e = hipEventRecord(st.after_match, s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        rc = launch_combine(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s);
+    } else {
+        if (ws->timing) {
+            e = hipEventRecord(st.before_match, s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        rc = launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s,
+                          ws->timing ? st.after_match : nullptr);
+    }
     if (rc) return rc;
+    if (!ws->timing) return DFA_OK;
     e = hipEventRecord(st.end, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     ws->stamps.push_back(st);
@@ -200,12 +237,13 @@ extern "C" int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms
     for (auto &st : ws->stamps) {
         float a = 0.f, b = 0.f;
         hipError_t e = hipEventSynchronize(st.end);
-        if (e == hipSuccess) e = hipEventElapsedTime(&a, st.begin, st.after_match);
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, st.before_match, st.after_match);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, st.begin, st.end);
         if (e != hipSuccess && rc == DFA_OK) rc = hip_fail(e, "dfa_timing_read");
         m += a;
         c += b;
         (void)hipEventDestroy(st.begin);
+        (void)hipEventDestroy(st.before_match);
         (void)hipEventDestroy(st.after_match);
         (void)hipEventDestroy(st.end);
     }

@@ -141,9 +141,43 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         off[mode][K] = (uint32_t)st[mode].size();
         if (st[mode].empty()) st[mode].push_back(0);  // keep the device array non-empty
     }
+    double slots = 0.0;   // wavefront slots the one-chunk-per-wave matcher would spend
     for (int b = 0; b < 256; ++b)
-        if (byte_class[b] >= 0) { mean_iset += class_size[byte_class[b]]; ++nvalid_bytes; }
+        if (byte_class[b] >= 0) {
+            mean_iset += class_size[byte_class[b]];
+            slots += 64.0 * ((class_size[byte_class[b]] + 63) / 64);
+            ++nvalid_bytes;
+        }
+    const double wave_util = slots > 0 ? mean_iset / slots : 0.0;
     if (nvalid_bytes) mean_iset /= nvalid_bytes;
+
+    // ---- packed-pair matcher layouts -------------------------------------
+    // Layout 1 keeps the byte code small (2 * class, one byte) and puts the
+    // class offset inside a state row; rows are an odd number of dwords so
+    // that distinct states of one column fall into distinct LDS banks.
+    // Layout 2 (class-major, 16-bit codes) serves alphabets with more classes.
+    uint32_t layout = 0, rowbytes = 0;
+    std::vector<uint16_t> stab;
+    std::vector<uint16_t> code(256, kCodeInvalid);
+    {
+        uint32_t R = (2 * K + 3) / 4 * 4;
+        if ((R / 4) % 2 == 0) R += 4;
+        if (2 * K <= 255 && (uint64_t)(nq - 1) * R <= 0xFFFF && (uint64_t)nq * R + 1024 <= (uint64_t)lds) {
+            layout = 1;
+            rowbytes = R;
+            stab.assign(align_up((size_t)nq * R, 16) / 2, 0);
+            for (uint32_t s = 0; s < nq; ++s)
+                for (uint32_t c = 0; c < class_sym.size(); ++c)
+                    stab[(size_t)s * (R / 2) + c] = (uint16_t)(R * delta[(uint64_t)s * nsym + class_sym[c]]);
+            for (int b = 0; b < 256; ++b)
+                if (byte_class[b] >= 0) code[b] = (uint16_t)(2 * byte_class[b]);
+        } else if ((uint64_t)(K - 1) * colstride < kCodeInvalid) {
+            layout = 2;
+            for (int b = 0; b < 256; ++b)
+                if (byte_class[b] >= 0) code[b] = (uint16_t)((uint32_t)byte_class[b] * colstride);
+        }
+    }
+    if (stab.empty()) stab.assign(8, 0);
 
     std::vector<uint32_t> accept_bits((nq + 31) / 32, 0);
     for (uint32_t k = 0; k < nacc; ++k) accept_bits[accepting[k] >> 5] |= 1u << (accepting[k] & 31);
@@ -167,6 +201,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         i_pos[m] = add(pos[m].data(), pos[m].size() * 2);
     }
     size_t i_acc = add(accept_bits.data(), accept_bits.size() * 4);
+    size_t i_code = add(code.data(), code.size() * 2);
+    size_t i_stab = add(stab.data(), stab.size() * 2);
     const size_t arena_bytes = align_up(at, 256);
 
     dfa *d = new (std::nothrow) dfa();
@@ -186,6 +222,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     auto ptr = [&](size_t i) { return (const void *)((const uint8_t *)d->arena + pieces[i].at); };
     d->arena_bytes = arena_bytes;
     d->nsym = nsym;
+    d->wave_util = wave_util;
     DevDFA &v = d->dev;
     v.table = (const uint16_t *)ptr(i_table);
     v.lut = (const uint32_t *)ptr(i_lut);
@@ -197,6 +234,11 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         d->setmax_host[m] = setmax[m];
     }
     v.accept_bits = (const uint32_t *)ptr(i_acc);
+    v.code = (const uint16_t *)ptr(i_code);
+    v.stab = (const uint16_t *)ptr(i_stab);
+    v.layout = layout;
+    v.rowbytes = rowbytes;
+    v.stab_bytes = layout == 1 ? (uint32_t)(stab.size() * 2) : (uint32_t)table_bytes;
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;
@@ -213,6 +255,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.mean_iset = mean_iset;
     inf.table_bytes = table_bytes;
     inf.device_bytes = arena_bytes;
+    inf.packed_layout = layout;
     *out = d;
     return DFA_OK;
 }

@@ -22,6 +22,7 @@ constexpr uint16_t kBadPos = 0xFFFF;      // "not in the next set": invariant vi
 constexpr uint16_t kFlagSymbol = 0x8000;  // msize bit: chunk held a byte outside Sigma
 constexpr uint32_t kLutInvalid = 0xFFFFFFFFu;
 constexpr uint32_t kMaxStates = 32767;
+constexpr uint16_t kCodeInvalid = 0xFFFF;
 
 // Device-resident compiled DFA, passed by value to kernels.
 struct DevDFA {
@@ -32,6 +33,16 @@ struct DevDFA {
     const uint16_t *pos[2];      // [K][Q]: position of s in the class's set,
                                  //  kTerm|s for absorbing s, kBadPos otherwise
     const uint32_t *accept_bits; // ceil(Q/32) words
+    // Packed-pair matcher: per-byte stream codes and the table they index.
+    //  layout 1 (state-major): code = 2 * class; stab[s][c] = R * delta(s, c),
+    //           R = row bytes; an LDS address is R * s + code.
+    //  layout 2 (class-major): code = class * colstride; the table is `table`
+    //           (entries 2 * delta); an LDS address is code + 2 * s.
+    const uint16_t *code;        // [256]; kCodeInvalid for bytes outside Sigma
+    const uint16_t *stab;        // layout 1 table (nq rows of R bytes)
+    uint32_t layout;             // 0 = packed matcher unavailable, 1, 2
+    uint32_t rowbytes;           // R (layout 1)
+    uint32_t stab_bytes;         // bytes staged for the packed matcher, multiple of 16
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -50,6 +61,7 @@ struct dfa {
     dfa_info_t info{};
     uint32_t nsym = 0;
     uint32_t setmax_host[2] = {0, 0};
+    double wave_util = 0.0;      // lane utilisation of one-chunk-per-wave matching (lookahead 1)
 };
 
 namespace dfaspec {
@@ -76,6 +88,13 @@ struct MatchPlan {
     uint64_t msize_entries = 0;
     uint32_t waves_per_block = 4;
     uint32_t blocks = 0;
+    // packed-pair matcher
+    bool packed = false;
+    uint32_t blocks2 = 0;        // persistent grid
+    uint32_t threads2 = 256;     // threads per block (more for large tables)
+    uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)
+    uint32_t code_bytes = 1;     // 1 (layout 1) or 2 (layout 2)
+    uint64_t max_tiles = 0;      // upper bound on wave-tiles of pairs
 };
 
 int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p);
@@ -83,6 +102,18 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
 int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                  uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
                  uint32_t *d_boundaries, hipStream_t s, hipEvent_t ev_after_match);
+int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
+                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
+                   uint32_t *d_boundaries, hipStream_t s);
+// ev_before_matcher (may be null) is recorded after the preparation kernels,
+// right before the packed matcher kernel.
+int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
+                  void *codes, uint32_t *block_bad, uint32_t *bsum, uint32_t *first,
+                  uint32_t *tile_first, uint16_t *ccls, uint16_t *maps, uint16_t *msize,
+                  hipStream_t s, hipEvent_t ev_before_matcher);
+int set_match2_lds_limit(int lds);
+uint32_t match2_tile_pairs();
+uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();
 int device_cu_count();
 

@@ -21,12 +21,14 @@
 // all maps to one; chunk 0's domain is the single start state, so the top
 // map has one entry: the final state.  A down-sweep over the same levels
 // recovers the state at every chunk boundary (Eq. 8 applied left to right).
+#include <cstdlib>
+
 #include "dfa_internal.h"
 
 namespace dfaspec {
 
 constexpr int kWave = 64;
-constexpr int kMaxSlots = 16;   // states per lane per pass: up to 1024 per wave
+constexpr int kMaxSlots = 8;    // states per lane per pass: up to 512 per wave (64 VGPRs, no spills)
 
 struct MatchArgs {
     DevDFA d;
@@ -323,6 +325,7 @@ DevProps &props() {
                     p.lds = (int)pr.sharedMemPerBlock;
                 (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_compose),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, p.lds);
+                (void)set_match2_lds_limit(p.lds);
             }
             p.cus = pr.multiProcessorCount;
             p.ok = true;
@@ -355,6 +358,33 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         chunk = (chunk + 63) / 64 * 64;
         chunk = std::max<uint64_t>(chunk, 256);
     }
+    const char *force = std::getenv("DFA_KERNEL");
+    // Packed pairs pay a translation pass and per-lane code loads; they win
+    // when one chunk per wavefront would leave many lanes idle (sets far from
+    // a multiple of 64).  Small inputs are launch-bound; the one-chunk-per-wave
+    // path needs fewer launches.  DFA_KERNEL=1 / =2 force either kernel.
+    const bool idle_lanes = p->lookahead == 0 ? false : d->wave_util < 0.85;
+    p->packed = d->dev.layout != 0 && !(force && force[0] == '1') &&
+                ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'));
+    if (p->packed) {
+        const uint32_t per_cu = std::max<uint32_t>(
+            1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(d->dev.stab_bytes, 1024u)));
+        // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
+        p->threads2 = 64u * std::min<uint32_t>(16u, std::max<uint32_t>(4u, (32u + per_cu - 1) / per_cu));
+        p->blocks2 = (uint32_t)cus * per_cu;
+        p->code_bytes = d->dev.layout == 1 ? 1u : 2u;
+        p->tblocks = (uint32_t)std::min<uint64_t>((n + 4095) / 4096, (uint64_t)cus * 8u);
+        if (chunk_req == 0) {
+            // about six wave-tiles of pairs per resident wavefront
+            const double mean = std::max(1.0, p->lookahead ? d->info.mean_iset
+                                                            : (double)d->setmax_host[0]);
+            const double tiles = 6.0 * p->blocks2 * (p->threads2 / 64.0);
+            const double nch_target = tiles * match2_tile_pairs() / mean;
+            chunk = (uint64_t)((double)n / std::max(1.0, nch_target));
+            chunk = (chunk + 63) / 64 * 64;
+            chunk = std::max<uint64_t>(chunk, 256);
+        }
+    }
     p->chunk = chunk;
     const uint64_t nch = (n + chunk - 1) / chunk;
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
@@ -384,6 +414,9 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     p->msize_entries = soff;
     p->blocks = (uint32_t)std::min<uint64_t>((nch + p->waves_per_block - 1) / p->waves_per_block,
                                              0x7FFFFFFFull);
+    p->max_tiles = (nch * (uint64_t)setmax + match2_tile_pairs() - 1) / match2_tile_pairs() + 1;
+    if (p->packed && nch * (uint64_t)setmax >= 0xFFFFFFFFull)
+        return fail(DFA_E_TOOBIG, "too many (chunk, state) pairs; raise chunk_len");
     return DFA_OK;
 }
 
@@ -396,6 +429,7 @@ int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchP
         if (e == hipSuccess && ev_after_match) e = hipEventRecord(ev_after_match, s);
         return e == hipSuccess ? DFA_OK : hip_fail(e, "k_empty launch");
     }
+    if (p.packed) return fail(DFA_E_INVAL, "launch_match: plan is for the packed matcher");
     MatchArgs a;
     a.d = d->dev;
     a.in = d_in;
@@ -415,6 +449,13 @@ int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchP
         e = hipEventRecord(ev_after_match, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
+    return launch_combine(d, d_in, start, p, maps, msize, bvals, d_result, d_boundaries, s);
+}
+
+int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
+                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
+                   uint32_t *d_boundaries, hipStream_t s) {
+    hipError_t e;
     for (uint32_t l = 0; l < p.levels; ++l) {
         const size_t lds = (size_t)p.group * p.stride * 2u;
         hipLaunchKernelGGL(k_compose, dim3(p.level_count[l + 1]), dim3(256), lds, s,

@@ -26,6 +26,14 @@ def dfa_mod():
     return dfa
 
 
+@pytest.fixture(autouse=True)
+def packed_matcher_by_default(monkeypatch):
+    """Run every case through the packed-pair matcher wherever the DFA's layout
+    allows it (the planner alone would pick the one-chunk-per-wave kernel for
+    inputs under 4 MiB); tests that want the other kernel override this."""
+    monkeypatch.setenv("DFA_KERNEL", "2")
+
+
 def say(*a):
     print(*a, flush=True, file=sys.stderr)
 
@@ -299,3 +307,63 @@ def test_batch_equals_individual(dfa_mod):
         ofin, oacc = oracle.membership(ws[k].delta, ws[k].byte_to_symbol, ws[k].q0,
                                        ws[k].accepting, x)
         assert (res[i, 0], bool(res[i, 1]), res[i, 2]) == (ofin, oacc, 0), i
+
+
+# ---------------------------------------------------------------------------
+# Both matcher kernels: packed pairs (default where the layout fits) and one
+# chunk per wavefront (forced with DFA_KERNEL=1; the only one for tables that
+# need more than 64 KiB of LDS)
+# ---------------------------------------------------------------------------
+@pytest.fixture
+def one_chunk_per_wave(monkeypatch):
+    monkeypatch.setenv("DFA_KERNEL", "1")
+
+
+@pytest.mark.parametrize("chunk", [0, 1000, 4096])
+def test_first_generation_kernel_c2_and_c1(dfa_mod, one_chunk_per_wave, chunk):
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(2 * (1 << 20) + 9), chunk=chunk)
+    check(dfa_mod, configs.c1_dfa(4), configs.c1_input(300_007), chunk=chunk)
+
+
+def test_first_generation_kernel_large_sets(dfa_mod, one_chunk_per_wave):
+    check(dfa_mod, configs.c3_protein_dfa(), configs.c3_protein_input(4 * (1 << 20) + 1),
+          chunk=65536)
+
+
+def test_planner_default_small_and_large(dfa_mod, monkeypatch):
+    """Without an override: small inputs take the one-chunk-per-wave kernel,
+    large ones the packed kernel; both agree with the oracle."""
+    monkeypatch.delenv("DFA_KERNEL", raising=False)
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(1 << 20))
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(6 * (1 << 20) + 3))
+
+
+def test_layouts_reported(dfa_mod):
+    assert dfa_mod.DFA.from_workload(configs.c2_dfa()).info().packed_layout == 1
+    assert dfa_mod.DFA.from_workload(configs.c3_protein_dfa()).info().packed_layout == 1
+    assert dfa_mod.DFA.from_workload(configs.c3_byte_dfa()).info().packed_layout == 2
+    assert dfa_mod.DFA.from_workload(configs.c1_dfa(1)).info().packed_layout == 2
+
+
+def test_table_beyond_64k_uses_first_generation_kernel(dfa_mod):
+    """700 states x 80 classes = 112 KB class-major table: no packed layout
+    fits 16-bit codes, so every chunk goes through the one-chunk-per-wave path."""
+    w = column_dfa(21, 22, 700, 80)
+    d = dfa_mod.DFA.from_workload(w)
+    assert d.info().packed_layout == 0 and d.info().table_bytes > 65536
+    x = streams.uniform_bytes(21, 1_000_003)
+    check(dfa_mod, w, x)
+    check(dfa_mod, w, x, chunk=3333)
+
+
+@pytest.mark.parametrize("offset", [1, 3, 8, 15])
+def test_unaligned_device_input(dfa_mod, offset):
+    """Input tensors that start at any byte offset (torch slices)."""
+    import torch
+    w = configs.c2_dfa()
+    x = configs.c2_input(400_000 + offset)
+    t = to_dev(x)[offset:]
+    d = dfa_mod.DFA.from_workload(w)
+    r = dfa_mod.result_tuple(dfa_mod.dfa_match_async(d, t))
+    torch.cuda.synchronize()
+    assert r[:3] == (*oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x[offset:]), 0)

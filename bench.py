@@ -76,15 +76,43 @@ def set_sizes(w) -> np.ndarray:
     return sizes
 
 
+def image_sizes(w, x: np.ndarray, chunk: int, nch: int, r: int) -> np.ndarray:
+    """|image of Q under the r bytes before chunk i| minus absorbing states, i >= 1."""
+    d = w.delta.astype(np.int32)
+    nq = d.shape[0]
+    absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
+    sym = w.byte_to_symbol.astype(np.int64)
+    out = np.zeros(nch - 1, dtype=np.int64)
+    batch = max(1, (1 << 24) // max(nq, 1))
+    for b0 in range(1, nch, batch):
+        idx = np.arange(b0, min(nch, b0 + batch), dtype=np.int64)
+        p = idx * chunk
+        rr = np.minimum(r, p)
+        S = np.broadcast_to(np.arange(nq, dtype=np.int32), (idx.size, nq)).copy()
+        for t in range(int(rr.max())):
+            # step t of the lookahead string w[p - rr + t]; rows with rr <= t are done
+            live = t < rr
+            pos = np.where(live, p - rr + t, 0)
+            a = sym[x[pos]]
+            S = np.where(live[:, None], d[S, a[:, None]], S)
+        S.sort(axis=1)
+        distinct = np.concatenate([np.ones((S.shape[0], 1), bool), S[:, 1:] != S[:, :-1]], axis=1)
+        out[idx - 1] = (distinct & ~absorbing[S]).sum(axis=1)
+    return out
+
+
 def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int) -> int:
-    """len(c_0) + sum_{i>=1} |I_{sigma_i}| len(c_i) (Algorithm 3's work)."""
+    """len(c_0) + sum_{i>=1} |I_i| len(c_i) (Algorithm 3's work; I_i is the
+    chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13)."""
     n = x.size
     nch = (n + chunk - 1) // chunk
     lens = np.full(nch, chunk, dtype=np.int64)
     lens[-1] = n - chunk * (nch - 1)
     if nch == 1:
         return int(lens[0])
-    if lookahead:
+    if lookahead >= 2:
+        m = image_sizes(w, x, chunk, nch, lookahead)
+    elif lookahead == 1:
         sizes = set_sizes(w)
         look = x[chunk - 1: chunk * (nch - 1): chunk]
         m = sizes[w.byte_to_symbol[look]]
@@ -102,7 +130,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3p", "c3b"])
     ap.add_argument("--chunk", type=int, default=0, help="bytes per chunk (0 = planner)")
-    ap.add_argument("--lookahead", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--lookahead", type=int, default=1,
+                    help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
@@ -165,8 +194,8 @@ def main() -> int:
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
     lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
-    packed = info.packed_layout != 0 and os.environ.get("DFA_KERNEL", "") != "1"
-    kernel = f"k_match2<{info.packed_layout}>" if packed else "k_match"
+    plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead)
+    kernel = f"k_match2<{info.packed_layout}>" if plan.kernel == 1 else "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
     achieved = lookups / (matcher_avg_ms * 1e-3)
     line = {

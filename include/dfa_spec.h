@@ -81,9 +81,14 @@ typedef struct dfa_info {
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
 typedef struct dfa_match_opts {
     uint64_t chunk_len;       /* bytes per chunk; 0 = planner's choice */
-    uint32_t lookahead;       /* 1 = one-symbol reverse lookahead (Algorithm 3,
-                                 default); 0 = every chunk from all non-absorbing
-                                 states (Algorithm 2, the ablation) */
+    uint32_t lookahead;       /* reverse-lookahead symbols r:
+                                 1 = one-symbol sets I_sigma (Algorithm 3, default);
+                                 0 = every chunk from all non-absorbing states
+                                     (Algorithm 2, the ablation);
+                                 2..64 = the exact image of Q under the r bytes
+                                     before each chunk (Eq. 13, computed per chunk
+                                     on the device; DFAs without a packed layout
+                                     use r = 1, with the same result) */
     uint32_t reserved;
 } dfa_match_opts_t;
 
@@ -154,6 +159,17 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * number of chunks. */
 int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
                     uint64_t *chunk_len, uint64_t *num_chunks);
+
+/* What the planner picks for (d, len, opts). */
+typedef struct dfa_plan_info {
+    uint64_t chunk_len;       /* bytes per chunk */
+    uint64_t num_chunks;
+    uint32_t kernel;          /* 0: one chunk per wavefront; 1: packed (chunk, state) pairs */
+    uint32_t lookahead;       /* effective reverse-lookahead symbols r */
+    uint32_t blocks;          /* matcher grid */
+    uint32_t threads;         /* threads per block */
+} dfa_plan_info_t;
+int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 
 /* ---------------------------------------------------------------------------
  * dfa_match_batch -- many (DFA, string) pairs of uneven size in one persistent

@@ -44,6 +44,12 @@ class dfa_match_opts_t(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class dfa_plan_info_t(ctypes.Structure):
+    _fields_ = [("chunk_len", ctypes.c_uint64), ("num_chunks", ctypes.c_uint64),
+                ("kernel", ctypes.c_uint32), ("lookahead", ctypes.c_uint32),
+                ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -81,6 +87,9 @@ def lib() -> ctypes.CDLL:
     L.dfa_plan_chunks.restype = I
     L.dfa_plan_chunks.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
                                   ctypes.POINTER(U64), ctypes.POINTER(U64)]
+    L.dfa_plan.restype = I
+    L.dfa_plan.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
+                           ctypes.POINTER(dfa_plan_info_t)]
     L.dfa_match_batch.restype = I
     L.dfa_match_batch.argtypes = [P, P, P, ctypes.c_size_t, P, P]
     L.dfa_timing_enable.restype = I
@@ -201,6 +210,13 @@ def dfa_plan_chunks(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> T
     _check(lib().dfa_plan_chunks(d.handle, int(n), ctypes.byref(o), ctypes.byref(c),
                                  ctypes.byref(k)))
     return int(c.value), int(k.value)
+
+
+def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> dfa_plan_info_t:
+    out = dfa_plan_info_t()
+    o = _opts(chunk_len, lookahead)
+    _check(lib().dfa_plan(d.handle, int(n), ctypes.byref(o), ctypes.byref(out)))
+    return out
 
 
 def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,

@@ -92,7 +92,8 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     const size_t map_bytes = a256(p.map_entries * 2);
     const size_t sz_bytes = a256(p.msize_entries * 2);
     size_t need = map_bytes + 2 * sz_bytes;
-    size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0;
+    size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0,
+           bits_off = 0, mem_off = 0;
     if (p.packed && len) {
         need += a256(((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64);
         bad_off = need;
@@ -105,6 +106,12 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         need += a256((p.max_tiles + 1) * 4);
         ccls_off = need;
         need += a256((uint64_t)p.nch * 2);
+        if (p.lookahead == 2) {
+            bits_off = need;
+            need += a256((uint64_t)p.nch * p.bitmap_words * 4);
+            mem_off = need;
+            need += a256(((uint64_t)p.nch * p.stride + 1) * 2);
+        }
     }
     rc = ensure(&ws->buf, &ws->bytes, need + 256);
     if (rc) return rc;
@@ -123,17 +130,25 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         if (e != hipSuccess) return hip_fail(e, "timing events");
     }
     if (p.packed && len) {
-        rc = launch_match2(d, d_in, start, p, base + code_off, (uint32_t *)(base + bad_off),
-                           (uint32_t *)(base + bsum_off), (uint32_t *)(base + first_off),
-                           (uint32_t *)(base + tf_off),
-                           (uint16_t *)(base + ccls_off), maps, msize, s,
+        PackedBufs pb;
+        pb.codes = base + code_off;
+        pb.block_bad = (uint32_t *)(base + bad_off);
+        pb.bsum = (uint32_t *)(base + bsum_off);
+        pb.first = (uint32_t *)(base + first_off);
+        pb.tile_first = (uint32_t *)(base + tf_off);
+        pb.ccls = (uint16_t *)(base + ccls_off);
+        if (p.lookahead == 2) {
+            pb.bits = (uint32_t *)(base + bits_off);
+            pb.members = (uint16_t *)(base + mem_off);
+        }
+        rc = launch_match2(d, d_in, start, p, pb, maps, msize, s,
                            ws->timing ? st.before_match : nullptr);
         if (rc) return rc;
         if (ws->timing) {
             e = hipEventRecord(st.after_match, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
-        rc = launch_combine(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s);
+        rc = launch_combine(d, d_in, start, p, maps, msize, bvals, &pb, d_result, d_bound, s);
     } else {
         if (ws->timing) {
             e = hipEventRecord(st.before_match, s);
@@ -175,6 +190,22 @@ extern "C" int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_
     if (rc) return rc;
     if (chunk_len) *chunk_len = p.chunk;
     if (num_chunks) *num_chunks = p.nch;
+    return DFA_OK;
+}
+
+extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
+                        dfa_plan_info_t *out) {
+    if (!d || !out) return fail(DFA_E_INVAL, "dfa_plan: NULL argument");
+    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
+    MatchPlan p;
+    int rc = plan_match(d, len, chunk, opts ? opts->lookahead : 1u, &p);
+    if (rc) return rc;
+    out->chunk_len = p.chunk;
+    out->num_chunks = p.nch;
+    out->kernel = p.packed ? 1u : 0u;
+    out->lookahead = p.r;
+    out->blocks = p.packed ? p.blocks2 : p.blocks;
+    out->threads = p.packed ? p.threads2 : p.waves_per_block * 64u;
     return DFA_OK;
 }
 

@@ -77,7 +77,9 @@ struct MatchPlan {
     uint64_t n = 0;
     uint64_t chunk = 0;
     uint32_t nch = 0;
-    uint32_t lookahead = 1;
+    uint32_t lookahead = 1;      // set mode: 0 all states, 1 I_sigma, 2 exact image of r bytes
+    uint32_t r = 1;              // reverse-lookahead symbols (mode 2: r >= 2)
+    uint32_t bitmap_words = 0;   // mode 2: words per chunk bitmap
     uint32_t stride = 0;         // map entries per chunk (>= largest set)
     uint32_t group = 0;          // maps combined per compose step
     uint32_t levels = 0;         // compose levels above level 0
@@ -102,15 +104,32 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
 int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                  uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
                  uint32_t *d_boundaries, hipStream_t s, hipEvent_t ev_after_match);
+// Per-call buffers of the packed-pair matcher (workspace views).
+struct PackedBufs {
+    void *codes = nullptr;           // translated stream
+    uint32_t *block_bad = nullptr;   // per translation block: byte outside Sigma
+    uint32_t *bsum = nullptr;        // scan block sums
+    uint32_t *first = nullptr;       // [nch + 1] first pair of each chunk
+    uint32_t *tile_first = nullptr;  // owner chunk of each wave-tile's first pair
+    uint16_t *ccls = nullptr;        // lookahead (or window) class per chunk
+    uint32_t *bits = nullptr;        // r >= 2: start-set bitmaps
+    uint16_t *members = nullptr;     // r >= 2: sorted start sets, indexed by pair
+};
+// The packed path stores level-0 maps indexed by pair (maps[first[i] + p]);
+// pb is null for the one-chunk-per-wave path (maps[i * stride + p]).
 int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
-                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
-                   uint32_t *d_boundaries, hipStream_t s);
+                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
+                   uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s);
 // ev_before_matcher (may be null) is recorded after the preparation kernels,
 // right before the packed matcher kernel.
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
-                  void *codes, uint32_t *block_bad, uint32_t *bsum, uint32_t *first,
-                  uint32_t *tile_first, uint16_t *ccls, uint16_t *maps, uint16_t *msize,
-                  hipStream_t s, hipEvent_t ev_before_matcher);
+                  const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
+                  hipEvent_t ev_before_matcher);
+int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
+                    const uint16_t *msize0, uint16_t *out_maps, uint16_t *out_msize,
+                    hipStream_t s);
+int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
+                 const uint16_t *bv_up, uint16_t *bv0, hipStream_t s);
 int set_match2_lds_limit(int lds);
 uint32_t match2_tile_pairs();
 uint32_t match2_scan_blocks(uint32_t nch);

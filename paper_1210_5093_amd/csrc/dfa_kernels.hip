@@ -240,7 +240,8 @@ __global__ void k_down(const uint16_t *__restrict__ maps_l, uint32_t n_l, uint32
 // Level-0 boundary values -> states in the caller's numbering.
 __global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
                                uint32_t nch, uint32_t start, uint32_t mode,
-                               const uint16_t *__restrict__ bv0, uint32_t *__restrict__ out) {
+                               const uint16_t *__restrict__ bv0, const uint32_t *__restrict__ first,
+                               const uint16_t *__restrict__ members, uint32_t *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nch) return;
     const uint32_t v = bv0[i];
@@ -249,6 +250,8 @@ __global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_
         s = v & 0x7FFFu;
     } else if (i == 0) {
         s = start;
+    } else if (mode == 2) {
+        s = (v < first[i + 1] - first[i]) ? members[first[i] + v] : 0xFFFFFFFFu;
     } else {
         const uint32_t e = d.lut[in[(uint64_t)i * chunk - 1]];
         if (e == kLutInvalid) {
@@ -341,8 +344,15 @@ int device_cu_count() { return props().cus; }
 int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p) {
     *p = MatchPlan();
     p->n = n;
-    p->lookahead = lookahead ? 1u : 0u;
-    const uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead], 1u);
+    // r >= 2 needs the packed matcher (bitmaps); without a packed layout the
+    // one-symbol sets are used, which give the same result.
+    if (lookahead >= 2 && d->dev.layout == 0) lookahead = 1;
+    if (lookahead > 64) return fail(DFA_E_INVAL, "lookahead must be at most 64 symbols");
+    p->r = lookahead;
+    p->lookahead = lookahead >= 2 ? 2u : lookahead;
+    p->bitmap_words = (d->dev.nq + 31) / 32;
+    // sets with r >= 2 are subsets of the one-symbol sets (Lemma, Section 4.3)
+    const uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
     p->stride = (setmax + 7u) & ~7u;
     const int lds = device_lds_bytes();
     const int cus = std::max(device_cu_count(), 1);
@@ -364,8 +374,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // a multiple of 64).  Small inputs are launch-bound; the one-chunk-per-wave
     // path needs fewer launches.  DFA_KERNEL=1 / =2 force either kernel.
     const bool idle_lanes = p->lookahead == 0 ? false : d->wave_util < 0.85;
-    p->packed = d->dev.layout != 0 && !(force && force[0] == '1') &&
-                ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'));
+    p->packed = d->dev.layout != 0 &&
+                (p->lookahead == 2 ||
+                 (!(force && force[0] == '1') &&
+                  ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
     if (p->packed) {
         const uint32_t per_cu = std::max<uint32_t>(
             1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(d->dev.stab_bytes, 1024u)));
@@ -376,8 +388,9 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         p->tblocks = (uint32_t)std::min<uint64_t>((n + 4095) / 4096, (uint64_t)cus * 8u);
         if (chunk_req == 0) {
             // about six wave-tiles of pairs per resident wavefront
-            const double mean = std::max(1.0, p->lookahead ? d->info.mean_iset
-                                                            : (double)d->setmax_host[0]);
+            const double mean = std::max(1.0, p->lookahead == 0 ? (double)d->setmax_host[0]
+                                              : p->lookahead == 1 ? d->info.mean_iset
+                                                                  : 0.5 * d->info.mean_iset);
             const double tiles = 6.0 * p->blocks2 * (p->threads2 / 64.0);
             const double nch_target = tiles * match2_tile_pairs() / mean;
             chunk = (uint64_t)((double)n / std::max(1.0, nch_target));
@@ -449,14 +462,21 @@ int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchP
         e = hipEventRecord(ev_after_match, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    return launch_combine(d, d_in, start, p, maps, msize, bvals, d_result, d_boundaries, s);
+    return launch_combine(d, d_in, start, p, maps, msize, bvals, nullptr, d_result, d_boundaries,
+                          s);
 }
 
 int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
-                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
-                   uint32_t *d_boundaries, hipStream_t s) {
+                   uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
+                   uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s) {
     hipError_t e;
     for (uint32_t l = 0; l < p.levels; ++l) {
+        if (l == 0 && pb) {
+            int rc = launch_compose0(p, maps, pb->first, msize, maps + p.level_off[1],
+                                     msize + p.msize_off[1], s);
+            if (rc) return rc;
+            continue;
+        }
         const size_t lds = (size_t)p.group * p.stride * 2u;
         hipLaunchKernelGGL(k_compose, dim3(p.level_count[l + 1]), dim3(256), lds, s,
                            maps + p.level_off[l], msize + p.msize_off[l], p.level_count[l],
@@ -472,6 +492,12 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
     if (d_boundaries) {
         // bvals reuses the msize offsets (one value per map at every level)
         for (int l = (int)p.levels; l >= 1; --l) {
+            if (l == 1 && pb) {
+                const uint16_t *up = (p.levels == 1) ? nullptr : bvals + p.msize_off[1];
+                int rc = launch_down0(p, maps, pb->first, up, bvals, s);
+                if (rc) return rc;
+                continue;
+            }
             const uint32_t n_up = p.level_count[l];
             const uint16_t *up = (l == (int)p.levels) ? nullptr : bvals + p.msize_off[l];
             hipLaunchKernelGGL(k_down, dim3((n_up + 255) / 256), dim3(256), 0, s,
@@ -483,7 +509,8 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
                                (const uint16_t *)nullptr, 1u, bvals);
         }
         hipLaunchKernelGGL(k_bound_states, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev,
-                           d_in, p.chunk, p.nch, start, p.lookahead, bvals, d_boundaries);
+                           d_in, p.chunk, p.nch, start, p.lookahead, bvals,
+                           pb ? pb->first : nullptr, pb ? pb->members : nullptr, d_boundaries);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "boundary kernels launch");
     }

@@ -23,6 +23,7 @@
 // sizes = first pair of each chunk), k_match2 (persistent tiles of pairs).
 // The sparse maps it writes have the same form as the one-chunk-per-wave
 // matcher's, so the combination kernels are shared.
+#include <algorithm>
 #include <type_traits>
 
 #include "dfa_internal.h"
@@ -154,15 +155,51 @@ __global__ void k_chunkinfo(DevDFA d, const uint8_t *__restrict__ in, uint64_t c
     ccls[i] = (uint16_t)cls;
 }
 
+// Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
+// the image of Q under the r' = min(r, p) bytes before it (p = i*C), minus the
+// absorbing states; the true state at p lies in it, and so does the end state
+// of every walk of chunk i-1 from its own start set.  Unlike the paper's
+// precomputed I_{sigma_1..sigma_r} tables (|Sigma|^r of them), the image is
+// computed for the actual lookahead string: the image of Q under its first
+// byte is I_{sigma_1} (a precomputed class set), so every (chunk, state of
+// I_{sigma_1}) "window pair" walks the remaining r'-1 bytes and sets its end
+// state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
+// lays out the start sets as sorted member lists.
+//
+// k_chunkinfo_w: window class and |I_{sigma_1}| per chunk; clears the bitmaps.
+__global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
+                              uint32_t nch, uint32_t r, uint32_t W,
+                              uint16_t *__restrict__ msize, uint16_t *__restrict__ ccls,
+                              uint32_t *__restrict__ bits) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    for (uint32_t k = 0; k < W; ++k) bits[(size_t)i * W + k] = 0;
+    uint32_t m = 0, cls = 0;
+    if (i > 0) {
+        const uint64_t p = (uint64_t)i * chunk;
+        const uint32_t rr = (uint32_t)min<uint64_t>(r, p);
+        const uint32_t e = d.lut[in[p - rr]];
+        if (e != kLutInvalid) {
+            cls = e >> 24;
+            m = d.set_off[1][cls + 1] - d.set_off[1][cls];
+        }
+    }
+    msize[i] = (uint16_t)m;
+    ccls[i] = (uint16_t)cls;
+}
+
 // Exclusive scan of the set sizes in three phases: first[i] = sum_{k<i} m_k,
 // first[nch] = number of pairs, tile_first[w] = chunk holding pair w * kTile2.
-// Phase 2 also folds the translation flags into the flag bit of chunk 0's
-// size, from where the compose levels carry it up.
+// Sizes come from msize (SRC 0) or from the popcounts of the start-set
+// bitmaps (SRC 1: chunk 0 holds the start state; the sizes are also written to
+// msize and the sorted member lists to members[first[i] ..]).  Phase 2 folds
+// the translation flags into the flag bit of chunk 0's size, from where the
+// compose levels carry it up.
 constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanItems = 4;
 constexpr uint32_t kScanBlock = kScanThreads * kScanItems;   // chunks per scan block
 
-// Inclusive scan of one value per thread across the workgroup (in place).
+// Inclusive scan of one value per thread across the workgroup.
 __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *part) {
     const uint32_t t = threadIdx.x;
     part[t] = v;
@@ -176,14 +213,33 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *p
     return part[t];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_sums(const uint16_t *__restrict__ msize,
-                                                    uint32_t nch, uint32_t *__restrict__ bsum) {
+struct ScanSrc {
+    uint16_t *msize;
+    const uint32_t *bits;    // SRC 1
+    uint32_t W;
+    uint32_t nch;
+};
+
+template <int SRC>
+__device__ __forceinline__ uint32_t scan_size(const ScanSrc &q, uint64_t i) {
+    if constexpr (SRC == 0) {
+        return q.msize[i] & 0x7FFFu;
+    } else {
+        if (i == 0) return 1u;
+        uint32_t m = 0;
+        for (uint32_t k = 0; k < q.W; ++k) m += __popc(q.bits[i * q.W + k]);
+        return m;
+    }
+}
+
+template <int SRC>
+__global__ __launch_bounds__(1024) void k_scan_sums(ScanSrc q, uint32_t *__restrict__ bsum) {
     __shared__ uint32_t part[kScanThreads];
     const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     uint32_t v = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k)
-        if (base + k < nch) v += msize[base + k] & 0x7FFFu;
+        if (base + k < q.nch) v += scan_size<SRC>(q, base + k);
     const uint32_t inc = block_inclusive_scan(v, part);
     if (threadIdx.x == blockDim.x - 1) bsum[blockIdx.x] = inc;
 }
@@ -214,35 +270,64 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ bsum, 
     }
     if (t == T - 1) first[nch] = inc;
     __syncthreads();
-    if (t == 0 && bad_any) msize[0] = (uint16_t)(msize[0] | kFlagSymbol);
+    if (t == 0 && bad_any && msize) msize[0] = (uint16_t)(msize[0] | kFlagSymbol);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_apply(const uint16_t *__restrict__ msize,
-                                                     uint32_t nch,
-                                                     const uint32_t *__restrict__ boff,
+template <int SRC>
+__global__ __launch_bounds__(1024) void k_scan_apply(ScanSrc q, const uint32_t *__restrict__ boff,
                                                      uint32_t *__restrict__ first,
-                                                     uint32_t *__restrict__ tile_first) {
+                                                     uint32_t *__restrict__ tile_first,
+                                                     uint16_t *__restrict__ members,
+                                                     uint32_t start) {
     __shared__ uint32_t part[kScanThreads];
     const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     uint32_t m[kScanItems], v = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k) {
-        m[k] = base + k < nch ? (msize[base + k] & 0x7FFFu) : 0u;
+        m[k] = base + k < q.nch ? scan_size<SRC>(q, base + k) : 0u;
         v += m[k];
     }
     const uint32_t inc = block_inclusive_scan(v, part);
     uint32_t run = boff[blockIdx.x] + inc - v;
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k) {
-        if (base + k < nch) {
-            first[base + k] = run;
+        const uint64_t i = base + k;
+        if (i < q.nch) {
+            first[i] = run;
             if (m[k]) {
                 for (uint32_t w = (run + kTile2 - 1) / kTile2; w <= (run + m[k] - 1) / kTile2; ++w)
-                    tile_first[w] = (uint32_t)(base + k);
+                    tile_first[w] = (uint32_t)i;
+            }
+            if constexpr (SRC == 1) {
+                if (i == 0) {
+                    members[run] = (uint16_t)start;
+                    q.msize[0] = (uint16_t)((q.msize[0] & kFlagSymbol) | 1u);
+                } else {
+                    uint32_t j = run;
+                    for (uint32_t kk = 0; kk < q.W; ++kk) {
+                        uint32_t w = q.bits[i * q.W + kk];
+                        while (w) {
+                            members[j++] = (uint16_t)(32u * kk + (uint32_t)__builtin_ctz(w));
+                            w &= w - 1;
+                        }
+                    }
+                    q.msize[i] = (uint16_t)m[k];
+                }
             }
         }
         run += m[k];
     }
+}
+
+// Position of state e in the sorted member list [lo, hi), or kBadPos.
+__device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ members, uint32_t lo,
+                                                uint32_t hi, uint32_t e) {
+    uint32_t a = lo, b = hi;
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if (members[mid] < e) a = mid + 1; else b = mid;
+    }
+    return (a < hi && members[a] == e) ? a - lo : kBadPos;
 }
 
 struct Match2Args {
@@ -252,12 +337,15 @@ struct Match2Args {
     uint64_t chunk;
     uint32_t nch;
     uint32_t start;
-    uint32_t mode;
-    uint32_t stride;
+    uint32_t mode;           // 0, 1, 2 (see MatchPlan::lookahead)
+    uint32_t r;              // window passes: lookahead symbols
     const uint32_t *first;   // [nch + 1]
     const uint32_t *tile_first;
     const uint16_t *ccls;    // [nch]
-    uint16_t *maps;
+    const uint16_t *members; // mode 2: sorted start sets
+    uint32_t *bits;          // window pass: start-set bitmaps
+    uint32_t W;
+    uint16_t *maps;          // level-0 maps, indexed by pair
 };
 
 // Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
@@ -291,14 +379,77 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
 }
 
 template <int L>
+__device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(L == 1 ? d.stab : d.table);
+    uint4 *dst = reinterpret_cast<uint4 *>(smem);
+    for (uint32_t i = threadIdx.x; i < d.stab_bytes / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+// Owner chunk of pair P: the last i with first[i] <= P, searched in the
+// tile's window [lo, hi) (first[lo] <= P < first[hi]).
+__device__ __forceinline__ uint32_t owner_chunk(const uint32_t *__restrict__ first, uint32_t lo,
+                                                uint32_t hi, uint32_t P) {
+    while (hi > lo + 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (first[mid] <= P) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Window pass: pair P of chunk c starts at the (P - first[c])-th state of
+// I_{sigma_1} and walks w[p - r' + 1, p); its end state joins chunk c's set.
+template <int L>
+__global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table<L>(a.d, smem);
+    using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
+    const uint32_t lane = threadIdx.x & (kWave2 - 1);
+    const uint32_t waves = blockDim.x / kWave2;
+    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    const uint32_t total = a.first[a.nch];
+    const uint32_t ntiles = (total + kTile2 - 1) / kTile2;
+    const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
+    const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
+    for (uint32_t tile = wave_id; tile < ntiles; tile += gridDim.x * waves) {
+        const uint32_t lo0 = a.tile_first[tile];
+        const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
+        uint32_t st[kSlots2], ci[kSlots2], len[kSlots2];
+        uint64_t beg[kSlots2];
+#pragma unroll
+        for (int j = 0; j < kSlots2; ++j) {
+            const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+            const bool valid = P < total;
+            const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
+            uint32_t s = 0;
+            const uint64_t p = (uint64_t)c * a.chunk;
+            const uint32_t rr = (uint32_t)min<uint64_t>(a.r, p);
+            if (valid) s = a.d.set_st[1][a.d.set_off[1][a.ccls[c]] + (P - a.first[c])];
+            st[j] = R * s;
+            ci[j] = valid ? c : 0xFFFFFFFFu;
+            beg[j] = valid ? p - rr + 1 : 0;
+            len[j] = valid ? rr - 1 : 0;
+        }
+        for (uint32_t t = 0; t + 1 < a.r; ++t) {
+#pragma unroll
+            for (int j = 0; j < kSlots2; ++j)
+                if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[beg[j] + t]);
+        }
+#pragma unroll
+        for (int j = 0; j < kSlots2; ++j) {
+            if (ci[j] != 0xFFFFFFFFu) {
+                const uint32_t e = st[j] / R;
+                if (a.d.pos[1][e] != (uint16_t)(kTerm | e))   // class-0 row: absorbing marker
+                    atomicOr(&a.bits[(size_t)ci[j] * a.W + (e >> 5)], 1u << (e & 31));
+            }
+        }
+    }
+}
+
+template <int L>
 __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(L == 1 ? a.d.stab : a.d.table);
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        for (uint32_t i = threadIdx.x; i < a.d.stab_bytes / 16; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
+    stage_table<L>(a.d, smem);
     using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
     constexpr uint32_t kPer16 = 16 / sizeof(CodeT);   // codes per 16 bytes
     const uint32_t lane = threadIdx.x & (kWave2 - 1);
@@ -321,16 +472,15 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
         for (int j = 0; j < kSlots2; ++j) {
             const uint32_t P = tile * kTile2 + j * kWave2 + lane;
             const bool valid = P < total;
-            uint32_t lo = lo0, hi = hi0;   // first[lo] <= P < first[hi]
-            while (valid && hi > lo + 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.first[mid] <= P) lo = mid; else hi = mid;
-            }
-            const uint32_t c = valid ? lo : 0u;
+            const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
             uint32_t s = 0;
             if (valid) {
-                s = (c == 0) ? a.start
-                             : a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
+                if (c == 0)
+                    s = a.start;
+                else if (a.mode == 2)
+                    s = a.members[P];
+                else
+                    s = a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
             }
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
@@ -357,60 +507,137 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
             if (ci[j] != 0xFFFFFFFFu) {
                 const uint32_t e = st[j] / R;
                 const uint32_t c = ci[j];
-                const uint32_t p = tile * kTile2 + j * kWave2 + lane - a.first[c];
+                const uint32_t P = tile * kTile2 + j * kWave2 + lane;
                 uint16_t v;
                 if (c + 1 == a.nch) {
                     v = (uint16_t)(kTerm | e);
+                } else if (a.mode == 2) {
+                    const uint16_t ab = a.d.pos[1][e];   // class-0 row: kTerm|e iff absorbing
+                    v = ab == (uint16_t)(kTerm | e)
+                            ? ab
+                            : (uint16_t)member_rank(a.members, a.first[c + 1], a.first[c + 2], e);
                 } else {
                     v = a.d.pos[a.mode][(size_t)a.ccls[c + 1] * a.d.nq + e];
                 }
-                a.maps[(size_t)c * a.stride + p] = v;
+                a.maps[P] = v;
             }
         }
     }
 }
 
+// Level-0 maps indexed by pair (chunk i's entries at first[i] ..) -> one
+// strided map per group of G chunks (Eq. 9), as k_compose does for strided
+// levels.
+__global__ __launch_bounds__(256) void k_compose0(const uint16_t *__restrict__ maps0,
+                                                  const uint32_t *__restrict__ first,
+                                                  const uint16_t *__restrict__ msize0,
+                                                  uint32_t nch, uint32_t stride, uint32_t G,
+                                                  uint16_t *__restrict__ out_maps,
+                                                  uint16_t *__restrict__ out_msize) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t flag;
+    const uint32_t g = blockIdx.x;
+    const uint32_t c0 = g * G;
+    const uint32_t cnt = min(G, nch - c0);
+    uint32_t *off = reinterpret_cast<uint32_t *>(smem);             // cnt + 1 offsets
+    uint16_t *sm = reinterpret_cast<uint16_t *>(smem + 4 * (G + 1));
+    if (threadIdx.x == 0) flag = 0;
+    const uint32_t base = first[c0];
+    for (uint32_t t = threadIdx.x; t <= cnt; t += blockDim.x) off[t] = first[c0 + t] - base;
+    __syncthreads();
+    if (threadIdx.x < cnt && (msize0[c0 + threadIdx.x] & kFlagSymbol)) atomicOr(&flag, 1u);
+    const uint32_t entries = off[cnt];
+    for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) sm[i] = maps0[base + i];
+    __syncthreads();
+    const uint32_t m = off[1];
+    for (uint32_t p = threadIdx.x; p < m; p += blockDim.x) {
+        uint32_t v = sm[p];
+        for (uint32_t t = 1; t < cnt && !(v & kTerm); ++t)
+            v = (v < off[t + 1] - off[t]) ? sm[off[t] + v] : kBadPos;
+        out_maps[(size_t)g * stride + p] = (uint16_t)v;
+    }
+    if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m | (flag ? kFlagSymbol : 0));
+}
+
+// Down-sweep into pair-indexed level-0 maps: bv0[i] = value at chunk i's start.
+__global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__restrict__ first,
+                        uint32_t nch, uint32_t G, const uint16_t *__restrict__ bv_up,
+                        uint32_t n_up, uint16_t *__restrict__ bv0) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_up) return;
+    uint32_t v = bv_up ? bv_up[g] : 0u;
+    const uint32_t c0 = g * G;
+    const uint32_t cnt = min(G, nch - c0);
+    for (uint32_t t = 0; t < cnt; ++t) {
+        const uint32_t c = c0 + t;
+        bv0[c] = (uint16_t)v;
+        if (!(v & kTerm)) v = (v < first[c + 1] - first[c]) ? maps0[first[c] + v] : kBadPos;
+    }
+}
+
 // ---------------------------------------------------------------------------
-int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
-                  void *codes, uint32_t *block_bad, uint32_t *bsum, uint32_t *first,
-                  uint32_t *tile_first, uint16_t *ccls, uint16_t *maps, uint16_t *msize,
-                  hipStream_t s, hipEvent_t ev_before_matcher) {
-    const uint32_t L = d->dev.layout;
-    const uint32_t tblocks = p.tblocks;
-    if (L == 1)
-        hipLaunchKernelGGL(k_translate<uint8_t>, dim3(tblocks), dim3(256), 0, s, d_in, p.n,
-                           d->dev.code, (uint8_t *)codes, block_bad);
-    else
-        hipLaunchKernelGGL(k_translate<uint16_t>, dim3(tblocks), dim3(256), 0, s, d_in, p.n,
-                           d->dev.code, (uint16_t *)codes, block_bad);
-    hipLaunchKernelGGL(k_chunkinfo, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
-                       p.chunk, p.nch, p.lookahead, msize, ccls);
+namespace {
+template <int SRC>
+void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint16_t *flag_msize,
+                 uint32_t start, hipStream_t s) {
     const uint32_t nsb = (p.nch + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_sums, dim3(nsb), dim3(kScanThreads), 0, s, msize, p.nch, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, nsb, msize, p.nch,
-                       block_bad, tblocks, first);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kScanThreads), 0, s, msize, p.nch, bsum,
-                       first, tile_first);
+    hipLaunchKernelGGL(k_scan_sums<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, b.bsum, nsb, flag_msize,
+                       p.nch, b.block_bad, flag_msize ? p.tblocks : 0u, b.first);
+    hipLaunchKernelGGL(k_scan_apply<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum, b.first,
+                       b.tile_first, b.members, start);
+}
+}  // namespace
+
+int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
+                  const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
+                  hipEvent_t ev_before_matcher) {
+    const uint32_t L = d->dev.layout;
+    if (L == 1)
+        hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                           d->dev.code, (uint8_t *)b.codes, b.block_bad);
+    else
+        hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                           d->dev.code, (uint16_t *)b.codes, b.block_bad);
+    Match2Args a;
+    a.d = d->dev;
+    a.codes = b.codes;
+    a.n = p.n;
+    a.chunk = p.chunk;
+    a.nch = p.nch;
+    a.start = start;
+    a.mode = p.lookahead;
+    a.r = p.r;
+    a.first = b.first;
+    a.tile_first = b.tile_first;
+    a.ccls = b.ccls;
+    a.members = b.members;
+    a.bits = b.bits;
+    a.W = p.bitmap_words;
+    a.maps = maps;
+    const size_t lds = d->dev.stab_bytes;
+    ScanSrc q{msize, b.bits, p.bitmap_words, p.nch};
+    if (p.lookahead == 2) {
+        // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
+        hipLaunchKernelGGL(k_chunkinfo_w, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
+                           p.chunk, p.nch, p.r, p.bitmap_words, msize, b.ccls, b.bits);
+        launch_scan<0>(p, q, b, nullptr, start, s);
+        if (L == 1)
+            hipLaunchKernelGGL(k_window2<1>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
+        else
+            hipLaunchKernelGGL(k_window2<2>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
+        launch_scan<1>(p, q, b, msize, start, s);
+    } else {
+        hipLaunchKernelGGL(k_chunkinfo, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
+                           p.chunk, p.nch, p.lookahead, msize, b.ccls);
+        launch_scan<0>(p, q, b, msize, start, s);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
     if (ev_before_matcher) {
         e = hipEventRecord(ev_before_matcher, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    Match2Args a;
-    a.d = d->dev;
-    a.codes = codes;
-    a.n = p.n;
-    a.chunk = p.chunk;
-    a.nch = p.nch;
-    a.start = start;
-    a.mode = p.lookahead;
-    a.stride = p.stride;
-    a.first = first;
-    a.tile_first = tile_first;
-    a.ccls = ccls;
-    a.maps = maps;
-    const size_t lds = d->dev.stab_bytes;
     if (L == 1)
         hipLaunchKernelGGL(k_match2<1>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
     else
@@ -419,13 +646,36 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
 }
 
+int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
+                    const uint16_t *msize0, uint16_t *out_maps, uint16_t *out_msize,
+                    hipStream_t s) {
+    const size_t lds = 4u * (p.group + 1) + 2u * (size_t)p.group * p.stride;
+    hipLaunchKernelGGL(k_compose0, dim3(p.level_count[1]), dim3(256), lds, s, maps0, first, msize0,
+                       p.nch, p.stride, p.group, out_maps, out_msize);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_compose0 launch");
+}
+
+int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
+                 const uint16_t *bv_up, uint16_t *bv0, hipStream_t s) {
+    const uint32_t n_up = p.levels >= 1 ? p.level_count[1] : 1u;
+    const uint32_t G = p.levels >= 1 ? p.group : 1u;
+    hipLaunchKernelGGL(k_down0, dim3((n_up + 255) / 256), dim3(256), 0, s, maps0, first, p.nch, G,
+                       bv_up, n_up, bv0);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_down0 launch");
+}
+
 int set_match2_lds_limit(int lds) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_match2<1>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_match2<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    return e == hipSuccess ? DFA_OK : DFA_E_DEVICE;
+    const void *fns[] = {reinterpret_cast<const void *>(&k_match2<1>),
+                         reinterpret_cast<const void *>(&k_match2<2>),
+                         reinterpret_cast<const void *>(&k_window2<1>),
+                         reinterpret_cast<const void *>(&k_window2<2>),
+                         reinterpret_cast<const void *>(&k_compose0)};
+    for (const void *f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return DFA_E_DEVICE;
+    return DFA_OK;
 }
 
 uint32_t match2_tile_pairs() { return kTile2; }

@@ -1,0 +1,72 @@
+"""Full-size large-DFA configuration: 10 GiB inputs, chunk sweep 4 KiB - 1 MiB.
+
+The oracle walks each 10 GiB input once (Algorithm 1, one host core) and
+records the prefix states at every 1 MiB boundary; every GPU run of the sweep
+must reproduce the final state, the accept bit and every sampled boundary
+state (each 1 MiB boundary is a chunk boundary for all chunk lengths of the
+sweep).  Tolerance 0."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+MiB = 1 << 20
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+@pytest.fixture(scope="module")
+def dfa_mod():
+    import torch
+    import paper_1210_5093_amd as dfa
+    assert torch.cuda.is_available()
+    dfa.lib()
+    return dfa
+
+
+def run_sweep(dfa_mod, w, gen, n=configs.C3_BYTES, lookaheads=(1,)):
+    import torch
+    t0 = time.time()
+    x = np.empty(n, dtype=np.uint8)
+    gen(n, out=x)
+    say(f"generated {n} bytes in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    probes = list(range(0, n + 1, MiB))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    say(f"oracle walk {time.time() - t0:.1f}s final {fin}")
+    dev = torch.from_numpy(x).to("cuda")
+    del x
+    d = dfa_mod.DFA.from_workload(w)
+    for r in lookaheads:
+        for chunk in configs.C3_CHUNKS:
+            _, nch = dfa_mod.dfa_plan_chunks(d, n, chunk, r)
+            bnd = torch.empty(nch + 1, dtype=torch.int32, device="cuda")
+            res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=chunk, lookahead=r,
+                                            boundaries=True, bound_out=bnd)
+            torch.cuda.synchronize()
+            g = dfa_mod.result_tuple(res)
+            say(f"r={r} chunk={chunk} chunks={nch} gpu={g[:3]}")
+            assert g[:3] == (fin, acc, 0)
+            step = MiB // chunk
+            b = bnd[::step].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(b[:len(ps)], ps.astype(np.int64)), f"chunk {chunk}"
+            del bnd
+    d.close()
+
+
+def test_c3_protein_10gib_chunk_sweep(dfa_mod):
+    run_sweep(dfa_mod, configs.c3_protein_dfa(), configs.c3_protein_input, lookaheads=(1, 8))
+
+
+def test_c3_byte_10gib_chunk_sweep(dfa_mod):
+    run_sweep(dfa_mod, configs.c3_byte_dfa(), configs.c3_byte_input, lookaheads=(1,))

@@ -367,3 +367,60 @@ def test_unaligned_device_input(dfa_mod, offset):
     r = dfa_mod.result_tuple(dfa_mod.dfa_match_async(d, t))
     torch.cuda.synchronize()
     assert r[:3] == (*oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x[offset:]), 0)
+
+
+# ---------------------------------------------------------------------------
+# Multi-symbol reverse lookahead (Eq. 13), exact per-chunk image sets
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("r", [2, 3, 4, 8, 16])
+def test_multi_symbol_lookahead_c2(dfa_mod, r):
+    w = configs.c2_dfa()
+    x = configs.c2_input(3 * (1 << 20) + 11)
+    check(dfa_mod, w, x, chunk=0, lookahead=r)
+    check(dfa_mod, w, x, chunk=4099, lookahead=r)
+
+
+@pytest.mark.parametrize("r", [2, 4, 64])
+def test_multi_symbol_lookahead_other_dfas(dfa_mod, r):
+    check(dfa_mod, configs.c3_protein_dfa(), configs.c3_protein_input(2 * (1 << 20) + 1),
+          chunk=8192, lookahead=r)
+    check(dfa_mod, configs.c1_dfa(2), configs.c1_input(400_000), chunk=1000, lookahead=r)
+    check(dfa_mod, configs.c3_byte_dfa(), configs.c3_byte_input(1 << 20), chunk=4096, lookahead=r)
+    pd = from_pattern(patterns.pattern_dfa(32, contains=False))
+    check(dfa_mod, pd, configs.c2_input(300_000), chunk=777, lookahead=r)
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 3, 5, 7])
+def test_lookahead_longer_than_chunks(dfa_mod, chunk):
+    """r larger than the chunk length: the lookahead string spans earlier
+    chunks, and chunks with p < r use r' = p (the whole prefix)."""
+    g, w = golden_workload("example_dfa.json")
+    x = np.frombuffer(g["input36"].encode(), dtype=np.uint8)
+    for r in (2, 4, 9):
+        fin, acc, _ = check(dfa_mod, w, x, chunk=chunk, lookahead=r)
+        assert fin == g["derived"]["final_state_input36"]
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(20_000), chunk=chunk * 13, lookahead=6)
+
+
+def test_lookahead_shrinks_sets_and_keeps_result(dfa_mod):
+    """Lemma (Section 4.3): more lookahead never enlarges a start set, so the
+    result is unchanged and the work (lookups) does not grow."""
+    import bench
+    w = configs.c2_dfa()
+    x = configs.c2_input(1 << 20)
+    work = [bench.algorithmic_lookups(w, x, 4096, r) for r in (1, 2, 4, 8)]
+    assert all(a >= b for a, b in zip(work, work[1:]))
+    res = {check(dfa_mod, w, x, chunk=4096, lookahead=r) for r in (0, 1, 2, 4, 8)}
+    assert len(res) == 1
+
+
+@pytest.mark.parametrize("pos", [4095, 4090, 8191])
+def test_invalid_byte_inside_lookahead_window(dfa_mod, pos):
+    w = configs.c2_dfa()
+    x = configs.c2_input(50_000).copy()
+    x[pos] = ord("Z")
+    d = dfa_mod.DFA.from_workload(w)
+    import torch
+    res, _ = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=4096, lookahead=8)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL

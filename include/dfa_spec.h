@@ -75,7 +75,7 @@ typedef struct dfa_info {
     uint32_t packed_layout;   /* 0: one-chunk-per-wavefront matcher only;
                                  1: packed-pair matcher, state-major table;
                                  2: packed-pair matcher, class-major table */
-    uint32_t reserved;
+    uint32_t lookahead_tables;/* r0: sets I_{c_1..c_k} precomputed for k <= r0 */
 } dfa_info_t;
 
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
@@ -160,6 +160,16 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
 int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
                     uint64_t *chunk_len, uint64_t *num_chunks);
 
+/* Initial-state set for a string of k reverse-lookahead bytes (Eq. 13: the
+ * image of Q under the string, absorbing states left out), read from the
+ * tables dfa_create precomputed (k <= dfa_info.lookahead_tables).
+ *   bytes: host, k bytes in matching order.  out: host, cap entries.
+ *   *count receives the set size (states written in ascending order, at most
+ *   cap).  Returns DFA_E_SYMBOL for a byte outside Sigma, DFA_E_INVAL if k is
+ *   0 or beyond the tables. */
+int dfa_lookahead_set(const dfa_t *d, const uint8_t *bytes, uint32_t k, uint16_t *out,
+                      uint32_t cap, uint32_t *count);
+
 /* What the planner picks for (d, len, opts). */
 typedef struct dfa_plan_info {
     uint64_t chunk_len;       /* bytes per chunk */
@@ -172,16 +182,78 @@ typedef struct dfa_plan_info {
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 
 /* ---------------------------------------------------------------------------
- * dfa_match_batch -- many (DFA, string) pairs of uneven size in one persistent
- * launch (the paper's representation holds several DFAs and strings in one
- * table and input array, Section 5).
- *   dfas:      host array of `count` handles (may repeat).
- *   d_inputs:  host array of `count` device pointers.
+ * Batches: many (DFA, string) pairs of uneven size in one persistent launch
+ * (the paper's representation holds several DFAs and strings in one table and
+ * input array, Section 5).  Every string is cut into chunks; one launch
+ * matches all chunks of all strings (each from its one-symbol initial-state
+ * set, Algorithm 3), then the per-string maps are composed (Eq. 9).  Each
+ * string's record equals what dfa_match_async writes for it alone.
+ *
+ * dfa_batch_create -- plan a batch and upload its descriptors (synchronous).
+ *   dfas:      host array of `count` handles (may repeat; must outlive the batch).
+ *   d_inputs:  host array of `count` device pointers (must stay valid and may
+ *              change contents between runs; the pointers are fixed).
  *   lens:      host array of `count` lengths.
- *   d_results: device, count dfa_result_t records, written on the stream.
- * Each pair's record equals what dfa_match_async would write for it alone. */
+ *   opts:      NULL or chunk_len (0 = planner) with lookahead 1.
+ * dfa_batch_run -- enqueue the whole batch on `stream`: no host work, no
+ *   allocation, so it may be captured into a HIP graph.
+ *   d_results: device, count dfa_result_t records.
+ * dfa_batch_graph_launch -- capture dfa_batch_run into a HIP graph once (per
+ *   d_results pointer) and replay it; `stream` must not be the null stream.
+ * dfa_batch_info -- chunk length used and number of matcher tasks. */
+typedef struct dfa_batch dfa_batch_t;
+int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
+                     const size_t *lens, size_t count, const dfa_match_opts_t *opts,
+                     dfa_batch_t **out);
+int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results);
+int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results);
+int dfa_batch_info(const dfa_batch_t *b, uint64_t *chunk_len, uint32_t *tasks);
+void dfa_batch_destroy(dfa_batch_t *b);
+
+/* dfa_match_batch -- one-shot batch: plan, run on `stream`, wait for the
+ *   stream, release the plan.  Returns once d_results holds every record. */
 int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
                     const size_t *lens, size_t count, void *stream, uint32_t *d_results);
+
+/* ---------------------------------------------------------------------------
+ * Serving: DFAs registered once stay resident; clients submit (DFA id,
+ * device string) requests at any time and poll or wait for their records.  A
+ * dispatcher thread admits requests in arrival order while the in-flight
+ * budget allows (input bytes plus the batch arena's estimate) and packs them
+ * into batches that run concurrently on `streams` non-blocking streams
+ * (continuous batching: requests arriving while batches run join the next
+ * one).  Each record equals the request's result alone.  Dispatching
+ * allocates nothing; the slots' device arenas and pinned buffers are made at
+ * creation.
+ *   dfa_server_create:   opts may be NULL (defaults below).
+ *   dfa_server_register: the DFA must outlive the server; *id receives its id.
+ *   dfa_server_submit:   d_input (device) must stay valid until the ticket is
+ *                        done; DFA_E_TOOBIG if one request exceeds the budget.
+ *   dfa_server_poll:     DFA_OK and the record once done (the ticket is then
+ *                        released), DFA_E_NOTREADY before.
+ *   dfa_server_wait:     blocks until the ticket is done.
+ *   dfa_server_destroy:  finishes every submitted request, then releases. */
+typedef struct dfa_server dfa_server_t;
+typedef struct dfa_server_opts {
+    uint64_t budget_bytes;    /* in-flight device bytes (0 = 16 GiB) */
+    uint32_t max_inflight;    /* in-flight requests (0 = 4096) */
+    uint32_t streams;         /* concurrent batches (0 = 4) */
+    uint32_t max_batch;       /* requests per batch (0 = 256) */
+    uint32_t reserved;
+    uint64_t slot_bytes;      /* device arena per concurrent batch (0 = 256 MiB) */
+} dfa_server_opts_t;
+typedef struct dfa_server_stats {
+    uint64_t submitted, completed, batches, bytes;
+    uint64_t inflight, pending;
+} dfa_server_stats_t;
+int dfa_server_create(const dfa_server_opts_t *opts, dfa_server_t **out);
+int dfa_server_register(dfa_server_t *srv, const dfa_t *d, uint32_t *id);
+int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
+                      uint64_t *ticket);
+int dfa_server_poll(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
+int dfa_server_wait(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
+int dfa_server_stats(dfa_server_t *srv, dfa_server_stats_t *out);
+void dfa_server_destroy(dfa_server_t *srv);
 
 /* ---------------------------------------------------------------------------
  * Instrumentation.  With timing on for a stream, every match call on it

@@ -36,7 +36,7 @@ class dfa_info_t(ctypes.Structure):
                 ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
                 ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("packed_layout", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("lookahead_tables", ctypes.c_uint32)]
 
 
 class dfa_match_opts_t(ctypes.Structure):
@@ -48,6 +48,23 @@ class dfa_plan_info_t(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint64), ("num_chunks", ctypes.c_uint64),
                 ("kernel", ctypes.c_uint32), ("lookahead", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+
+
+class dfa_result_t(ctypes.Structure):
+    _fields_ = [("final_state", ctypes.c_uint32), ("accepted", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("num_chunks", ctypes.c_uint32)]
+
+
+class dfa_server_opts_t(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
+
+
+class dfa_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("inflight", ctypes.c_uint64), ("pending", ctypes.c_uint64)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -87,9 +104,36 @@ def lib() -> ctypes.CDLL:
     L.dfa_plan_chunks.restype = I
     L.dfa_plan_chunks.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
                                   ctypes.POINTER(U64), ctypes.POINTER(U64)]
+    L.dfa_lookahead_set.restype = I
+    L.dfa_lookahead_set.argtypes = [P, P, U32, P, U32, ctypes.POINTER(U32)]
     L.dfa_plan.restype = I
     L.dfa_plan.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
                            ctypes.POINTER(dfa_plan_info_t)]
+    L.dfa_batch_create.restype = I
+    L.dfa_batch_create.argtypes = [P, P, P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
+                                   ctypes.POINTER(P)]
+    L.dfa_batch_run.restype = I
+    L.dfa_batch_run.argtypes = [P, P, P]
+    L.dfa_batch_graph_launch.restype = I
+    L.dfa_batch_graph_launch.argtypes = [P, P, P]
+    L.dfa_batch_info.restype = I
+    L.dfa_batch_info.argtypes = [P, ctypes.POINTER(U64), ctypes.POINTER(U32)]
+    L.dfa_batch_destroy.restype = None
+    L.dfa_batch_destroy.argtypes = [P]
+    L.dfa_server_create.restype = I
+    L.dfa_server_create.argtypes = [ctypes.POINTER(dfa_server_opts_t), ctypes.POINTER(P)]
+    L.dfa_server_register.restype = I
+    L.dfa_server_register.argtypes = [P, P, ctypes.POINTER(U32)]
+    L.dfa_server_submit.restype = I
+    L.dfa_server_submit.argtypes = [P, U32, P, ctypes.c_size_t, ctypes.POINTER(U64)]
+    L.dfa_server_poll.restype = I
+    L.dfa_server_poll.argtypes = [P, U64, ctypes.POINTER(dfa_result_t)]
+    L.dfa_server_wait.restype = I
+    L.dfa_server_wait.argtypes = [P, U64, ctypes.POINTER(dfa_result_t)]
+    L.dfa_server_stats.restype = I
+    L.dfa_server_stats.argtypes = [P, ctypes.POINTER(dfa_server_stats_t)]
+    L.dfa_server_destroy.restype = None
+    L.dfa_server_destroy.argtypes = [P]
     L.dfa_match_batch.restype = I
     L.dfa_match_batch.argtypes = [P, P, P, ctypes.c_size_t, P, P]
     L.dfa_timing_enable.restype = I
@@ -212,6 +256,16 @@ def dfa_plan_chunks(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> T
     return int(c.value), int(k.value)
 
 
+def dfa_lookahead_set(d: DFA, lookahead_bytes) -> List[int]:
+    """Precomputed initial-state set for k lookahead bytes (Eq. 13)."""
+    b = np.frombuffer(bytes(lookahead_bytes), dtype=np.uint8)
+    out = np.zeros(d.num_states, dtype=np.uint16)
+    cnt = ctypes.c_uint32()
+    _check(lib().dfa_lookahead_set(d.handle, b.ctypes.data, int(b.size), out.ctypes.data,
+                                   int(out.size), ctypes.byref(cnt)))
+    return out[:cnt.value].tolist()
+
+
 def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> dfa_plan_info_t:
     out = dfa_plan_info_t()
     o = _opts(chunk_len, lookahead)
@@ -266,6 +320,108 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
     _check(lib().dfa_timing_read(_stream_handle(stream), ctypes.byref(m), ctypes.byref(c),
                                  ctypes.byref(k)))
     return float(m.value), float(c.value), int(k.value)
+
+
+class Batch:
+    """A planned batch of (DFA, device string) pairs (dfa_batch_create)."""
+
+    def __init__(self, dfas: Sequence[DFA], inputs: Sequence, chunk_len: int = 0):
+        self._dfas = list(dfas)          # keep the DFAs alive
+        self._inputs = list(inputs)      # and the device strings
+        count = len(self._dfas)
+        assert len(self._inputs) == count
+        self.count = count
+        hs = (ctypes.c_void_p * max(count, 1))(*[x.handle.value for x in self._dfas])
+        ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None
+                                                 for t in self._inputs])
+        ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in self._inputs])
+        o = _opts(chunk_len, 1)
+        h = ctypes.c_void_p()
+        _check(lib().dfa_batch_create(hs, ps, ls, count, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, results, stream=None):
+        _check(lib().dfa_batch_run(self._h, _stream_handle(stream), results.data_ptr()))
+        return results
+
+    def graph_launch(self, results, stream):
+        _check(lib().dfa_batch_graph_launch(self._h, _stream_handle(stream), results.data_ptr()))
+        return results
+
+    def info(self) -> Tuple[int, int]:
+        c, t = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().dfa_batch_info(self._h, ctypes.byref(c), ctypes.byref(t)))
+        return int(c.value), int(t.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().dfa_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over resident DFAs (dfa_server_*)."""
+
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, streams: int = 0,
+                 max_batch: int = 0, slot_bytes: int = 0):
+        o = dfa_server_opts_t(budget_bytes, max_inflight, streams, max_batch, 0, slot_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().dfa_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._dfas = []
+        self._live = {}          # ticket -> device tensor kept alive until done
+
+    def register(self, d: DFA) -> int:
+        i = ctypes.c_uint32()
+        _check(lib().dfa_server_register(self._h, d.handle, ctypes.byref(i)))
+        self._dfas.append(d)
+        return int(i.value)
+
+    def submit(self, dfa_id: int, d_input) -> int:
+        t = ctypes.c_uint64()
+        n = int(d_input.numel())
+        _check(lib().dfa_server_submit(self._h, int(dfa_id), d_input.data_ptr() if n else None, n,
+                                       ctypes.byref(t)))
+        self._live[int(t.value)] = d_input
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        r = dfa_result_t()
+        rc = lib().dfa_server_poll(self._h, int(ticket), ctypes.byref(r))
+        if rc == DFA_E_NOTREADY:
+            return None
+        _check(rc)
+        self._live.pop(int(ticket), None)
+        return int(r.final_state), bool(r.accepted), int(r.flags), int(r.num_chunks)
+
+    def wait(self, ticket: int):
+        r = dfa_result_t()
+        _check(lib().dfa_server_wait(self._h, int(ticket), ctypes.byref(r)))
+        self._live.pop(int(ticket), None)
+        return int(r.final_state), bool(r.accepted), int(r.flags), int(r.num_chunks)
+
+    def stats(self) -> dfa_server_stats_t:
+        s = dfa_server_stats_t()
+        _check(lib().dfa_server_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().dfa_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def result_tuple(result) -> Tuple[int, bool, int, int]:

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdfaspec.so")
 PROBE = os.path.join(HERE, "lds_peak_probe")
-SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip", "dfa_match2.hip"]
+SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip", "dfa_match2.hip",
+           "dfa_batch.hip", "dfa_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions stay disabled in all device code.

@@ -93,7 +93,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     const size_t sz_bytes = a256(p.msize_entries * 2);
     size_t need = map_bytes + 2 * sz_bytes;
     size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0,
-           bits_off = 0, mem_off = 0;
+           bits_off = 0, mem_off = 0, cset_off = 0;
     if (p.packed && len) {
         need += a256(((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64);
         bad_off = need;
@@ -106,6 +106,8 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         need += a256((p.max_tiles + 1) * 4);
         ccls_off = need;
         need += a256((uint64_t)p.nch * 2);
+        cset_off = need;
+        need += a256((uint64_t)p.nch * 4);
         if (p.lookahead == 2) {
             bits_off = need;
             need += a256((uint64_t)p.nch * p.bitmap_words * 4);
@@ -137,6 +139,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         pb.first = (uint32_t *)(base + first_off);
         pb.tile_first = (uint32_t *)(base + tf_off);
         pb.ccls = (uint16_t *)(base + ccls_off);
+        pb.cset = (uint32_t *)(base + cset_off);
         if (p.lookahead == 2) {
             pb.bits = (uint32_t *)(base + bits_off);
             pb.members = (uint16_t *)(base + mem_off);
@@ -244,12 +247,15 @@ extern "C" int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d
                                uint32_t *d_results) {
     if (count && (!dfas || !d_inputs || !lens || !d_results))
         return fail(DFA_E_INVAL, "dfa_match_batch: NULL argument");
-    for (size_t i = 0; i < count; ++i) {
-        int rc = run_match(dfas[i], d_inputs[i], lens[i], DFA_Q0, nullptr, (hipStream_t)stream,
-                           d_results + 4 * i, nullptr);
-        if (rc) return rc;
-    }
-    return DFA_OK;
+    if (!count) return DFA_OK;
+    dfa_batch_t *b = nullptr;
+    int rc = dfa_batch_create(dfas, d_inputs, lens, count, nullptr, &b);
+    if (rc) return rc;
+    rc = dfa_batch_run(b, stream, d_results);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    dfa_batch_destroy(b);
+    if (rc) return rc;
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "dfa_match_batch: hipStreamSynchronize");
 }
 
 extern "C" int dfa_timing_enable(void *stream, int on) {

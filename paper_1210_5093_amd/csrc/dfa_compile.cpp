@@ -151,6 +151,68 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     const double wave_util = slots > 0 ? mean_iset / slots : 0.0;
     if (nvalid_bytes) mean_iset /= nvalid_bytes;
 
+    // ---- multi-symbol initial-state sets (Eq. 13; Algorithm 4 generalised)
+    // Level k holds I_{c_1..c_k} for every class string: level 1 is I_c, and
+    // level k is delta(level k-1, c_k) without absorbing states (absorbing
+    // states stay absorbing, so this is the exact image of Q).  Levels are
+    // added while they fit a budget of 512K states and 256K sets (a few ms).
+    std::vector<uint32_t> mset_off;
+    std::vector<uint16_t> mset_st;
+    uint32_t moff[kMaxMsetLevel + 1] = {0}, mst[kMaxMsetLevel + 1] = {0};
+    uint32_t r0 = 0;
+    double mset_mean_k[kMaxMsetLevel + 1] = {0.0};
+    {
+        const uint32_t Kc = (uint32_t)class_sym.size();
+        std::vector<uint32_t> prev_off, cur_off;
+        std::vector<uint16_t> prev_st, cur_st;
+        if (Kc > 0) {
+            prev_off.assign(off[1].begin(), off[1].begin() + Kc + 1);
+            prev_st.assign(st[1].begin(), st[1].begin() + off[1][Kc]);
+            r0 = 1;
+            mset_mean_k[1] = (double)prev_st.size() / Kc;
+            moff[1] = 0;
+            mst[1] = 0;
+            mset_off = prev_off;
+            mset_st = prev_st;
+            std::vector<uint32_t> mark(nq, 0);
+            uint32_t stamp = 0;
+            for (uint32_t k = 2; k <= kMaxMsetLevel; ++k) {
+                const uint64_t nsets = (uint64_t)(prev_off.size() - 1) * Kc;
+                if (nsets > (1u << 18)) break;
+                cur_off.assign(1, 0);
+                cur_st.clear();
+                bool over = false;
+                for (uint64_t parent = 0; parent + 1 < prev_off.size() && !over; ++parent) {
+                    for (uint32_t c = 0; c < Kc; ++c) {
+                        ++stamp;
+                        const size_t base = cur_st.size();
+                        for (uint32_t j = prev_off[parent]; j < prev_off[parent + 1]; ++j) {
+                            const uint32_t t = delta[(uint64_t)prev_st[j] * nsym + class_sym[c]];
+                            if (!absorbing[t] && mark[t] != stamp) {
+                                mark[t] = stamp;
+                                cur_st.push_back((uint16_t)t);
+                            }
+                        }
+                        std::sort(cur_st.begin() + base, cur_st.end());
+                        cur_off.push_back((uint32_t)cur_st.size());
+                        if (mset_st.size() + cur_st.size() > (1u << 19)) { over = true; break; }
+                    }
+                }
+                if (over) break;
+                mset_mean_k[k] = cur_off.size() > 1 ? (double)cur_st.size() / (cur_off.size() - 1) : 0.0;
+                moff[k] = (uint32_t)mset_off.size();
+                mst[k] = (uint32_t)mset_st.size();
+                mset_off.insert(mset_off.end(), cur_off.begin(), cur_off.end());
+                mset_st.insert(mset_st.end(), cur_st.begin(), cur_st.end());
+                prev_off.swap(cur_off);
+                prev_st.swap(cur_st);
+                r0 = k;
+            }
+        }
+        if (mset_off.empty()) mset_off.assign(2, 0);
+        if (mset_st.empty()) mset_st.assign(1, 0);
+    }
+
     // ---- packed-pair matcher layouts -------------------------------------
     // Layout 1 keeps the byte code small (2 * class, one byte) and puts the
     // class offset inside a state row; rows are an odd number of dwords so
@@ -202,6 +264,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     }
     size_t i_acc = add(accept_bits.data(), accept_bits.size() * 4);
     size_t i_code = add(code.data(), code.size() * 2);
+    size_t i_moff = add(mset_off.data(), mset_off.size() * 4);
+    size_t i_mst = add(mset_st.data(), mset_st.size() * 2);
     size_t i_stab = add(stab.data(), stab.size() * 2);
     const size_t arena_bytes = align_up(at, 256);
 
@@ -223,6 +287,10 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     d->arena_bytes = arena_bytes;
     d->nsym = nsym;
     d->wave_util = wave_util;
+    for (uint32_t k = 0; k <= kMaxMsetLevel; ++k) d->mset_mean[k] = mset_mean_k[k];
+    d->h_mset_off = mset_off;
+    d->h_mset_st = mset_st;
+    for (int b = 0; b < 256; ++b) d->h_byte_class[b] = (int16_t)byte_class[b];
     DevDFA &v = d->dev;
     v.table = (const uint16_t *)ptr(i_table);
     v.lut = (const uint32_t *)ptr(i_lut);
@@ -235,6 +303,13 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     }
     v.accept_bits = (const uint32_t *)ptr(i_acc);
     v.code = (const uint16_t *)ptr(i_code);
+    v.mset_off = (const uint32_t *)ptr(i_moff);
+    v.mset_st = (const uint16_t *)ptr(i_mst);
+    for (uint32_t k = 0; k <= kMaxMsetLevel; ++k) {
+        v.moff[k] = moff[k];
+        v.mst[k] = mst[k];
+    }
+    v.r0 = r0;
     v.stab = (const uint16_t *)ptr(i_stab);
     v.layout = layout;
     v.rowbytes = rowbytes;
@@ -256,6 +331,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.table_bytes = table_bytes;
     inf.device_bytes = arena_bytes;
     inf.packed_layout = layout;
+    inf.lookahead_tables = r0;
     *out = d;
     return DFA_OK;
 }
@@ -264,6 +340,23 @@ extern "C" void dfa_destroy(dfa_t *d) {
     if (!d) return;
     if (d->arena) (void)hipFree(d->arena);
     delete d;
+}
+
+extern "C" int dfa_lookahead_set(const dfa_t *d, const uint8_t *bytes, uint32_t k, uint16_t *out,
+                                 uint32_t cap, uint32_t *count) {
+    if (!d || (k && !bytes) || !count) return fail(DFA_E_INVAL, "dfa_lookahead_set: NULL argument");
+    if (k == 0 || k > d->dev.r0) return fail(DFA_E_INVAL, "dfa_lookahead_set: k out of range");
+    uint64_t id = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+        const int c = d->h_byte_class[bytes[j]];
+        if (c < 0) return fail(DFA_E_SYMBOL, "dfa_lookahead_set: byte outside Sigma");
+        id = id * d->dev.nclass + (uint64_t)c;
+    }
+    const uint32_t lo = d->h_mset_off[d->dev.moff[k] + id];
+    const uint32_t hi = d->h_mset_off[d->dev.moff[k] + id + 1];
+    *count = hi - lo;
+    for (uint32_t j = 0; j < hi - lo && j < cap; ++j) out[j] = d->h_mset_st[d->dev.mst[k] + lo + j];
+    return DFA_OK;
 }
 
 extern "C" int dfa_info(const dfa_t *d, dfa_info_t *out) {

@@ -22,6 +22,7 @@ constexpr uint16_t kBadPos = 0xFFFF;      // "not in the next set": invariant vi
 constexpr uint16_t kFlagSymbol = 0x8000;  // msize bit: chunk held a byte outside Sigma
 constexpr uint32_t kLutInvalid = 0xFFFFFFFFu;
 constexpr uint32_t kMaxStates = 32767;
+constexpr uint32_t kMaxMsetLevel = 8;   // precomputed multi-symbol sets up to this r
 constexpr uint16_t kCodeInvalid = 0xFFFF;
 
 // Device-resident compiled DFA, passed by value to kernels.
@@ -38,6 +39,14 @@ struct DevDFA {
     //           R = row bytes; an LDS address is R * s + code.
     //  layout 2 (class-major): code = class * colstride; the table is `table`
     //           (entries 2 * delta); an LDS address is code + 2 * s.
+    // Multi-symbol initial-state sets I_{c_1..c_k} (Eq. 13) over class strings,
+    // k = 1..r0; set id = c_1 K^(k-1) + ... + c_k; level k's offsets start at
+    // mset_off[moff[k]], its states at mset_st[mst[k]] (sorted ascending).
+    const uint32_t *mset_off;
+    const uint16_t *mset_st;
+    uint32_t moff[kMaxMsetLevel + 1];
+    uint32_t mst[kMaxMsetLevel + 1];
+    uint32_t r0;
     const uint16_t *code;        // [256]; kCodeInvalid for bytes outside Sigma
     const uint16_t *stab;        // layout 1 table (nq rows of R bytes)
     uint32_t layout;             // 0 = packed matcher unavailable, 1, 2
@@ -62,6 +71,11 @@ struct dfa {
     uint32_t nsym = 0;
     uint32_t setmax_host[2] = {0, 0};
     double wave_util = 0.0;      // lane utilisation of one-chunk-per-wave matching (lookahead 1)
+    double mset_mean[dfaspec::kMaxMsetLevel + 1] = {};   // mean precomputed set size per level
+    // host copies for dfa_lookahead_set
+    std::vector<uint32_t> h_mset_off;
+    std::vector<uint16_t> h_mset_st;
+    int16_t h_byte_class[256] = {};
 };
 
 namespace dfaspec {
@@ -77,7 +91,8 @@ struct MatchPlan {
     uint64_t n = 0;
     uint64_t chunk = 0;
     uint32_t nch = 0;
-    uint32_t lookahead = 1;      // set mode: 0 all states, 1 I_sigma, 2 exact image of r bytes
+    uint32_t lookahead = 1;      // set mode: 0 all states, 1 I_sigma, 2 image of r > r0 bytes
+                                 // (window pass), 3 precomputed I_{c_1..c_r} (r <= r0)
     uint32_t r = 1;              // reverse-lookahead symbols (mode 2: r >= 2)
     uint32_t bitmap_words = 0;   // mode 2: words per chunk bitmap
     uint32_t stride = 0;         // map entries per chunk (>= largest set)
@@ -111,7 +126,8 @@ struct PackedBufs {
     uint32_t *bsum = nullptr;        // scan block sums
     uint32_t *first = nullptr;       // [nch + 1] first pair of each chunk
     uint32_t *tile_first = nullptr;  // owner chunk of each wave-tile's first pair
-    uint16_t *ccls = nullptr;        // lookahead (or window) class per chunk
+    uint16_t *ccls = nullptr;        // lookahead class per chunk (r = 0, 1)
+    uint32_t *cset = nullptr;        // precomputed-set id per chunk (r >= 2)
     uint32_t *bits = nullptr;        // r >= 2: start-set bitmaps
     uint16_t *members = nullptr;     // r >= 2: sorted start sets, indexed by pair
 };
@@ -131,6 +147,26 @@ int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *f
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                  const uint16_t *bv_up, uint16_t *bv0, hipStream_t s);
 int set_match2_lds_limit(int lds);
+
+// Batches (dfa_batch.hip): a host-side plan -- descriptor bytes to upload to
+// the start of a device region of total_bytes -- and a launcher that only
+// enqueues device work.
+struct BatchPlan {
+    std::vector<uint8_t> desc;   // first desc_bytes of the device region
+    size_t o_dfas = 0, o_reqs = 0, o_tasks = 0, o_groups = 0;
+    size_t desc_bytes = 0;
+    size_t o_counter = 0, o_maps = 0, o_msize = 0;
+    size_t total_bytes = 0;
+    uint32_t count = 0, ntasks = 0, max_levels = 0;
+    std::vector<uint32_t> groups_per_level;
+    std::vector<size_t> group_base;
+    uint32_t blocks = 0, threads = 0;
+    size_t lds_match = 0, lds_compose = 0;
+    uint64_t chunk = 0;
+};
+int plan_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
+               size_t count, uint64_t chunk_req, BatchPlan *out);
+int launch_batch(const BatchPlan &p, void *dev_base, hipStream_t s, uint32_t *d_results);
 uint32_t match2_tile_pairs();
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();

@@ -23,121 +23,9 @@
 // recovers the state at every chunk boundary (Eq. 8 applied left to right).
 #include <cstdlib>
 
-#include "dfa_internal.h"
+#include "dfa_walk1.h"
 
 namespace dfaspec {
-
-constexpr int kWave = 64;
-constexpr int kMaxSlots = 8;    // states per lane per pass: up to 512 per wave (64 VGPRs, no spills)
-
-struct MatchArgs {
-    DevDFA d;
-    const uint8_t *in;
-    uint64_t n;
-    uint64_t chunk;
-    uint32_t nch;
-    uint32_t start;
-    uint32_t mode;      // 1 = initial-state sets, 0 = all non-absorbing states
-    uint32_t stride;    // map entries per chunk
-    uint16_t *maps;
-    uint16_t *msize;
-};
-
-__device__ __forceinline__ uint16_t lds_u16(const uint8_t *base, uint32_t byte_off) {
-    return *reinterpret_cast<const uint16_t *>(base + byte_off);
-}
-
-// One pass over the chunk [beg, end) for up to KS * 64 start states.  st[j]
-// holds 2 * state (a byte offset inside a table column).  Returns true in
-// every lane if some byte of the chunk is outside Sigma.
-template <int KS>
-__device__ __forceinline__ bool walk_pass(const uint8_t *tab, const uint32_t *lut,
-                                          const uint8_t *__restrict__ in, uint64_t beg,
-                                          uint64_t end, uint32_t (&st)[KS > 0 ? KS : 1],
-                                          uint32_t lane) {
-    bool bad = false;
-    uint64_t blk = beg;
-    uint32_t nb = (uint32_t)min<uint64_t>(kWave, end - blk);
-    uint32_t byte = lane < nb ? in[blk + lane] : 0u;
-    while (true) {
-        uint32_t e = lut[byte];
-        bool inval = (lane < nb) && (e == kLutInvalid);
-        bad |= inval;
-        uint32_t co = (e == kLutInvalid) ? 0u : (e & 0xFFFFFFu);
-        // prefetch the next block's bytes while this block is walked
-        uint64_t nblk = blk + kWave;
-        uint32_t nnb = nblk < end ? (uint32_t)min<uint64_t>(kWave, end - nblk) : 0u;
-        uint32_t nbyte = lane < nnb ? in[nblk + lane] : 0u;
-        if (KS > 0) {
-            if (nb == kWave) {
-#pragma unroll 16
-                for (int t = 0; t < kWave; ++t) {
-                    uint32_t s = __builtin_amdgcn_readlane(co, t);
-#pragma unroll
-                    for (int j = 0; j < KS; ++j) st[j] = lds_u16(tab, s + st[j]);
-                }
-            } else {
-                for (uint32_t t = 0; t < nb; ++t) {
-                    uint32_t s = __builtin_amdgcn_readlane(co, t);
-#pragma unroll
-                    for (int j = 0; j < KS; ++j) st[j] = lds_u16(tab, s + st[j]);
-                }
-            }
-        }
-        if (nnb == 0) break;
-        blk = nblk;
-        nb = nnb;
-        byte = nbyte;
-    }
-    return __builtin_amdgcn_read_exec() != 0 && __any(bad);
-}
-
-template <int KS>
-__device__ __forceinline__ bool run_pass(const MatchArgs &a, const uint8_t *tab,
-                                         const uint32_t *lut, uint32_t chunk_id, uint64_t beg,
-                                         uint64_t end, const uint16_t *set, uint32_t base,
-                                         uint32_t m, uint32_t next_class, uint32_t lane) {
-    uint32_t st[KS > 0 ? KS : 1];
-#pragma unroll
-    for (int j = 0; j < (KS > 0 ? KS : 1); ++j) {
-        uint32_t p = base + j * kWave + lane;
-        uint32_t s = 0;
-        if (p < m) s = set ? set[p] : a.start;
-        st[j] = 2u * s;
-    }
-    bool bad = walk_pass<KS>(tab, lut, a.in, beg, end, st, lane);
-    if (KS > 0) {
-        const bool last = (chunk_id + 1 == a.nch);
-        const uint16_t *pos = a.d.pos[a.mode] + (size_t)next_class * a.d.nq;
-        uint16_t *out = a.maps + (size_t)chunk_id * a.stride;
-#pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            uint32_t p = base + j * kWave + lane;
-            if (p < m) {
-                uint32_t e = st[j] >> 1;
-                out[p] = last ? (uint16_t)(kTerm | e) : pos[e];
-            }
-        }
-    }
-    return bad;
-}
-
-// Calls run_pass<ks> for a runtime ks in 1..K (a chain of uniform branches).
-template <int K>
-__device__ __forceinline__ bool dispatch_pass(uint32_t ks, const MatchArgs &a, const uint8_t *tab,
-                                              const uint32_t *lut, uint32_t chunk_id,
-                                              uint64_t beg, uint64_t end, const uint16_t *set,
-                                              uint32_t base, uint32_t m, uint32_t next_class,
-                                              uint32_t lane) {
-    if constexpr (K == 0) {
-        return false;
-    } else {
-        if (ks == K)
-            return run_pass<K>(a, tab, lut, chunk_id, beg, end, set, base, m, next_class, lane);
-        return dispatch_pass<K - 1>(ks, a, tab, lut, chunk_id, beg, end, set, base, m,
-                                    next_class, lane);
-    }
-}
 
 __global__ __launch_bounds__(1024, 8) void k_match(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -156,39 +44,8 @@ __global__ __launch_bounds__(1024, 8) void k_match(MatchArgs a) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
     const uint32_t waves = blockDim.x / kWave;
-    for (uint32_t c = blockIdx.x * waves + wave; c < a.nch; c += gridDim.x * waves) {
-        const uint64_t beg = (uint64_t)c * a.chunk;
-        const uint64_t end = min(beg + a.chunk, a.n);
-        const uint16_t *set = nullptr;
-        uint32_t m = 1;
-        if (c > 0) {
-            uint32_t e = lut[a.in[beg - 1]];
-            if (e == kLutInvalid) {
-                m = 0;   // the preceding chunk reports the byte
-            } else {
-                uint32_t cls = e >> 24;
-                uint32_t o0 = a.d.set_off[a.mode][cls];
-                m = a.d.set_off[a.mode][cls + 1] - o0;
-                set = a.d.set_st[a.mode] + o0;
-            }
-        }
-        uint32_t next_class = 0;
-        if (c + 1 < a.nch) {
-            uint32_t e = lut[a.in[end - 1]];
-            next_class = (e == kLutInvalid) ? 0u : (e >> 24);
-        }
-        bool bad = false;
-        if (m == 0) {
-            bad = run_pass<0>(a, tab, lut, c, beg, end, set, 0, 0, next_class, lane);
-        } else {
-            for (uint32_t base = 0; base < m; base += kMaxSlots * kWave) {
-                const uint32_t ks = min<uint32_t>(kMaxSlots, (m - base + kWave - 1) / kWave);
-                bad |= dispatch_pass<kMaxSlots>(ks, a, tab, lut, c, beg, end, set, base, m,
-                                                next_class, lane);
-            }
-        }
-        if (lane == 0) a.msize[c] = (uint16_t)(m | (bad ? kFlagSymbol : 0));
-    }
+    for (uint32_t c = blockIdx.x * waves + wave; c < a.nch; c += gridDim.x * waves)
+        match_one_chunk(a, tab, lut, c, lane);
 }
 
 // Compose G consecutive maps of one level into one map of the next (Eq. 9).
@@ -210,13 +67,7 @@ __global__ __launch_bounds__(256) void k_compose(const uint16_t *__restrict__ in
     for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) sm[i] = src[i];
     __syncthreads();
     const uint32_t m = in_msize[first] & 0x7FFFu;
-    for (uint32_t p = threadIdx.x; p < m; p += blockDim.x) {
-        uint32_t v = sm[p];
-        for (uint32_t t = 1; t < cnt && !(v & kTerm); ++t) {
-            v = (v < stride) ? sm[t * stride + v] : kBadPos;
-        }
-        out_maps[(size_t)g * stride + p] = (uint16_t)v;
-    }
+    compose_staged(sm, cnt, stride, m, out_maps + (size_t)g * stride);
     if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m | (flag ? kFlagSymbol : 0));
 }
 
@@ -241,7 +92,9 @@ __global__ void k_down(const uint16_t *__restrict__ maps_l, uint32_t n_l, uint32
 __global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
                                uint32_t nch, uint32_t start, uint32_t mode,
                                const uint16_t *__restrict__ bv0, const uint32_t *__restrict__ first,
-                               const uint16_t *__restrict__ members, uint32_t *__restrict__ out) {
+                               const uint16_t *__restrict__ members,
+                               const uint32_t *__restrict__ cset, uint32_t r,
+                               uint32_t *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nch) return;
     const uint32_t v = bv0[i];
@@ -252,6 +105,11 @@ __global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_
         s = start;
     } else if (mode == 2) {
         s = (v < first[i + 1] - first[i]) ? members[first[i] + v] : 0xFFFFFFFFu;
+    } else if (mode == 3) {
+        const uint32_t k = (uint32_t)min<uint64_t>(r, (uint64_t)i * chunk);
+        const uint32_t lo = d.mset_off[d.moff[k] + cset[i]];
+        const uint32_t hi = d.mset_off[d.moff[k] + cset[i] + 1];
+        s = (v < hi - lo) ? d.mset_st[d.mst[k] + lo + v] : 0xFFFFFFFFu;
     } else {
         const uint32_t e = d.lut[in[(uint64_t)i * chunk - 1]];
         if (e == kLutInvalid) {
@@ -349,7 +207,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     if (lookahead >= 2 && d->dev.layout == 0) lookahead = 1;
     if (lookahead > 64) return fail(DFA_E_INVAL, "lookahead must be at most 64 symbols");
     p->r = lookahead;
-    p->lookahead = lookahead >= 2 ? 2u : lookahead;
+    p->lookahead = lookahead <= 1 ? lookahead : (lookahead <= d->dev.r0 ? 3u : 2u);
     p->bitmap_words = (d->dev.nq + 31) / 32;
     // sets with r >= 2 are subsets of the one-symbol sets (Lemma, Section 4.3)
     const uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
@@ -375,7 +233,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // path needs fewer launches.  DFA_KERNEL=1 / =2 force either kernel.
     const bool idle_lanes = p->lookahead == 0 ? false : d->wave_util < 0.85;
     p->packed = d->dev.layout != 0 &&
-                (p->lookahead == 2 ||
+                (p->lookahead >= 2 ||
                  (!(force && force[0] == '1') &&
                   ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
     if (p->packed) {
@@ -390,7 +248,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
             // about six wave-tiles of pairs per resident wavefront
             const double mean = std::max(1.0, p->lookahead == 0 ? (double)d->setmax_host[0]
                                               : p->lookahead == 1 ? d->info.mean_iset
-                                                                  : 0.5 * d->info.mean_iset);
+                                              : d->mset_mean[std::min(p->r, d->dev.r0)]);
             const double tiles = 6.0 * p->blocks2 * (p->threads2 / 64.0);
             const double nch_target = tiles * match2_tile_pairs() / mean;
             chunk = (uint64_t)((double)n / std::max(1.0, nch_target));
@@ -510,7 +368,8 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
         }
         hipLaunchKernelGGL(k_bound_states, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev,
                            d_in, p.chunk, p.nch, start, p.lookahead, bvals,
-                           pb ? pb->first : nullptr, pb ? pb->members : nullptr, d_boundaries);
+                           pb ? pb->first : nullptr, pb ? pb->members : nullptr,
+                           pb ? pb->cset : nullptr, p.r, d_boundaries);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "boundary kernels launch");
     }

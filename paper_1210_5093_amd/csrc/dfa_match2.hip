@@ -166,26 +166,65 @@ __global__ void k_chunkinfo(DevDFA d, const uint8_t *__restrict__ in, uint64_t c
 // state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
 // lays out the start sets as sorted member lists.
 //
-// k_chunkinfo_w: window class and |I_{sigma_1}| per chunk; clears the bitmaps.
+// Class-string id of the k bytes at in[pos ..] (first byte most significant);
+// *bad is set if one of them is outside Sigma.
+__device__ __forceinline__ uint32_t class_string_id(const DevDFA &d, const uint8_t *__restrict__ in,
+                                                    uint64_t pos, uint32_t k, bool *bad) {
+    uint32_t id = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t e = d.lut[in[pos + j]];
+        if (e == kLutInvalid) { *bad = true; return 0; }
+        id = id * d.nclass + (e >> 24);
+    }
+    return id;
+}
+
+__device__ __forceinline__ uint32_t mset_begin(const DevDFA &d, uint32_t k, uint32_t id) {
+    return d.mset_off[d.moff[k] + id];
+}
+__device__ __forceinline__ uint32_t mset_end(const DevDFA &d, uint32_t k, uint32_t id) {
+    return d.mset_off[d.moff[k] + id + 1];
+}
+
+// r <= r0: the start set of chunk i >= 1 is the precomputed I_{c_1..c_k} of
+// its k = min(r, p) lookahead bytes (Eq. 13).
+__global__ void k_chunkinfo_m(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
+                              uint32_t nch, uint32_t r, uint16_t *__restrict__ msize,
+                              uint32_t *__restrict__ cset) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    uint32_t m = 1, id = 0;
+    if (i > 0) {
+        const uint64_t p = (uint64_t)i * chunk;
+        const uint32_t k = (uint32_t)min<uint64_t>(r, p);
+        bool bad = false;
+        id = class_string_id(d, in, p - k, k, &bad);
+        m = bad ? 0u : mset_end(d, k, id) - mset_begin(d, k, id);
+    }
+    msize[i] = (uint16_t)m;
+    cset[i] = id;
+}
+
+// r > r0: window pairs start from the precomputed set of the window's first
+// k0 = min(r', r0) bytes; cset holds that set's id.  Clears the bitmaps.
 __global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
                               uint32_t nch, uint32_t r, uint32_t W,
-                              uint16_t *__restrict__ msize, uint16_t *__restrict__ ccls,
+                              uint16_t *__restrict__ msize, uint32_t *__restrict__ cset,
                               uint32_t *__restrict__ bits) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nch) return;
     for (uint32_t k = 0; k < W; ++k) bits[(size_t)i * W + k] = 0;
-    uint32_t m = 0, cls = 0;
+    uint32_t m = 0, id = 0;
     if (i > 0) {
         const uint64_t p = (uint64_t)i * chunk;
         const uint32_t rr = (uint32_t)min<uint64_t>(r, p);
-        const uint32_t e = d.lut[in[p - rr]];
-        if (e != kLutInvalid) {
-            cls = e >> 24;
-            m = d.set_off[1][cls + 1] - d.set_off[1][cls];
-        }
+        const uint32_t k0 = min(rr, d.r0);
+        bool bad = false;
+        id = class_string_id(d, in, p - rr, k0, &bad);
+        m = bad ? 0u : mset_end(d, k0, id) - mset_begin(d, k0, id);
     }
     msize[i] = (uint16_t)m;
-    ccls[i] = (uint16_t)cls;
+    cset[i] = id;
 }
 
 // Exclusive scan of the set sizes in three phases: first[i] = sum_{k<i} m_k,
@@ -341,7 +380,8 @@ struct Match2Args {
     uint32_t r;              // window passes: lookahead symbols
     const uint32_t *first;   // [nch + 1]
     const uint32_t *tile_first;
-    const uint16_t *ccls;    // [nch]
+    const uint16_t *ccls;    // [nch] modes 0, 1: lookahead class
+    const uint32_t *cset;    // [nch] modes 2, 3: precomputed set id
     const uint16_t *members; // mode 2: sorted start sets
     uint32_t *bits;          // window pass: start-set bitmaps
     uint32_t W;
@@ -424,24 +464,32 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
             uint32_t s = 0;
             const uint64_t p = (uint64_t)c * a.chunk;
             const uint32_t rr = (uint32_t)min<uint64_t>(a.r, p);
-            if (valid) s = a.d.set_st[1][a.d.set_off[1][a.ccls[c]] + (P - a.first[c])];
+            const uint32_t k0 = min(rr, a.d.r0);
+            if (valid)
+                s = a.d.mset_st[a.d.mst[k0] + mset_begin(a.d, k0, a.cset[c]) + (P - a.first[c])];
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
-            beg[j] = valid ? p - rr + 1 : 0;
-            len[j] = valid ? rr - 1 : 0;
+            beg[j] = valid ? p - rr + k0 : 0;
+            len[j] = valid ? rr - k0 : 0;
         }
-        for (uint32_t t = 0; t + 1 < a.r; ++t) {
+        uint32_t maxlen = 0;
+#pragma unroll
+        for (int j = 0; j < kSlots2; ++j) maxlen = max(maxlen, len[j]);
+        for (uint32_t t = 0; t < maxlen; ++t) {
 #pragma unroll
             for (int j = 0; j < kSlots2; ++j)
                 if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[beg[j] + t]);
         }
 #pragma unroll
         for (int j = 0; j < kSlots2; ++j) {
-            if (ci[j] != 0xFFFFFFFFu) {
-                const uint32_t e = st[j] / R;
-                if (a.d.pos[1][e] != (uint16_t)(kTerm | e))   // class-0 row: absorbing marker
-                    atomicOr(&a.bits[(size_t)ci[j] * a.W + (e >> 5)], 1u << (e & 31));
-            }
+            // walks of one chunk converge, and its pairs sit in adjacent lanes:
+            // skip the atomic when the previous lane already set the same bit
+            const uint32_t e = st[j] / R;
+            const uint32_t prev_c = __shfl_up(ci[j], 1);
+            const uint32_t prev_e = __shfl_up(e, 1);
+            const bool dup = lane > 0 && prev_c == ci[j] && prev_e == e;
+            if (ci[j] != 0xFFFFFFFFu && !dup && a.d.pos[1][e] != (uint16_t)(kTerm | e))
+                atomicOr(&a.bits[(size_t)ci[j] * a.W + (e >> 5)], 1u << (e & 31));
         }
     }
 }
@@ -475,12 +523,16 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
             const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
             uint32_t s = 0;
             if (valid) {
-                if (c == 0)
+                if (c == 0) {
                     s = a.start;
-                else if (a.mode == 2)
+                } else if (a.mode == 2) {
                     s = a.members[P];
-                else
+                } else if (a.mode == 3) {
+                    const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)c * a.chunk);
+                    s = a.d.mset_st[a.d.mst[k] + mset_begin(a.d, k, a.cset[c]) + (P - a.first[c])];
+                } else {
                     s = a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
+                }
             }
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
@@ -516,6 +568,14 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
                     v = ab == (uint16_t)(kTerm | e)
                             ? ab
                             : (uint16_t)member_rank(a.members, a.first[c + 1], a.first[c + 2], e);
+                } else if (a.mode == 3) {
+                    const uint16_t ab = a.d.pos[1][e];
+                    const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)(c + 1) * a.chunk);
+                    const uint32_t id = a.cset[c + 1];
+                    v = ab == (uint16_t)(kTerm | e)
+                            ? ab
+                            : (uint16_t)member_rank(a.d.mset_st + a.d.mst[k], mset_begin(a.d, k, id),
+                                                    mset_end(a.d, k, id), e);
                 } else {
                     v = a.d.pos[a.mode][(size_t)a.ccls[c + 1] * a.d.nq + e];
                 }
@@ -611,6 +671,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.first = b.first;
     a.tile_first = b.tile_first;
     a.ccls = b.ccls;
+    a.cset = b.cset;
     a.members = b.members;
     a.bits = b.bits;
     a.W = p.bitmap_words;
@@ -620,13 +681,17 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
         hipLaunchKernelGGL(k_chunkinfo_w, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
-                           p.chunk, p.nch, p.r, p.bitmap_words, msize, b.ccls, b.bits);
+                           p.chunk, p.nch, p.r, p.bitmap_words, msize, b.cset, b.bits);
         launch_scan<0>(p, q, b, nullptr, start, s);
         if (L == 1)
             hipLaunchKernelGGL(k_window2<1>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
         else
             hipLaunchKernelGGL(k_window2<2>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
         launch_scan<1>(p, q, b, msize, start, s);
+    } else if (p.lookahead == 3) {
+        hipLaunchKernelGGL(k_chunkinfo_m, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
+                           p.chunk, p.nch, p.r, msize, b.cset);
+        launch_scan<0>(p, q, b, msize, start, s);
     } else {
         hipLaunchKernelGGL(k_chunkinfo, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
                            p.chunk, p.nch, p.lookahead, msize, b.ccls);

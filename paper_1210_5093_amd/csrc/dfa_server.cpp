@@ -1,0 +1,338 @@
+// Serving loop: resident DFAs, admission by device-memory budget, continuous
+// batching.
+//
+// Clients submit (DFA id, device string) requests at any time.  A dispatcher
+// thread admits requests in arrival order while the in-flight byte budget and
+// the in-flight request cap allow, packs the admitted ones into a batch (one
+// persistent matcher launch, see dfa_batch.hip) and runs it on a free slot:
+// each slot owns a stream, a device arena, pinned staging for the batch
+// descriptors and pinned result records, so dispatching allocates nothing.
+// Several slots run at once, so requests that arrive while earlier batches
+// are on the GPU join the next batch and overlap with them.  A batch's
+// results are copied to pinned memory on its stream; when its event
+// completes, the dispatcher publishes the records and releases the budget.
+// Every record equals what the request gives alone (same kernels, same
+// chunking rule, exact integer results).
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+
+#include "dfa_internal.h"
+
+using namespace dfaspec;
+
+namespace {
+
+struct Request {
+    uint64_t ticket;
+    uint32_t id;
+    const uint8_t *in;
+    size_t len;
+    uint64_t cost;   // admitted bytes: input + arena estimate
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    void *staging = nullptr;        // pinned, descriptors
+    size_t staging_bytes = 0;
+    uint32_t *d_results = nullptr;
+    uint32_t *h_results = nullptr;  // pinned
+    bool busy = false;
+    std::vector<Request> reqs;
+    uint64_t cost = 0;
+};
+
+struct Done {
+    dfa_result_t r;
+};
+
+}  // namespace
+
+struct dfa_server {
+    dfa_server_opts_t opts{};
+    int device = 0;
+    std::vector<const dfa_t *> dfas;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_submit;   // dispatcher waits for work
+    std::condition_variable cv_done;     // clients wait for results
+    std::deque<Request> pending;
+    std::unordered_map<uint64_t, Done> done;
+    uint64_t next_ticket = 1;
+    uint64_t inflight_bytes = 0;
+    uint32_t inflight_reqs = 0;
+    bool stop = false;
+    int error = DFA_OK;
+    std::thread worker;
+    dfa_server_stats_t stats{};
+};
+
+namespace {
+
+uint64_t request_cost(const dfa_t *d, size_t len) {
+    // input bytes + map arena of the batch path at 1 KiB chunks (an upper bound)
+    const uint64_t stride = (std::max<uint32_t>(d->setmax_host[1], 1u) + 7u) & ~7u;
+    return (uint64_t)len + ((uint64_t)len / 1024 + 2) * stride * 2 * 2;
+}
+
+void publish(dfa_server *srv, Slot &sl) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (size_t k = 0; k < sl.reqs.size(); ++k) {
+        Done dn;
+        std::memcpy(&dn.r, sl.h_results + 4 * k, sizeof(dfa_result_t));
+        srv->done.emplace(sl.reqs[k].ticket, dn);
+        srv->stats.completed++;
+    }
+    srv->inflight_bytes -= sl.cost;
+    srv->inflight_reqs -= (uint32_t)sl.reqs.size();
+    sl.reqs.clear();
+    sl.cost = 0;
+    sl.busy = false;
+    srv->cv_done.notify_all();
+}
+
+// Plans and launches the given requests on a slot.  Returns false (and
+// leaves the slot idle) if the batch does not fit the slot's arena.
+int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *fits) {
+    *fits = true;
+    std::vector<const dfa_t *> ds(reqs.size());
+    std::vector<const uint8_t *> ins(reqs.size());
+    std::vector<size_t> lens(reqs.size());
+    for (size_t k = 0; k < reqs.size(); ++k) {
+        ds[k] = srv->dfas[reqs[k].id];
+        ins[k] = reqs[k].in;
+        lens[k] = reqs[k].len;
+    }
+    BatchPlan plan;
+    int rc = plan_batch(ds.data(), ins.data(), lens.data(), reqs.size(), 0, &plan);
+    if (rc) return rc;
+    if (plan.total_bytes > sl.arena_bytes || plan.desc_bytes > sl.staging_bytes ||
+        reqs.size() > srv->opts.max_batch) {
+        *fits = false;
+        return DFA_OK;
+    }
+    std::memcpy(sl.staging, plan.desc.data(), plan.desc_bytes);
+    hipError_t e = hipMemcpyAsync(sl.arena, sl.staging, plan.desc_bytes, hipMemcpyHostToDevice,
+                                  sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "server: descriptor upload");
+    rc = launch_batch(plan, sl.arena, sl.stream, sl.d_results);
+    if (rc) return rc;
+    e = hipMemcpyAsync(sl.h_results, sl.d_results, reqs.size() * sizeof(dfa_result_t),
+                       hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "server: result readback");
+    sl.reqs = std::move(reqs);
+    sl.busy = true;
+    return DFA_OK;
+}
+
+void dispatcher(dfa_server *srv) {
+    (void)hipSetDevice(srv->device);
+    while (true) {
+        // 1. completions
+        bool any_busy = false;
+        for (auto &sl : srv->slots) {
+            if (!sl.busy) continue;
+            hipError_t q = hipEventQuery(sl.done);
+            if (q == hipSuccess) {
+                publish(srv, sl);
+            } else if (q != hipErrorNotReady) {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->error = hip_fail(q, "server: batch failed");
+                srv->stop = true;
+            } else {
+                any_busy = true;
+            }
+        }
+        // 2. admission + dispatch into free slots
+        std::unique_lock<std::mutex> lk(srv->mu);
+        if (srv->stop && srv->pending.empty() && !any_busy) break;
+        if (srv->stop && srv->error) break;
+        for (auto &sl : srv->slots) {
+            if (sl.busy || srv->pending.empty()) continue;
+            std::vector<Request> take;
+            uint64_t cost = 0;
+            while (!srv->pending.empty() && take.size() < srv->opts.max_batch) {
+                const Request &r = srv->pending.front();
+                if (srv->inflight_reqs + take.size() + 1 > srv->opts.max_inflight) break;
+                if (srv->inflight_bytes + cost + r.cost > srv->opts.budget_bytes && !take.empty())
+                    break;
+                if (srv->inflight_bytes + cost + r.cost > srv->opts.budget_bytes &&
+                    srv->inflight_bytes > 0)
+                    break;   // wait for memory to free up
+                cost += r.cost;
+                take.push_back(r);
+                srv->pending.pop_front();
+            }
+            if (take.empty()) break;
+            srv->inflight_bytes += cost;
+            srv->inflight_reqs += (uint32_t)take.size();
+            srv->stats.batches++;
+            lk.unlock();
+            // shrink the batch until it fits the slot's arena
+            bool fits = false;
+            int rc = DFA_OK;
+            std::vector<Request> put_back;
+            while (!take.empty()) {
+                std::vector<Request> attempt = take;
+                rc = launch_on_slot(srv, sl, attempt, &fits);
+                if (rc || fits) break;
+                put_back.insert(put_back.begin(), take.back());
+                take.pop_back();
+            }
+            lk.lock();
+            if (rc || take.empty()) {
+                if (!rc) rc = fail(DFA_E_TOOBIG, "server: a request exceeds the slot arena");
+                srv->error = rc;
+                srv->stop = true;
+                break;
+            }
+            sl.cost = 0;
+            for (auto &r : take) sl.cost += r.cost;
+            uint64_t back_cost = 0;
+            for (auto it = put_back.rbegin(); it != put_back.rend(); ++it) {
+                back_cost += it->cost;
+                srv->pending.push_front(*it);
+            }
+            srv->inflight_bytes -= back_cost;
+            srv->inflight_reqs -= (uint32_t)put_back.size();
+        }
+        if (srv->pending.empty() || std::all_of(srv->slots.begin(), srv->slots.end(),
+                                                [](const Slot &s) { return s.busy; })) {
+            // wait briefly for submissions or completions
+            srv->cv_submit.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 200));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int dfa_server_create(const dfa_server_opts_t *opts, dfa_server_t **out) {
+    if (!out) return fail(DFA_E_INVAL, "dfa_server_create: out is NULL");
+    *out = nullptr;
+    std::unique_ptr<dfa_server> srv(new dfa_server());
+    dfa_server_opts_t o{};
+    if (opts) o = *opts;
+    if (!o.budget_bytes) o.budget_bytes = 16ull << 30;
+    if (!o.max_inflight) o.max_inflight = 4096;
+    if (!o.streams) o.streams = 4;
+    if (!o.max_batch) o.max_batch = 256;
+    if (!o.slot_bytes) o.slot_bytes = 256ull << 20;
+    srv->opts = o;
+    hipError_t e = hipGetDevice(&srv->device);
+    if (e != hipSuccess) return hip_fail(e, "dfa_server_create: hipGetDevice");
+    srv->slots.resize(o.streams);
+    for (auto &sl : srv->slots) {
+        // non-blocking streams at the default priority
+        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(&sl.arena, o.slot_bytes);
+        sl.arena_bytes = o.slot_bytes;
+        sl.staging_bytes = std::min<size_t>(o.slot_bytes, 64u << 20);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.staging, sl.staging_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_results, (size_t)o.max_batch * sizeof(dfa_result_t));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&sl.h_results, (size_t)o.max_batch * sizeof(dfa_result_t),
+                              hipHostMallocDefault);
+        if (e != hipSuccess) {
+            dfa_server_destroy(srv.release());
+            return fail(DFA_E_NOMEM, "dfa_server_create: slot allocation failed");
+        }
+    }
+    srv->worker = std::thread(dispatcher, srv.get());
+    *out = srv.release();
+    return DFA_OK;
+}
+
+extern "C" int dfa_server_register(dfa_server_t *srv, const dfa_t *d, uint32_t *id) {
+    if (!srv || !d || !id) return fail(DFA_E_INVAL, "dfa_server_register: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *id = (uint32_t)srv->dfas.size();
+    srv->dfas.push_back(d);
+    return DFA_OK;
+}
+
+extern "C" int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
+                                 uint64_t *ticket) {
+    if (!srv || !ticket || (len && !d_input)) return fail(DFA_E_INVAL, "dfa_server_submit: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->error) return srv->error;
+    if (srv->stop) return fail(DFA_E_INVAL, "dfa_server_submit: server is stopping");
+    if (id >= srv->dfas.size()) return fail(DFA_E_INVAL, "dfa_server_submit: unknown DFA id");
+    Request r;
+    r.ticket = srv->next_ticket++;
+    r.id = id;
+    r.in = d_input;
+    r.len = len;
+    r.cost = request_cost(srv->dfas[id], len);
+    if (r.cost > srv->opts.budget_bytes)
+        return fail(DFA_E_TOOBIG, "dfa_server_submit: request exceeds the memory budget");
+    srv->pending.push_back(r);
+    srv->stats.submitted++;
+    srv->stats.bytes += len;
+    *ticket = r.ticket;
+    srv->cv_submit.notify_one();
+    return DFA_OK;
+}
+
+extern "C" int dfa_server_poll(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out) {
+    if (!srv || !out) return fail(DFA_E_INVAL, "dfa_server_poll: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end()) return srv->error ? srv->error : DFA_E_NOTREADY;
+    *out = it->second.r;
+    srv->done.erase(it);
+    return DFA_OK;
+}
+
+extern "C" int dfa_server_wait(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out) {
+    if (!srv || !out) return fail(DFA_E_INVAL, "dfa_server_wait: NULL argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    while (true) {
+        auto it = srv->done.find(ticket);
+        if (it != srv->done.end()) {
+            *out = it->second.r;
+            srv->done.erase(it);
+            return DFA_OK;
+        }
+        if (srv->error) return srv->error;
+        srv->cv_done.wait_for(lk, std::chrono::milliseconds(10));
+    }
+}
+
+extern "C" int dfa_server_stats(dfa_server_t *srv, dfa_server_stats_t *out) {
+    if (!srv || !out) return fail(DFA_E_INVAL, "dfa_server_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->stats;
+    out->inflight = srv->inflight_reqs;
+    out->pending = srv->pending.size();
+    return DFA_OK;
+}
+
+extern "C" void dfa_server_destroy(dfa_server_t *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv_submit.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    for (auto &sl : srv->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.arena) (void)hipFree(sl.arena);
+        if (sl.d_results) (void)hipFree(sl.d_results);
+        if (sl.staging) (void)hipHostFree(sl.staging);
+        if (sl.h_results) (void)hipHostFree(sl.h_results);
+    }
+    delete srv;
+}

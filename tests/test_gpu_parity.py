@@ -424,3 +424,44 @@ def test_invalid_byte_inside_lookahead_window(dfa_mod, pos):
     res, _ = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=4096, lookahead=8)
     torch.cuda.synchronize()
     assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+
+
+# ---------------------------------------------------------------------------
+# Precomputed multi-symbol sets (Eq. 13) against the oracle's definition
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["c2", "c1", "c3b", "motiv", "example"])
+def test_precomputed_lookahead_sets_match_eq13(dfa_mod, which):
+    if which == "c2":
+        w = configs.c2_dfa()
+    elif which == "c1":
+        w = configs.c1_dfa(3)
+    elif which == "c3b":
+        w = configs.c3_byte_dfa()
+    else:
+        _, w = golden_workload("motivating_dfa.json" if which == "motiv" else "example_dfa.json")
+    d = dfa_mod.DFA.from_workload(w)
+    r0 = d.info().lookahead_tables
+    assert r0 >= 1
+    ab = oracle.absorbing(w.delta)
+    valid = np.nonzero(w.byte_to_symbol < w.num_symbols)[0].astype(np.uint8)
+    rng = np.random.default_rng(7)
+    for k in range(1, r0 + 1):
+        for _ in range(40):
+            u = rng.choice(valid, k)
+            expect = np.nonzero(oracle.iset_word(w.delta, w.byte_to_symbol[u], ab))[0].tolist()
+            assert dfa_mod.dfa_lookahead_set(d, u.tobytes()) == expect, (k, u)
+    if which == "motiv":
+        assert dfa_mod.dfa_lookahead_set(d, b"a") == [0]
+        assert dfa_mod.dfa_lookahead_set(d, b"b") == [1]
+    if which == "example":
+        assert dfa_mod.dfa_lookahead_set(d, b"a") == [1, 3]
+        assert dfa_mod.dfa_lookahead_set(d, b"b") == [2, 3]
+
+
+@pytest.mark.parametrize("r", [2, 3, 5, 7, 9, 12])
+def test_precomputed_and_window_lookahead_c2_bench_size(dfa_mod, r):
+    """Lookahead within the precomputed tables (r <= r0) and beyond them (window
+    pass from the r0-symbol sets), at the bench size with planner chunking."""
+    w = configs.c2_dfa()
+    x = configs.c2_input(32 * (1 << 20) + 5)
+    check(dfa_mod, w, x, lookahead=r)

@@ -81,3 +81,105 @@ def c3_protein_input(n: int, first: int = 0, out=None) -> np.ndarray:
 
 def c3_byte_input(n: int, first: int = 0, out=None) -> np.ndarray:
     return streams.uniform_bytes(C3_BYTE_INPUT_SEED, n, first, out=out)
+
+
+# ---------------------------------------------------------------------------
+# C4 batched / C5 served
+# ---------------------------------------------------------------------------
+import functools
+import json
+import math
+import os
+
+_POOL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prosite_pool.json")
+
+
+@functools.lru_cache(maxsize=1)
+def prosite_pool():
+    """(seed, states) of pattern DFAs recorded by make_prosite_pool.py."""
+    with open(_POOL_PATH) as f:
+        return [tuple(x) for x in json.load(f)["pool"]]
+
+
+def pool_seed(target: int, rng) -> int:
+    """A pattern seed whose minimal DFA has target +-10% states (nearest if none)."""
+    pool = prosite_pool()
+    lo, hi = 0.9 * target, 1.1 * target
+    cands = [s for s, q in pool if lo <= q <= hi]
+    if cands:
+        return int(cands[int(rng.integers(0, len(cands)))])
+    return int(min(pool, key=lambda sq: abs(sq[1] - target))[0])
+
+
+@functools.lru_cache(maxsize=None)
+def _pattern_dfa_cached(seed: int):
+    return from_pattern(patterns.pattern_dfa(seed, max_states=1400))
+
+
+@functools.lru_cache(maxsize=None)
+def _column_dfa_cached(col_seed: int, map_seed: int, q: int, k: int):
+    return column_dfa(col_seed, map_seed, q, k)
+
+
+def log_uniform_int(rng, lo: float, hi: float) -> int:
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def batch_workload(count: int = 1024, seed: int = 7, min_len: int = 1 << 10,
+                   max_len: int = 64 << 20, min_states: int = 8, max_states: int = 512,
+                   byte_limit: int = 512):
+    """Requests of the batched configuration: (DFA, length, input kind, input seed).
+
+    Per request (default_rng(seed)): byte alphabet with probability 1/2, else
+    the 20-letter protein alphabet; |Q| log-uniform in [min_states, max_states]
+    (byte DFAs above byte_limit states become protein DFAs); byte DFAs take 64
+    distinct random columns (column_dfa), protein DFAs a pattern DFA within 10%
+    of the target size; length log-uniform in [min_len, max_len]; the input is
+    stream 1000 + i (uniform bytes or residues)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        byte = rng.random() < 0.5
+        q = log_uniform_int(rng, min_states, max_states)
+        n = log_uniform_int(rng, min_len, max_len)
+        if byte and q <= byte_limit:
+            w = _column_dfa_cached(100000 + i, 200000 + i, q, 64)
+            kind = "bytes"
+        else:
+            w = _pattern_dfa_cached(pool_seed(q, rng))
+            kind = "residues"
+        out.append((w, n, kind, 1000 + i))
+    return out
+
+
+def request_input(kind: str, seed: int, n: int, out=None) -> np.ndarray:
+    if kind == "bytes":
+        return streams.uniform_bytes(seed, n, out=out)
+    return streams.residues(seed, n, out=out)
+
+
+def served_workload(count: int = 10500, seed: int = 8, n_dfas: int = 64, min_len: int = 4 << 10,
+                    max_len: int = 16 << 20, min_states: int = 8, max_states: int = 1288,
+                    byte_limit: int = 512, request_seed: int = 9):
+    """The served configuration: 64 resident DFAs (default_rng(seed): |Q|
+    log-uniform in [8, 1288]; byte alphabet only up to 512 states, protein
+    pattern DFAs otherwise and for half of the rest) and `count` requests
+    (default_rng(request_seed)): DFA id uniform, length log-uniform in
+    [4 KiB, 16 MiB], input stream 5000 + k matching the DFA's alphabet.
+    Returns (dfas, [(dfa id, length, input kind, input seed)])."""
+    rng = np.random.default_rng(seed)
+    dfas = []
+    for i in range(n_dfas):
+        q = log_uniform_int(rng, min_states, max_states)
+        if q <= byte_limit and rng.random() < 0.5:
+            dfas.append(_column_dfa_cached(300000 + i, 400000 + i, q, 64))
+        else:
+            dfas.append(_pattern_dfa_cached(pool_seed(q, rng)))
+    rr = np.random.default_rng(request_seed)
+    reqs = []
+    for k in range(count):
+        i = int(rr.integers(0, n_dfas))
+        n = log_uniform_int(rr, min_len, max_len)
+        kind = "residues" if dfas[i].num_symbols == 20 else "bytes"
+        reqs.append((i, n, kind, 5000 + k))
+    return dfas, reqs

@@ -155,6 +155,21 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
                  const dfa_match_opts_t *opts, void *stream, uint32_t *d_result,
                  uint32_t *d_boundaries);
 
+/* lookahead value meaning "use what dfa_autotune chose for this DFA and a
+ * length of this order (one symbol if it was never tuned)". */
+#define DFA_LOOKAHEAD_AUTO 0xFFFFFFFFu
+
+/* dfa_autotune -- time candidate (lookahead r, chunk length) settings on the
+ * caller's device input and keep the fastest.  Every candidate gives the same
+ * result (the method is exact); only speed differs.  Inputs beyond 256 MiB
+ * are tuned on their first 256 MiB.  The choice is cached per DFA and
+ * power-of-two length bucket and used by calls with lookahead
+ * DFA_LOOKAHEAD_AUTO.
+ *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
+ *   fastest candidate's time per call (may be NULL).  Synchronises `stream`. */
+int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
+                 dfa_match_opts_t *best, double *best_ms);
+
 /* Chunk length the library would use for (d, len, opts), and the resulting
  * number of chunks. */
 int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
@@ -208,6 +223,11 @@ int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
 int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_info(const dfa_batch_t *b, uint64_t *chunk_len, uint32_t *tasks);
+/* dfa_batch_tune -- time the batch at the planner's chunk length and at 1/4,
+ * 1/2, 2x and 4x of it; *chunk_len receives the fastest (pass it to
+ * dfa_batch_create).  Allocates temporary plans; synchronises `stream`. */
+int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
+                   size_t count, void *stream, uint64_t *chunk_len, double *best_ms);
 void dfa_batch_destroy(dfa_batch_t *b);
 
 /* dfa_match_batch -- one-shot batch: plan, run on `stream`, wait for the
@@ -253,13 +273,23 @@ int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, si
 int dfa_server_poll(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
 int dfa_server_wait(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
 int dfa_server_stats(dfa_server_t *srv, dfa_server_stats_t *out);
+/* dfa_server_drain -- move up to `cap` finished records into `out` (in no
+ * particular order) and release their tickets; *count receives how many.
+ * submit_ns is when dfa_server_submit accepted the request, done_ns when its
+ * record became visible on the host, both CLOCK_MONOTONIC nanoseconds. */
+typedef struct dfa_server_done {
+    uint64_t ticket;
+    dfa_result_t result;
+    uint64_t submit_ns, done_ns;
+} dfa_server_done_t;
+int dfa_server_drain(dfa_server_t *srv, dfa_server_done_t *out, size_t cap, size_t *count);
 void dfa_server_destroy(dfa_server_t *srv);
 
 /* ---------------------------------------------------------------------------
- * Instrumentation.  With timing on for a stream, every match call on it
- * records HIP events around its chunk-matcher kernel (the preparation
- * kernels before it excluded) and around the whole
- * call (no work is skipped or reordered).  dfa_timing_read waits for those
+ * Instrumentation.  With timing on for a stream, every match call and every
+ * dfa_batch_run on it records HIP events around its chunk-matcher kernel (the
+ * preparation kernels before it excluded) and around the whole call (no work
+ * is skipped or reordered; graph launches are not instrumented).  dfa_timing_read waits for those
  * events, returns the summed milliseconds and the number of calls, and
  * clears the record. */
 int dfa_timing_enable(void *stream, int on);

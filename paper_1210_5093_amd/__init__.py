@@ -21,6 +21,7 @@ DFA_OK = 0
 DFA_E_INVAL, DFA_E_NOMEM, DFA_E_DEVICE, DFA_E_SYMBOL = -1, -2, -3, -4
 DFA_E_TOOBIG, DFA_E_SPECULATION, DFA_E_BUSY, DFA_E_NOTREADY = -5, -6, -7, -8
 DFA_Q0 = 0xFFFFFFFF
+DFA_LOOKAHEAD_AUTO = 0xFFFFFFFF
 FLAG_SYMBOL, FLAG_SPECULATION = 1, 2
 
 
@@ -53,6 +54,11 @@ class dfa_plan_info_t(ctypes.Structure):
 class dfa_result_t(ctypes.Structure):
     _fields_ = [("final_state", ctypes.c_uint32), ("accepted", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("num_chunks", ctypes.c_uint32)]
+
+
+class dfa_server_done_t(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("result", dfa_result_t),
+                ("submit_ns", ctypes.c_uint64), ("done_ns", ctypes.c_uint64)]
 
 
 class dfa_server_opts_t(ctypes.Structure):
@@ -120,6 +126,15 @@ def lib() -> ctypes.CDLL:
     L.dfa_batch_info.argtypes = [P, ctypes.POINTER(U64), ctypes.POINTER(U32)]
     L.dfa_batch_destroy.restype = None
     L.dfa_batch_destroy.argtypes = [P]
+    L.dfa_server_drain.restype = I
+    L.dfa_server_drain.argtypes = [P, ctypes.POINTER(dfa_server_done_t), ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    L.dfa_autotune.restype = I
+    L.dfa_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(dfa_match_opts_t),
+                               ctypes.POINTER(ctypes.c_double)]
+    L.dfa_batch_tune.restype = I
+    L.dfa_batch_tune.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.POINTER(U64),
+                                 ctypes.POINTER(ctypes.c_double)]
     L.dfa_server_create.restype = I
     L.dfa_server_create.argtypes = [ctypes.POINTER(dfa_server_opts_t), ctypes.POINTER(P)]
     L.dfa_server_register.restype = I
@@ -322,6 +337,28 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
     return float(m.value), float(c.value), int(k.value)
 
 
+def dfa_autotune(d: DFA, d_input, stream=None) -> Tuple[int, int, float]:
+    """Tune (lookahead, chunk length) on a device input: (r, chunk, ms per call)."""
+    o = dfa_match_opts_t()
+    ms = ctypes.c_double()
+    n = int(d_input.numel())
+    _check(lib().dfa_autotune(d.handle, d_input.data_ptr() if n else None, n,
+                              _stream_handle(stream), ctypes.byref(o), ctypes.byref(ms)))
+    return int(o.lookahead), int(o.chunk_len), float(ms.value)
+
+
+def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None) -> Tuple[int, float]:
+    count = len(dfas)
+    hs = (ctypes.c_void_p * max(count, 1))(*[x.handle.value for x in dfas])
+    ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None for t in inputs])
+    ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in inputs])
+    c = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    _check(lib().dfa_batch_tune(hs, ps, ls, count, _stream_handle(stream), ctypes.byref(c),
+                                ctypes.byref(ms)))
+    return int(c.value), float(ms.value)
+
+
 class Batch:
     """A planned batch of (DFA, device string) pairs (dfa_batch_create)."""
 
@@ -405,6 +442,23 @@ class Server:
         _check(lib().dfa_server_wait(self._h, int(ticket), ctypes.byref(r)))
         self._live.pop(int(ticket), None)
         return int(r.final_state), bool(r.accepted), int(r.flags), int(r.num_chunks)
+
+    def drain(self, cap: int = 4096):
+        """Finished records: list of (ticket, (final, accepted, flags, chunks),
+        submit_ns, done_ns), CLOCK_MONOTONIC nanoseconds."""
+        if getattr(self, "_drain_buf", None) is None or len(self._drain_buf) < cap:
+            self._drain_buf = (dfa_server_done_t * cap)()
+        n = ctypes.c_size_t()
+        _check(lib().dfa_server_drain(self._h, self._drain_buf, cap, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            e = self._drain_buf[k]
+            t = int(e.ticket)
+            self._live.pop(t, None)
+            r = e.result
+            out.append((t, (int(r.final_state), bool(r.accepted), int(r.flags), int(r.num_chunks)),
+                        int(e.submit_ns), int(e.done_ns)))
+        return out
 
     def stats(self) -> dfa_server_stats_t:
         s = dfa_server_stats_t()

@@ -75,14 +75,44 @@ uint64_t env_chunk() {
     return v ? std::strtoull(v, nullptr, 10) : 0;
 }
 
+// Autotuner cache: (DFA, length bucket) -> options.
+std::mutex g_tune_mutex;
+std::map<std::pair<const dfa_t *, int>, dfa_match_opts_t> g_tuned;
+
+int length_bucket(size_t len) {
+    int b = 0;
+    while ((len >> b) > 1) ++b;
+    return b;
+}
+
+dfa_match_opts_t resolve_opts(const dfa_t *d, size_t len, const dfa_match_opts_t *opts) {
+    dfa_match_opts_t o{};
+    o.lookahead = 1;
+    if (opts) o = *opts;
+    if (o.lookahead == DFA_LOOKAHEAD_AUTO) {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tuned.find({d, length_bucket(len)});
+        if (it != g_tuned.end()) {
+            const uint64_t user_chunk = o.chunk_len;
+            o = it->second;
+            if (user_chunk) o.chunk_len = user_chunk;
+        } else {
+            o.lookahead = 1;
+        }
+    }
+    return o;
+}
+
 int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
-              const dfa_match_opts_t *opts, hipStream_t s, uint32_t *d_result,
+              const dfa_match_opts_t *opts_in, hipStream_t s, uint32_t *d_result,
               uint32_t *d_bound) {
     if (!d || !d_result || (len && !d_in)) return fail(DFA_E_INVAL, "match: NULL argument");
     if (start == DFA_Q0) start = d->dev.q0;
     if (start >= d->dev.nq) return fail(DFA_E_INVAL, "match: start state out of range");
-    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
-    uint32_t look = opts ? opts->lookahead : 1u;
+    const dfa_match_opts_t resolved = resolve_opts(d, len, opts_in);
+    const dfa_match_opts_t *opts = &resolved;
+    uint64_t chunk = opts->chunk_len ? opts->chunk_len : env_chunk();
+    uint32_t look = opts->lookahead;
     MatchPlan p;
     int rc = plan_match(d, len, chunk, look, &p);
     if (rc) return rc;
@@ -184,24 +214,26 @@ extern "C" int dfa_match_async(const dfa_t *d, const uint8_t *d_input, size_t le
                      nullptr);
 }
 
-extern "C" int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
+extern "C" int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_t *opts_in,
                                uint64_t *chunk_len, uint64_t *num_chunks) {
     if (!d) return fail(DFA_E_INVAL, "dfa_plan_chunks: NULL dfa");
-    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
+    const dfa_match_opts_t o = resolve_opts(d, len, opts_in);
+    uint64_t chunk = o.chunk_len ? o.chunk_len : env_chunk();
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, opts ? opts->lookahead : 1u, &p);
+    int rc = plan_match(d, len, chunk, o.lookahead, &p);
     if (rc) return rc;
     if (chunk_len) *chunk_len = p.chunk;
     if (num_chunks) *num_chunks = p.nch;
     return DFA_OK;
 }
 
-extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts,
+extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts_in,
                         dfa_plan_info_t *out) {
     if (!d || !out) return fail(DFA_E_INVAL, "dfa_plan: NULL argument");
-    uint64_t chunk = opts && opts->chunk_len ? opts->chunk_len : env_chunk();
+    const dfa_match_opts_t o = resolve_opts(d, len, opts_in);
+    uint64_t chunk = o.chunk_len ? o.chunk_len : env_chunk();
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, opts ? opts->lookahead : 1u, &p);
+    int rc = plan_match(d, len, chunk, o.lookahead, &p);
     if (rc) return rc;
     out->chunk_len = p.chunk;
     out->num_chunks = p.nch;
@@ -257,6 +289,151 @@ extern "C" int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d
     if (rc) return rc;
     return e == hipSuccess ? DFA_OK : hip_fail(e, "dfa_match_batch: hipStreamSynchronize");
 }
+
+extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
+                            dfa_match_opts_t *best, double *best_ms) {
+    if (!d || (len && !d_input)) return fail(DFA_E_INVAL, "dfa_autotune: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = std::min<size_t>(len, 256u << 20);
+    uint32_t *res = nullptr;
+    hipError_t e = hipMalloc(&res, 4 * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(DFA_E_NOMEM, "dfa_autotune: hipMalloc");
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    // candidates: r = 1 .. r0 + 2 (capped at 10), chunk = planner and powers of two
+    // (tables without a packed layout support only r = 1; chunk counts are
+    // bounded so that no candidate's maps exceed 1 GiB)
+    std::vector<uint32_t> rs;
+    const uint32_t rmax = d->dev.layout ? std::min<uint32_t>(d->dev.r0 + 2, 10) : 1u;
+    for (uint32_t r = 1; r <= rmax; ++r) rs.push_back(r);
+    std::vector<uint64_t> chunks = {0};
+    const uint64_t per_chunk = 2ull * std::max<uint32_t>(d->setmax_host[0], 1u);
+    for (uint64_t c = 256; c <= (1u << 20) && c <= std::max<size_t>(n, 256); c *= 2) {
+        const uint64_t nch = (n + c - 1) / c;
+        if (nch <= (1u << 20) && nch * per_chunk <= (1ull << 30)) chunks.push_back(c);
+    }
+    dfa_match_opts_t pick{};
+    pick.lookahead = 1;
+    double pick_ms = 1e30;
+    int rc = DFA_OK;
+    for (uint32_t r : rs) {
+        for (uint64_t c : chunks) {
+            dfa_match_opts_t o{};
+            o.chunk_len = c;
+            o.lookahead = r;
+            double t_best = 1e30;
+            for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+                if (rep > 0) (void)hipEventRecord(a, s);
+                rc = run_match(d, d_input, n, DFA_Q0, &o, s, res, nullptr);
+                if (rep > 0) {
+                    (void)hipEventRecord(b, s);
+                    (void)hipEventSynchronize(b);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    t_best = std::min<double>(t_best, ms);
+                }
+            }
+            if (rc) break;
+            if (t_best < pick_ms) {
+                pick_ms = t_best;
+                pick = o;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(res);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tuned[{d, length_bucket(len)}] = pick;
+    }
+    if (best) *best = pick;
+    if (best_ms) *best_ms = pick_ms * (double)len / (double)std::max<size_t>(n, 1);
+    return DFA_OK;
+}
+
+extern "C" int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
+                              const size_t *lens, size_t count, void *stream, uint64_t *chunk_len,
+                              double *best_ms) {
+    if (!chunk_len) return fail(DFA_E_INVAL, "dfa_batch_tune: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    BatchPlan p0;
+    int rc = plan_batch(dfas, d_inputs, lens, count, 0, &p0);
+    if (rc) return rc;
+    uint32_t *res = nullptr;
+    hipError_t e = hipMalloc(&res, std::max<size_t>(count, 1) * 4 * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(DFA_E_NOMEM, "dfa_batch_tune: hipMalloc");
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    uint64_t pick = p0.chunk;
+    double pick_ms = 1e30;
+    const double mult[] = {0.25, 0.5, 1.0, 2.0, 4.0};
+    for (double m : mult) {
+        const uint64_t c = std::max<uint64_t>(256, (uint64_t)(p0.chunk * m) / 64 * 64);
+        dfa_match_opts_t o{};
+        o.chunk_len = c;
+        o.lookahead = 1;
+        dfa_batch_t *bt = nullptr;
+        rc = dfa_batch_create(dfas, d_inputs, lens, count, &o, &bt);
+        if (rc) break;
+        double t_best = 1e30;
+        for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+            if (rep > 0) (void)hipEventRecord(a, s);
+            rc = dfa_batch_run(bt, stream, res);
+            if (rep > 0) {
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t_best = std::min<double>(t_best, ms);
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        dfa_batch_destroy(bt);
+        if (rc) break;
+        if (t_best < pick_ms) {
+            pick_ms = t_best;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(res);
+    if (rc) return rc;
+    *chunk_len = pick;
+    if (best_ms) *best_ms = pick_ms;
+    return DFA_OK;
+}
+
+namespace dfaspec {
+bool timing_begin(hipStream_t s, hipEvent_t ev[4]) {
+    Workspace *ws = workspace_for(s);
+    if (!ws || !ws->timing) return false;
+    for (int k = 0; k < 4; ++k) ev[k] = nullptr;
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+            (void)hipGetLastError();
+            return false;
+        }
+    (void)hipEventRecord(ev[0], s);
+    return true;
+}
+
+int timing_end(hipStream_t s, hipEvent_t ev[4]) {
+    Workspace *ws = workspace_for(s);
+    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    hipError_t e = hipEventRecord(ev[3], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ws->stamps.push_back({ev[0], ev[1], ev[2], ev[3]});
+    return DFA_OK;
+}
+}  // namespace dfaspec
 
 extern "C" int dfa_timing_enable(void *stream, int on) {
     Workspace *ws = workspace_for((hipStream_t)stream);

@@ -307,16 +307,16 @@ int plan_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const s
     if (!groups.empty())
         std::memcpy(P.desc.data() + P.o_groups, groups.data(), groups.size() * sizeof(BatchGroup));
     if (!g_batch_attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_match),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_compose),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&k_batch_match), lds) != DFA_OK ||
+            allow_dynamic_lds(reinterpret_cast<const void *>(&k_batch_compose), lds) != DFA_OK)
+            return fail(DFA_E_DEVICE, "batch plan: cannot enable the device's LDS size");
         g_batch_attr_set = true;
     }
     return DFA_OK;
 }
 
-int launch_batch(const BatchPlan &P, void *dev_base, hipStream_t s, uint32_t *d_results) {
+int launch_batch(const BatchPlan &P, void *dev_base, hipStream_t s, uint32_t *d_results,
+                 hipEvent_t ev_before_match, hipEvent_t ev_after_match) {
     if (!P.count) return DFA_OK;
     uint8_t *base = (uint8_t *)dev_base;
     const DevDFA *dfas = (const DevDFA *)(base + P.o_dfas);
@@ -334,8 +334,10 @@ int launch_batch(const BatchPlan &P, void *dev_base, hipStream_t s, uint32_t *d_
     a.counter = counter;
     a.maps = maps;
     a.msize = msize;
+    if (ev_before_match) (void)hipEventRecord(ev_before_match, s);
     if (P.ntasks)
         hipLaunchKernelGGL(k_batch_match, dim3(P.blocks), dim3(P.threads), P.lds_match, s, a);
+    if (ev_after_match) (void)hipEventRecord(ev_after_match, s);
     for (uint32_t l = 0; l < P.max_levels; ++l)
         if (P.groups_per_level[l])
             hipLaunchKernelGGL(k_batch_compose, dim3(P.groups_per_level[l]), dim3(256), P.lds_compose,
@@ -382,7 +384,16 @@ extern "C" int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *
 
 extern "C" int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results) {
     if (!b || (b->plan.count && !d_results)) return fail(DFA_E_INVAL, "dfa_batch_run: NULL argument");
-    return launch_batch(b->plan, b->blob, (hipStream_t)stream, d_results);
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipEvent_t ev[4];
+    const bool timed = hipStreamIsCapturing(s, &cap) == hipSuccess &&
+                       cap == hipStreamCaptureStatusNone && timing_begin(s, ev);
+    int rc = launch_batch(b->plan, b->blob, s, d_results, timed ? ev[1] : nullptr,
+                          timed ? ev[2] : nullptr);
+    if (!timed) return rc;
+    const int rc2 = timing_end(s, ev);
+    return rc ? rc : rc2;
 }
 
 extern "C" int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results) {

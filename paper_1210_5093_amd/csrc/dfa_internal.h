@@ -147,6 +147,7 @@ int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *f
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                  const uint16_t *bv_up, uint16_t *bv0, hipStream_t s);
 int set_match2_lds_limit(int lds);
+int allow_dynamic_lds(const void *f, int lds);
 
 // Batches (dfa_batch.hip): a host-side plan -- descriptor bytes to upload to
 // the start of a device region of total_bytes -- and a launcher that only
@@ -166,7 +167,15 @@ struct BatchPlan {
 };
 int plan_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
                size_t count, uint64_t chunk_req, BatchPlan *out);
-int launch_batch(const BatchPlan &p, void *dev_base, hipStream_t s, uint32_t *d_results);
+int launch_batch(const BatchPlan &p, void *dev_base, hipStream_t s, uint32_t *d_results,
+                 hipEvent_t ev_before_match = nullptr, hipEvent_t ev_after_match = nullptr);
+
+// Timing hooks of dfa_timing_enable for entry points outside the single-
+// string path.  timing_begin returns false (and creates nothing) when timing
+// is off for the stream; otherwise it creates ev[0..3] and records ev[0].
+// timing_end records ev[3] and keeps the four events for dfa_timing_read.
+bool timing_begin(hipStream_t s, hipEvent_t ev[4]);
+int timing_end(hipStream_t s, hipEvent_t ev[4]);
 uint32_t match2_tile_pairs();
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();

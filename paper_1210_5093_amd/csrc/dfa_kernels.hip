@@ -157,6 +157,24 @@ __global__ void k_empty(DevDFA d, uint32_t start, uint32_t *__restrict__ result,
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Let kernel f use dynamic LDS up to `lds` bytes minus its static LDS.  Asks
+// only when the current limit is lower, and leaves no error pending on the
+// thread (the launch paths check hipGetLastError after their launches).
+int allow_dynamic_lds(const void *f, int lds) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return DFA_E_DEVICE;
+    }
+    const int need = lds - (int)fa.sharedSizeBytes;
+    if (need <= fa.maxDynamicSharedSizeBytes) return DFA_OK;
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return DFA_E_DEVICE;
+    }
+    return DFA_OK;
+}
+
 namespace {
 struct DevProps {
     int lds = 0;
@@ -180,12 +198,9 @@ DevProps &props() {
             if (p.lds <= 0) p.lds = (int)pr.sharedMemPerBlock;
             if ((int)pr.sharedMemPerBlock < p.lds) {
                 // dynamic LDS beyond the default per-block limit needs opting in
-                if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_match),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        p.lds) != hipSuccess)
+                if (allow_dynamic_lds(reinterpret_cast<const void *>(&k_match), p.lds) != DFA_OK)
                     p.lds = (int)pr.sharedMemPerBlock;
-                (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_compose),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, p.lds);
+                (void)allow_dynamic_lds(reinterpret_cast<const void *>(&k_compose), p.lds);
                 (void)set_match2_lds_limit(p.lds);
             }
             p.cus = pr.multiProcessorCount;

@@ -737,10 +737,10 @@ int set_match2_lds_limit(int lds) {
                          reinterpret_cast<const void *>(&k_window2<1>),
                          reinterpret_cast<const void *>(&k_window2<2>),
                          reinterpret_cast<const void *>(&k_compose0)};
+    int rc = DFA_OK;
     for (const void *f : fns)
-        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return DFA_E_DEVICE;
-    return DFA_OK;
+        if (allow_dynamic_lds(f, lds) != DFA_OK) rc = DFA_E_DEVICE;
+    return rc;
 }
 
 uint32_t match2_tile_pairs() { return kTile2; }

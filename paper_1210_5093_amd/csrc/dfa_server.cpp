@@ -22,14 +22,23 @@
 #include <thread>
 #include <unordered_map>
 
+#include <time.h>
+
 #include "dfa_internal.h"
 
 using namespace dfaspec;
 
 namespace {
 
+uint64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
 struct Request {
     uint64_t ticket;
+    uint64_t submit_ns;
     uint32_t id;
     const uint8_t *in;
     size_t len;
@@ -52,6 +61,7 @@ struct Slot {
 
 struct Done {
     dfa_result_t r;
+    uint64_t submit_ns, done_ns;
 };
 
 }  // namespace
@@ -84,10 +94,13 @@ uint64_t request_cost(const dfa_t *d, size_t len) {
 }
 
 void publish(dfa_server *srv, Slot &sl) {
+    const uint64_t t = now_ns();
     std::lock_guard<std::mutex> lk(srv->mu);
     for (size_t k = 0; k < sl.reqs.size(); ++k) {
         Done dn;
         std::memcpy(&dn.r, sl.h_results + 4 * k, sizeof(dfa_result_t));
+        dn.submit_ns = sl.reqs[k].submit_ns;
+        dn.done_ns = t;
         srv->done.emplace(sl.reqs[k].ticket, dn);
         srv->stats.completed++;
     }
@@ -268,6 +281,7 @@ extern "C" int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *
     if (srv->stop) return fail(DFA_E_INVAL, "dfa_server_submit: server is stopping");
     if (id >= srv->dfas.size()) return fail(DFA_E_INVAL, "dfa_server_submit: unknown DFA id");
     Request r;
+    r.submit_ns = now_ns();
     r.ticket = srv->next_ticket++;
     r.id = id;
     r.in = d_input;
@@ -306,6 +320,23 @@ extern "C" int dfa_server_wait(dfa_server_t *srv, uint64_t ticket, dfa_result_t 
         if (srv->error) return srv->error;
         srv->cv_done.wait_for(lk, std::chrono::milliseconds(10));
     }
+}
+
+extern "C" int dfa_server_drain(dfa_server_t *srv, dfa_server_done_t *out, size_t cap,
+                                size_t *count) {
+    if (!srv || !count || (cap && !out)) return fail(DFA_E_INVAL, "dfa_server_drain: NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    size_t k = 0;
+    for (auto it = srv->done.begin(); it != srv->done.end() && k < cap;) {
+        out[k].ticket = it->first;
+        out[k].result = it->second.r;
+        out[k].submit_ns = it->second.submit_ns;
+        out[k].done_ns = it->second.done_ns;
+        ++k;
+        it = srv->done.erase(it);
+    }
+    *count = k;
+    return srv->error;
 }
 
 extern "C" int dfa_server_stats(dfa_server_t *srv, dfa_server_stats_t *out) {

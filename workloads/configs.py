@@ -183,3 +183,11 @@ def served_workload(count: int = 10500, seed: int = 8, n_dfas: int = 64, min_len
         kind = "residues" if dfas[i].num_symbols == 20 else "bytes"
         reqs.append((i, n, kind, 5000 + k))
     return dfas, reqs
+
+
+def served_arrivals(count: int, rate: float, seed: int = 9) -> np.ndarray:
+    """Arrival times (seconds from the start) of a Poisson process with `rate`
+    requests per second: cumulative sums of exponential gaps drawn from
+    default_rng(seed + 1), a stream separate from the requests' own."""
+    rng = np.random.default_rng(seed + 1)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))

@@ -1,4 +1,5 @@
-"""Build ``libdfaspec.so`` (HIP, gfx950 only) in-tree with hipcc."""
+"""Build ``libdfaspec.so`` (HIP, gfx950 only) in-tree with hipcc, and the
+host multicore matcher ``libdfahost.so`` with the host C++ compiler."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdfaspec.so")
 PROBE = os.path.join(HERE, "lds_peak_probe")
+HOST_LIB = os.path.join(HERE, "libdfahost.so")
+CXX = os.environ.get("CXX", "g++")
 SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip", "dfa_match2.hip",
            "dfa_batch.hip", "dfa_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -45,7 +48,19 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(PROBE + ".tmp", PROBE)
+    build_host(verbose)
     return LIB
+
+
+def build_host(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "csrc", "host_spec.cpp")
+    cmd = [CXX, "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
+           "-I", os.path.join(ROOT, "include"), "-o", HOST_LIB + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(HOST_LIB + ".tmp", HOST_LIB)
+    return HOST_LIB
 
 
 if __name__ == "__main__":

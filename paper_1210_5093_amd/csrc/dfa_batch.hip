@@ -399,6 +399,8 @@ extern "C" int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results) 
 extern "C" int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results) {
     if (!b) return fail(DFA_E_INVAL, "dfa_batch_graph_launch: NULL batch");
     hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(DFA_E_INVAL, "dfa_batch_graph_launch: capture needs a created stream, "
+                                     "not the default stream");
     if (b->exec && b->graph_results != d_results) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);

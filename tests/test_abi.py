@@ -1,5 +1,6 @@
-"""The C-ABI library loads and exports every function declared in
-include/dfa_spec.h (no compute call: this runs without a GPU)."""
+"""The C-ABI libraries load and export every function declared in
+include/dfa_spec.h (GPU library) and include/dfa_host.h (host multicore
+matcher); no GPU compute call is made, so this runs without a GPU."""
 import ctypes
 import os
 import re
@@ -9,10 +10,11 @@ import pytest
 from conftest import ROOT
 
 HEADER = os.path.join(ROOT, "include", "dfa_spec.h")
+HOST_HEADER = os.path.join(ROOT, "include", "dfa_host.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dfa_\w+)\s*\(", text, flags=re.M)))
 
@@ -49,3 +51,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(RuntimeError):
         pkg.lib()
+
+
+def test_host_library_exports_every_declared_symbol():
+    from paper_1210_5093_amd import host
+    if not os.path.exists(host.HOST_LIB_PATH):
+        from paper_1210_5093_amd import build
+        build.build_host()
+    L = host.lib()
+    fns = declared_functions(HOST_HEADER)
+    assert "dfa_host_match" in fns and "dfa_host_partition" in fns
+    missing = [f for f in fns if not hasattr(L, f)]
+    assert not missing, missing

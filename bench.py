@@ -45,6 +45,42 @@ LDS_LOOKUP_PEAK = N_CU * CLOCK_HZ * LDS_LOOKUPS_PER_CU_CLK   # lookups/s
 HBM_PEAK_GBS = 8000.0
 
 
+# Sources whose change invalidates stored counter readings of the matcher.
+KERNEL_SOURCES = ["dfa_match2.hip", "dfa_kernels.hip", "dfa_internal.h", "dfa_walk1.h"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1210_5093_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str, lookahead: int, chunk: int):
+    """HBM bytes per launch from a committed counter summary in profiles/, if it
+    was taken on the current kernel sources with the same configuration.
+
+    A summary carries a line
+    ``traffic: kernel=K workload=W lookahead=R chunk=C bytes=B sources=D``
+    where B = scaled FETCH_SIZE + WRITE_SIZE per launch and D the digest of
+    the matcher sources when the counters were read."""
+    import glob
+    import re
+    digest = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                m = re.search(r"traffic: kernel=(\S+) workload=(\S+) lookahead=(\d+) "
+                              r"chunk=(\d+) bytes=(\d+) sources=([0-9a-f]+)", line)
+                if m and m.group(1) == kernel and m.group(2) == workload and \
+                        int(m.group(3)) == lookahead and int(m.group(4)) == chunk and \
+                        m.group(6) == digest:
+                    return int(m.group(5)), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -527,9 +563,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3p", "c3b", "c4", "c5"])
     ap.add_argument("--chunk", type=int, default=0, help="bytes per chunk (0 = planner)")
-    ap.add_argument("--lookahead", type=int, default=1,
-                    help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64)")
+    ap.add_argument("--lookahead", type=int, default=-1,
+                    help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64; "
+                         "-1 = pick r and the chunk length with the autotuner, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="print the autotuner's lookahead and chunk length, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
@@ -566,6 +605,19 @@ def main() -> int:
     info = d.info()
     dev_in = torch.from_numpy(x).to("cuda")
     result = torch.empty(4, dtype=torch.int32, device="cuda")
+    tuned = None
+    if args.lookahead < 0:
+        t0 = time.perf_counter()
+        r, c, ms = dfa.dfa_autotune(d, dev_in, stream)
+        tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4),
+                 "tuning_s": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'} ({ms:.3f} ms)")
+        args.lookahead = r
+        if not args.chunk:
+            args.chunk = c
+        if args.tune_only:
+            print(r, c, flush=True)
+            return 0
     chunk, nch = dfa.dfa_plan_chunks(d, nbytes, args.chunk, args.lookahead)
     opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result)
 
@@ -605,6 +657,7 @@ def main() -> int:
     kernel = f"k_match2<{info.packed_layout}>" if plan.kernel == 1 else "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
     achieved = lookups / (matcher_avg_ms * 1e-3)
+    traffic, traffic_src = stored_traffic(kernel, args.workload, args.lookahead, int(chunk))
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -625,6 +678,7 @@ def main() -> int:
             "classes": int(info.num_classes),
             "imax": int(info.imax),
             "lookahead": args.lookahead,
+            "chosen_by": "autotuner (dfa_autotune, untimed)" if tuned else "command line",
             "chunk_bytes": int(chunk),
             "chunks": int(nch),
             "lookups_per_byte": round(lookups / nbytes, 3),
@@ -636,7 +690,8 @@ def main() -> int:
             "peak": round(LDS_LOOKUP_PEAK / 1e9, 1),
             "unit": "Glookup/s",
             "frac": round(achieved / LDS_LOOKUP_PEAK, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
             "kernel_avg_ms": round(matcher_avg_ms, 4),
             "hbm_frac": round(nbytes / (matcher_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
         },

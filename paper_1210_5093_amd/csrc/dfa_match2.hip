@@ -26,55 +26,9 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "dfa_internal.h"
+#include "dfa_pairs.h"
 
 namespace dfaspec {
-
-constexpr int kWave2 = 64;
-constexpr int kSlots2 = 4;                 // pairs per lane per tile
-constexpr int kTile2 = kWave2 * kSlots2;   // pairs per wave-tile
-
-typedef __attribute__((address_space(3))) const uint16_t lds_u16_t;
-__device__ __forceinline__ uint32_t lds_ld(uint32_t addr) {
-    return *(lds_u16_t *)(size_t)addr;
-}
-
-// state_offset + selected byte (layout 1) or 16-bit word (layout 2) of w.
-template <int L, int K>
-__device__ __forceinline__ uint32_t add_sel(uint32_t s, uint32_t w) {
-    uint32_t r;
-    if constexpr (L == 1) {
-        if constexpr (K == 0)
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(s), "v"(w));
-        else if constexpr (K == 1)
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(s), "v"(w));
-        else if constexpr (K == 2)
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(s), "v"(w));
-        else
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(s), "v"(w));
-    } else {
-        if constexpr (K == 0)
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0" : "=v"(r) : "v"(s), "v"(w));
-        else
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1" : "=v"(r) : "v"(s), "v"(w));
-    }
-    return r;
-}
-
-// Apply the codes packed in one dword (4 one-byte or 2 two-byte codes).
-template <int L>
-__device__ __forceinline__ uint32_t step_dword(uint32_t s, uint32_t w) {
-    if constexpr (L == 1) {
-        s = lds_ld(add_sel<1, 0>(s, w));
-        s = lds_ld(add_sel<1, 1>(s, w));
-        s = lds_ld(add_sel<1, 2>(s, w));
-        s = lds_ld(add_sel<1, 3>(s, w));
-    } else {
-        s = lds_ld(add_sel<2, 0>(s, w));
-        s = lds_ld(add_sel<2, 1>(s, w));
-    }
-    return s;
-}
 
 // ---------------------------------------------------------------------------
 // Translation: code[i] = code_lut[in[i]]; per-block flag if a byte is outside
@@ -166,26 +120,6 @@ __global__ void k_chunkinfo(DevDFA d, const uint8_t *__restrict__ in, uint64_t c
 // state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
 // lays out the start sets as sorted member lists.
 //
-// Class-string id of the k bytes at in[pos ..] (first byte most significant);
-// *bad is set if one of them is outside Sigma.
-__device__ __forceinline__ uint32_t class_string_id(const DevDFA &d, const uint8_t *__restrict__ in,
-                                                    uint64_t pos, uint32_t k, bool *bad) {
-    uint32_t id = 0;
-    for (uint32_t j = 0; j < k; ++j) {
-        const uint32_t e = d.lut[in[pos + j]];
-        if (e == kLutInvalid) { *bad = true; return 0; }
-        id = id * d.nclass + (e >> 24);
-    }
-    return id;
-}
-
-__device__ __forceinline__ uint32_t mset_begin(const DevDFA &d, uint32_t k, uint32_t id) {
-    return d.mset_off[d.moff[k] + id];
-}
-__device__ __forceinline__ uint32_t mset_end(const DevDFA &d, uint32_t k, uint32_t id) {
-    return d.mset_off[d.moff[k] + id + 1];
-}
-
 // r <= r0: the start set of chunk i >= 1 is the precomputed I_{c_1..c_k} of
 // its k = min(r, p) lookahead bytes (Eq. 13).
 __global__ void k_chunkinfo_m(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
@@ -358,17 +292,6 @@ __global__ __launch_bounds__(1024) void k_scan_apply(ScanSrc q, const uint32_t *
     }
 }
 
-// Position of state e in the sorted member list [lo, hi), or kBadPos.
-__device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ members, uint32_t lo,
-                                                uint32_t hi, uint32_t e) {
-    uint32_t a = lo, b = hi;
-    while (a < b) {
-        const uint32_t mid = (a + b) >> 1;
-        if (members[mid] < e) a = mid + 1; else b = mid;
-    }
-    return (a < hi && members[a] == e) ? a - lo : kBadPos;
-}
-
 struct Match2Args {
     DevDFA d;
     const void *codes;       // translated stream (1- or 2-byte codes)
@@ -388,53 +311,12 @@ struct Match2Args {
     uint16_t *maps;          // level-0 maps, indexed by pair
 };
 
-// Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
-// 16-byte-aligned chunk (o16 = its first code's offset in 16-byte units),
-// read as uint4 blocks with one block of prefetch.
-template <int L>
-__device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
-                                          const uint32_t (&o16)[kSlots2], uint32_t blocks,
-                                          uint32_t (&st)[kSlots2]) {
-    uint4 cur[kSlots2], nxt[kSlots2];
-#pragma unroll
-    for (int j = 0; j < kSlots2; ++j) cur[j] = codes16[o16[j]];
-    for (uint32_t b = 1; ; ++b) {
-        const bool more = b < blocks;
-        if (more) {
-#pragma unroll
-            for (int j = 0; j < kSlots2; ++j) nxt[j] = codes16[(size_t)o16[j] + b];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int j = 0; j < kSlots2; ++j) {
-                const uint32_t w = q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w;
-                st[j] = step_dword<L>(st[j], w);
-            }
-        }
-        if (!more) break;
-#pragma unroll
-        for (int j = 0; j < kSlots2; ++j) cur[j] = nxt[j];
-    }
-}
-
 template <int L>
 __device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
     const uint4 *src = reinterpret_cast<const uint4 *>(L == 1 ? d.stab : d.table);
     uint4 *dst = reinterpret_cast<uint4 *>(smem);
     for (uint32_t i = threadIdx.x; i < d.stab_bytes / 16; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
-}
-
-// Owner chunk of pair P: the last i with first[i] <= P, searched in the
-// tile's window [lo, hi) (first[lo] <= P < first[hi]).
-__device__ __forceinline__ uint32_t owner_chunk(const uint32_t *__restrict__ first, uint32_t lo,
-                                                uint32_t hi, uint32_t P) {
-    while (hi > lo + 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (first[mid] <= P) lo = mid; else hi = mid;
-    }
-    return lo;
 }
 
 // Window pass: pair P of chunk c starts at the (P - first[c])-th state of

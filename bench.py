@@ -214,7 +214,9 @@ def host_threads() -> int:
         return max(1, min(16, os.cpu_count() or 1))
 
 
-def batch_lookups(pairs, buf, offs, chunk) -> int:
+def batch_lookups(pairs, buf, offs, chunk, look=1, levels=None) -> int:
+    """Algorithmic lookups of a batch: per string, len(c_0) + sum |I_i| len(c_i),
+    I_i the start set for r = min(look, the DFA's precomputed levels)."""
     cache = {}
     total = 0
     for k, w in enumerate(pairs):
@@ -222,17 +224,20 @@ def batch_lookups(pairs, buf, offs, chunk) -> int:
         n = x.size
         if n == 0:
             continue
-        if id(w) not in cache:
-            cache[id(w)] = set_sizes(w)
-        sizes = cache[id(w)]
+        r = 1 if look <= 1 or levels is None else max(1, min(look, levels[k]))
         nch = (n + chunk - 1) // chunk
         if nch == 1:
             total += n
             continue
         lens = np.full(nch, chunk, dtype=np.int64)
         lens[-1] = n - chunk * (nch - 1)
-        look = x[chunk - 1: chunk * (nch - 1): chunk]
-        m = sizes[w.byte_to_symbol[look]]
+        if r >= 2:
+            m = image_sizes(w, x, chunk, nch, r)
+        else:
+            if id(w) not in cache:
+                cache[id(w)] = set_sizes(w)
+            lookb = x[chunk - 1: chunk * (nch - 1): chunk]
+            m = cache[id(w)][w.byte_to_symbol[lookb]]
         total += int(lens[0] + (m * lens[1:]).sum())
     return total
 
@@ -260,10 +265,11 @@ def bench_batched(args, dfa, torch, stream) -> int:
     count = len(wl)
 
     t0 = time.perf_counter()
-    chunk, tune_ms = dfa.dfa_batch_tune(ds, ins, stream)
+    chunk, look, tune_ms = dfa.dfa_batch_tune(ds, ins, stream)
     tune_wall = time.perf_counter() - t0
-    log(f"[bench] tuned chunk {chunk} ({tune_ms:.2f} ms/run, tuning took {tune_wall:.1f}s)")
-    b = dfa.Batch(ds, ins, chunk_len=chunk)
+    log(f"[bench] tuned chunk {chunk}, lookahead {look} ({tune_ms:.2f} ms/run, "
+        f"tuning took {tune_wall:.1f}s)")
+    b = dfa.Batch(ds, ins, chunk_len=chunk, lookahead=look)
     _, ntasks = b.info() if hasattr(b, "info") else (chunk, 0)
     res = torch.empty((count, 4), dtype=torch.int32, device="cuda")
 
@@ -309,7 +315,8 @@ def bench_batched(args, dfa, torch, stream) -> int:
     plain_ms = ev0.elapsed_time(ev1) / plain_steps
     got_plain = [tuple(int(v) & 0xFFFFFFFF for v in row) for row in res_plain.cpu().tolist()]
 
-    lookups = batch_lookups(pairs, buf, offs, chunk)
+    levels = [int(d.info().lookahead_tables) if d.info().packed_layout else 1 for d in ds]
+    lookups = batch_lookups(pairs, buf, offs, chunk, look, levels)
     achieved = lookups / (matcher_avg * 1e-3)
     value = total / (graph_ms * 1e-3) / 1e9
     line = {
@@ -333,12 +340,13 @@ def bench_batched(args, dfa, torch, stream) -> int:
             "pairs": count,
             "distinct_dfas": len(handles),
             "chunk_bytes": int(chunk),
+            "lookahead": look,
             "chunk_from": "autotuner (dfa_batch_tune)",
             "lookups_per_byte": round(lookups / total, 3),
         },
         "roofline": {
             "bound": "lds",
-            "kernel": "k_batch_match",
+            "kernel": "k_b2_match" if all(d.info().packed_layout for d in ds) else "k_batch_match",
             "achieved": round(achieved / 1e9, 2),
             "peak": round(LDS_LOOKUP_PEAK / 1e9, 1),
             "unit": "Glookup/s",

@@ -199,23 +199,31 @@ int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_
 /* ---------------------------------------------------------------------------
  * Batches: many (DFA, string) pairs of uneven size in one persistent launch
  * (the paper's representation holds several DFAs and strings in one table and
- * input array, Section 5).  Every string is cut into chunks; one launch
- * matches all chunks of all strings (each from its one-symbol initial-state
- * set, Algorithm 3), then the per-string maps are composed (Eq. 9).  Each
- * string's record equals what dfa_match_async writes for it alone.
+ * input array, Section 5).  Every string is cut into chunks of one length;
+ * one launch matches all (chunk, start state) pairs of all strings, each
+ * chunk from its reverse-lookahead set (Eq. 11, or Eq. 13's I_{c1..ck} with
+ * k = min(lookahead, the DFA's precomputed levels)), then the per-string maps
+ * are composed (Eq. 9).  When every DFA has a packed layout (dfa_info_t::
+ * packed_layout != 0) the pairs are packed onto lanes as in the single-string
+ * packed matcher; otherwise one wavefront walks one chunk (one-symbol
+ * lookahead only).  Each string's record equals what dfa_match_async writes
+ * for it alone.
  *
  * dfa_batch_create -- plan a batch and upload its descriptors (synchronous).
  *   dfas:      host array of `count` handles (may repeat; must outlive the batch).
  *   d_inputs:  host array of `count` device pointers (must stay valid and may
  *              change contents between runs; the pointers are fixed).
  *   lens:      host array of `count` lengths.
- *   opts:      NULL or chunk_len (0 = planner) with lookahead 1.
+ *   opts:      NULL (planner chunk length, lookahead 1) or chunk_len (0 =
+ *              planner) and lookahead 1 .. 64 (above 1 only for packed
+ *              layouts).
  * dfa_batch_run -- enqueue the whole batch on `stream`: no host work, no
  *   allocation, so it may be captured into a HIP graph.
  *   d_results: device, count dfa_result_t records.
  * dfa_batch_graph_launch -- capture dfa_batch_run into a HIP graph once (per
  *   d_results pointer) and replay it; `stream` must not be the null stream.
- * dfa_batch_info -- chunk length used and number of matcher tasks. */
+ * dfa_batch_info -- chunk length used and number of chunks (packed-pair
+ *   batch) or matcher tasks (one chunk per wavefront). */
 typedef struct dfa_batch dfa_batch_t;
 int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
                      const size_t *lens, size_t count, const dfa_match_opts_t *opts,
@@ -224,10 +232,12 @@ int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_info(const dfa_batch_t *b, uint64_t *chunk_len, uint32_t *tasks);
 /* dfa_batch_tune -- time the batch at the planner's chunk length and at 1/4,
- * 1/2, 2x and 4x of it; *chunk_len receives the fastest (pass it to
- * dfa_batch_create).  Allocates temporary plans; synchronises `stream`. */
+ * 1/2, 2x and 4x of it, with lookahead 1, 2, 3, 4, 6 and 8 (1 only when a
+ * DFA lacks a packed layout); *best receives the fastest chunk_len and
+ * lookahead (pass it to dfa_batch_create), *best_ms its time per run.
+ * Allocates temporary plans; synchronises `stream`. */
 int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
-                   size_t count, void *stream, uint64_t *chunk_len, double *best_ms);
+                   size_t count, void *stream, dfa_match_opts_t *best, double *best_ms);
 void dfa_batch_destroy(dfa_batch_t *b);
 
 /* dfa_match_batch -- one-shot batch: plan, run on `stream`, wait for the

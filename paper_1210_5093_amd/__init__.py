@@ -133,7 +133,7 @@ def lib() -> ctypes.CDLL:
     L.dfa_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(dfa_match_opts_t),
                                ctypes.POINTER(ctypes.c_double)]
     L.dfa_batch_tune.restype = I
-    L.dfa_batch_tune.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.POINTER(U64),
+    L.dfa_batch_tune.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.POINTER(dfa_match_opts_t),
                                  ctypes.POINTER(ctypes.c_double)]
     L.dfa_server_create.restype = I
     L.dfa_server_create.argtypes = [ctypes.POINTER(dfa_server_opts_t), ctypes.POINTER(P)]
@@ -347,22 +347,24 @@ def dfa_autotune(d: DFA, d_input, stream=None) -> Tuple[int, int, float]:
     return int(o.lookahead), int(o.chunk_len), float(ms.value)
 
 
-def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None) -> Tuple[int, float]:
+def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None) -> Tuple[int, int, float]:
+    """Tune a batch: (chunk length, lookahead, ms per run)."""
     count = len(dfas)
     hs = (ctypes.c_void_p * max(count, 1))(*[x.handle.value for x in dfas])
     ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None for t in inputs])
     ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in inputs])
-    c = ctypes.c_uint64()
+    o = dfa_match_opts_t()
     ms = ctypes.c_double()
-    _check(lib().dfa_batch_tune(hs, ps, ls, count, _stream_handle(stream), ctypes.byref(c),
+    _check(lib().dfa_batch_tune(hs, ps, ls, count, _stream_handle(stream), ctypes.byref(o),
                                 ctypes.byref(ms)))
-    return int(c.value), float(ms.value)
+    return int(o.chunk_len), int(o.lookahead), float(ms.value)
 
 
 class Batch:
     """A planned batch of (DFA, device string) pairs (dfa_batch_create)."""
 
-    def __init__(self, dfas: Sequence[DFA], inputs: Sequence, chunk_len: int = 0):
+    def __init__(self, dfas: Sequence[DFA], inputs: Sequence, chunk_len: int = 0,
+                 lookahead: int = 1):
         self._dfas = list(dfas)          # keep the DFAs alive
         self._inputs = list(inputs)      # and the device strings
         count = len(self._dfas)
@@ -372,7 +374,7 @@ class Batch:
         ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None
                                                  for t in self._inputs])
         ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in self._inputs])
-        o = _opts(chunk_len, 1)
+        o = _opts(chunk_len, lookahead)
         h = ctypes.c_void_p()
         _check(lib().dfa_batch_create(hs, ps, ls, count, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

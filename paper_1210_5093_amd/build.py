@@ -13,7 +13,7 @@ PROBE = os.path.join(HERE, "lds_peak_probe")
 HOST_LIB = os.path.join(HERE, "libdfahost.so")
 CXX = os.environ.get("CXX", "g++")
 SOURCES = ["dfa_compile.cpp", "dfa_api.cpp", "dfa_kernels.hip", "dfa_match2.hip",
-           "dfa_batch.hip", "dfa_server.cpp"]
+           "dfa_batch.hip", "dfa_batch2.hip", "dfa_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions stay disabled in all device code.

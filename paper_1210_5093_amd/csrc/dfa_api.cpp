@@ -357,55 +357,70 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
 }
 
 extern "C" int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
-                              const size_t *lens, size_t count, void *stream, uint64_t *chunk_len,
-                              double *best_ms) {
-    if (!chunk_len) return fail(DFA_E_INVAL, "dfa_batch_tune: NULL argument");
+                              const size_t *lens, size_t count, void *stream,
+                              dfa_match_opts_t *best, double *best_ms) {
+    if (!best) return fail(DFA_E_INVAL, "dfa_batch_tune: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     BatchPlan p0;
     int rc = plan_batch(dfas, d_inputs, lens, count, 0, &p0);
     if (rc) return rc;
+    uint64_t base_chunk = p0.chunk;
+    const bool packed = count > 0 && batch2_supported(dfas, count);
+    if (packed) {
+        Batch2Plan q0;
+        rc = plan_batch2(dfas, d_inputs, lens, count, 0, 1, &q0);
+        if (rc) return rc;
+        base_chunk = q0.chunk;
+    }
     uint32_t *res = nullptr;
     hipError_t e = hipMalloc(&res, std::max<size_t>(count, 1) * 4 * sizeof(uint32_t));
     if (e != hipSuccess) return fail(DFA_E_NOMEM, "dfa_batch_tune: hipMalloc");
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    uint64_t pick = p0.chunk;
+    dfa_match_opts_t pick{};
+    pick.chunk_len = base_chunk;
+    pick.lookahead = 1;
     double pick_ms = 1e30;
     const double mult[] = {0.25, 0.5, 1.0, 2.0, 4.0};
-    for (double m : mult) {
-        const uint64_t c = std::max<uint64_t>(256, (uint64_t)(p0.chunk * m) / 64 * 64);
-        dfa_match_opts_t o{};
-        o.chunk_len = c;
-        o.lookahead = 1;
-        dfa_batch_t *bt = nullptr;
-        rc = dfa_batch_create(dfas, d_inputs, lens, count, &o, &bt);
-        if (rc) break;
-        double t_best = 1e30;
-        for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
-            if (rep > 0) (void)hipEventRecord(a, s);
-            rc = dfa_batch_run(bt, stream, res);
-            if (rep > 0) {
-                (void)hipEventRecord(b, s);
-                (void)hipEventSynchronize(b);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, a, b);
-                t_best = std::min<double>(t_best, ms);
+    std::vector<uint32_t> looks = {1};
+    if (packed) looks = {1, 2, 3, 4, 6, 8};
+    for (uint32_t look : looks) {
+        for (double m : mult) {
+            const uint64_t c = std::max<uint64_t>(256, (uint64_t)(base_chunk * m) / 64 * 64);
+            dfa_match_opts_t o{};
+            o.chunk_len = c;
+            o.lookahead = look;
+            dfa_batch_t *bt = nullptr;
+            rc = dfa_batch_create(dfas, d_inputs, lens, count, &o, &bt);
+            if (rc) break;
+            double t_best = 1e30;
+            for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+                if (rep > 0) (void)hipEventRecord(a, s);
+                rc = dfa_batch_run(bt, stream, res);
+                if (rep > 0) {
+                    (void)hipEventRecord(b, s);
+                    (void)hipEventSynchronize(b);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    t_best = std::min<double>(t_best, ms);
+                }
+            }
+            (void)hipStreamSynchronize(s);
+            dfa_batch_destroy(bt);
+            if (rc) break;
+            if (t_best < pick_ms) {
+                pick_ms = t_best;
+                pick = o;
             }
         }
-        (void)hipStreamSynchronize(s);
-        dfa_batch_destroy(bt);
         if (rc) break;
-        if (t_best < pick_ms) {
-            pick_ms = t_best;
-            pick = c;
-        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipFree(res);
     if (rc) return rc;
-    *chunk_len = pick;
+    *best = pick;
     if (best_ms) *best_ms = pick_ms;
     return DFA_OK;
 }

@@ -16,6 +16,7 @@
 // dfa_batch_run does no host work and allocates nothing, so it can be
 // captured into a HIP graph and replayed.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -353,7 +354,9 @@ int launch_batch(const BatchPlan &P, void *dev_base, hipStream_t s, uint32_t *d_
 using namespace dfaspec;
 
 struct dfa_batch {
+    int kind = 1;            // 1: one chunk per wavefront; 2: packed pairs (dfa_batch2.hip)
     BatchPlan plan;
+    Batch2Plan plan2;
     void *blob = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -365,14 +368,27 @@ extern "C" int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *
                                 dfa_batch_t **out) {
     if (!out) return fail(DFA_E_INVAL, "dfa_batch_create: out is NULL");
     *out = nullptr;
-    if (opts && opts->lookahead != 1)
-        return fail(DFA_E_INVAL, "dfa_batch_create: batches use one-symbol lookahead");
+    const uint32_t look = opts ? opts->lookahead : 1u;
+    if (look == 0 || look > 64)
+        return fail(DFA_E_INVAL, "dfa_batch_create: lookahead must be 1 .. 64");
     std::unique_ptr<dfa_batch> b(new dfa_batch());
-    int rc = plan_batch(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, &b->plan);
+    // the packed-pair batch unless a DFA lacks a packed layout (or the
+    // environment asks for the first-generation kernel: DFA_BATCH_KERNEL=1)
+    const char *env = getenv("DFA_BATCH_KERNEL");
+    const bool force1 = env && atoi(env) == 1;
+    b->kind = (!force1 && (count == 0 || batch2_supported(dfas, count))) ? 2 : 1;
+    if (b->kind == 1 && look != 1)
+        return fail(DFA_E_INVAL, "dfa_batch_create: this batch needs one-symbol lookahead");
+    int rc = b->kind == 2
+                 ? plan_batch2(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, look, &b->plan2)
+                 : plan_batch(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, &b->plan);
     if (rc) return rc;
-    hipError_t e = hipMalloc(&b->blob, b->plan.total_bytes);
+    const size_t total = b->kind == 2 ? b->plan2.total_bytes : b->plan.total_bytes;
+    const size_t desc_bytes = b->kind == 2 ? b->plan2.desc_bytes : b->plan.desc_bytes;
+    const void *desc = b->kind == 2 ? (const void *)b->plan2.desc.data() : (const void *)b->plan.desc.data();
+    hipError_t e = hipMalloc(&b->blob, total);
     if (e != hipSuccess) return fail(DFA_E_NOMEM, "dfa_batch_create: hipMalloc failed");
-    e = hipMemcpy(b->blob, b->plan.desc.data(), b->plan.desc_bytes, hipMemcpyHostToDevice);
+    e = hipMemcpy(b->blob, desc, desc_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(b->blob);
         b->blob = nullptr;
@@ -383,14 +399,18 @@ extern "C" int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *
 }
 
 extern "C" int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results) {
-    if (!b || (b->plan.count && !d_results)) return fail(DFA_E_INVAL, "dfa_batch_run: NULL argument");
+    if (!b) return fail(DFA_E_INVAL, "dfa_batch_run: NULL batch");
+    const uint32_t count = b->kind == 2 ? b->plan2.count : b->plan.count;
+    if (count && !d_results) return fail(DFA_E_INVAL, "dfa_batch_run: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hipEvent_t ev[4];
     const bool timed = hipStreamIsCapturing(s, &cap) == hipSuccess &&
                        cap == hipStreamCaptureStatusNone && timing_begin(s, ev);
-    int rc = launch_batch(b->plan, b->blob, s, d_results, timed ? ev[1] : nullptr,
-                          timed ? ev[2] : nullptr);
+    int rc = b->kind == 2 ? launch_batch2(b->plan2, b->blob, s, d_results, timed ? ev[1] : nullptr,
+                                          timed ? ev[2] : nullptr)
+                          : launch_batch(b->plan, b->blob, s, d_results, timed ? ev[1] : nullptr,
+                                         timed ? ev[2] : nullptr);
     if (!timed) return rc;
     const int rc2 = timing_end(s, ev);
     return rc ? rc : rc2;
@@ -440,7 +460,7 @@ extern "C" void dfa_batch_destroy(dfa_batch_t *b) {
 
 extern "C" int dfa_batch_info(const dfa_batch_t *b, uint64_t *chunk_len, uint32_t *tasks) {
     if (!b) return fail(DFA_E_INVAL, "dfa_batch_info: NULL batch");
-    if (chunk_len) *chunk_len = b->plan.chunk;
-    if (tasks) *tasks = b->plan.ntasks;
+    if (chunk_len) *chunk_len = b->kind == 2 ? b->plan2.chunk : b->plan.chunk;
+    if (tasks) *tasks = b->kind == 2 ? b->plan2.nchunks : b->plan.ntasks;
     return DFA_OK;
 }

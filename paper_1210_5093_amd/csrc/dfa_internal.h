@@ -170,12 +170,39 @@ int plan_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const s
 int launch_batch(const BatchPlan &p, void *dev_base, hipStream_t s, uint32_t *d_results,
                  hipEvent_t ev_before_match = nullptr, hipEvent_t ev_after_match = nullptr);
 
+// Batched packed-pair path (dfa_batch2.hip): all DFAs need a packed layout.
+struct Batch2Plan {
+    std::vector<uint8_t> desc;   // first desc_bytes of the device region
+    size_t o_dfas = 0, o_strs = 0, o_reqs = 0, o_groups = 0, o_segs = 0, o_items = 0;
+    size_t o_chunk_str = 0, desc_bytes = 0;
+    size_t o_counter = 0, o_str_bad = 0, o_msize0 = 0, o_cset = 0, o_first_raw = 0;
+    size_t o_first2 = 0, o_bsum = 0, o_tile_raw = 0, o_tile_first2 = 0, o_gtile = 0;
+    size_t o_gtask = 0, o_gend = 0, o_maps0 = 0, o_maps = 0, o_msize = 0, o_codes = 0;
+    size_t total_bytes = 0;
+    uint32_t count = 0, nchunks = 0, ngroups = 0, nsegs = 0, max_levels = 0;
+    std::vector<uint32_t> items_per_level;
+    std::vector<size_t> item_base;
+    uint64_t chunk = 0;
+    uint32_t task_slot = 0, wpb = 4, blocks = 0, tblocks = 0;
+    size_t lds_match = 0, lds_compose0 = 0, lds_compose = 0;
+};
+bool batch2_supported(const dfa_t *const *dfas, size_t count);
+int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
+                size_t count, uint64_t chunk_req, uint32_t lookahead, Batch2Plan *out);
+int launch_batch2(const Batch2Plan &p, void *dev_base, hipStream_t s, uint32_t *d_results,
+                  hipEvent_t ev_before_match = nullptr, hipEvent_t ev_after_match = nullptr);
+
 // Timing hooks of dfa_timing_enable for entry points outside the single-
 // string path.  timing_begin returns false (and creates nothing) when timing
 // is off for the stream; otherwise it creates ev[0..3] and records ev[0].
 // timing_end records ev[3] and keeps the four events for dfa_timing_read.
 bool timing_begin(hipStream_t s, hipEvent_t ev[4]);
 int timing_end(hipStream_t s, hipEvent_t ev[4]);
+// Exclusive scan of msize[0..nch) (low 15 bits): first[i], first[nch] = total,
+// tile_first[w] = chunk holding pair w * match2_tile_pairs().  bsum holds
+// match2_scan_blocks(nch) words.
+int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
+                     uint32_t *tile_first, hipStream_t s);
 uint32_t match2_tile_pairs();
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();

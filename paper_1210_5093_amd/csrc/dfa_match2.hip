@@ -593,6 +593,20 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
 }
 
+int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
+                     uint32_t *tile_first, hipStream_t s) {
+    if (nch == 0) return DFA_OK;
+    const uint32_t nsb = (nch + kScanBlock - 1) / kScanBlock;
+    ScanSrc q{msize, nullptr, 0, nch};
+    hipLaunchKernelGGL(k_scan_sums<0>, dim3(nsb), dim3(kScanThreads), 0, s, q, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, nsb,
+                       (uint16_t *)nullptr, nch, (const uint32_t *)nullptr, 0u, first);
+    hipLaunchKernelGGL(k_scan_apply<0>, dim3(nsb), dim3(kScanThreads), 0, s, q, bsum, first,
+                       tile_first, (uint16_t *)nullptr, 0u);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "size scan launch");
+}
+
 int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                     const uint16_t *msize0, uint16_t *out_maps, uint16_t *out_msize,
                     hipStream_t s) {

@@ -88,6 +88,15 @@ __device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ mem
 // Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
 // 16-byte-aligned chunk (o16 = its first code's offset in 16-byte units),
 // read as uint4 blocks with one block of prefetch.
+// One step of every slot with code K of its dword.
+template <int L, int K>
+__device__ __forceinline__ void step_slots(uint32_t (&st)[kSlots2], const uint32_t (&w)[kSlots2]) {
+#pragma unroll
+    for (int j = 0; j < kSlots2; ++j) st[j] = add_sel<L, K>(st[j], w[j]);
+#pragma unroll
+    for (int j = 0; j < kSlots2; ++j) st[j] = lds_ld(st[j]);
+}
+
 template <int L>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
                                           const uint32_t (&o16)[kSlots2], uint32_t blocks,
@@ -103,10 +112,17 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            uint32_t w[kSlots2];
 #pragma unroll
-            for (int j = 0; j < kSlots2; ++j) {
-                const uint32_t w = q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w;
-                st[j] = step_dword<L>(st[j], w);
+            for (int j = 0; j < kSlots2; ++j)
+                w[j] = q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w;
+            // round-robin over the slots, one code at a time, so that the
+            // slots' independent chains keep several LDS loads in flight
+            step_slots<L, 0>(st, w);
+            step_slots<L, 1>(st, w);
+            if constexpr (L == 1) {
+                step_slots<L, 2>(st, w);
+                step_slots<L, 3>(st, w);
             }
         }
         if (!more) break;

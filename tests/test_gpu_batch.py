@@ -129,6 +129,103 @@ def test_batch_edge_cases(dfa_mod):
         b.close()
 
 
+@pytest.fixture
+def first_generation_batch(monkeypatch):
+    """Batches created inside the test use one chunk per wavefront."""
+    monkeypatch.setenv("DFA_BATCH_KERNEL", "1")
+
+
+def test_first_generation_batch_matches_oracle(dfa_mod, first_generation_batch):
+    import torch
+    wl = configs.batch_workload(count=64, seed=31, max_len=2 << 20)
+    ds, xs, ins = make(dfa_mod, wl)
+    expect = oracle_records([w for w, _, _, _ in wl], xs)
+    b = dfa_mod.Batch(ds, ins)
+    chunk, nch = b.info()
+    res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
+    b.run(res)
+    torch.cuda.synchronize()
+    check_records(res, expect)
+    b.close()
+    with pytest.raises(dfa_mod.DFAError):
+        dfa_mod.Batch(ds, ins, lookahead=2)
+
+
+@pytest.mark.parametrize("look", [2, 3, 4, 8])
+def test_packed_batch_multi_symbol_lookahead(dfa_mod, look):
+    import torch
+    wl = configs.batch_workload(count=80, seed=40 + look, max_len=4 << 20)
+    ds, xs, ins = make(dfa_mod, wl)
+    expect = oracle_records([w for w, _, _, _ in wl], xs)
+    for chunk in (0, 4096, 65536):
+        b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look)
+        res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
+        b.run(res)
+        torch.cuda.synchronize()
+        check_records(res, expect)
+        b.close()
+
+
+def test_packed_batch_ragged_and_invalid(dfa_mod):
+    """Strings of 0, 1, C-1, C, C+1 and 3C+5 bytes; bytes outside Sigma at a
+    chunk's first byte, at a lookahead byte and at the last byte."""
+    import torch
+    C = 1024
+    w, wb = configs.c2_dfa(), configs.c3_byte_dfa()
+    d, db = dfa_mod.DFA.from_workload(w), dfa_mod.DFA.from_workload(wb)
+    lens = [0, 1, C - 1, C, C + 1, 3 * C + 5, 5 * C]
+    xs, ds, ws = [], [], []
+    for k, n in enumerate(lens):
+        xs.append(configs.c2_input(n, seed=300 + k).copy())
+        ds.append(d)
+        ws.append(w)
+        xs.append(streams.uniform_bytes(400 + k, n))
+        ds.append(db)
+        ws.append(wb)
+    bad = []
+    for pos in (C, C - 1, 5 * C - 1):
+        x = configs.c2_input(5 * C, seed=500 + pos).copy()
+        x[pos] = ord("#")
+        xs.append(x)
+        ds.append(d)
+        ws.append(w)
+        bad.append(len(xs) - 1)
+    ins = [torch.from_numpy(np.array(x)).to("cuda") for x in xs]
+    for look in (1, 3):
+        b = dfa_mod.Batch(ds, ins, chunk_len=C, lookahead=look)
+        res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
+        b.run(res)
+        torch.cuda.synchronize()
+        r = res.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        for k, x in enumerate(xs):
+            if k in bad:
+                assert r[k, 2] & dfa_mod.FLAG_SYMBOL, k
+                continue
+            fin, acc = oracle.membership(ws[k].delta, ws[k].byte_to_symbol, ws[k].q0,
+                                         ws[k].accepting, x)
+            assert (r[k, 0], r[k, 1], r[k, 2], r[k, 3]) == \
+                (fin, int(acc), 0, (x.size + C - 1) // C), (look, k)
+        b.close()
+
+
+def test_packed_batch_graph_replays(dfa_mod):
+    import torch
+    wl = configs.batch_workload(count=48, seed=77, max_len=1 << 20)
+    ds, xs, ins = make(dfa_mod, wl)
+    expect = oracle_records([w for w, _, _, _ in wl], xs)
+    b = dfa_mod.Batch(ds, ins, lookahead=4)
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        res = torch.full((len(ds), 4), -1, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(s):
+            b.graph_launch(res, s)
+        torch.cuda.synchronize()
+        check_records(res, expect)
+        res.fill_(0)          # eager work between replays
+        torch.cuda.synchronize()
+    b.close()
+
+
 def test_full_batched_configuration(dfa_mod):
     """1024 pairs, DFAs 8-512 states, strings 1 KiB - 64 MiB (5.7 GiB)."""
     import torch

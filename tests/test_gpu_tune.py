@@ -67,10 +67,10 @@ def test_batch_tune_matches_oracle(dfa_mod):
         x = configs.request_input(kind, seed, n)
         xs.append(x)
         ins.append(torch.from_numpy(x).to("cuda"))
-    chunk, ms = dfa_mod.dfa_batch_tune(ds, ins)
-    say(f"batch tuned chunk={chunk} {ms:.3f} ms")
-    assert chunk >= 256 and chunk % 64 == 0
-    b = dfa_mod.Batch(ds, ins, chunk_len=chunk)
+    chunk, look, ms = dfa_mod.dfa_batch_tune(ds, ins)
+    say(f"batch tuned chunk={chunk} lookahead={look} {ms:.3f} ms")
+    assert chunk >= 256 and chunk % 64 == 0 and 1 <= look <= 8
+    b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look)
     res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
     b.run(res)
     torch.cuda.synchronize()

@@ -93,6 +93,12 @@ def workload(name: str):
                 f"{configs.C2_PATTERN_SEED} ({w.num_states} states, 20 amino-acid letters); "
                 "256 MiB residues, stream seed 4")
         return w, (lambda n, out=None: configs.c2_input(n, out=out)), configs.C2_BYTES, desc
+    if name == "c2a":
+        from workloads import from_pattern, patterns
+        w = from_pattern(patterns.pattern_dfa(configs.C2_PATTERN_SEED, contains=False))
+        desc = ("protein-style, anchored: minimal DFA of P alone (rejecting sink), pattern seed "
+                f"{configs.C2_PATTERN_SEED} ({w.num_states} states); 256 MiB residues, stream seed 4")
+        return w, (lambda n, out=None: configs.c2_input(n, out=out)), configs.C2_BYTES, desc
     if name == "c1":
         w = configs.c1_dfa(1)
         return w, (lambda n, out=None: configs.c1_input(n)), configs.C1_BYTES, \
@@ -265,11 +271,11 @@ def bench_batched(args, dfa, torch, stream) -> int:
     count = len(wl)
 
     t0 = time.perf_counter()
-    chunk, look, tune_ms = dfa.dfa_batch_tune(ds, ins, stream)
+    chunk, look, tune_ms, ex = dfa.dfa_batch_tune(ds, ins, stream)
     tune_wall = time.perf_counter() - t0
-    log(f"[bench] tuned chunk {chunk}, lookahead {look} ({tune_ms:.2f} ms/run, "
+    log(f"[bench] tuned chunk {chunk}, lookahead {look}, early exit {ex} ({tune_ms:.2f} ms/run, "
         f"tuning took {tune_wall:.1f}s)")
-    b = dfa.Batch(ds, ins, chunk_len=chunk, lookahead=look)
+    b = dfa.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
     _, ntasks = b.info() if hasattr(b, "info") else (chunk, 0)
     res = torch.empty((count, 4), dtype=torch.int32, device="cuda")
 
@@ -569,12 +575,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3p", "c3b", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2a", "c3p", "c3b", "c4", "c5"])
     ap.add_argument("--chunk", type=int, default=0, help="bytes per chunk (0 = planner)")
     ap.add_argument("--lookahead", type=int, default=-1,
                     help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64; "
                          "-1 = pick r and the chunk length with the autotuner, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--early-exit", action="store_true",
+                    help="stop a wavefront's walks once all its pairs are absorbing")
     ap.add_argument("--tune-only", action="store_true",
                     help="print the autotuner's lookahead and chunk length, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -616,18 +624,21 @@ def main() -> int:
     tuned = None
     if args.lookahead < 0:
         t0 = time.perf_counter()
-        r, c, ms = dfa.dfa_autotune(d, dev_in, stream)
-        tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4),
+        r, c, ms, ex = dfa.dfa_autotune(d, dev_in, stream)
+        tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4), "early_exit": ex,
                  "tuning_s": round(time.perf_counter() - t0, 2)}
-        log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'} ({ms:.3f} ms)")
+        log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex} "
+            f"({ms:.3f} ms)")
+        args.early_exit = args.early_exit or ex
         args.lookahead = r
         if not args.chunk:
             args.chunk = c
         if args.tune_only:
-            print(r, c, flush=True)
+            print(r, c, int(ex), flush=True)
             return 0
     chunk, nch = dfa.dfa_plan_chunks(d, nbytes, args.chunk, args.lookahead)
-    opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result)
+    opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result,
+                early_exit=args.early_exit)
 
     if args.calibrate_copy:
         scratch = torch.empty_like(dev_in)
@@ -687,6 +698,7 @@ def main() -> int:
             "imax": int(info.imax),
             "lookahead": args.lookahead,
             "chosen_by": "autotuner (dfa_autotune, untimed)" if tuned else "command line",
+            "early_exit": bool(args.early_exit),
             "chunk_bytes": int(chunk),
             "chunks": int(nch),
             "lookups_per_byte": round(lookups / nbytes, 3),

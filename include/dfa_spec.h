@@ -89,8 +89,15 @@ typedef struct dfa_match_opts {
                                      before each chunk (Eq. 13, computed per chunk
                                      on the device; DFAs without a packed layout
                                      use r = 1, with the same result) */
-    uint32_t reserved;
+    uint32_t flags;           /* DFA_MATCH_* bits, 0 = none */
 } dfa_match_opts_t;
+
+/* flags bit: a wavefront stops walking its (chunk, state) pairs once every one
+ * of them sits in an absorbing state (the paper's error state, Section 3: a
+ * walk that reaches it can stop).  The result is unchanged; the saving depends
+ * on the input.  Honoured by the packed-pair matchers (single string and
+ * batch) for DFAs with an absorbing state; ignored otherwise. */
+#define DFA_MATCH_EARLY_EXIT 1u
 
 /* ---------------------------------------------------------------------------
  * dfa_create -- compile a DFA (Q, Sigma, delta, q0, F) (Section 2.1) and keep
@@ -164,7 +171,9 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * result (the method is exact); only speed differs.  Inputs beyond 256 MiB
  * are tuned on their first 256 MiB.  The choice is cached per DFA and
  * power-of-two length bucket and used by calls with lookahead
- * DFA_LOOKAHEAD_AUTO.
+ * DFA_LOOKAHEAD_AUTO.  For a DFA with an absorbing state the best setting is
+ * timed again with DFA_MATCH_EARLY_EXIT, which is kept (in best->flags) if
+ * faster.
  *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
  *   fastest candidate's time per call (may be NULL).  Synchronises `stream`. */
 int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
@@ -231,10 +240,11 @@ int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
 int dfa_batch_run(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_graph_launch(dfa_batch_t *b, void *stream, uint32_t *d_results);
 int dfa_batch_info(const dfa_batch_t *b, uint64_t *chunk_len, uint32_t *tasks);
-/* dfa_batch_tune -- time the batch at the planner's chunk length and at 1/4,
- * 1/2, 2x and 4x of it, with lookahead 1, 2, 3, 4, 6 and 8 (1 only when a
- * DFA lacks a packed layout); *best receives the fastest chunk_len and
- * lookahead (pass it to dfa_batch_create), *best_ms its time per run.
+/* dfa_batch_tune -- time the batch at the planner's chunk length and at the
+ * powers of two from 1 KiB to 64 KiB, with lookahead 1, 2, 3, 4, 6 and 8 (1
+ * only when a DFA lacks a packed layout), then the best of them with
+ * DFA_MATCH_EARLY_EXIT when a DFA has an absorbing state; *best receives the
+ * fastest options (pass them to dfa_batch_create), *best_ms its time per run.
  * Allocates temporary plans; synchronises `stream`. */
 int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
                    size_t count, void *stream, dfa_match_opts_t *best, double *best_ms);

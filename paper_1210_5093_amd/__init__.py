@@ -42,7 +42,7 @@ class dfa_info_t(ctypes.Structure):
 
 class dfa_match_opts_t(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint64), ("lookahead", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
 
 
 class dfa_plan_info_t(ctypes.Structure):
@@ -179,8 +179,11 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream or None
 
 
-def _opts(chunk_len: int = 0, lookahead: int = 1) -> dfa_match_opts_t:
-    return dfa_match_opts_t(int(chunk_len), int(lookahead), 0)
+MATCH_EARLY_EXIT = 1
+
+
+def _opts(chunk_len: int = 0, lookahead: int = 1, early_exit: bool = False) -> dfa_match_opts_t:
+    return dfa_match_opts_t(int(chunk_len), int(lookahead), MATCH_EARLY_EXIT if early_exit else 0)
 
 
 class DFA:
@@ -290,7 +293,7 @@ def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> dfa_plan
 
 def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
                  lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
-                 bound_out=None):
+                 bound_out=None, early_exit: bool = False):
     """Test with options; optionally the state at every chunk boundary.
     Returns (result tensor, boundaries tensor or None)."""
     import torch
@@ -302,7 +305,7 @@ def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 
         bnd = bound_out if bound_out is not None else torch.empty(
             nch + 1, dtype=torch.int32, device="cuda")
         assert bnd.numel() >= nch + 1
-    o = _opts(chunk_len, lookahead)
+    o = _opts(chunk_len, lookahead, early_exit)
     _check(lib().dfa_match_ex(d.handle, d_input.data_ptr() if n else None, n,
                               DFA_Q0 if start is None else int(start), ctypes.byref(o),
                               _stream_handle(stream), result.data_ptr(),
@@ -337,18 +340,19 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
     return float(m.value), float(c.value), int(k.value)
 
 
-def dfa_autotune(d: DFA, d_input, stream=None) -> Tuple[int, int, float]:
-    """Tune (lookahead, chunk length) on a device input: (r, chunk, ms per call)."""
+def dfa_autotune(d: DFA, d_input, stream=None) -> Tuple[int, int, float, bool]:
+    """Tune on a device input: (lookahead r, chunk length, ms per call, early exit)."""
     o = dfa_match_opts_t()
     ms = ctypes.c_double()
     n = int(d_input.numel())
     _check(lib().dfa_autotune(d.handle, d_input.data_ptr() if n else None, n,
                               _stream_handle(stream), ctypes.byref(o), ctypes.byref(ms)))
-    return int(o.lookahead), int(o.chunk_len), float(ms.value)
+    return int(o.lookahead), int(o.chunk_len), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT)
 
 
-def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None) -> Tuple[int, int, float]:
-    """Tune a batch: (chunk length, lookahead, ms per run)."""
+def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None
+                   ) -> Tuple[int, int, float, bool]:
+    """Tune a batch: (chunk length, lookahead, ms per run, early exit)."""
     count = len(dfas)
     hs = (ctypes.c_void_p * max(count, 1))(*[x.handle.value for x in dfas])
     ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None for t in inputs])
@@ -357,14 +361,14 @@ def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None) -> Tuple[
     ms = ctypes.c_double()
     _check(lib().dfa_batch_tune(hs, ps, ls, count, _stream_handle(stream), ctypes.byref(o),
                                 ctypes.byref(ms)))
-    return int(o.chunk_len), int(o.lookahead), float(ms.value)
+    return int(o.chunk_len), int(o.lookahead), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT)
 
 
 class Batch:
     """A planned batch of (DFA, device string) pairs (dfa_batch_create)."""
 
     def __init__(self, dfas: Sequence[DFA], inputs: Sequence, chunk_len: int = 0,
-                 lookahead: int = 1):
+                 lookahead: int = 1, early_exit: bool = False):
         self._dfas = list(dfas)          # keep the DFAs alive
         self._inputs = list(inputs)      # and the device strings
         count = len(self._dfas)
@@ -374,7 +378,7 @@ class Batch:
         ps = (ctypes.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None
                                                  for t in self._inputs])
         ls = (ctypes.c_size_t * max(count, 1))(*[int(t.numel()) for t in self._inputs])
-        o = _opts(chunk_len, lookahead)
+        o = _opts(chunk_len, lookahead, early_exit)
         h = ctypes.c_void_p()
         _check(lib().dfa_batch_create(hs, ps, ls, count, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -115,6 +115,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     uint32_t look = opts->lookahead;
     MatchPlan p;
     int rc = plan_match(d, len, chunk, look, &p);
+    p.early_exit = p.packed && (opts->flags & DFA_MATCH_EARLY_EXIT) && d->dev.nabs > 0;
     if (rc) return rc;
     Workspace *ws = workspace_for(s);
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
@@ -342,6 +343,27 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
         }
         if (rc) break;
     }
+    if (rc == DFA_OK && d->dev.nabs > 0 && d->dev.layout != 0) {
+        // the best setting again with early exit at absorbing states
+        dfa_match_opts_t o = pick;
+        o.flags |= DFA_MATCH_EARLY_EXIT;
+        double t_best = 1e30;
+        for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+            if (rep > 0) (void)hipEventRecord(a, s);
+            rc = run_match(d, d_input, n, DFA_Q0, &o, s, res, nullptr);
+            if (rep > 0) {
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t_best = std::min<double>(t_best, ms);
+            }
+        }
+        if (rc == DFA_OK && t_best < pick_ms) {
+            pick_ms = t_best;
+            pick = o;
+        }
+    }
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -382,12 +404,14 @@ extern "C" int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_
     pick.chunk_len = base_chunk;
     pick.lookahead = 1;
     double pick_ms = 1e30;
-    const double mult[] = {0.25, 0.5, 1.0, 2.0, 4.0};
+    // chunk candidates: the planner's and powers of two from 1 KiB to 64 KiB
+    std::vector<uint64_t> cands = {std::max<uint64_t>(256, base_chunk / 64 * 64)};
+    for (uint64_t c = 1024; c <= (64u << 10); c *= 2)
+        if (c != cands[0]) cands.push_back(c);
     std::vector<uint32_t> looks = {1};
     if (packed) looks = {1, 2, 3, 4, 6, 8};
     for (uint32_t look : looks) {
-        for (double m : mult) {
-            const uint64_t c = std::max<uint64_t>(256, (uint64_t)(base_chunk * m) / 64 * 64);
+        for (uint64_t c : cands) {
             dfa_match_opts_t o{};
             o.chunk_len = c;
             o.lookahead = look;
@@ -415,6 +439,33 @@ extern "C" int dfa_batch_tune(const dfa_t *const *dfas, const uint8_t *const *d_
             }
         }
         if (rc) break;
+    }
+    bool any_abs = false;
+    for (size_t i = 0; i < count; ++i) any_abs = any_abs || dfas[i]->dev.nabs > 0;
+    if (rc == DFA_OK && packed && any_abs) {
+        // the best setting again with early exit at absorbing states
+        dfa_match_opts_t o = pick;
+        o.flags |= DFA_MATCH_EARLY_EXIT;
+        dfa_batch_t *bt = nullptr;
+        rc = dfa_batch_create(dfas, d_inputs, lens, count, &o, &bt);
+        double t_best = 1e30;
+        for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+            if (rep > 0) (void)hipEventRecord(a, s);
+            rc = dfa_batch_run(bt, stream, res);
+            if (rep > 0) {
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t_best = std::min<double>(t_best, ms);
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        if (bt) dfa_batch_destroy(bt);
+        if (rc == DFA_OK && t_best < pick_ms) {
+            pick_ms = t_best;
+            pick = o;
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

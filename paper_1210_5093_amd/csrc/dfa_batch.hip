@@ -380,7 +380,8 @@ extern "C" int dfa_batch_create(const dfa_t *const *dfas, const uint8_t *const *
     if (b->kind == 1 && look != 1)
         return fail(DFA_E_INVAL, "dfa_batch_create: this batch needs one-symbol lookahead");
     int rc = b->kind == 2
-                 ? plan_batch2(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, look, &b->plan2)
+                 ? plan_batch2(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, look, &b->plan2,
+                               opts ? opts->flags : 0u)
                  : plan_batch(dfas, d_inputs, lens, count, opts ? opts->chunk_len : 0, &b->plan);
     if (rc) return rc;
     const size_t total = b->kind == 2 ? b->plan2.total_bytes : b->plan.total_bytes;

@@ -97,6 +97,7 @@ struct B2Args {
     uint16_t *msize;
     uint32_t task_slot;          // LDS byte offset of the task broadcast word
     uint32_t wpb;                // waves per matcher workgroup = tiles per task
+    uint32_t early_exit;         // stop a tile once all its pairs are absorbing
 };
 
 __global__ void k_b2_reset(B2Args a) {
@@ -284,9 +285,7 @@ __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32
     const uint32_t lo0 = a.tile_first2[tile];
     const uint32_t hi0 = tile + 1 < tile_end ? a.tile_first2[tile + 1] + 1 : gr.chunk_hi;
     const uint32_t R = L == 1 ? d.rowbytes : 2u;
-    const bool aligned_chunks = (a.chunk % kPer16) == 0;
-    uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2];
-    bool ok = aligned_chunks;
+    uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2], len[kSlots2];
 #pragma unroll
     for (int j = 0; j < kSlots2; ++j) {
         const uint32_t P = tile * kTile2 + j * kWave2 + lane;
@@ -310,34 +309,17 @@ __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32
         }
         st[j] = R * q;
         ci[j] = valid ? c : 0xFFFFFFFFu;
-        o16[j] = aligned_chunks
-                     ? (uint32_t)((s.code_off / sizeof(CodeT) + (uint64_t)i * a.chunk) / kPer16)
-                     : 0u;
-        ok = ok && (!valid || i + 1 < s.nch || s.n - (uint64_t)i * a.chunk == a.chunk);
+        // chunk starts are whole 16-byte units: the chunk length is a
+        // multiple of 64 and every code stream starts 16-byte aligned
+        o16[j] = (uint32_t)((s.code_off / sizeof(CodeT) + (uint64_t)i * a.chunk) / kPer16);
+        len[j] = (uint32_t)min<uint64_t>(a.chunk, s.n - (uint64_t)i * a.chunk);
     }
-    const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
-    if (__all(ok)) {
-        walk_fast<L>(reinterpret_cast<const uint4 *>(a.codes), o16,
-                     (uint32_t)(a.chunk / kPer16), st);
-    } else {
-        uint64_t base[kSlots2], len[kSlots2];
+    uint32_t live = 0;
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
-            base[j] = 0;
-            len[j] = 0;
-            if (ci[j] != 0xFFFFFFFFu) {
-                const B2Str s = a.strs[a.chunk_str[ci[j]]];
-                const uint64_t p = (uint64_t)(ci[j] - s.chunk0) * a.chunk;
-                base[j] = s.code_off / sizeof(CodeT) + p;
-                len[j] = min<uint64_t>(a.chunk, s.n - p);
-            }
-        }
-        for (uint64_t t = 0; t < a.chunk; ++t) {
-#pragma unroll
-            for (int j = 0; j < kSlots2; ++j)
-                if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[base[j] + t]);
-        }
-    }
+    for (int j = 0; j < kSlots2; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
+    const bool ex = a.early_exit && d.nabs > 0;
+    walk_var<L>(reinterpret_cast<const uint4 *>(a.codes), o16, len, st, ex ? d.abs_off : 0u,
+                d.abs_shift, live);
 #pragma unroll
     for (int j = 0; j < kSlots2; ++j) {
         if (ci[j] == 0xFFFFFFFFu) continue;
@@ -384,7 +366,7 @@ __global__ __launch_bounds__(1024) void k_b2_match(B2Args a) {
         const B2Group gr = a.groups[k];
         const DevDFA &d = a.dfas[gr.dfa];
         if (gr.dfa != cur) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(gr.layout == 1 ? d.stab : d.table);
+            const uint4 *src = reinterpret_cast<const uint4 *>(d.stab);
             uint4 *dst = reinterpret_cast<uint4 *>(smem);
             for (uint32_t x = threadIdx.x; x < d.stab_bytes / 16; x += blockDim.x) dst[x] = src[x];
             __syncthreads();
@@ -486,9 +468,11 @@ bool batch2_supported(const dfa_t *const *dfas, size_t count) {
 }
 
 int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
-                size_t count, uint64_t chunk_req, uint32_t lookahead, Batch2Plan *out) {
+                size_t count, uint64_t chunk_req, uint32_t lookahead, Batch2Plan *out,
+                uint32_t flags) {
     Batch2Plan &P = *out;
     P = Batch2Plan();
+    P.early_exit = (flags & DFA_MATCH_EARLY_EXIT) ? 1u : 0u;
     if (count && (!dfas || !d_inputs || !lens)) return fail(DFA_E_INVAL, "batch plan: NULL argument");
     if (count > 0x7FFFFFFFull) return fail(DFA_E_TOOBIG, "batch plan: too many strings");
     const int lds = device_lds_bytes();
@@ -522,12 +506,14 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
     for (auto *d : uniq) max_stab = std::max(max_stab, d->dev.stab_bytes);
     if ((size_t)max_stab + 16 > (size_t)lds) return fail(DFA_E_TOOBIG, "batch plan: table exceeds LDS");
 
-    // chunk length: about four resident tiles' worth of pairs per wave slot
+    // chunk length: about 64 wave-tiles of pairs per resident wave slot, so
+    // that chains stay short (the matcher is latency bound when they are
+    // long) while the per-chunk work stays small
     uint64_t chunk = chunk_req;
     if (!chunk) {
         double work = 0.0;
         for (size_t i = 0; i < count; ++i) work += (double)lens[i] * mean_set(dfas[i]);
-        const double target_pairs = 4.0 * cus * 16.0 * kTile2;
+        const double target_pairs = 64.0 * cus * 16.0 * kTile2;
         chunk = (uint64_t)std::max(1024.0, work / target_pairs);
         chunk = std::min<uint64_t>((chunk + 63) / 64 * 64, 1u << 20);
     }
@@ -719,6 +705,7 @@ int launch_batch2(const Batch2Plan &P, void *dev_base, hipStream_t s, uint32_t *
     a.msize = (uint16_t *)(base + P.o_msize);
     a.task_slot = P.task_slot;
     a.wpb = P.wpb;
+    a.early_exit = P.early_exit;
     const B2Seg *segs = (const B2Seg *)(base + P.o_segs);
     const B2Item *items = (const B2Item *)(base + P.o_items);
 

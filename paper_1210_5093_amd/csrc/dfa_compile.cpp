@@ -239,6 +239,33 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
                 if (byte_class[b] >= 0) code[b] = (uint16_t)((uint32_t)byte_class[b] * colstride);
         }
     }
+    // staged image of the packed matcher: table, then the absorbing-state
+    // bitmap indexed by (LDS state offset >> shift): R * s / 4 for layout 1,
+    // 2 * s / 2 for layout 2
+    uint32_t abs_off = 0, abs_shift = 0;
+    if (layout != 0) {
+        if (layout == 2) {   // the class-major table itself
+            stab.assign(table.begin(), table.end());
+        }
+        stab.resize(align_up(stab.size() * 2, 16) / 2, 0);
+        abs_off = (uint32_t)(stab.size() * 2);
+        abs_shift = layout == 1 ? 2u : 1u;
+        const uint32_t unit = layout == 1 ? rowbytes / 4 : 1u;   // bitmap index per state
+        std::vector<uint32_t> bits(((uint64_t)nq * unit + 31) / 32, 0);
+        for (uint32_t q = 0; q < nq; ++q)
+            if (absorbing[q]) bits[(q * unit) >> 5] |= 1u << ((q * unit) & 31);
+        const size_t words = align_up(bits.size() * 4, 16) / 4;
+        bits.resize(words, 0);
+        for (uint32_t w : bits) {
+            stab.push_back((uint16_t)(w & 0xFFFF));
+            stab.push_back((uint16_t)(w >> 16));
+        }
+        if ((uint64_t)stab.size() * 2 + 16 > (uint64_t)lds) {
+            layout = 0;   // no room for the bitmap: one chunk per wavefront only
+            stab.clear();
+            abs_off = abs_shift = 0;
+        }
+    }
     if (stab.empty()) stab.assign(8, 0);
 
     std::vector<uint32_t> accept_bits((nq + 31) / 32, 0);
@@ -313,7 +340,10 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.stab = (const uint16_t *)ptr(i_stab);
     v.layout = layout;
     v.rowbytes = rowbytes;
-    v.stab_bytes = layout == 1 ? (uint32_t)(stab.size() * 2) : (uint32_t)table_bytes;
+    v.stab_bytes = layout != 0 ? (uint32_t)(stab.size() * 2) : (uint32_t)table_bytes;
+    v.abs_off = abs_off;
+    v.abs_shift = abs_shift;
+    v.nabs = nabs;
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;

@@ -51,7 +51,12 @@ struct DevDFA {
     const uint16_t *stab;        // layout 1 table (nq rows of R bytes)
     uint32_t layout;             // 0 = packed matcher unavailable, 1, 2
     uint32_t rowbytes;           // R (layout 1)
-    uint32_t stab_bytes;         // bytes staged for the packed matcher, multiple of 16
+    uint32_t stab_bytes;         // bytes staged for the packed matcher, multiple of 16:
+                                 //  the table (stab for layout 1, a copy of `table`
+                                 //  for layout 2), then the absorbing-state bitmap
+    uint32_t abs_off;            // LDS byte offset of that bitmap; bit (LDS state
+    uint32_t abs_shift;          //  offset >> abs_shift) is set iff the state is absorbing
+    uint32_t nabs;               // number of absorbing states
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -107,6 +112,7 @@ struct MatchPlan {
     uint32_t blocks = 0;
     // packed-pair matcher
     bool packed = false;
+    bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
     uint32_t blocks2 = 0;        // persistent grid
     uint32_t threads2 = 256;     // threads per block (more for large tables)
     uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)
@@ -183,12 +189,13 @@ struct Batch2Plan {
     std::vector<uint32_t> items_per_level;
     std::vector<size_t> item_base;
     uint64_t chunk = 0;
-    uint32_t task_slot = 0, wpb = 4, blocks = 0, tblocks = 0;
+    uint32_t task_slot = 0, wpb = 4, blocks = 0, tblocks = 0, early_exit = 0;
     size_t lds_match = 0, lds_compose0 = 0, lds_compose = 0;
 };
 bool batch2_supported(const dfa_t *const *dfas, size_t count);
 int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const size_t *lens,
-                size_t count, uint64_t chunk_req, uint32_t lookahead, Batch2Plan *out);
+                size_t count, uint64_t chunk_req, uint32_t lookahead, Batch2Plan *out,
+                uint32_t flags = 0);
 int launch_batch2(const Batch2Plan &p, void *dev_base, hipStream_t s, uint32_t *d_results,
                   hipEvent_t ev_before_match = nullptr, hipEvent_t ev_after_match = nullptr);
 

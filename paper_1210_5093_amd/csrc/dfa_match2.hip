@@ -309,11 +309,13 @@ struct Match2Args {
     uint32_t *bits;          // window pass: start-set bitmaps
     uint32_t W;
     uint16_t *maps;          // level-0 maps, indexed by pair
+    uint32_t exit_base;      // early exit: LDS byte offset of the absorbing bitmap (0 = off)
+    uint32_t exit_shift;
 };
 
 template <int L>
 __device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(L == 1 ? d.stab : d.table);
+    const uint4 *src = reinterpret_cast<const uint4 *>(d.stab);
     uint4 *dst = reinterpret_cast<uint4 *>(smem);
     for (uint32_t i = threadIdx.x; i < d.stab_bytes / 16; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
@@ -396,8 +398,7 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
     for (uint32_t tile = wave_id; tile < ntiles; tile += total_waves) {
         const uint32_t lo0 = a.tile_first[tile];
         const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
-        uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2];
-        bool ok = aligned_chunks;
+        uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2], len[kSlots2];
 #pragma unroll
         for (int j = 0; j < kSlots2; ++j) {
             const uint32_t P = tile * kTile2 + j * kWave2 + lane;
@@ -419,11 +420,16 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
             o16[j] = aligned_chunks ? (uint32_t)((uint64_t)c * a.chunk / kPer16) : 0u;
-            ok = ok && (!valid || c + 1 < a.nch || a.n - (uint64_t)c * a.chunk == a.chunk);
+            // pairs past the end shadow chunk 0 from state 0 (loads stay in
+            // bounds; their end states are discarded)
+            len[j] = (uint32_t)min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk);
         }
-        if (__all(ok)) {
-            walk_fast<L>(reinterpret_cast<const uint4 *>(codes), o16,
-                         (uint32_t)(a.chunk / kPer16), st);
+        if (aligned_chunks) {
+            uint32_t live = 0;
+#pragma unroll
+            for (int j = 0; j < kSlots2; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
+            walk_var<L>(reinterpret_cast<const uint4 *>(codes), o16, len, st, a.exit_base,
+                        a.exit_shift, live);
         } else {
             // general path: per-lane code loads, chunks of any length and alignment
             for (uint64_t t = 0; t < a.chunk; ++t) {
@@ -558,6 +564,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.bits = b.bits;
     a.W = p.bitmap_words;
     a.maps = maps;
+    a.exit_base = p.early_exit ? d->dev.abs_off : 0u;
+    a.exit_shift = d->dev.abs_shift;
     const size_t lds = d->dev.stab_bytes;
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch};
     if (p.lookahead == 2) {

@@ -88,6 +88,27 @@ __device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ mem
 // Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
 // 16-byte-aligned chunk (o16 = its first code's offset in 16-byte units),
 // read as uint4 blocks with one block of prefetch.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32_t;
+__device__ __forceinline__ uint32_t lds_ld32(uint32_t addr) {
+    return *(lds_u32_t *)(size_t)addr;
+}
+
+// True in every lane when every live slot of the wavefront sits in an
+// absorbing state (bit st >> shift of the LDS bitmap at byte `base`).
+__device__ __forceinline__ bool wave_absorbed(const uint32_t (&st)[kSlots2], uint32_t live,
+                                              uint32_t base, uint32_t shift) {
+    bool dead = true;
+#pragma unroll
+    for (int j = 0; j < kSlots2; ++j) {
+        if ((live >> j) & 1u) {
+            const uint32_t idx = st[j] >> shift;
+            const uint32_t w = lds_ld32(base + ((idx >> 5) << 2));
+            dead = dead && ((w >> (idx & 31)) & 1u);
+        }
+    }
+    return __all(dead);
+}
+
 // One step of every slot with code K of its dword.
 template <int L, int K>
 __device__ __forceinline__ void step_slots(uint32_t (&st)[kSlots2], const uint32_t (&w)[kSlots2]) {
@@ -97,10 +118,14 @@ __device__ __forceinline__ void step_slots(uint32_t (&st)[kSlots2], const uint32
     for (int j = 0; j < kSlots2; ++j) st[j] = lds_ld(st[j]);
 }
 
+// With exit_base != 0 the walk stops early (every 4 blocks it checks) once
+// every live slot of the wavefront is absorbing: the rest of the chunk cannot
+// change those states.
 template <int L>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
                                           const uint32_t (&o16)[kSlots2], uint32_t blocks,
-                                          uint32_t (&st)[kSlots2]) {
+                                          uint32_t (&st)[kSlots2], uint32_t exit_base = 0,
+                                          uint32_t exit_shift = 0, uint32_t live = 0) {
     uint4 cur[kSlots2], nxt[kSlots2];
 #pragma unroll
     for (int j = 0; j < kSlots2; ++j) cur[j] = codes16[o16[j]];
@@ -126,8 +151,51 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
             }
         }
         if (!more) break;
+        if (exit_base && (b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
 #pragma unroll
         for (int j = 0; j < kSlots2; ++j) cur[j] = nxt[j];
+    }
+}
+
+// Walk pairs whose chunks may end inside a 16-byte block: len[j] codes from
+// 16-byte unit o16[j].  All slots first walk their common whole blocks on
+// the fast path; then each slot finishes its own remaining blocks, stepping
+// only over codes it owns (the last block is read whole: code streams are
+// padded to whole blocks).
+template <int L>
+__device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
+                                         const uint32_t (&o16)[kSlots2],
+                                         const uint32_t (&len)[kSlots2], uint32_t (&st)[kSlots2],
+                                         uint32_t exit_base = 0, uint32_t exit_shift = 0,
+                                         uint32_t live = 0) {
+    constexpr uint32_t kPer16 = L == 1 ? 16u : 8u;
+    uint32_t common = len[0] / kPer16, most = (len[0] + kPer16 - 1) / kPer16;
+#pragma unroll
+    for (int j = 1; j < kSlots2; ++j) {
+        common = min(common, len[j] / kPer16);
+        most = max(most, (len[j] + kPer16 - 1) / kPer16);
+    }
+    if (common > 0) walk_fast<L>(codes16, o16, common, st, exit_base, exit_shift, live);
+    for (uint32_t b = common; b < most; ++b) {
+#pragma unroll
+        for (int j = 0; j < kSlots2; ++j) {
+            if (b * kPer16 >= len[j]) continue;
+            const uint32_t cnt = min(kPer16, len[j] - b * kPer16);
+            const uint4 v = codes16[(size_t)o16[j] + b];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (L == 1) {
+                    if (4 * q + 0 < cnt) st[j] = lds_ld(add_sel<1, 0>(st[j], w[q]));
+                    if (4 * q + 1 < cnt) st[j] = lds_ld(add_sel<1, 1>(st[j], w[q]));
+                    if (4 * q + 2 < cnt) st[j] = lds_ld(add_sel<1, 2>(st[j], w[q]));
+                    if (4 * q + 3 < cnt) st[j] = lds_ld(add_sel<1, 3>(st[j], w[q]));
+                } else {
+                    if (2 * q + 0 < cnt) st[j] = lds_ld(add_sel<2, 0>(st[j], w[q]));
+                    if (2 * q + 1 < cnt) st[j] = lds_ld(add_sel<2, 1>(st[j], w[q]));
+                }
+            }
+        }
     }
 }
 

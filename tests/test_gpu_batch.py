@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import configs, streams
+from workloads import configs, from_pattern, patterns, streams
 
 pytestmark = pytest.mark.gpu
 
@@ -242,3 +242,20 @@ def test_full_batched_configuration(dfa_mod):
     torch.cuda.synchronize()
     check_records(res, expect)
     b.close()
+
+
+def test_packed_batch_early_exit(dfa_mod):
+    """Anchored and "contains" pattern DFAs with early exit: same records."""
+    import torch
+    ws = [from_pattern(patterns.pattern_dfa(s, contains=bool(s % 2))) for s in range(20, 32)]
+    xs = [configs.c2_input((1 << 16) * (k + 1) + 13 * k, seed=600 + k) for k in range(len(ws))]
+    ds = [dfa_mod.DFA.from_workload(w) for w in ws]
+    ins = [torch.from_numpy(x).to("cuda") for x in xs]
+    expect = oracle_records(ws, xs)
+    for look in (1, 3):
+        b = dfa_mod.Batch(ds, ins, chunk_len=2048, lookahead=look, early_exit=True)
+        res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
+        b.run(res)
+        torch.cuda.synchronize()
+        check_records(res, expect)
+        b.close()

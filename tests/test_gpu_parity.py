@@ -465,3 +465,48 @@ def test_precomputed_and_window_lookahead_c2_bench_size(dfa_mod, r):
     w = configs.c2_dfa()
     x = configs.c2_input(32 * (1 << 20) + 5)
     check(dfa_mod, w, x, lookahead=r)
+
+
+# ---------------------------------------------------------------------------
+# Early exit at absorbing states (the walks of a wavefront stop once all of
+# them sit in an absorbing state): results and boundary states unchanged.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,contains", [(32, False), (7, False), (32, True), (5825, True)])
+@pytest.mark.parametrize("look", [1, 4])
+def test_early_exit_matches_oracle(dfa_mod, seed, contains, look):
+    import torch
+    w = from_pattern(patterns.pattern_dfa(seed, contains=contains))
+    n = 6 << 20
+    x = configs.c2_input(n, seed=900 + seed)
+    probes = list(range(0, n + 1, 4096))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = torch.from_numpy(x).to("cuda")
+    for ex in (False, True):
+        res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=4096, lookahead=look, boundaries=True,
+                                        early_exit=ex)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), ex
+        b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        assert np.array_equal(b, ps.astype(np.int64)), ex
+    d.close()
+
+
+def test_early_exit_ragged_and_invalid(dfa_mod):
+    import torch
+    w = from_pattern(patterns.pattern_dfa(32, contains=False))
+    d = dfa_mod.DFA.from_workload(w)
+    for n in (4 << 20, (4 << 20) + 77):
+        x = configs.c2_input(n, seed=n % 1000).copy()
+        fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
+        res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=1024,
+                                      early_exit=True)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0)
+        x[n - 5] = ord("#")
+        res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=1024,
+                                      early_exit=True)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()

@@ -40,8 +40,8 @@ def test_autotuned_setting_matches_oracle(dfa_mod, which, n):
     fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
     d = dfa_mod.DFA.from_workload(w)
     dev = torch.from_numpy(x).to("cuda")
-    r, chunk, ms = dfa_mod.dfa_autotune(d, dev)
-    say(f"{which}: tuned r={r} chunk={chunk} {ms:.3f} ms")
+    r, chunk, ms, ex = dfa_mod.dfa_autotune(d, dev)
+    say(f"{which}: tuned r={r} chunk={chunk} early_exit={ex} {ms:.3f} ms")
     assert 1 <= r <= 10 and ms > 0
     res, _ = dfa_mod.dfa_match_ex(d, dev, lookahead=dfa_mod.DFA_LOOKAHEAD_AUTO)
     torch.cuda.synchronize()
@@ -67,10 +67,10 @@ def test_batch_tune_matches_oracle(dfa_mod):
         x = configs.request_input(kind, seed, n)
         xs.append(x)
         ins.append(torch.from_numpy(x).to("cuda"))
-    chunk, look, ms = dfa_mod.dfa_batch_tune(ds, ins)
-    say(f"batch tuned chunk={chunk} lookahead={look} {ms:.3f} ms")
+    chunk, look, ms, ex = dfa_mod.dfa_batch_tune(ds, ins)
+    say(f"batch tuned chunk={chunk} lookahead={look} early_exit={ex} {ms:.3f} ms")
     assert chunk >= 256 and chunk % 64 == 0 and 1 <= look <= 8
-    b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look)
+    b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
     res = torch.empty((len(ds), 4), dtype=torch.int32, device="cuda")
     b.run(res)
     torch.cuda.synchronize()

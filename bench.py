@@ -150,6 +150,64 @@ def image_sizes(w, x: np.ndarray, chunk: int, nch: int, r: int) -> np.ndarray:
     return out
 
 
+def start_sets(w, x: np.ndarray, chunk: int, nch: int, r: int):
+    """Per chunk i >= 1 its start states (padded with -1): the image of Q under
+    the min(r, i*C) bytes before it (r >= 1; r = 0: all states), absorbing
+    states left out."""
+    d = w.delta.astype(np.int32)
+    nq = d.shape[0]
+    absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
+    sym = w.byte_to_symbol.astype(np.int64)
+    rows = []
+    batch = max(1, (1 << 24) // max(nq, 1))
+    for b0 in range(1, nch, batch):
+        idx = np.arange(b0, min(nch, b0 + batch), dtype=np.int64)
+        S = np.broadcast_to(np.arange(nq, dtype=np.int32), (idx.size, nq)).copy()
+        p = idx * chunk
+        rr = np.minimum(r, p)
+        for t in range(int(rr.max()) if r > 0 else 0):
+            live = t < rr
+            pos = np.where(live, p - rr + t, 0)
+            S = np.where(live[:, None], d[S, sym[x[pos]][:, None]], S)
+        S.sort(axis=1)
+        keep = np.concatenate([np.ones((S.shape[0], 1), bool), S[:, 1:] != S[:, :-1]], axis=1)
+        keep &= ~absorbing[S]
+        S = np.where(keep, S, -1)
+        S = -np.sort(-S, axis=1)   # members first
+        rows.append(S[:, :max(1, int(keep.sum(axis=1).max()))])
+    return rows
+
+
+def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int) -> int:
+    """Lookups of Algorithm 3 when every walk stops at the first absorbing
+    state it reaches (the least work early exit can do; the kernel checks
+    every 64 bytes, so it does at least this much)."""
+    d = w.delta.astype(np.int32)
+    nq = d.shape[0]
+    absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
+    sym = w.byte_to_symbol.astype(np.int64)
+    n = x.size
+    nch = (n + chunk - 1) // chunk
+    pcs, pss = [np.zeros(1, np.int64)], [np.array([start], np.int64)]
+    base = 1
+    for S in start_sets(w, x, chunk, nch, max(lookahead, 1) if lookahead else 0):
+        rr, cc = np.nonzero(S >= 0)
+        pcs.append(rr + base)
+        pss.append(S[rr, cc].astype(np.int64))
+        base += S.shape[0]
+    pc, ps = np.concatenate(pcs), np.concatenate(pss)
+    lens = np.minimum(chunk, n - pc * chunk)
+    total = 0
+    for t in range(chunk):
+        if pc.size == 0:
+            break
+        ps = d[ps, sym[x[pc * chunk + t]]]
+        total += pc.size
+        alive = (~absorbing[ps]) & (t + 1 < lens)
+        pc, ps, lens = pc[alive], ps[alive], lens[alive]
+    return int(total)
+
+
 def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int) -> int:
     """len(c_0) + sum_{i>=1} |I_i| len(c_i) (Algorithm 3's work; I_i is the
     chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13)."""
@@ -629,7 +687,10 @@ def main() -> int:
                  "tuning_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex} "
             f"({ms:.3f} ms)")
-        args.early_exit = args.early_exit or ex
+        # the timed run uses early exit only when asked for (--early-exit):
+        # its work depends on the data, so the roofline would need the
+        # smaller exact count
+        tuned["early_exit_used"] = bool(args.early_exit)
         args.lookahead = r
         if not args.chunk:
             args.chunk = c
@@ -671,7 +732,10 @@ def main() -> int:
 
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
-    lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
+    if args.early_exit:
+        lookups = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0))
+    else:
+        lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
     plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead)
     kernel = f"k_match2<{info.packed_layout}>" if plan.kernel == 1 else "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
@@ -699,6 +763,7 @@ def main() -> int:
             "lookahead": args.lookahead,
             "chosen_by": "autotuner (dfa_autotune, untimed)" if tuned else "command line",
             "early_exit": bool(args.early_exit),
+            "tuner": tuned,
             "chunk_bytes": int(chunk),
             "chunks": int(nch),
             "lookups_per_byte": round(lookups / nbytes, 3),

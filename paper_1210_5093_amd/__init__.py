@@ -64,7 +64,7 @@ class dfa_server_done_t(ctypes.Structure):
 class dfa_server_opts_t(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
+                ("lookahead", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
 
 
 class dfa_server_stats_t(ctypes.Structure):
@@ -412,8 +412,9 @@ class Server:
     """Continuous-batching server over resident DFAs (dfa_server_*)."""
 
     def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, streams: int = 0,
-                 max_batch: int = 0, slot_bytes: int = 0):
-        o = dfa_server_opts_t(budget_bytes, max_inflight, streams, max_batch, 0, slot_bytes)
+                 max_batch: int = 0, slot_bytes: int = 0, lookahead: int = 0):
+        o = dfa_server_opts_t(budget_bytes, max_inflight, streams, max_batch, lookahead,
+                              slot_bytes)
         h = ctypes.c_void_p()
         _check(lib().dfa_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -18,6 +18,7 @@
 // The host plans everything that depends only on the lengths, so a run
 // allocates nothing and can be captured in a HIP graph.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -98,6 +99,8 @@ struct B2Args {
     uint32_t task_slot;          // LDS byte offset of the task broadcast word
     uint32_t wpb;                // waves per matcher workgroup = tiles per task
     uint32_t early_exit;         // stop a tile once all its pairs are absorbing
+    uint32_t slots;              // pairs per lane (2 or 4); a tile holds 64 * slots pairs
+    uint32_t tile;
 };
 
 __global__ void k_b2_reset(B2Args a) {
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_b2_groups(B2Args a) {
     for (uint32_t k = lo; k < hi; ++k) {
         const B2Group gr = a.groups[k];
         const uint32_t pairs = a.first_raw[gr.chunk_hi] - a.first_raw[gr.chunk_lo];
-        const uint32_t tk = (pairs + kTile2 - 1) / kTile2;
+        const uint32_t tk = (pairs + a.tile - 1) / a.tile;
         tiles += tk;
         tasks += (tk + a.wpb - 1) / a.wpb;
     }
@@ -234,17 +237,17 @@ __global__ __launch_bounds__(1024) void k_b2_groups(B2Args a) {
     for (uint32_t k = lo; k < hi; ++k) {
         const B2Group gr = a.groups[k];
         const uint32_t pairs = a.first_raw[gr.chunk_hi] - a.first_raw[gr.chunk_lo];
-        const uint32_t tk = (pairs + kTile2 - 1) / kTile2;
+        const uint32_t tk = (pairs + a.tile - 1) / a.tile;
         a.gtile[k] = tile_run;
         a.gtask[k] = task_run;
-        a.gend[k] = tile_run * kTile2 + pairs;
+        a.gend[k] = tile_run * a.tile + pairs;
         tile_run += tk;
         task_run += (tk + a.wpb - 1) / a.wpb;
     }
     if (t == T - 1) {
         a.gtile[a.ngroups] = tile_total;
         a.gtask[a.ngroups] = task_total;
-        a.first2[a.nchunks] = tile_total * kTile2;
+        a.first2[a.nchunks] = tile_total * a.tile;
     }
 }
 
@@ -254,11 +257,11 @@ __global__ void k_b2_pairs(B2Args a) {
     if (g >= a.nchunks) return;
     const uint32_t k = a.strs[a.chunk_str[g]].group;
     const B2Group gr = a.groups[k];
-    const uint32_t A = a.gtile[k] * kTile2 + (a.first_raw[g] - a.first_raw[gr.chunk_lo]);
+    const uint32_t A = a.gtile[k] * a.tile + (a.first_raw[g] - a.first_raw[gr.chunk_lo]);
     const uint32_t m = a.msize0[g] & 0x7FFFu;
     a.first2[g] = A;
     if (m)
-        for (uint32_t w = (A + kTile2 - 1) / kTile2; w <= (A + m - 1) / kTile2; ++w)
+        for (uint32_t w = (A + a.tile - 1) / a.tile; w <= (A + m - 1) / a.tile; ++w)
             a.tile_first2[w] = g;
 }
 
@@ -274,9 +277,10 @@ __device__ __forceinline__ uint32_t group_of(const uint32_t *__restrict__ gtask,
 }
 
 // One wave-tile of group k (all pairs of one DFA), layout L.
-template <int L>
+template <int L, int S>
 __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32_t k,
                                         uint32_t tile, uint32_t lane) {
+    constexpr uint32_t kTile = kWave2 * S;
     using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
     constexpr uint32_t kPer16 = 16 / sizeof(CodeT);
     const uint32_t pair_end = a.gend[k];
@@ -285,10 +289,10 @@ __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32
     const uint32_t lo0 = a.tile_first2[tile];
     const uint32_t hi0 = tile + 1 < tile_end ? a.tile_first2[tile + 1] + 1 : gr.chunk_hi;
     const uint32_t R = L == 1 ? d.rowbytes : 2u;
-    uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2], len[kSlots2];
+    uint32_t st[S], ci[S], o16[S], len[S];   // len: codes per slot
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) {
-        const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+    for (int j = 0; j < S; ++j) {
+        const uint32_t P = tile * kTile + j * kWave2 + lane;
         const bool valid = P < pair_end;
         // a pair beyond the group's end shadows the tile's first pair (a real
         // chunk of this DFA) from state 0, so its loads stay valid; its end
@@ -316,18 +320,21 @@ __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32
     }
     uint32_t live = 0;
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
-    const bool ex = a.early_exit && d.nabs > 0;
-    walk_var<L>(reinterpret_cast<const uint4 *>(a.codes), o16, len, st, ex ? d.abs_off : 0u,
-                d.abs_shift, live);
+    for (int j = 0; j < S; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
+    auto len_of = [&](int j) -> uint32_t { return len[j]; };
+    if (a.early_exit && d.nabs > 0)
+        walk_var<L, S, true>(reinterpret_cast<const uint4 *>(a.codes), o16, len_of, st, d.abs_off,
+                             d.abs_shift, live);
+    else
+        walk_var<L, S, false>(reinterpret_cast<const uint4 *>(a.codes), o16, len_of, st);
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) {
+    for (int j = 0; j < S; ++j) {
         if (ci[j] == 0xFFFFFFFFu) continue;
         const uint32_t c = ci[j];
         const B2Str s = a.strs[a.chunk_str[c]];
         const uint32_t i = c - s.chunk0;
         const uint32_t e = st[j] / R;
-        const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+        const uint32_t P = tile * kTile + j * kWave2 + lane;
         uint16_t v;
         if (i + 1 == s.nch) {
             v = (uint16_t)(kTerm | e);
@@ -374,10 +381,13 @@ __global__ __launch_bounds__(1024) void k_b2_match(B2Args a) {
         }
         const uint32_t tile = a.gtile[k] + (t - a.gtask[k]) * a.wpb + wave;
         if (tile < a.gtile[k + 1]) {
-            if (gr.layout == 1)
-                b2_tile<1>(a, d, k, tile, lane);
-            else
-                b2_tile<2>(a, d, k, tile, lane);
+            if (gr.layout == 1) {
+                if (a.slots == 2) b2_tile<1, 2>(a, d, k, tile, lane);
+                else b2_tile<1, 4>(a, d, k, tile, lane);
+            } else {
+                if (a.slots == 2) b2_tile<2, 2>(a, d, k, tile, lane);
+                else b2_tile<2, 4>(a, d, k, tile, lane);
+            }
         }
         __syncthreads();   // the table may be restaged by the next task
     }
@@ -473,6 +483,10 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
     Batch2Plan &P = *out;
     P = Batch2Plan();
     P.early_exit = (flags & DFA_MATCH_EARLY_EXIT) ? 1u : 0u;
+    // two pairs per lane (shorter tiles); DFA_SLOTS=4 forces four
+    const char *fs = std::getenv("DFA_SLOTS");
+    P.slots = fs && fs[0] == '4' ? 4u : 2u;
+    const uint32_t kTile = match2_tile_pairs(P.slots);
     if (count && (!dfas || !d_inputs || !lens)) return fail(DFA_E_INVAL, "batch plan: NULL argument");
     if (count > 0x7FFFFFFFull) return fail(DFA_E_TOOBIG, "batch plan: too many strings");
     const int lds = device_lds_bytes();
@@ -513,7 +527,7 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
     if (!chunk) {
         double work = 0.0;
         for (size_t i = 0; i < count; ++i) work += (double)lens[i] * mean_set(dfas[i]);
-        const double target_pairs = 64.0 * cus * 16.0 * kTile2;
+        const double target_pairs = 64.0 * cus * 16.0 * kTile;
         chunk = (uint64_t)std::max(1024.0, work / target_pairs);
         chunk = std::min<uint64_t>((chunk + 63) / 64 * 64, 1u << 20);
     }
@@ -586,17 +600,17 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
             P.max_levels = std::max(P.max_levels, L);
             compose_stage = std::max(compose_stage, (size_t)q.G * q.stride * 2);
             compose0_stage = std::max(compose0_stage, 4 * ((size_t)q.G + 1) +
-                                                          2 * ((size_t)q.G * setmax + kTile2));
+                                                          2 * ((size_t)q.G * setmax + kTile));
         }
         gr.chunk_hi = (uint32_t)chunk_str.size();
         groups.push_back(gr);
-        pairs_ub += kTile2;   // alignment of the group's first pair
+        pairs_ub += kTile;   // alignment of the group's first pair
     }
-    if (pairs_ub > 0xFFFFFFFFull - 2 * kTile2) return fail(DFA_E_TOOBIG, "batch plan: too many pairs");
+    if (pairs_ub > 0xFFFFFFFFull - 2 * kTile) return fail(DFA_E_TOOBIG, "batch plan: too many pairs");
     P.nchunks = (uint32_t)chunk_str.size();
     P.ngroups = (uint32_t)groups.size();
     P.nsegs = (uint32_t)segs.size();
-    const uint64_t tiles_ub = pairs_ub / kTile2 + groups.size() + 2;
+    const uint64_t tiles_ub = pairs_ub / kTile + groups.size() + 2;
 
     // composition items per level (level l -> l + 1, l = 0 .. max_levels - 1)
     std::vector<B2Item> items;
@@ -636,7 +650,7 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
     P.o_gtile = place(((size_t)groups.size() + 1) * 4);
     P.o_gtask = place(((size_t)groups.size() + 1) * 4);
     P.o_gend = place((size_t)groups.size() * 4);
-    P.o_maps0 = place((size_t)(pairs_ub + kTile2) * 2);
+    P.o_maps0 = place((size_t)(pairs_ub + kTile) * 2);
     P.o_maps = place((size_t)map_entries * 2);
     P.o_msize = place((size_t)size_entries * 2);
     P.o_codes = place((size_t)code_bytes + 2 * chunk + 16);
@@ -706,6 +720,8 @@ int launch_batch2(const Batch2Plan &P, void *dev_base, hipStream_t s, uint32_t *
     a.task_slot = P.task_slot;
     a.wpb = P.wpb;
     a.early_exit = P.early_exit;
+    a.slots = P.slots;
+    a.tile = match2_tile_pairs(P.slots);
     const B2Seg *segs = (const B2Seg *)(base + P.o_segs);
     const B2Item *items = (const B2Item *)(base + P.o_items);
 
@@ -715,7 +731,7 @@ int launch_batch2(const Batch2Plan &P, void *dev_base, hipStream_t s, uint32_t *
             hipLaunchKernelGGL(k_b2_translate, dim3(P.tblocks), dim3(256), 0, s, a, segs, P.nsegs);
         hipLaunchKernelGGL(k_b2_chunkinfo, dim3((P.nchunks + 255) / 256), dim3(256), 0, s, a);
         int rc = launch_size_scan(P.nchunks, a.msize0, (uint32_t *)(base + P.o_bsum), a.first_raw,
-                                  (uint32_t *)(base + P.o_tile_raw), s);
+                                  (uint32_t *)(base + P.o_tile_raw), a.tile, s);
         if (rc) return rc;
         hipLaunchKernelGGL(k_b2_groups, dim3(1), dim3(1024), 0, s, a);
         hipLaunchKernelGGL(k_b2_pairs, dim3((P.nchunks + 255) / 256), dim3(256), 0, s, a);

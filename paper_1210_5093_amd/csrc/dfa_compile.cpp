@@ -161,6 +161,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     uint32_t moff[kMaxMsetLevel + 1] = {0}, mst[kMaxMsetLevel + 1] = {0};
     uint32_t r0 = 0;
     double mset_mean_k[kMaxMsetLevel + 1] = {0.0};
+    uint32_t mset_max_k[kMaxMsetLevel + 1] = {0};
     {
         const uint32_t Kc = (uint32_t)class_sym.size();
         std::vector<uint32_t> prev_off, cur_off;
@@ -170,6 +171,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
             prev_st.assign(st[1].begin(), st[1].begin() + off[1][Kc]);
             r0 = 1;
             mset_mean_k[1] = (double)prev_st.size() / Kc;
+            mset_max_k[1] = setmax[1];
             moff[1] = 0;
             mst[1] = 0;
             mset_off = prev_off;
@@ -200,6 +202,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
                 }
                 if (over) break;
                 mset_mean_k[k] = cur_off.size() > 1 ? (double)cur_st.size() / (cur_off.size() - 1) : 0.0;
+                for (size_t q = 0; q + 1 < cur_off.size(); ++q)
+                    mset_max_k[k] = std::max<uint32_t>(mset_max_k[k], cur_off[q + 1] - cur_off[q]);
                 moff[k] = (uint32_t)mset_off.size();
                 mst[k] = (uint32_t)mset_st.size();
                 mset_off.insert(mset_off.end(), cur_off.begin(), cur_off.end());
@@ -314,7 +318,10 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     d->arena_bytes = arena_bytes;
     d->nsym = nsym;
     d->wave_util = wave_util;
-    for (uint32_t k = 0; k <= kMaxMsetLevel; ++k) d->mset_mean[k] = mset_mean_k[k];
+    for (uint32_t k = 0; k <= kMaxMsetLevel; ++k) {
+        d->mset_mean[k] = mset_mean_k[k];
+        d->mset_max[k] = mset_max_k[k];
+    }
     d->h_mset_off = mset_off;
     d->h_mset_st = mset_st;
     for (int b = 0; b < 256; ++b) d->h_byte_class[b] = (int16_t)byte_class[b];

@@ -77,6 +77,7 @@ struct dfa {
     uint32_t setmax_host[2] = {0, 0};
     double wave_util = 0.0;      // lane utilisation of one-chunk-per-wave matching (lookahead 1)
     double mset_mean[dfaspec::kMaxMsetLevel + 1] = {};   // mean precomputed set size per level
+    uint32_t mset_max[dfaspec::kMaxMsetLevel + 1] = {};  // largest precomputed set per level
     // host copies for dfa_lookahead_set
     std::vector<uint32_t> h_mset_off;
     std::vector<uint16_t> h_mset_st;
@@ -113,6 +114,7 @@ struct MatchPlan {
     // packed-pair matcher
     bool packed = false;
     bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
+    uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
     uint32_t blocks2 = 0;        // persistent grid
     uint32_t threads2 = 256;     // threads per block (more for large tables)
     uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)
@@ -147,9 +149,6 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
                   hipEvent_t ev_before_matcher);
-int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
-                    const uint16_t *msize0, uint16_t *out_maps, uint16_t *out_msize,
-                    hipStream_t s);
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                  const uint16_t *bv_up, uint16_t *bv0, hipStream_t s);
 int set_match2_lds_limit(int lds);
@@ -189,7 +188,7 @@ struct Batch2Plan {
     std::vector<uint32_t> items_per_level;
     std::vector<size_t> item_base;
     uint64_t chunk = 0;
-    uint32_t task_slot = 0, wpb = 4, blocks = 0, tblocks = 0, early_exit = 0;
+    uint32_t task_slot = 0, wpb = 4, blocks = 0, tblocks = 0, early_exit = 0, slots = 2;
     size_t lds_match = 0, lds_compose0 = 0, lds_compose = 0;
 };
 bool batch2_supported(const dfa_t *const *dfas, size_t count);
@@ -206,13 +205,14 @@ int launch_batch2(const Batch2Plan &p, void *dev_base, hipStream_t s, uint32_t *
 bool timing_begin(hipStream_t s, hipEvent_t ev[4]);
 int timing_end(hipStream_t s, hipEvent_t ev[4]);
 // Exclusive scan of msize[0..nch) (low 15 bits): first[i], first[nch] = total,
-// tile_first[w] = chunk holding pair w * match2_tile_pairs().  bsum holds
+// tile_first[w] = chunk holding pair w * tile.  bsum holds
 // match2_scan_blocks(nch) words.
 int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
-                     uint32_t *tile_first, hipStream_t s);
-uint32_t match2_tile_pairs();
+                     uint32_t *tile_first, uint32_t tile, hipStream_t s);
+uint32_t match2_tile_pairs(uint32_t slots);
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();
+size_t tree_lds_bytes(uint32_t G, uint32_t stride);   // LDS of k_compose_tree
 int device_cu_count();
 
 }  // namespace dfaspec

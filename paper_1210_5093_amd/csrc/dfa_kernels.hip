@@ -71,6 +71,68 @@ __global__ __launch_bounds__(256) void k_compose(const uint16_t *__restrict__ in
     if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m | (flag ? kFlagSymbol : 0));
 }
 
+// Compose groups of up to G consecutive maps (Eq. 9) by a log-depth tree in
+// LDS: in round k, the map of every member t with t % 2^(k+1) == 0 (covering
+// members t .. t + 2^k - 1) absorbs the map of member t + 2^k, entry by entry
+// and in place, all entries of the group in parallel.  After ceil(log2 G)
+// rounds member 0's map covers the whole group; its domain is the group's
+// first set.  Input maps are pair-indexed (`first` != null: member t's entries
+// start at first[t] - first[group start]) or strided (`stride_in` entries per
+// map, domain sizes in in_msize).  Output maps are strided.
+__global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restrict__ in_maps,
+                                                       const uint32_t *__restrict__ first,
+                                                       const uint16_t *__restrict__ in_msize,
+                                                       uint32_t n_in, uint32_t stride_in,
+                                                       uint32_t G, uint32_t emax,
+                                                       uint16_t *__restrict__ out_maps,
+                                                       uint32_t stride_out,
+                                                       uint16_t *__restrict__ out_msize) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t flag;
+    uint32_t *off = reinterpret_cast<uint32_t *>(smem);                      // [G + 1]
+    uint16_t *dom = reinterpret_cast<uint16_t *>(smem + 4 * (G + 1));        // [G]
+    uint16_t *owner = dom + ((G + 1) & ~1u);                                  // [emax]
+    uint16_t *sm = owner + emax;                                              // [emax]
+    const uint32_t g = blockIdx.x, T = blockDim.x;
+    const uint32_t c0 = g * G;
+    const uint32_t cnt = min(G, n_in - c0);
+    if (threadIdx.x == 0) flag = 0;
+    const uint64_t base = first ? (uint64_t)first[c0] : (uint64_t)c0 * stride_in;
+    for (uint32_t t = threadIdx.x; t <= cnt; t += T)
+        off[t] = first ? first[c0 + t] - (uint32_t)base : t * stride_in;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < cnt; t += T) {
+        const uint16_t ms = in_msize[c0 + t];
+        if (ms & kFlagSymbol) atomicOr(&flag, 1u);
+        dom[t] = first ? (uint16_t)(off[t + 1] - off[t]) : (uint16_t)(ms & 0x7FFFu);
+    }
+    const uint32_t E = off[cnt];
+    for (uint32_t e = threadIdx.x; e < E; e += T) {
+        sm[e] = in_maps[base + e];
+        owner[e] = 0xFFFFu;
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < cnt; t += T)
+        for (uint32_t e = off[t]; e < off[t] + dom[t]; ++e) owner[e] = (uint16_t)t;
+    __syncthreads();
+    for (uint32_t step = 1; step < cnt; step <<= 1) {
+        for (uint32_t e = threadIdx.x; e < E; e += T) {
+            const uint32_t t = owner[e];
+            if (t == 0xFFFFu || (t & (2 * step - 1)) != 0 || t + step >= cnt) continue;
+            uint32_t v = sm[e];
+            if (!(v & kTerm)) {
+                const uint32_t u = t + step;
+                v = v < dom[u] ? sm[off[u] + v] : kBadPos;
+                sm[e] = (uint16_t)v;
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t m0 = dom[0];
+    for (uint32_t p = threadIdx.x; p < m0; p += T) out_maps[(size_t)g * stride_out + p] = sm[p];
+    if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m0 | (flag ? kFlagSymbol : 0));
+}
+
 // Down-sweep: the value at the start of group g (bv_up[g], or position 0 at
 // the top) is pushed through the group's member maps; bv_l[i] receives the
 // value at the start of member i.
@@ -201,6 +263,7 @@ DevProps &props() {
                 if (allow_dynamic_lds(reinterpret_cast<const void *>(&k_match), p.lds) != DFA_OK)
                     p.lds = (int)pr.sharedMemPerBlock;
                 (void)allow_dynamic_lds(reinterpret_cast<const void *>(&k_compose), p.lds);
+                (void)allow_dynamic_lds(reinterpret_cast<const void *>(&k_compose_tree), p.lds);
                 (void)set_match2_lds_limit(p.lds);
             }
             p.cus = pr.multiProcessorCount;
@@ -210,6 +273,10 @@ DevProps &props() {
     return p;
 }
 }  // namespace
+
+size_t tree_lds_bytes(uint32_t G, uint32_t stride) {
+    return 4u * ((size_t)G + 1) + 2u * (((size_t)G + 1) & ~(size_t)1) + 4u * (size_t)G * stride + 16u;
+}
 
 int device_lds_bytes() { return props().lds; }
 int device_cu_count() { return props().cus; }
@@ -224,8 +291,13 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     p->r = lookahead;
     p->lookahead = lookahead <= 1 ? lookahead : (lookahead <= d->dev.r0 ? 3u : 2u);
     p->bitmap_words = (d->dev.nq + 31) / 32;
-    // sets with r >= 2 are subsets of the one-symbol sets (Lemma, Section 4.3)
-    const uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
+    // sets with r >= 2 are subsets of the one-symbol sets (Lemma, Section 4.3),
+    // and of the precomputed set of their last r' <= r0 symbols
+    uint32_t setmax = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
+    if (p->lookahead >= 2) {
+        const uint32_t k = std::min(p->r, d->dev.r0);
+        if (k >= 1 && d->mset_max[k] > 0) setmax = std::max<uint32_t>(d->mset_max[k], 1u);
+    }
     p->stride = (setmax + 7u) & ~7u;
     const int lds = device_lds_bytes();
     const int cus = std::max(device_cu_count(), 1);
@@ -252,6 +324,15 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                  (!(force && force[0] == '1') &&
                   ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
     if (p->packed) {
+        // two pairs per lane when the start sets are small (many chunks per
+        // tile: shorter tiles spread the chains over more wavefronts), four
+        // when they are large (more independent walks per wavefront);
+        // DFA_SLOTS=2 / =4 forces either
+        const double mean_set = std::max(1.0, p->lookahead == 0 ? (double)d->setmax_host[0]
+                                              : p->lookahead == 1 ? d->info.mean_iset
+                                              : d->mset_mean[std::min(p->r, d->dev.r0)]);
+        const char *fs = std::getenv("DFA_SLOTS");
+        p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 24.0 ? 2u : 4u);
         const uint32_t per_cu = std::max<uint32_t>(
             1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(d->dev.stab_bytes, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
@@ -265,7 +346,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                                               : p->lookahead == 1 ? d->info.mean_iset
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
             const double tiles = 6.0 * p->blocks2 * (p->threads2 / 64.0);
-            const double nch_target = tiles * match2_tile_pairs() / mean;
+            const double nch_target = tiles * match2_tile_pairs(p->slots) / mean;
             chunk = (uint64_t)((double)n / std::max(1.0, nch_target));
             chunk = (chunk + 63) / 64 * 64;
             chunk = std::max<uint64_t>(chunk, 256);
@@ -275,9 +356,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     const uint64_t nch = (n + chunk - 1) / chunk;
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
-    // compose fan-in: G maps of `stride` entries staged in LDS
+    // compose fan-in: G maps of `stride` entries (plus their owner indices)
+    // staged in LDS for the tree composition
     const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);
-    p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(64, stage / (2ull * p->stride)));
+    p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(1024, stage / (4ull * p->stride + 8)));
     uint64_t cnt = nch, moff = 0, soff = 0;
     uint32_t L = 0;
     p->level_count[0] = (uint32_t)cnt;
@@ -300,7 +382,8 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     p->msize_entries = soff;
     p->blocks = (uint32_t)std::min<uint64_t>((nch + p->waves_per_block - 1) / p->waves_per_block,
                                              0x7FFFFFFFull);
-    p->max_tiles = (nch * (uint64_t)setmax + match2_tile_pairs() - 1) / match2_tile_pairs() + 1;
+    p->max_tiles = (nch * (uint64_t)setmax + match2_tile_pairs(p->slots) - 1) /
+                       match2_tile_pairs(p->slots) + 1;
     if (p->packed && nch * (uint64_t)setmax >= 0xFFFFFFFFull)
         return fail(DFA_E_TOOBIG, "too many (chunk, state) pairs; raise chunk_len");
     return DFA_OK;
@@ -343,20 +426,17 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
                    uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
                    uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s) {
     hipError_t e;
+    const uint32_t emax = p.group * p.stride;
+    const size_t lds = tree_lds_bytes(p.group, p.stride);
     for (uint32_t l = 0; l < p.levels; ++l) {
-        if (l == 0 && pb) {
-            int rc = launch_compose0(p, maps, pb->first, msize, maps + p.level_off[1],
-                                     msize + p.msize_off[1], s);
-            if (rc) return rc;
-            continue;
-        }
-        const size_t lds = (size_t)p.group * p.stride * 2u;
-        hipLaunchKernelGGL(k_compose, dim3(p.level_count[l + 1]), dim3(256), lds, s,
-                           maps + p.level_off[l], msize + p.msize_off[l], p.level_count[l],
-                           p.stride, p.group, maps + p.level_off[l + 1],
+        // level 0 of the packed matcher is pair-indexed; every other level strided
+        const uint32_t *first = (l == 0 && pb) ? pb->first : nullptr;
+        hipLaunchKernelGGL(k_compose_tree, dim3(p.level_count[l + 1]), dim3(1024), lds, s,
+                           maps + p.level_off[l], first, msize + p.msize_off[l], p.level_count[l],
+                           p.stride, p.group, emax, maps + p.level_off[l + 1], p.stride,
                            msize + p.msize_off[l + 1]);
         e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "k_compose launch");
+        if (e != hipSuccess) return hip_fail(e, "k_compose_tree launch");
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d->dev, maps + p.level_off[p.levels],
                        msize + p.msize_off[p.levels], p.nch, d_result, d_boundaries);

@@ -24,6 +24,7 @@
 // The sparse maps it writes have the same form as the one-chunk-per-wave
 // matcher's, so the combination kernels are shared.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "dfa_pairs.h"
@@ -162,7 +163,7 @@ __global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t
 }
 
 // Exclusive scan of the set sizes in three phases: first[i] = sum_{k<i} m_k,
-// first[nch] = number of pairs, tile_first[w] = chunk holding pair w * kTile2.
+// first[nch] = number of pairs, tile_first[w] = chunk holding pair w * tile.
 // Sizes come from msize (SRC 0) or from the popcounts of the start-set
 // bitmaps (SRC 1: chunk 0 holds the start state; the sizes are also written to
 // msize and the sorted member lists to members[first[i] ..]).  Phase 2 folds
@@ -191,6 +192,7 @@ struct ScanSrc {
     const uint32_t *bits;    // SRC 1
     uint32_t W;
     uint32_t nch;
+    uint32_t tile;           // pairs per wave-tile
 };
 
 template <int SRC>
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(ScanSrc q, const uint32_t *
         if (i < q.nch) {
             first[i] = run;
             if (m[k]) {
-                for (uint32_t w = (run + kTile2 - 1) / kTile2; w <= (run + m[k] - 1) / kTile2; ++w)
+                for (uint32_t w = (run + q.tile - 1) / q.tile; w <= (run + m[k] - 1) / q.tile; ++w)
                     tile_first[w] = (uint32_t)i;
             }
             if constexpr (SRC == 1) {
@@ -323,8 +325,9 @@ __device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
 
 // Window pass: pair P of chunk c starts at the (P - first[c])-th state of
 // I_{sigma_1} and walks w[p - r' + 1, p); its end state joins chunk c's set.
-template <int L>
+template <int L, int S>
 __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
+    constexpr uint32_t kTile = kWave2 * S;
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
@@ -332,17 +335,17 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
     const uint32_t waves = blockDim.x / kWave2;
     const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
     const uint32_t total = a.first[a.nch];
-    const uint32_t ntiles = (total + kTile2 - 1) / kTile2;
+    const uint32_t ntiles = (total + kTile - 1) / kTile;
     const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
     const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
     for (uint32_t tile = wave_id; tile < ntiles; tile += gridDim.x * waves) {
         const uint32_t lo0 = a.tile_first[tile];
         const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
-        uint32_t st[kSlots2], ci[kSlots2], len[kSlots2];
-        uint64_t beg[kSlots2];
+        uint32_t st[S], ci[S], len[S];
+        uint64_t beg[S];
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
-            const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+        for (int j = 0; j < S; ++j) {
+            const uint32_t P = tile * kTile + j * kWave2 + lane;
             const bool valid = P < total;
             const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
             uint32_t s = 0;
@@ -358,14 +361,14 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
         }
         uint32_t maxlen = 0;
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) maxlen = max(maxlen, len[j]);
+        for (int j = 0; j < S; ++j) maxlen = max(maxlen, len[j]);
         for (uint32_t t = 0; t < maxlen; ++t) {
 #pragma unroll
-            for (int j = 0; j < kSlots2; ++j)
+            for (int j = 0; j < S; ++j)
                 if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[beg[j] + t]);
         }
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
+        for (int j = 0; j < S; ++j) {
             // walks of one chunk converge, and its pairs sit in adjacent lanes:
             // skip the atomic when the previous lane already set the same bit
             const uint32_t e = st[j] / R;
@@ -378,8 +381,12 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
     }
 }
 
-template <int L>
-__global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
+// S: slots (pairs) per lane; EXIT: early exit at absorbing states.  The
+// four-slot walk without exit is held to 64 VGPRs (8 waves per SIMD; a few
+// values spill once per tile, outside the walk).
+template <int L, int S, bool EXIT>
+__global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Match2Args a) {
+    constexpr uint32_t kTile = kWave2 * S;
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
     const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
     const uint32_t total_waves = gridDim.x * waves;
     const uint32_t total = a.first[a.nch];
-    const uint32_t ntiles = (total + kTile2 - 1) / kTile2;
+    const uint32_t ntiles = (total + kTile - 1) / kTile;
     const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
     const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
     // full chunks start on 16-byte boundaries iff the chunk length does
@@ -398,10 +405,10 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
     for (uint32_t tile = wave_id; tile < ntiles; tile += total_waves) {
         const uint32_t lo0 = a.tile_first[tile];
         const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
-        uint32_t st[kSlots2], ci[kSlots2], o16[kSlots2], len[kSlots2];
+        uint32_t st[S], ci[S], o16[S];
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
-            const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+        for (int j = 0; j < S; ++j) {
+            const uint32_t P = tile * kTile + j * kWave2 + lane;
             const bool valid = P < total;
             const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
             uint32_t s = 0;
@@ -420,21 +427,24 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
             o16[j] = aligned_chunks ? (uint32_t)((uint64_t)c * a.chunk / kPer16) : 0u;
-            // pairs past the end shadow chunk 0 from state 0 (loads stay in
-            // bounds; their end states are discarded)
-            len[j] = (uint32_t)min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk);
         }
         if (aligned_chunks) {
             uint32_t live = 0;
 #pragma unroll
-            for (int j = 0; j < kSlots2; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
-            walk_var<L>(reinterpret_cast<const uint4 *>(codes), o16, len, st, a.exit_base,
-                        a.exit_shift, live);
+            for (int j = 0; j < S; ++j) live |= (ci[j] != 0xFFFFFFFFu ? 1u : 0u) << j;
+            // pairs past the end shadow chunk 0 from state 0 (loads stay in
+            // bounds; their end states are discarded)
+            auto len_of = [&](int j) -> uint32_t {
+                const uint64_t c = ci[j] == 0xFFFFFFFFu ? 0u : ci[j];
+                return (uint32_t)min<uint64_t>(a.chunk, a.n - c * a.chunk);
+            };
+            walk_var<L, S, EXIT>(reinterpret_cast<const uint4 *>(codes), o16, len_of, st,
+                                  a.exit_base, a.exit_shift, live);
         } else {
             // general path: per-lane code loads, chunks of any length and alignment
             for (uint64_t t = 0; t < a.chunk; ++t) {
 #pragma unroll
-                for (int j = 0; j < kSlots2; ++j) {
+                for (int j = 0; j < S; ++j) {
                     if (ci[j] != 0xFFFFFFFFu) {
                         const uint64_t pos = (uint64_t)ci[j] * a.chunk + t;
                         if (pos < a.n) st[j] = lds_ld(st[j] + (uint32_t)codes[pos]);
@@ -443,11 +453,11 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
             }
         }
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
+        for (int j = 0; j < S; ++j) {
             if (ci[j] != 0xFFFFFFFFu) {
                 const uint32_t e = st[j] / R;
                 const uint32_t c = ci[j];
-                const uint32_t P = tile * kTile2 + j * kWave2 + lane;
+                const uint32_t P = tile * kTile + j * kWave2 + lane;
                 uint16_t v;
                 if (c + 1 == a.nch) {
                     v = (uint16_t)(kTerm | e);
@@ -473,40 +483,6 @@ __global__ __launch_bounds__(1024, 8) void k_match2(Match2Args a) {
     }
 }
 
-// Level-0 maps indexed by pair (chunk i's entries at first[i] ..) -> one
-// strided map per group of G chunks (Eq. 9), as k_compose does for strided
-// levels.
-__global__ __launch_bounds__(256) void k_compose0(const uint16_t *__restrict__ maps0,
-                                                  const uint32_t *__restrict__ first,
-                                                  const uint16_t *__restrict__ msize0,
-                                                  uint32_t nch, uint32_t stride, uint32_t G,
-                                                  uint16_t *__restrict__ out_maps,
-                                                  uint16_t *__restrict__ out_msize) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t flag;
-    const uint32_t g = blockIdx.x;
-    const uint32_t c0 = g * G;
-    const uint32_t cnt = min(G, nch - c0);
-    uint32_t *off = reinterpret_cast<uint32_t *>(smem);             // cnt + 1 offsets
-    uint16_t *sm = reinterpret_cast<uint16_t *>(smem + 4 * (G + 1));
-    if (threadIdx.x == 0) flag = 0;
-    const uint32_t base = first[c0];
-    for (uint32_t t = threadIdx.x; t <= cnt; t += blockDim.x) off[t] = first[c0 + t] - base;
-    __syncthreads();
-    if (threadIdx.x < cnt && (msize0[c0 + threadIdx.x] & kFlagSymbol)) atomicOr(&flag, 1u);
-    const uint32_t entries = off[cnt];
-    for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) sm[i] = maps0[base + i];
-    __syncthreads();
-    const uint32_t m = off[1];
-    for (uint32_t p = threadIdx.x; p < m; p += blockDim.x) {
-        uint32_t v = sm[p];
-        for (uint32_t t = 1; t < cnt && !(v & kTerm); ++t)
-            v = (v < off[t + 1] - off[t]) ? sm[off[t] + v] : kBadPos;
-        out_maps[(size_t)g * stride + p] = (uint16_t)v;
-    }
-    if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m | (flag ? kFlagSymbol : 0));
-}
-
 // Down-sweep into pair-indexed level-0 maps: bv0[i] = value at chunk i's start.
 __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__restrict__ first,
                         uint32_t nch, uint32_t G, const uint16_t *__restrict__ bv_up,
@@ -529,11 +505,34 @@ template <int SRC>
 void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint16_t *flag_msize,
                  uint32_t start, hipStream_t s) {
     const uint32_t nsb = (p.nch + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_sums<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum);
+    ScanSrc qq = q;
+    qq.tile = kWave2 * p.slots;
+    hipLaunchKernelGGL(k_scan_sums<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, qq, b.bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, b.bsum, nsb, flag_msize,
                        p.nch, b.block_bad, flag_msize ? p.tblocks : 0u, b.first);
-    hipLaunchKernelGGL(k_scan_apply<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum, b.first,
+    hipLaunchKernelGGL(k_scan_apply<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, qq, b.bsum, b.first,
                        b.tile_first, b.members, start);
+}
+}  // namespace
+
+namespace {
+const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
+    static const void *const tab[2][2][2] = {
+        {{reinterpret_cast<const void *>(&k_match2<1, 2, false>),
+          reinterpret_cast<const void *>(&k_match2<1, 2, true>)},
+         {reinterpret_cast<const void *>(&k_match2<1, 4, false>),
+          reinterpret_cast<const void *>(&k_match2<1, 4, true>)}},
+        {{reinterpret_cast<const void *>(&k_match2<2, 2, false>),
+          reinterpret_cast<const void *>(&k_match2<2, 2, true>)},
+         {reinterpret_cast<const void *>(&k_match2<2, 4, false>),
+          reinterpret_cast<const void *>(&k_match2<2, 4, true>)}}};
+    return tab[L == 1 ? 0 : 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
+}
+const void *window2_kernel(uint32_t L, uint32_t slots) {
+    static const void *const tab[2][2] = {
+        {reinterpret_cast<const void *>(&k_window2<1, 2>), reinterpret_cast<const void *>(&k_window2<1, 4>)},
+        {reinterpret_cast<const void *>(&k_window2<2, 2>), reinterpret_cast<const void *>(&k_window2<2, 4>)}};
+    return tab[L == 1 ? 0 : 1][slots >= 4 ? 1 : 0];
 }
 }  // namespace
 
@@ -567,16 +566,16 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.exit_base = p.early_exit ? d->dev.abs_off : 0u;
     a.exit_shift = d->dev.abs_shift;
     const size_t lds = d->dev.stab_bytes;
-    ScanSrc q{msize, b.bits, p.bitmap_words, p.nch};
+    ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
         hipLaunchKernelGGL(k_chunkinfo_w, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
                            p.chunk, p.nch, p.r, p.bitmap_words, msize, b.cset, b.bits);
         launch_scan<0>(p, q, b, nullptr, start, s);
-        if (L == 1)
-            hipLaunchKernelGGL(k_window2<1>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
-        else
-            hipLaunchKernelGGL(k_window2<2>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
+        const void *wf = window2_kernel(L, p.slots);
+        void *wargs[] = {&a};
+        hipError_t we = hipLaunchKernel(wf, dim3(p.blocks2), dim3(p.threads2), wargs, lds, s);
+        if (we != hipSuccess) return hip_fail(we, "k_window2 launch");
         launch_scan<1>(p, q, b, msize, start, s);
     } else if (p.lookahead == 3) {
         hipLaunchKernelGGL(k_chunkinfo_m, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
@@ -593,19 +592,19 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         e = hipEventRecord(ev_before_matcher, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    if (L == 1)
-        hipLaunchKernelGGL(k_match2<1>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_match2<2>, dim3(p.blocks2), dim3(p.threads2), lds, s, a);
+    const void *fn = match2_kernel(L, p.slots, p.early_exit);
+    void *args[] = {&a};
+    e = hipLaunchKernel(fn, dim3(p.blocks2), dim3(p.threads2), args, lds, s);
+    if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
     e = hipGetLastError();
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
 }
 
 int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
-                     uint32_t *tile_first, hipStream_t s) {
+                     uint32_t *tile_first, uint32_t tile, hipStream_t s) {
     if (nch == 0) return DFA_OK;
     const uint32_t nsb = (nch + kScanBlock - 1) / kScanBlock;
-    ScanSrc q{msize, nullptr, 0, nch};
+    ScanSrc q{msize, nullptr, 0, nch, tile};
     hipLaunchKernelGGL(k_scan_sums<0>, dim3(nsb), dim3(kScanThreads), 0, s, q, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, nsb,
                        (uint16_t *)nullptr, nch, (const uint32_t *)nullptr, 0u, first);
@@ -613,16 +612,6 @@ int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *fi
                        tile_first, (uint16_t *)nullptr, 0u);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? DFA_OK : hip_fail(e, "size scan launch");
-}
-
-int launch_compose0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
-                    const uint16_t *msize0, uint16_t *out_maps, uint16_t *out_msize,
-                    hipStream_t s) {
-    const size_t lds = 4u * (p.group + 1) + 2u * (size_t)p.group * p.stride;
-    hipLaunchKernelGGL(k_compose0, dim3(p.level_count[1]), dim3(256), lds, s, maps0, first, msize0,
-                       p.nch, p.stride, p.group, out_maps, out_msize);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_compose0 launch");
 }
 
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
@@ -635,19 +624,21 @@ int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *firs
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_down0 launch");
 }
 
+
 int set_match2_lds_limit(int lds) {
-    const void *fns[] = {reinterpret_cast<const void *>(&k_match2<1>),
-                         reinterpret_cast<const void *>(&k_match2<2>),
-                         reinterpret_cast<const void *>(&k_window2<1>),
-                         reinterpret_cast<const void *>(&k_window2<2>),
-                         reinterpret_cast<const void *>(&k_compose0)};
+    const void *fns[] = {match2_kernel(1, 2, false), match2_kernel(1, 2, true),
+                         match2_kernel(1, 4, false), match2_kernel(1, 4, true),
+                         match2_kernel(2, 2, false), match2_kernel(2, 2, true),
+                         match2_kernel(2, 4, false), match2_kernel(2, 4, true),
+                         window2_kernel(1, 2), window2_kernel(1, 4),
+                         window2_kernel(2, 2), window2_kernel(2, 4)};
     int rc = DFA_OK;
     for (const void *f : fns)
         if (allow_dynamic_lds(f, lds) != DFA_OK) rc = DFA_E_DEVICE;
     return rc;
 }
 
-uint32_t match2_tile_pairs() { return kTile2; }
+uint32_t match2_tile_pairs(uint32_t slots) { return kWave2 * slots; }
 uint32_t match2_scan_blocks(uint32_t nch) { return (nch + kScanBlock - 1) / kScanBlock; }
 
 }  // namespace dfaspec

@@ -9,8 +9,8 @@
 namespace dfaspec {
 
 constexpr int kWave2 = 64;
-constexpr int kSlots2 = 4;                 // pairs per lane per tile
-constexpr int kTile2 = kWave2 * kSlots2;   // pairs per wave-tile
+// A wave-tile holds 64 * S pairs: S slots (independent walks) per lane.  The
+// matchers are compiled for S = 2 and S = 4; the plan picks one.
 
 typedef __attribute__((address_space(3))) const uint16_t lds_u16_t;
 __device__ __forceinline__ uint32_t lds_ld(uint32_t addr) {
@@ -95,11 +95,12 @@ __device__ __forceinline__ uint32_t lds_ld32(uint32_t addr) {
 
 // True in every lane when every live slot of the wavefront sits in an
 // absorbing state (bit st >> shift of the LDS bitmap at byte `base`).
-__device__ __forceinline__ bool wave_absorbed(const uint32_t (&st)[kSlots2], uint32_t live,
+template <int S>
+__device__ __forceinline__ bool wave_absorbed(const uint32_t (&st)[S], uint32_t live,
                                               uint32_t base, uint32_t shift) {
     bool dead = true;
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) {
+    for (int j = 0; j < S; ++j) {
         if ((live >> j) & 1u) {
             const uint32_t idx = st[j] >> shift;
             const uint32_t w = lds_ld32(base + ((idx >> 5) << 2));
@@ -110,77 +111,91 @@ __device__ __forceinline__ bool wave_absorbed(const uint32_t (&st)[kSlots2], uin
 }
 
 // One step of every slot with code K of its dword.
-template <int L, int K>
-__device__ __forceinline__ void step_slots(uint32_t (&st)[kSlots2], const uint32_t (&w)[kSlots2]) {
+template <int L, int K, int S>
+__device__ __forceinline__ void step_slots(uint32_t (&st)[S], const uint32_t (&w)[S]) {
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) st[j] = add_sel<L, K>(st[j], w[j]);
+    for (int j = 0; j < S; ++j) st[j] = add_sel<L, K>(st[j], w[j]);
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) st[j] = lds_ld(st[j]);
+    for (int j = 0; j < S; ++j) st[j] = lds_ld(st[j]);
 }
 
-// With exit_base != 0 the walk stops early (every 4 blocks it checks) once
+// With EXIT the walk stops early (every 4 blocks it checks) once
 // every live slot of the wavefront is absorbing: the rest of the chunk cannot
 // change those states.
-template <int L>
+template <int L, int S, bool EXIT = false, int PF = 1>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
-                                          const uint32_t (&o16)[kSlots2], uint32_t blocks,
-                                          uint32_t (&st)[kSlots2], uint32_t exit_base = 0,
+                                          const uint32_t (&o16)[S], uint32_t blocks,
+                                          uint32_t (&st)[S], uint32_t exit_base = 0,
                                           uint32_t exit_shift = 0, uint32_t live = 0) {
-    uint4 cur[kSlots2], nxt[kSlots2];
+    // PF blocks of prefetch: cur is block b - 1, ahead[k] is block b - 1 + k + 1
+    uint4 cur[S], ahead[PF][S];
 #pragma unroll
-    for (int j = 0; j < kSlots2; ++j) cur[j] = codes16[o16[j]];
+    for (int j = 0; j < S; ++j) cur[j] = codes16[o16[j]];
+#pragma unroll
+    for (int k = 0; k + 1 < PF; ++k)
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if ((uint32_t)(k + 1) < blocks) ahead[k][j] = codes16[(size_t)o16[j] + k + 1];
     for (uint32_t b = 1; ; ++b) {
         const bool more = b < blocks;
-        if (more) {
+        const uint32_t far = b + PF - 1;
+        if (far < blocks) {
 #pragma unroll
-            for (int j = 0; j < kSlots2; ++j) nxt[j] = codes16[(size_t)o16[j] + b];
+            for (int j = 0; j < S; ++j) ahead[PF - 1][j] = codes16[(size_t)o16[j] + far];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            uint32_t w[kSlots2];
+            uint32_t w[S];
 #pragma unroll
-            for (int j = 0; j < kSlots2; ++j)
+            for (int j = 0; j < S; ++j)
                 w[j] = q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w;
             // round-robin over the slots, one code at a time, so that the
             // slots' independent chains keep several LDS loads in flight
-            step_slots<L, 0>(st, w);
-            step_slots<L, 1>(st, w);
+            step_slots<L, 0, S>(st, w);
+            step_slots<L, 1, S>(st, w);
             if constexpr (L == 1) {
-                step_slots<L, 2>(st, w);
-                step_slots<L, 3>(st, w);
+                step_slots<L, 2, S>(st, w);
+                step_slots<L, 3, S>(st, w);
             }
         }
         if (!more) break;
-        if (exit_base && (b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
+        if constexpr (EXIT)
+            if ((b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) cur[j] = nxt[j];
+        for (int j = 0; j < S; ++j) {
+            cur[j] = ahead[0][j];
+#pragma unroll
+            for (int k = 0; k + 1 < PF; ++k) ahead[k][j] = ahead[k + 1][j];
+        }
     }
 }
 
-// Walk pairs whose chunks may end inside a 16-byte block: len[j] codes from
-// 16-byte unit o16[j].  All slots first walk their common whole blocks on
-// the fast path; then each slot finishes its own remaining blocks, stepping
-// only over codes it owns (the last block is read whole: code streams are
-// padded to whole blocks).
-template <int L>
+// Walk pairs whose chunks may end inside a 16-byte block: slot j walks
+// len_of(j) codes from 16-byte unit o16[j].  All slots first walk their
+// common whole blocks on the fast path; then each slot finishes its own
+// remaining blocks, stepping only over codes it owns (the last block is read
+// whole: code streams are padded to whole blocks).  len_of recomputes a
+// slot's length, so no per-slot length stays live through the fast path.
+template <int L, int S, bool EXIT = false, typename LenFn>
 __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
-                                         const uint32_t (&o16)[kSlots2],
-                                         const uint32_t (&len)[kSlots2], uint32_t (&st)[kSlots2],
-                                         uint32_t exit_base = 0, uint32_t exit_shift = 0,
-                                         uint32_t live = 0) {
+                                         const uint32_t (&o16)[S], LenFn len_of,
+                                         uint32_t (&st)[S], uint32_t exit_base = 0,
+                                         uint32_t exit_shift = 0, uint32_t live = 0) {
     constexpr uint32_t kPer16 = L == 1 ? 16u : 8u;
-    uint32_t common = len[0] / kPer16, most = (len[0] + kPer16 - 1) / kPer16;
+    uint32_t common = 0xFFFFFFFFu, most = 0;
 #pragma unroll
-    for (int j = 1; j < kSlots2; ++j) {
-        common = min(common, len[j] / kPer16);
-        most = max(most, (len[j] + kPer16 - 1) / kPer16);
+    for (int j = 0; j < S; ++j) {
+        const uint32_t len = len_of(j);
+        common = min(common, len / kPer16);
+        most = max(most, (len + kPer16 - 1) / kPer16);
     }
-    if (common > 0) walk_fast<L>(codes16, o16, common, st, exit_base, exit_shift, live);
+    if (common > 0) walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live);
     for (uint32_t b = common; b < most; ++b) {
 #pragma unroll
-        for (int j = 0; j < kSlots2; ++j) {
-            if (b * kPer16 >= len[j]) continue;
-            const uint32_t cnt = min(kPer16, len[j] - b * kPer16);
+        for (int j = 0; j < S; ++j) {
+            const uint32_t len = len_of(j);
+            if (b * kPer16 >= len) continue;
+            const uint32_t cnt = min(kPer16, len - b * kPer16);
             const uint4 v = codes16[(size_t)o16[j] + b];
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll

@@ -88,9 +88,10 @@ struct dfa_server {
 namespace {
 
 uint64_t request_cost(const dfa_t *d, size_t len) {
-    // input bytes + map arena of the batch path at 1 KiB chunks (an upper bound)
+    // input bytes + two-byte codes + maps of the batch path at 1 KiB chunks
+    // (an upper bound)
     const uint64_t stride = (std::max<uint32_t>(d->setmax_host[1], 1u) + 7u) & ~7u;
-    return (uint64_t)len + ((uint64_t)len / 1024 + 2) * stride * 2 * 2;
+    return 3ull * len + 64 + ((uint64_t)len / 1024 + 2) * stride * 2 * 2;
 }
 
 void publish(dfa_server *srv, Slot &sl) {
@@ -124,19 +125,27 @@ int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *
         ins[k] = reqs[k].in;
         lens[k] = reqs[k].len;
     }
+    // the packed-pair batch when every DFA has a packed layout
+    const bool packed = batch2_supported(ds.data(), ds.size());
     BatchPlan plan;
-    int rc = plan_batch(ds.data(), ins.data(), lens.data(), reqs.size(), 0, &plan);
+    Batch2Plan plan2;
+    int rc = packed ? plan_batch2(ds.data(), ins.data(), lens.data(), reqs.size(), 0,
+                                  std::max<uint32_t>(srv->opts.lookahead, 1u), &plan2)
+                    : plan_batch(ds.data(), ins.data(), lens.data(), reqs.size(), 0, &plan);
     if (rc) return rc;
-    if (plan.total_bytes > sl.arena_bytes || plan.desc_bytes > sl.staging_bytes ||
+    const size_t total = packed ? plan2.total_bytes : plan.total_bytes;
+    const size_t desc_bytes = packed ? plan2.desc_bytes : plan.desc_bytes;
+    if (total > sl.arena_bytes || desc_bytes > sl.staging_bytes ||
         reqs.size() > srv->opts.max_batch) {
         *fits = false;
         return DFA_OK;
     }
-    std::memcpy(sl.staging, plan.desc.data(), plan.desc_bytes);
-    hipError_t e = hipMemcpyAsync(sl.arena, sl.staging, plan.desc_bytes, hipMemcpyHostToDevice,
+    std::memcpy(sl.staging, packed ? plan2.desc.data() : plan.desc.data(), desc_bytes);
+    hipError_t e = hipMemcpyAsync(sl.arena, sl.staging, desc_bytes, hipMemcpyHostToDevice,
                                   sl.stream);
     if (e != hipSuccess) return hip_fail(e, "server: descriptor upload");
-    rc = launch_batch(plan, sl.arena, sl.stream, sl.d_results);
+    rc = packed ? launch_batch2(plan2, sl.arena, sl.stream, sl.d_results)
+                : launch_batch(plan, sl.arena, sl.stream, sl.d_results);
     if (rc) return rc;
     e = hipMemcpyAsync(sl.h_results, sl.d_results, reqs.size() * sizeof(dfa_result_t),
                        hipMemcpyDeviceToHost, sl.stream);
@@ -238,7 +247,8 @@ extern "C" int dfa_server_create(const dfa_server_opts_t *opts, dfa_server_t **o
     if (!o.max_inflight) o.max_inflight = 4096;
     if (!o.streams) o.streams = 4;
     if (!o.max_batch) o.max_batch = 256;
-    if (!o.slot_bytes) o.slot_bytes = 256ull << 20;
+    if (!o.slot_bytes) o.slot_bytes = 1ull << 30;
+    if (o.lookahead > 64) return fail(DFA_E_INVAL, "dfa_server_create: lookahead above 64");
     srv->opts = o;
     hipError_t e = hipGetDevice(&srv->device);
     if (e != hipSuccess) return hip_fail(e, "dfa_server_create: hipGetDevice");

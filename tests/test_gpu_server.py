@@ -102,3 +102,46 @@ def test_poll_before_and_after(dfa_mod):
     fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
     assert r[:3] == (fin, acc, 0)
     srv.close()
+
+
+def test_served_multi_symbol_lookahead_and_first_generation_dfas(dfa_mod):
+    """Batches with lookahead 4 (packed pairs), and batches that hold a DFA
+    without a packed layout (one chunk per wavefront, lookahead 1)."""
+    import torch
+    from workloads import column_dfa
+    dfas, ds, reqs, inputs = served_setup(dfa_mod, 120, 1 << 20, seed=51)
+    expect = oracle_all(dfas, reqs, inputs)
+    srv = dfa_mod.Server(streams=2, max_batch=24, lookahead=4)
+    ids = [srv.register(d) for d in ds]
+    tickets = [srv.submit(ids[i], inputs[k][1]) for k, (i, _, _, _) in enumerate(reqs)]
+    got = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, (g, e) in enumerate(zip(got, expect)):
+        assert (g[0], g[1], g[2]) == (e[0], e[1], 0), k
+    # a 600-state, 64-class byte DFA has no packed layout (its LDS addresses
+    # exceed 16 bits); mixed into every batch it selects the first-generation path
+    wide = column_dfa(71, 72, 600, 64)
+    dw = dfa_mod.DFA.from_workload(wide)
+    assert dw.info().packed_layout == 0
+    xs = [configs.request_input("bytes", 7000 + k, 50_000 + 999 * k) for k in range(12)]
+    ins = [torch.from_numpy(x).to("cuda") for x in xs]
+    srv = dfa_mod.Server(streams=2, max_batch=8, lookahead=4)
+    iw = srv.register(dw)
+    i0 = reqs[0][0]
+    ib = srv.register(ds[i0])
+    tickets = []
+    for k, t in enumerate(ins):
+        tickets.append((srv.submit(iw, t), k, None))
+    same = [k for k, r in enumerate(reqs) if r[0] == i0][:6]
+    for k in same:
+        tickets.append((srv.submit(ib, inputs[k][1]), k, "pool"))
+    for t, k, which in tickets:
+        g = srv.wait(t)
+        if which is None:
+            fin, acc = oracle.membership(wide.delta, wide.byte_to_symbol, wide.q0,
+                                         wide.accepting, xs[k])
+        else:
+            fin, acc = expect[k]
+        assert (g[0], g[1], g[2]) == (fin, acc, 0), (k, which)
+    srv.close()
+    dw.close()

@@ -329,10 +329,14 @@ def bench_batched(args, dfa, torch, stream) -> int:
     count = len(wl)
 
     t0 = time.perf_counter()
-    chunk, look, tune_ms, ex = dfa.dfa_batch_tune(ds, ins, stream)
-    tune_wall = time.perf_counter() - t0
-    log(f"[bench] tuned chunk {chunk}, lookahead {look}, early exit {ex} ({tune_ms:.2f} ms/run, "
-        f"tuning took {tune_wall:.1f}s)")
+    if args.chunk > 0 and args.lookahead >= 1:
+        chunk, look, ex = args.chunk, args.lookahead, bool(args.early_exit)
+        chosen = "command line"
+    else:
+        chunk, look, tune_ms, ex = dfa.dfa_batch_tune(ds, ins, stream)
+        chosen = "autotuner (dfa_batch_tune, untimed)"
+        log(f"[bench] tuned chunk {chunk}, lookahead {look}, early exit {ex} ({tune_ms:.2f} "
+            f"ms/run, tuning took {time.perf_counter() - t0:.1f}s)")
     b = dfa.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
     _, ntasks = b.info() if hasattr(b, "info") else (chunk, 0)
     res = torch.empty((count, 4), dtype=torch.int32, device="cuda")
@@ -405,7 +409,8 @@ def bench_batched(args, dfa, torch, stream) -> int:
             "distinct_dfas": len(handles),
             "chunk_bytes": int(chunk),
             "lookahead": look,
-            "chunk_from": "autotuner (dfa_batch_tune)",
+            "early_exit": bool(ex),
+            "chosen_by": chosen,
             "lookups_per_byte": round(lookups / total, 3),
         },
         "roofline": {

@@ -279,9 +279,11 @@ typedef struct dfa_server_opts {
     uint32_t max_inflight;    /* in-flight requests (0 = 4096) */
     uint32_t streams;         /* concurrent batches (0 = 4) */
     uint32_t max_batch;       /* requests per batch (0 = 256) */
-    uint32_t lookahead;       /* reverse-lookahead symbols of the batches (0 = 1;
-                                 above 1 when every DFA of a batch has a packed
-                                 layout) */
+    uint32_t lookahead;       /* reverse-lookahead symbols of the batches (0 = 1).
+                                 Batches run on the packed-pair path when every
+                                 DFA has a packed layout and lookahead >= 2 or
+                                 the batch holds >= 256 MiB; otherwise one chunk
+                                 per wavefront (fewer launches) with lookahead 1 */
     uint64_t slot_bytes;      /* device arena per concurrent batch (0 = 1 GiB) */
 } dfa_server_opts_t;
 typedef struct dfa_server_stats {

@@ -38,6 +38,10 @@ struct Workspace {
     bool timing = false;
     struct Stamp { hipEvent_t begin, before_match, after_match, end; };
     std::vector<Stamp> stamps;    // one per timed call, read by dfa_timing_read
+    // second stream and events of the segmented translate/match pipeline
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_seg[kMaxSegments] = {};
 };
 
 namespace {
@@ -128,7 +132,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     if (p.packed && len) {
         need += a256(((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64);
         bad_off = need;
-        need += a256((uint64_t)p.tblocks * 4);
+        need += a256((uint64_t)p.tblocks * 4 * kMaxSegments);
         bsum_off = need;
         need += a256((uint64_t)match2_scan_blocks(p.nch) * 4 + 4);
         first_off = need;
@@ -174,6 +178,19 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         if (p.lookahead == 2) {
             pb.bits = (uint32_t *)(base + bits_off);
             pb.members = (uint16_t *)(base + mem_off);
+        }
+        if (p.segments > 1) {
+            if (!ws->aux) {
+                // non-blocking, default priority
+                e = hipStreamCreateWithFlags(&ws->aux, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming);
+                for (uint32_t k = 0; k < kMaxSegments && e == hipSuccess; ++k)
+                    e = hipEventCreateWithFlags(&ws->ev_seg[k], hipEventDisableTiming);
+                if (e != hipSuccess) return hip_fail(e, "pipeline stream");
+            }
+            pb.aux = ws->aux;
+            pb.ev_fork = ws->ev_fork;
+            for (uint32_t k = 0; k < kMaxSegments; ++k) pb.ev_seg[k] = ws->ev_seg[k];
         }
         rc = launch_match2(d, d_in, start, p, pb, maps, msize, s,
                            ws->timing ? st.before_match : nullptr);

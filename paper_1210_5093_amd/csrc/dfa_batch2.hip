@@ -355,7 +355,8 @@ __device__ __forceinline__ void b2_tile(const B2Args &a, const DevDFA &d, uint32
 
 // Persistent matcher: a task is up to a.wpb tiles of one group.  The
 // table sits at LDS address 0 (no static LDS in this kernel); the task word
-// is broadcast through LDS at a.task_slot.
+// is broadcast through LDS at a.task_slot.  S: pairs per lane.
+template <int S>
 __global__ __launch_bounds__(1024) void k_b2_match(B2Args a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t *s_task = reinterpret_cast<uint32_t *>(smem + a.task_slot);
@@ -381,13 +382,10 @@ __global__ __launch_bounds__(1024) void k_b2_match(B2Args a) {
         }
         const uint32_t tile = a.gtile[k] + (t - a.gtask[k]) * a.wpb + wave;
         if (tile < a.gtile[k + 1]) {
-            if (gr.layout == 1) {
-                if (a.slots == 2) b2_tile<1, 2>(a, d, k, tile, lane);
-                else b2_tile<1, 4>(a, d, k, tile, lane);
-            } else {
-                if (a.slots == 2) b2_tile<2, 2>(a, d, k, tile, lane);
-                else b2_tile<2, 4>(a, d, k, tile, lane);
-            }
+            if (gr.layout == 1)
+                b2_tile<1, S>(a, d, k, tile, lane);
+            else
+                b2_tile<2, S>(a, d, k, tile, lane);
         }
         __syncthreads();   // the table may be restaged by the next task
     }
@@ -678,7 +676,8 @@ int plan_batch2(const dfa_t *const *dfas, const uint8_t *const *d_inputs, const 
     P.blocks = (uint32_t)cus * per_cu;
     P.tblocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(P.nsegs, 1), (uint64_t)cus * 8);
     if (!g_b2_attr_set) {
-        if (allow_dynamic_lds(reinterpret_cast<const void *>(&k_b2_match), lds) != DFA_OK ||
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&k_b2_match<2>), lds) != DFA_OK ||
+            allow_dynamic_lds(reinterpret_cast<const void *>(&k_b2_match<4>), lds) != DFA_OK ||
             allow_dynamic_lds(reinterpret_cast<const void *>(&k_b2_compose0), lds) != DFA_OK ||
             allow_dynamic_lds(reinterpret_cast<const void *>(&k_b2_compose), lds) != DFA_OK)
             return fail(DFA_E_DEVICE, "batch plan: cannot enable the device's LDS size");
@@ -736,7 +735,10 @@ int launch_batch2(const Batch2Plan &P, void *dev_base, hipStream_t s, uint32_t *
         hipLaunchKernelGGL(k_b2_groups, dim3(1), dim3(1024), 0, s, a);
         hipLaunchKernelGGL(k_b2_pairs, dim3((P.nchunks + 255) / 256), dim3(256), 0, s, a);
         if (ev_before_match) (void)hipEventRecord(ev_before_match, s);
-        hipLaunchKernelGGL(k_b2_match, dim3(P.blocks), dim3(P.wpb * kWave2), P.lds_match, s, a);
+        if (P.slots == 2)
+            hipLaunchKernelGGL(k_b2_match<2>, dim3(P.blocks), dim3(P.wpb * kWave2), P.lds_match, s, a);
+        else
+            hipLaunchKernelGGL(k_b2_match<4>, dim3(P.blocks), dim3(P.wpb * kWave2), P.lds_match, s, a);
         if (ev_after_match) (void)hipEventRecord(ev_after_match, s);
         for (uint32_t l = 0; l < P.max_levels; ++l) {
             if (!P.items_per_level[l]) continue;

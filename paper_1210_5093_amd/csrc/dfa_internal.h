@@ -24,6 +24,7 @@ constexpr uint32_t kLutInvalid = 0xFFFFFFFFu;
 constexpr uint32_t kMaxStates = 32767;
 constexpr uint32_t kMaxMsetLevel = 8;   // precomputed multi-symbol sets up to this r
 constexpr uint16_t kCodeInvalid = 0xFFFF;
+constexpr uint32_t kMaxSegments = 4;      // translate/match pipeline segments
 
 // Device-resident compiled DFA, passed by value to kernels.
 struct DevDFA {
@@ -115,6 +116,7 @@ struct MatchPlan {
     bool packed = false;
     bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
+    uint32_t segments = 1;       // translate/match pipeline segments (1 .. kMaxSegments)
     uint32_t blocks2 = 0;        // persistent grid
     uint32_t threads2 = 256;     // threads per block (more for large tables)
     uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)
@@ -138,6 +140,11 @@ struct PackedBufs {
     uint32_t *cset = nullptr;        // precomputed-set id per chunk (r >= 2)
     uint32_t *bits = nullptr;        // r >= 2: start-set bitmaps
     uint16_t *members = nullptr;     // r >= 2: sorted start sets, indexed by pair
+    // segmented pipeline (MatchPlan::segments > 1): translation runs on `aux`,
+    // segment by segment, while the matcher works on the previous segment
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_seg[kMaxSegments] = {};
 };
 // The packed path stores level-0 maps indexed by pair (maps[first[i] + p]);
 // pb is null for the one-chunk-per-wave path (maps[i * stride + p]).

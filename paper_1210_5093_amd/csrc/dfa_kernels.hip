@@ -324,15 +324,15 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                  (!(force && force[0] == '1') &&
                   ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
     if (p->packed) {
-        // two pairs per lane when the start sets are small (many chunks per
+        // two pairs per lane when the start sets are tiny (many chunks per
         // tile: shorter tiles spread the chains over more wavefronts), four
-        // when they are large (more independent walks per wavefront);
+        // otherwise (more independent walks per wavefront);
         // DFA_SLOTS=2 / =4 forces either
         const double mean_set = std::max(1.0, p->lookahead == 0 ? (double)d->setmax_host[0]
                                               : p->lookahead == 1 ? d->info.mean_iset
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
         const char *fs = std::getenv("DFA_SLOTS");
-        p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 24.0 ? 2u : 4u);
+        p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 8.0 ? 2u : 4u);
         const uint32_t per_cu = std::max<uint32_t>(
             1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(d->dev.stab_bytes, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
@@ -354,6 +354,20 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     }
     p->chunk = chunk;
     const uint64_t nch = (n + chunk - 1) / chunk;
+    // Optional pipeline: translate segment k + 1 (on a second stream) while
+    // the matcher walks segment k.  Off by default: on MI355X the matcher
+    // loses more from the smaller per-launch tile count than the overlap
+    // gains (protein-style input, 5-symbol lookahead: 836 -> 662 GB/s with two
+    // segments).  DFA_SEGMENTS=2..4 turns it on.  The window pass (lookahead
+    // beyond the precomputed sets) reads codes before every chunk, so it keeps
+    // one segment; segment starts must be whole 16-code blocks (chunk
+    // lengths of 64k).
+    const bool can_split = p->packed && p->lookahead != 2 && chunk % 64 == 0;
+    if (const char *fs = std::getenv("DFA_SEGMENTS")) {
+        const int v = std::atoi(fs);
+        if (v >= 1 && v <= (int)kMaxSegments && can_split && nch >= (uint64_t)v)
+            p->segments = (uint32_t)v;
+    }
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
     // compose fan-in: G maps of `stride` entries (plus their owner indices)

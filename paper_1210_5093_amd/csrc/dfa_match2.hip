@@ -313,6 +313,7 @@ struct Match2Args {
     uint16_t *maps;          // level-0 maps, indexed by pair
     uint32_t exit_base;      // early exit: LDS byte offset of the absorbing bitmap (0 = off)
     uint32_t exit_shift;
+    uint32_t c_lo, c_hi;     // this launch walks the pairs of chunks [c_lo, c_hi)
 };
 
 template <int L>
@@ -397,19 +398,22 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     const uint32_t total_waves = gridDim.x * waves;
     const uint32_t total = a.first[a.nch];
     const uint32_t ntiles = (total + kTile - 1) / kTile;
+    // pairs of chunks [c_lo, c_hi): the tiles that overlap them
+    const uint32_t p_lo = a.first[a.c_lo], p_hi = a.first[a.c_hi];
+    const uint32_t t_lo = p_lo / kTile, t_hi = (p_hi + kTile - 1) / kTile;
     const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
     const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
     // full chunks start on 16-byte boundaries iff the chunk length does
     const bool aligned_chunks = (a.chunk % kPer16) == 0;
 
-    for (uint32_t tile = wave_id; tile < ntiles; tile += total_waves) {
+    for (uint32_t tile = t_lo + wave_id; tile < t_hi; tile += total_waves) {
         const uint32_t lo0 = a.tile_first[tile];
         const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
         uint32_t st[S], ci[S], o16[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const uint32_t P = tile * kTile + j * kWave2 + lane;
-            const bool valid = P < total;
+            const bool valid = P >= p_lo && P < p_hi;
             const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
             uint32_t s = 0;
             if (valid) {
@@ -483,6 +487,20 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     }
 }
 
+// Translation flags of a segmented run -> the symbol flag of chunk 0's size
+// (from where the composition carries it up).
+__global__ void k_fold_bad(const uint32_t *__restrict__ block_bad, uint32_t nbad,
+                           uint16_t *__restrict__ msize) {
+    __shared__ uint32_t any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t b = threadIdx.x; b < nbad; b += blockDim.x) bad |= block_bad[b];
+    if (bad) atomicOr(&any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0 && any) msize[0] = (uint16_t)(msize[0] | kFlagSymbol);
+}
+
 // Down-sweep into pair-indexed level-0 maps: bv0[i] = value at chunk i's start.
 __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__restrict__ first,
                         uint32_t nch, uint32_t G, const uint16_t *__restrict__ bv_up,
@@ -540,12 +558,32 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
                   hipEvent_t ev_before_matcher) {
     const uint32_t L = d->dev.layout;
-    if (L == 1)
-        hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
-                           d->dev.code, (uint8_t *)b.codes, b.block_bad);
-    else
-        hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
-                           d->dev.code, (uint16_t *)b.codes, b.block_bad);
+    const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
+    uint32_t cb[kMaxSegments + 1];
+    for (uint32_t k = 0; k <= nseg; ++k) cb[k] = (uint32_t)((uint64_t)p.nch * k / nseg);
+    hipStream_t ts = s;
+    if (nseg > 1) {
+        if (!b.aux || !b.ev_fork) return fail(DFA_E_DEVICE, "segmented match without an aux stream");
+        hipError_t fe = hipEventRecord(b.ev_fork, s);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
+        if (fe != hipSuccess) return hip_fail(fe, "fork to the translation stream");
+        ts = b.aux;
+    }
+    for (uint32_t k = 0; k < nseg; ++k) {
+        const uint64_t off = (uint64_t)cb[k] * p.chunk;
+        const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
+        uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
+        if (L == 1)
+            hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
+                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad);
+        else
+            hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
+                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad);
+        if (nseg > 1) {
+            hipError_t fe = hipEventRecord(b.ev_seg[k], ts);
+            if (fe != hipSuccess) return hip_fail(fe, "hipEventRecord (segment)");
+        }
+    }
     Match2Args a;
     a.d = d->dev;
     a.codes = b.codes;
@@ -565,6 +603,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.maps = maps;
     a.exit_base = p.early_exit ? d->dev.abs_off : 0u;
     a.exit_shift = d->dev.abs_shift;
+    a.c_lo = 0;
+    a.c_hi = p.nch;
     const size_t lds = d->dev.stab_bytes;
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     if (p.lookahead == 2) {
@@ -580,22 +620,32 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     } else if (p.lookahead == 3) {
         hipLaunchKernelGGL(k_chunkinfo_m, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
                            p.chunk, p.nch, p.r, msize, b.cset);
-        launch_scan<0>(p, q, b, msize, start, s);
+        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s);
     } else {
         hipLaunchKernelGGL(k_chunkinfo, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
                            p.chunk, p.nch, p.lookahead, msize, b.ccls);
-        launch_scan<0>(p, q, b, msize, start, s);
+        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
-    if (ev_before_matcher) {
-        e = hipEventRecord(ev_before_matcher, s);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    }
     const void *fn = match2_kernel(L, p.slots, p.early_exit);
-    void *args[] = {&a};
-    e = hipLaunchKernel(fn, dim3(p.blocks2), dim3(p.threads2), args, lds, s);
-    if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
+    for (uint32_t k = 0; k < nseg; ++k) {
+        if (nseg > 1) {
+            e = hipStreamWaitEvent(s, b.ev_seg[k], 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent (segment)");
+        }
+        if (k == 0 && ev_before_matcher) {
+            e = hipEventRecord(ev_before_matcher, s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        a.c_lo = cb[k];
+        a.c_hi = cb[k + 1];
+        void *args[] = {&a};
+        e = hipLaunchKernel(fn, dim3(p.blocks2), dim3(p.threads2), args, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
+    }
+    if (nseg > 1)
+        hipLaunchKernelGGL(k_fold_bad, dim3(1), dim3(256), 0, s, b.block_bad, nseg * p.tblocks, msize);
     e = hipGetLastError();
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
 }

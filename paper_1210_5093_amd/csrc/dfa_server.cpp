@@ -125,8 +125,14 @@ int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *
         ins[k] = reqs[k].in;
         lens[k] = reqs[k].len;
     }
-    // the packed-pair batch when every DFA has a packed layout
-    const bool packed = batch2_supported(ds.data(), ds.size());
+    // the packed-pair batch when every DFA has a packed layout and either
+    // multi-symbol lookahead is asked for or the batch is large; small
+    // batches take the one-chunk-per-wavefront batch, which needs fewer
+    // launches (lower latency)
+    uint64_t batch_bytes = 0;
+    for (size_t k = 0; k < reqs.size(); ++k) batch_bytes += reqs[k].len;
+    const bool packed = batch2_supported(ds.data(), ds.size()) &&
+                        (srv->opts.lookahead >= 2 || batch_bytes >= (256ull << 20));
     BatchPlan plan;
     Batch2Plan plan2;
     int rc = packed ? plan_batch2(ds.data(), ins.data(), lens.data(), reqs.size(), 0,

@@ -510,3 +510,76 @@ def test_early_exit_ragged_and_invalid(dfa_mod):
         torch.cuda.synchronize()
         assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
     d.close()
+
+
+# ---------------------------------------------------------------------------
+# Tree composition: chunk counts around the group size (up to 1024 maps per
+# group) and its powers, for one- and five-symbol lookahead.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nch", [1, 2, 3, 1023, 1024, 1025, 2047, 2049, 1024 * 1024 + 3])
+@pytest.mark.parametrize("look", [1, 5])
+def test_compose_tree_group_edges(dfa_mod, nch, look):
+    import torch
+    w = configs.c2_dfa()
+    C = 256
+    n = nch * C - (C // 2 if nch % 2 else 0)     # odd counts end with a ragged chunk
+    x = configs.c2_input(n, seed=nch % 977)
+    step = max(C, (n // 64) // C * C)
+    probes = list(range(0, n + 1, step))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    d = dfa_mod.DFA.from_workload(w)
+    res, bnd = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=C,
+                                    lookahead=look, boundaries=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res) == (fin, acc, 0, (n + C - 1) // C)
+    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(b[np.array(probes) // C], ps.astype(np.int64))
+    d.close()
+
+
+# ---------------------------------------------------------------------------
+# Segmented pipeline: translation of segment k + 1 on a second stream while
+# the matcher walks segment k.  Forced segment counts, boundary states, and a
+# byte outside Sigma in the last segment (its flag is folded after the walk).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("segs", [2, 3, 4])
+@pytest.mark.parametrize("look", [1, 4])
+def test_segmented_pipeline(dfa_mod, monkeypatch, segs, look):
+    import torch
+    monkeypatch.setenv("DFA_SEGMENTS", str(segs))
+    w = configs.c2_dfa()
+    C = 1024
+    n = 9 * (1 << 20) + 333
+    x = configs.c2_input(n, seed=segs * 10 + look).copy()
+    probes = list(range(0, n + 1, 64 * C))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = torch.from_numpy(x).to("cuda")
+    res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=C, lookahead=look, boundaries=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
+    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(b[np.array(probes) // C], ps.astype(np.int64))
+    x[n - 100] = ord("#")
+    res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=C, lookahead=look)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()
+
+
+def test_segmented_pipeline_large(dfa_mod, monkeypatch):
+    """Two segments on a 96 MiB input with the planner's chunk length."""
+    import torch
+    monkeypatch.setenv("DFA_SEGMENTS", "2")
+    w = configs.c2_dfa()
+    n = 96 << 20
+    x = configs.c2_input(n, seed=77)
+    fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = torch.from_numpy(x).to("cuda")
+    for look in (1, 5):
+        res, _ = dfa_mod.dfa_match_ex(d, dev, lookahead=look)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), look
+    d.close()

@@ -46,7 +46,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 # Sources whose change invalidates stored counter readings of the matcher.
-KERNEL_SOURCES = ["dfa_match2.hip", "dfa_kernels.hip", "dfa_internal.h", "dfa_walk1.h"]
+KERNEL_SOURCES = ["dfa_match2.hip", "dfa_kernels.hip", "dfa_internal.h", "dfa_walk1.h",
+                  "dfa_pairs.h"]
 
 
 def kernel_source_digest() -> str:

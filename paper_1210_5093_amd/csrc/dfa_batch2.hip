@@ -128,15 +128,10 @@ __global__ __launch_bounds__(256) void k_b2_translate(B2Args a, const B2Seg *__r
             const uint64_t pos = seg.beg + off;
             const uint32_t cnt = (uint32_t)min<uint64_t>(16, seg.len - off);
             uint8_t b[16];
-            if (cnt == 16 && ((reinterpret_cast<uintptr_t>(st.in + pos) & 15) == 0)) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(st.in + pos);
-                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            uint32_t w[4];
+            load16(st.in, pos, st.n, w);   // pos < seg.beg + seg.len <= n
 #pragma unroll
-                for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-            } else {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) b[k] = (uint32_t)k < cnt ? st.in[pos + k] : 0;
-            }
+            for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
             uint16_t c[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {

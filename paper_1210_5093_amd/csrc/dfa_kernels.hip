@@ -74,11 +74,13 @@ __global__ __launch_bounds__(256) void k_compose(const uint16_t *__restrict__ in
 // Compose groups of up to G consecutive maps (Eq. 9) by a log-depth tree in
 // LDS: in round k, the map of every member t with t % 2^(k+1) == 0 (covering
 // members t .. t + 2^k - 1) absorbs the map of member t + 2^k, entry by entry
-// and in place, all entries of the group in parallel.  After ceil(log2 G)
-// rounds member 0's map covers the whole group; its domain is the group's
-// first set.  Input maps are pair-indexed (`first` != null: member t's entries
-// start at first[t] - first[group start]) or strided (`stride_in` entries per
-// map, domain sizes in in_msize).  Output maps are strided.
+// and in place.  Round k touches only the entries of its active maps, so the
+// whole tree costs about one pass over the group's entries.  After
+// ceil(log2 G) rounds member 0's map covers the whole group; its domain is
+// the group's first set.  Input maps are pair-indexed (`first` != null: member
+// t's entries start at first[t] - first[group start]) or strided (`stride_in`
+// entries per map, domain sizes in in_msize); every domain holds at most
+// stride_in entries.  Output maps are strided.
 __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restrict__ in_maps,
                                                        const uint32_t *__restrict__ first,
                                                        const uint16_t *__restrict__ in_msize,
@@ -91,11 +93,12 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
     __shared__ uint32_t flag;
     uint32_t *off = reinterpret_cast<uint32_t *>(smem);                      // [G + 1]
     uint16_t *dom = reinterpret_cast<uint16_t *>(smem + 4 * (G + 1));        // [G]
-    uint16_t *owner = dom + ((G + 1) & ~1u);                                  // [emax]
-    uint16_t *sm = owner + emax;                                              // [emax]
+    uint16_t *sm = dom + ((G + 1) & ~1u);                                     // [emax]
     const uint32_t g = blockIdx.x, T = blockDim.x;
     const uint32_t c0 = g * G;
     const uint32_t cnt = min(G, n_in - c0);
+    const uint32_t W = stride_in;
+    const float invW = 1.0f / (float)W;
     if (threadIdx.x == 0) flag = 0;
     const uint64_t base = first ? (uint64_t)first[c0] : (uint64_t)c0 * stride_in;
     for (uint32_t t = threadIdx.x; t <= cnt; t += T)
@@ -107,18 +110,19 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
         dom[t] = first ? (uint16_t)(off[t + 1] - off[t]) : (uint16_t)(ms & 0x7FFFu);
     }
     const uint32_t E = off[cnt];
-    for (uint32_t e = threadIdx.x; e < E; e += T) {
-        sm[e] = in_maps[base + e];
-        owner[e] = 0xFFFFu;
-    }
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < cnt; t += T)
-        for (uint32_t e = off[t]; e < off[t] + dom[t]; ++e) owner[e] = (uint16_t)t;
+    for (uint32_t e = threadIdx.x; e < E; e += T) sm[e] = in_maps[base + e];
     __syncthreads();
     for (uint32_t step = 1; step < cnt; step <<= 1) {
-        for (uint32_t e = threadIdx.x; e < E; e += T) {
-            const uint32_t t = owner[e];
-            if (t == 0xFFFFu || (t & (2 * step - 1)) != 0 || t + step >= cnt) continue;
+        const uint32_t na = (cnt - step + 2 * step - 1) / (2 * step);   // maps with t + step < cnt
+        const uint32_t items = na * W;
+        for (uint32_t x = threadIdx.x; x < items; x += T) {
+            uint32_t i = (uint32_t)((float)x * invW);   // x / W, corrected below
+            if (i * W > x) --i;
+            else if ((i + 1) * W <= x) ++i;
+            const uint32_t j = x - i * W;
+            const uint32_t t = i * 2 * step;
+            if (j >= dom[t]) continue;
+            const uint32_t e = off[t] + j;
             uint32_t v = sm[e];
             if (!(v & kTerm)) {
                 const uint32_t u = t + step;
@@ -275,7 +279,7 @@ DevProps &props() {
 }  // namespace
 
 size_t tree_lds_bytes(uint32_t G, uint32_t stride) {
-    return 4u * ((size_t)G + 1) + 2u * (((size_t)G + 1) & ~(size_t)1) + 4u * (size_t)G * stride + 16u;
+    return 4u * ((size_t)G + 1) + 2u * (((size_t)G + 1) & ~(size_t)1) + 2u * (size_t)G * stride + 16u;
 }
 
 int device_lds_bytes() { return props().lds; }
@@ -370,10 +374,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     }
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
-    // compose fan-in: G maps of `stride` entries (plus their owner indices)
-    // staged in LDS for the tree composition
+    // compose fan-in: G maps of `stride` entries staged in LDS for the tree
+    // composition
     const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);
-    p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(1024, stage / (4ull * p->stride + 8)));
+    p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(1024, stage / (2ull * p->stride + 8)));
     uint64_t cnt = nch, moff = 0, soff = 0;
     uint32_t L = 0;
     p->level_count[0] = (uint32_t)cnt;

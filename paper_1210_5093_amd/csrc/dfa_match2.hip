@@ -50,16 +50,10 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
     for (uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; first < n;
          first += (uint64_t)gridDim.x * blockDim.x * 16) {
         uint8_t b[16];
-        const bool aligned = ((reinterpret_cast<uintptr_t>(in) & 15) == 0) && first + 16 <= n;
-        if (aligned) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(in + first);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        uint32_t w[4];
+        load16(in, first, n, w);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-        } else {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) b[k] = first + k < n ? in[first + k] : 0;
-        }
+        for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
         uint16_t c[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {

@@ -88,6 +88,50 @@ __device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ mem
 // Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
 // 16-byte-aligned chunk (o16 = its first code's offset in 16-byte units),
 // read as uint4 blocks with one block of prefetch.
+// The 16 input bytes at in[pos ..] (zero at and past n), read as whole
+// aligned words: one 16-byte load when in + pos is 16-byte aligned, two
+// loads and a byte funnel shift when it is not (then only while the second
+// word lies inside the input), single bytes at the very end.  pos is a
+// multiple of 16, so the misalignment is the same for every block of a
+// string.
+__device__ __forceinline__ void load16(const uint8_t *__restrict__ in, uint64_t pos, uint64_t n,
+                                       uint32_t (&o)[4]) {
+    const uint8_t *p = in + pos;
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(p) & 15u);
+    if (sh == 0 && pos + 16 <= n) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    } else if (pos + 32 <= n) {
+        const uint4 v0 = *reinterpret_cast<const uint4 *>(p - sh);
+        const uint4 v1 = *reinterpret_cast<const uint4 *>(p - sh + 16);
+        const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        const uint32_t r = sh & 3u;
+        switch (sh >> 2) {
+#define DFA_SEL(D)                                                                   \
+    case D:                                                                          \
+        for (int q = 0; q < 4; ++q) o[q] = __builtin_amdgcn_alignbyte(w[q + D + 1], w[q + D], r); \
+        break;
+            DFA_SEL(0)
+            DFA_SEL(1)
+            DFA_SEL(2)
+            default:
+            DFA_SEL(3)
+#undef DFA_SEL
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t i = pos + 4 * q + k;
+                v |= (i < n ? (uint32_t)in[i] : 0u) << (8 * k);
+            }
+            o[q] = v;
+        }
+    }
+}
+
 typedef __attribute__((address_space(3))) const uint32_t lds_u32_t;
 __device__ __forceinline__ uint32_t lds_ld32(uint32_t addr) {
     return *(lds_u32_t *)(size_t)addr;

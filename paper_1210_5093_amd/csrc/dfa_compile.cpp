@@ -16,6 +16,7 @@
 //    maps characters to symbol indices (Section 5, the IBase array); the
 //    class compression is this library's addition, so the table fits LDS.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -222,10 +223,41 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     // class offset inside a state row; rows are an odd number of dwords so
     // that distinct states of one column fall into distinct LDS banks.
     // Layout 2 (class-major, 16-bit codes) serves alphabets with more classes.
-    uint32_t layout = 0, rowbytes = 0;
+    // The direct variant indexes rows by the byte itself when every byte of
+    // Sigma is below 128 (code = 2 * byte fits one byte), so that the matcher
+    // can read the raw input.  Rows of R bytes overlap outside [lo, hi], the
+    // bytes of Sigma; the image spans R * (nq - 1) + 256 bytes, so that every
+    // address R * s + c (c even, c <= 254) lies inside it, and every word of it
+    // that is not a table entry holds 0 (state 0's offset).
+    uint32_t layout = 0, rowbytes = 0, direct = 0;
     std::vector<uint16_t> stab;
     std::vector<uint16_t> code(256, kCodeInvalid);
-    {
+    int lo = -1, hi = -1;
+    for (int b = 0; b < 256; ++b)
+        if (byte_class[b] >= 0) { if (lo < 0) lo = b; hi = b; }
+    const char *no_direct = std::getenv("DFA_DIRECT");   // "0": class rows only (diagnostic)
+    if (lo >= 0 && hi < 128 && !(no_direct && no_direct[0] == '0')) {
+        const uint32_t W = (uint32_t)(hi - lo + 1);
+        uint32_t R1 = (2 * W + 3) / 4 * 4;
+        if ((R1 / 4) % 2 == 0) R1 += 4;
+        for (uint32_t R : {R1, 2 * W}) {
+            const uint64_t span = (uint64_t)(nq - 1) * R + 256;
+            if (span > 0x10000 || span + (uint64_t)nq * R / 16 + 1024 > (uint64_t)lds) continue;
+            layout = 1;
+            direct = 1;
+            rowbytes = R;
+            stab.assign(align_up(span, 16) / 2, 0);
+            for (uint32_t q = 0; q < nq; ++q)
+                for (int b = lo; b <= hi; ++b)
+                    if (byte_class[b] >= 0)
+                        stab[((size_t)q * R + 2 * (uint32_t)b) / 2] =
+                            (uint16_t)(R * delta[(uint64_t)q * nsym + class_sym[byte_class[b]]]);
+            for (int b = 0; b < 256; ++b)
+                if (byte_class[b] >= 0) code[b] = (uint16_t)(2 * b);
+            break;
+        }
+    }
+    if (!direct) {
         uint32_t R = (2 * K + 3) / 4 * 4;
         if ((R / 4) % 2 == 0) R += 4;
         if (2 * K <= 255 && (uint64_t)(nq - 1) * R <= 0xFFFF && (uint64_t)nq * R + 1024 <= (uint64_t)lds) {
@@ -244,8 +276,9 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         }
     }
     // staged image of the packed matcher: table, then the absorbing-state
-    // bitmap indexed by (LDS state offset >> shift): R * s / 4 for layout 1,
-    // 2 * s / 2 for layout 2
+    // bitmap indexed by (LDS state offset >> shift): R * s / 4 for layout 1
+    // (R * s / 2 when a direct row is not a whole number of dwords), 2 * s / 2
+    // for layout 2
     uint32_t abs_off = 0, abs_shift = 0;
     if (layout != 0) {
         if (layout == 2) {   // the class-major table itself
@@ -253,8 +286,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         }
         stab.resize(align_up(stab.size() * 2, 16) / 2, 0);
         abs_off = (uint32_t)(stab.size() * 2);
-        abs_shift = layout == 1 ? 2u : 1u;
-        const uint32_t unit = layout == 1 ? rowbytes / 4 : 1u;   // bitmap index per state
+        abs_shift = layout == 1 && rowbytes % 4 == 0 ? 2u : 1u;
+        const uint32_t unit = layout == 1 ? rowbytes >> abs_shift : 1u;   // bitmap index per state
         std::vector<uint32_t> bits(((uint64_t)nq * unit + 31) / 32, 0);
         for (uint32_t q = 0; q < nq; ++q)
             if (absorbing[q]) bits[(q * unit) >> 5] |= 1u << ((q * unit) & 31);
@@ -266,6 +299,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         }
         if ((uint64_t)stab.size() * 2 + 16 > (uint64_t)lds) {
             layout = 0;   // no room for the bitmap: one chunk per wavefront only
+            direct = 0;
             stab.clear();
             abs_off = abs_shift = 0;
         }
@@ -346,6 +380,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.r0 = r0;
     v.stab = (const uint16_t *)ptr(i_stab);
     v.layout = layout;
+    v.direct = direct;
     v.rowbytes = rowbytes;
     v.stab_bytes = layout != 0 ? (uint32_t)(stab.size() * 2) : (uint32_t)table_bytes;
     v.abs_off = abs_off;
@@ -367,7 +402,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.mean_iset = mean_iset;
     inf.table_bytes = table_bytes;
     inf.device_bytes = arena_bytes;
-    inf.packed_layout = layout;
+    inf.packed_layout = direct ? 3u : layout;
     inf.lookahead_tables = r0;
     *out = d;
     return DFA_OK;

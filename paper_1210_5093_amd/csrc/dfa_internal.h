@@ -40,6 +40,14 @@ struct DevDFA {
     //           R = row bytes; an LDS address is R * s + code.
     //  layout 2 (class-major): code = class * colstride; the table is `table`
     //           (entries 2 * delta); an LDS address is code + 2 * s.
+    //  direct (a layout-1 variant for alphabets of bytes below 128): rows are
+    //           indexed by the byte itself, code = 2 * byte, so the matcher
+    //           derives codes from the raw input ((w & 0x7F7F7F7F) << 1 per
+    //           word) and needs no translation pass.  Row s starts at R * s;
+    //           entry (s, b) sits at R * s + 2 * b (rows overlap outside the
+    //           bytes of Sigma; every address R * s + c, c even <= 254, holds a
+    //           valid state offset, so a walk over an invalid byte stays in the
+    //           table while the validation pass reports the byte).
     // Multi-symbol initial-state sets I_{c_1..c_k} (Eq. 13) over class strings,
     // k = 1..r0; set id = c_1 K^(k-1) + ... + c_k; level k's offsets start at
     // mset_off[moff[k]], its states at mset_st[mst[k]] (sorted ascending).
@@ -51,6 +59,7 @@ struct DevDFA {
     const uint16_t *code;        // [256]; kCodeInvalid for bytes outside Sigma
     const uint16_t *stab;        // layout 1 table (nq rows of R bytes)
     uint32_t layout;             // 0 = packed matcher unavailable, 1, 2
+    uint32_t direct;             // layout 1 with byte-indexed rows (see above)
     uint32_t rowbytes;           // R (layout 1)
     uint32_t stab_bytes;         // bytes staged for the packed matcher, multiple of 16:
                                  //  the table (stab for layout 1, a copy of `table`

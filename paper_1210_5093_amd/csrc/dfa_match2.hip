@@ -15,6 +15,11 @@
 // selected byte/word of the loaded codes) and a single ds_read_u16:
 //   layout 1: LDS address = R * s + 2 * class  (state-major rows of R bytes)
 //   layout 2: LDS address = class * colstride + 2 * s  (class-major columns)
+// A direct layout-1 table (alphabets of bytes below 128) has byte-indexed
+// rows, LDS address = R * s + 2 * byte; the matcher (L = 3) then reads the
+// raw input and forms the codes itself, and the translation pass shrinks to a
+// validation pass (k_translate without output) that only flags bytes outside
+// Sigma.
 // The table sits at LDS address 0 (the kernel has no static LDS), so stored
 // table entries are LDS addresses themselves.
 //
@@ -34,9 +39,9 @@ namespace dfaspec {
 // ---------------------------------------------------------------------------
 // Translation: code[i] = code_lut[in[i]]; per-block flag if a byte is outside
 // Sigma.  Threads take 16 input bytes at a time (grid-stride); the output is
-// 16-byte aligned.
+// 16-byte aligned.  WRITE = false only validates (direct tables).
 // ---------------------------------------------------------------------------
-template <typename CodeT>
+template <typename CodeT, bool WRITE = true>
 __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ in, uint64_t n,
                                                    const uint16_t *__restrict__ code_lut,
                                                    CodeT *__restrict__ out,
@@ -62,7 +67,8 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
             bad |= (inside && v == kCodeInvalid) ? 1u : 0u;
             c[k] = (v == kCodeInvalid || !inside) ? (uint16_t)0 : v;
         }
-        if constexpr (sizeof(CodeT) == 1) {
+        if constexpr (!WRITE) {
+        } else if constexpr (sizeof(CodeT) == 1) {
             uint4 o;
             uint32_t *ow = reinterpret_cast<uint32_t *>(&o);
 #pragma unroll
@@ -376,6 +382,7 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
     }
 }
 
+// L: layout (3 = a direct layout-1 table walked over the raw input);
 // S: slots (pairs) per lane; EXIT: early exit at absorbing states.  The
 // four-slot walk without exit is held to 64 VGPRs (8 waves per SIMD; a few
 // values spill once per tile, outside the walk).
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     constexpr uint32_t kTile = kWave2 * S;
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
-    using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
+    using CodeT = typename std::conditional<L != 2, uint8_t, uint16_t>::type;
     constexpr uint32_t kPer16 = 16 / sizeof(CodeT);   // codes per 16 bytes
     const uint32_t lane = threadIdx.x & (kWave2 - 1);
     const uint32_t waves = blockDim.x / kWave2;
@@ -395,8 +402,11 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     // pairs of chunks [c_lo, c_hi): the tiles that overlap them
     const uint32_t p_lo = a.first[a.c_lo], p_hi = a.first[a.c_hi];
     const uint32_t t_lo = p_lo / kTile, t_hi = (p_hi + kTile - 1) / kTile;
-    const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
+    const uint32_t R = L != 2 ? a.d.rowbytes : 2u;
     const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
+    auto code_at = [&](uint64_t pos) -> uint32_t {
+        return L == 3 ? 2u * (codes[pos] & 0x7Fu) : (uint32_t)codes[pos];
+    };
     // full chunks start on 16-byte boundaries iff the chunk length does
     const bool aligned_chunks = (a.chunk % kPer16) == 0;
 
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
                 for (int j = 0; j < S; ++j) {
                     if (ci[j] != 0xFFFFFFFFu) {
                         const uint64_t pos = (uint64_t)ci[j] * a.chunk + t;
-                        if (pos < a.n) st[j] = lds_ld(st[j] + (uint32_t)codes[pos]);
+                        if (pos < a.n) st[j] = lds_ld(st[j] + code_at(pos));
                     }
                 }
             }
@@ -529,7 +539,7 @@ void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint
 
 namespace {
 const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
-    static const void *const tab[2][2][2] = {
+    static const void *const tab[3][2][2] = {
         {{reinterpret_cast<const void *>(&k_match2<1, 2, false>),
           reinterpret_cast<const void *>(&k_match2<1, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<1, 4, false>),
@@ -537,8 +547,12 @@ const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
         {{reinterpret_cast<const void *>(&k_match2<2, 2, false>),
           reinterpret_cast<const void *>(&k_match2<2, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<2, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<2, 4, true>)}}};
-    return tab[L == 1 ? 0 : 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
+          reinterpret_cast<const void *>(&k_match2<2, 4, true>)}},
+        {{reinterpret_cast<const void *>(&k_match2<3, 2, false>),
+          reinterpret_cast<const void *>(&k_match2<3, 2, true>)},
+         {reinterpret_cast<const void *>(&k_match2<3, 4, false>),
+          reinterpret_cast<const void *>(&k_match2<3, 4, true>)}}};
+    return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
 const void *window2_kernel(uint32_t L, uint32_t slots) {
     static const void *const tab[2][2] = {
@@ -551,7 +565,10 @@ const void *window2_kernel(uint32_t L, uint32_t slots) {
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
                   hipEvent_t ev_before_matcher) {
-    const uint32_t L = d->dev.layout;
+    // direct tables: the matcher reads the (16-byte aligned) input itself
+    const bool direct = d->dev.direct && p.lookahead != 2 && p.segments <= 1 &&
+                        (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+    const uint32_t L = direct ? 3u : d->dev.layout;
     const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
     uint32_t cb[kMaxSegments + 1];
     for (uint32_t k = 0; k <= nseg; ++k) cb[k] = (uint32_t)((uint64_t)p.nch * k / nseg);
@@ -567,7 +584,10 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint64_t off = (uint64_t)cb[k] * p.chunk;
         const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
         uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
-        if (L == 1)
+        if (direct)
+            hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, ts,
+                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad);
+        else if (L == 1)
             hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
                                end - off, d->dev.code, (uint8_t *)b.codes + off, bad);
         else
@@ -580,7 +600,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     }
     Match2Args a;
     a.d = d->dev;
-    a.codes = b.codes;
+    a.codes = direct ? static_cast<const void *>(d_in) : b.codes;
     a.n = p.n;
     a.chunk = p.chunk;
     a.nch = p.nch;
@@ -674,6 +694,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(1, 4, false), match2_kernel(1, 4, true),
                          match2_kernel(2, 2, false), match2_kernel(2, 2, true),
                          match2_kernel(2, 4, false), match2_kernel(2, 4, true),
+                         match2_kernel(3, 2, false), match2_kernel(3, 2, true),
+                         match2_kernel(3, 4, false), match2_kernel(3, 4, true),
                          window2_kernel(1, 2), window2_kernel(1, 4),
                          window2_kernel(2, 2), window2_kernel(2, 4)};
     int rc = DFA_OK;

@@ -2,6 +2,8 @@
 // See dfa_match2.hip for the layouts: a step adds the selected code byte
 // (layout 1) or word (layout 2) to the state's LDS offset and loads the next
 // state's offset with one ds_read_u16 from a table staged at LDS address 0.
+// L = 3 is layout 1 walked over the raw input of a direct table: each loaded
+// word of bytes becomes four codes 2 * (byte & 0x7F) before the steps.
 #pragma once
 
 #include "dfa_internal.h"
@@ -21,7 +23,7 @@ __device__ __forceinline__ uint32_t lds_ld(uint32_t addr) {
 template <int L, int K>
 __device__ __forceinline__ uint32_t add_sel(uint32_t s, uint32_t w) {
     uint32_t r;
-    if constexpr (L == 1) {
+    if constexpr (L != 2) {
         if constexpr (K == 0)
             asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(s), "v"(w));
         else if constexpr (K == 1)
@@ -37,6 +39,15 @@ __device__ __forceinline__ uint32_t add_sel(uint32_t s, uint32_t w) {
             asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1" : "=v"(r) : "v"(s), "v"(w));
     }
     return r;
+}
+
+// Codes of one loaded word: the word itself, or for L = 3 (raw bytes of a
+// direct table) 2 * (byte & 0x7F) per byte.  Bytes of Sigma are below 128, so
+// the mask only keeps the codes of invalid bytes even and below 256.
+template <int L>
+__device__ __forceinline__ uint32_t word_codes(uint32_t w) {
+    if constexpr (L == 3) return (w & 0x7F7F7F7Fu) << 1;
+    else return w;
 }
 
 // Apply the codes packed in one dword (4 one-byte or 2 two-byte codes).
@@ -192,12 +203,12 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
             uint32_t w[S];
 #pragma unroll
             for (int j = 0; j < S; ++j)
-                w[j] = q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w;
+                w[j] = word_codes<L>(q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w);
             // round-robin over the slots, one code at a time, so that the
             // slots' independent chains keep several LDS loads in flight
             step_slots<L, 0, S>(st, w);
             step_slots<L, 1, S>(st, w);
-            if constexpr (L == 1) {
+            if constexpr (L != 2) {
                 step_slots<L, 2, S>(st, w);
                 step_slots<L, 3, S>(st, w);
             }
@@ -217,15 +228,17 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
 // Walk pairs whose chunks may end inside a 16-byte block: slot j walks
 // len_of(j) codes from 16-byte unit o16[j].  All slots first walk their
 // common whole blocks on the fast path; then each slot finishes its own
-// remaining blocks, stepping only over codes it owns (the last block is read
-// whole: code streams are padded to whole blocks).  len_of recomputes a
-// slot's length, so no per-slot length stays live through the fast path.
+// remaining blocks, stepping only over codes it owns (the last block of a
+// translated stream is read whole, as code streams are padded to whole
+// blocks; raw input (L = 3) is read byte by byte past its last whole block).
+// len_of recomputes a slot's length, so no per-slot length stays live through
+// the fast path.
 template <int L, int S, bool EXIT = false, typename LenFn>
 __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
                                          const uint32_t (&o16)[S], LenFn len_of,
                                          uint32_t (&st)[S], uint32_t exit_base = 0,
                                          uint32_t exit_shift = 0, uint32_t live = 0) {
-    constexpr uint32_t kPer16 = L == 1 ? 16u : 8u;
+    constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
     uint32_t common = 0xFFFFFFFFu, most = 0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -240,11 +253,25 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
             const uint32_t len = len_of(j);
             if (b * kPer16 >= len) continue;
             const uint32_t cnt = min(kPer16, len - b * kPer16);
-            const uint4 v = codes16[(size_t)o16[j] + b];
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            uint32_t w[4];
+            if (L == 3 && cnt < kPer16) {
+                const uint8_t *p = reinterpret_cast<const uint8_t *>(codes16 + o16[j] + b);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if ((uint32_t)(4 * q + k) < cnt) v |= (uint32_t)p[4 * q + k] << (8 * k);
+                    w[q] = word_codes<L>(v);
+                }
+            } else {
+                const uint4 v = codes16[(size_t)o16[j] + b];
+                w[0] = word_codes<L>(v.x); w[1] = word_codes<L>(v.y);
+                w[2] = word_codes<L>(v.z); w[3] = word_codes<L>(v.w);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if constexpr (L == 1) {
+                if constexpr (L != 2) {
                     if (4 * q + 0 < cnt) st[j] = lds_ld(add_sel<1, 0>(st[j], w[q]));
                     if (4 * q + 1 < cnt) st[j] = lds_ld(add_sel<1, 1>(st[j], w[q]));
                     if (4 * q + 2 < cnt) st[j] = lds_ld(add_sel<1, 2>(st[j], w[q]));

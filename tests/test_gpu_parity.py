@@ -339,8 +339,10 @@ def test_planner_default_small_and_large(dfa_mod, monkeypatch):
 
 
 def test_layouts_reported(dfa_mod):
-    assert dfa_mod.DFA.from_workload(configs.c2_dfa()).info().packed_layout == 1
-    assert dfa_mod.DFA.from_workload(configs.c3_protein_dfa()).info().packed_layout == 1
+    # residue alphabets (bytes below 128) get byte-indexed rows (3); the
+    # 1297-state table needs rows of 50 bytes to stay inside 64 KiB
+    assert dfa_mod.DFA.from_workload(configs.c2_dfa()).info().packed_layout == 3
+    assert dfa_mod.DFA.from_workload(configs.c3_protein_dfa()).info().packed_layout == 3
     assert dfa_mod.DFA.from_workload(configs.c3_byte_dfa()).info().packed_layout == 2
     assert dfa_mod.DFA.from_workload(configs.c1_dfa(1)).info().packed_layout == 2
 
@@ -582,4 +584,81 @@ def test_segmented_pipeline_large(dfa_mod, monkeypatch):
         res, _ = dfa_mod.dfa_match_ex(d, dev, lookahead=look)
         torch.cuda.synchronize()
         assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), look
+    d.close()
+
+
+# ---------------------------------------------------------------------------
+# Direct tables (rows indexed by the byte itself; the matcher reads the raw
+# input and a validation pass replaces the translation): every kind of byte
+# outside Sigma, at chunk and block edges, on the whole-block walk (chunk
+# 2048) with one- and five-symbol lookahead.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("byte", [ord("B"), ord("0"), ord("z"), 0x00, 0x7F, 0x80, 0xC1, 0xFF])
+@pytest.mark.parametrize("pos", [0, 2047, 2048, 100_000, 200_002])
+def test_direct_table_invalid_bytes(dfa_mod, byte, pos):
+    w = configs.c2_dfa()
+    x = configs.c2_input(200_003).copy()
+    x[pos] = byte
+    with pytest.raises(oracle.InvalidSymbol):
+        oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
+    d = dfa_mod.DFA.from_workload(w)
+    assert d.info().packed_layout == 3
+    for look in (1, 5):
+        _, _, flags, _, _ = gpu_run(dfa_mod, d, x, chunk=2048, lookahead=look, boundaries=False)
+        assert flags & dfa_mod.FLAG_SYMBOL, look
+    d.close()
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 2047, 2049, 3 * 4096 + 5, 1_000_001])
+@pytest.mark.parametrize("look", [1, 3, 5])
+def test_direct_table_ragged_lengths(dfa_mod, n, look):
+    """Raw input is read byte by byte past its last whole 16-byte block."""
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(n, seed=40 + n % 97), chunk=2048,
+          lookahead=look)
+
+
+def test_direct_table_full_ascii_window(dfa_mod):
+    """128 symbols (bytes 0..127) with 128 distinct columns: too many classes
+    for one-byte class codes, so only the direct table gives a state-major
+    layout (rows of 65 dwords)."""
+    from workloads.dfas import DFA as W
+    rng = np.random.default_rng(11)
+    nq = 200
+    delta = rng.integers(0, nq, (nq, 128)).astype(np.uint32)
+    b2s = np.full(256, 0xFF, dtype=np.uint8)
+    b2s[:128] = np.arange(128)
+    w = W(delta, 0, np.array([1, 2, 3], dtype=np.uint32), b2s, "ascii-200")
+    d = dfa_mod.DFA.from_workload(w)
+    assert d.info().packed_layout == 3
+    d.close()
+    x = rng.integers(0, 128, 300_001).astype(np.uint8)
+    for look in (1, 2):
+        check(dfa_mod, w, x, chunk=4096, lookahead=look)
+    x[123_456] = 0x80
+    d = dfa_mod.DFA.from_workload(w)
+    assert gpu_run(dfa_mod, d, x, chunk=4096, boundaries=False)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()
+
+
+@pytest.mark.parametrize("offset", [0, 4, 8])
+def test_direct_table_early_exit_c3_protein(dfa_mod, offset):
+    """Rows of 50 bytes (the absorbing bitmap is then indexed in 2-byte units),
+    early exit on and off; a misaligned view takes the translating path."""
+    import torch
+    w = configs.c3_protein_dfa()
+    n = 3 << 20
+    x = configs.c3_protein_input(n + offset)[offset:]
+    probes = list(range(0, n + 1, 4096))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = to_dev(configs.c3_protein_input(n + offset))[offset:]
+    for ex in (False, True):
+        for look in (1, 4):
+            res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=4096, lookahead=look,
+                                            boundaries=True, early_exit=ex)
+            torch.cuda.synchronize()
+            assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), (ex, look)
+            b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(b, ps.astype(np.int64)), (ex, look)
     d.close()

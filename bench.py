@@ -179,10 +179,12 @@ def start_sets(w, x: np.ndarray, chunk: int, nch: int, r: int):
     return rows
 
 
-def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int) -> int:
+def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int,
+                       step: int = 1) -> int:
     """Lookups of Algorithm 3 when every walk stops at the first absorbing
     state it reaches (the least work early exit can do; the kernel checks
-    every 64 bytes, so it does at least this much)."""
+    every 64 bytes, so it does at least this much).  step = 2 counts table
+    reads of the two-symbol table (one per two symbols of a walk)."""
     d = w.delta.astype(np.int32)
     nq = d.shape[0]
     absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
@@ -203,19 +205,22 @@ def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int)
         if pc.size == 0:
             break
         ps = d[ps, sym[x[pc * chunk + t]]]
-        total += pc.size
+        if t % step == 0:
+            total += pc.size
         alive = (~absorbing[ps]) & (t + 1 < lens)
         pc, ps, lens = pc[alive], ps[alive], lens[alive]
     return int(total)
 
 
-def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int) -> int:
+def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int, step: int = 1) -> int:
     """len(c_0) + sum_{i>=1} |I_i| len(c_i) (Algorithm 3's work; I_i is the
-    chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13)."""
+    chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13).
+    step = 2: table reads of the two-symbol table, ceil(len / 2) per walk."""
     n = x.size
     nch = (n + chunk - 1) // chunk
     lens = np.full(nch, chunk, dtype=np.int64)
     lens[-1] = n - chunk * (nch - 1)
+    lens = (lens + step - 1) // step
     if nch == 1:
         return int(lens[0])
     if lookahead >= 2:
@@ -738,14 +743,22 @@ def main() -> int:
 
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
+    plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead)
+    step = int(plan.symbols_per_step) if plan.kernel == 1 else 1
     if args.early_exit:
         lookups = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0))
+        reads = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0), step) \
+            if step > 1 else lookups
     else:
         lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
-    plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead)
-    kernel = f"k_match2<{info.packed_layout}>" if plan.kernel == 1 else "k_match"
+        reads = algorithmic_lookups(w, x, chunk, args.lookahead, step) if step > 1 else lookups
+    if plan.kernel == 1:
+        lay = 4 if step == 2 else 3 if plan.raw_input else (2 if info.packed_layout == 2 else 1)
+        kernel = f"k_match2<{lay}>"
+    else:
+        kernel = "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
-    achieved = lookups / (matcher_avg_ms * 1e-3)
+    achieved = reads / (matcher_avg_ms * 1e-3)
     traffic, traffic_src = stored_traffic(kernel, args.workload, args.lookahead, int(chunk))
     line = {
         "metric": METRIC,
@@ -777,6 +790,8 @@ def main() -> int:
         "roofline": {
             "bound": "lds",
             "kernel": kernel,
+            "symbols_per_lookup": step,
+            "lookups_per_launch": int(reads),
             "achieved": round(achieved / 1e9, 2),
             "peak": round(LDS_LOOKUP_PEAK / 1e9, 1),
             "unit": "Glookup/s",

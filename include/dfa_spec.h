@@ -74,8 +74,14 @@ typedef struct dfa_info {
     uint64_t device_bytes;    /* device memory held by this dfa_t */
     uint32_t packed_layout;   /* 0: one-chunk-per-wavefront matcher only;
                                  1: packed-pair matcher, state-major table;
-                                 2: packed-pair matcher, class-major table */
+                                 2: packed-pair matcher, class-major table;
+                                 3: packed-pair matcher, state-major table with
+                                    rows indexed by the byte itself (every byte
+                                    of Sigma below 128): no translation pass */
     uint32_t lookahead_tables;/* r0: sets I_{c_1..c_k} precomputed for k <= r0 */
+    uint32_t pair_columns;    /* distinct two-symbol columns delta(delta(., a), b) of the
+                                 table that lets the packed matcher take two symbols
+                                 per lookup; 0 = no such table */
 } dfa_info_t;
 
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
@@ -202,6 +208,12 @@ typedef struct dfa_plan_info {
     uint32_t lookahead;       /* effective reverse-lookahead symbols r */
     uint32_t blocks;          /* matcher grid */
     uint32_t threads;         /* threads per block */
+    uint32_t symbols_per_step;/* 2: the packed matcher walks the two-symbol table (one
+                                 lookup per two input bytes, after a pass that turns
+                                 byte pairs into codes); 1 otherwise */
+    uint32_t raw_input;       /* 1: the packed matcher reads the input bytes themselves
+                                 (direct table: only a validation pass runs first) when
+                                 the input is 16-byte aligned */
 } dfa_plan_info_t;
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 

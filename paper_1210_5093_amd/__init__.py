@@ -37,7 +37,7 @@ class dfa_info_t(ctypes.Structure):
                 ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
                 ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("packed_layout", ctypes.c_uint32),
-                ("lookahead_tables", ctypes.c_uint32)]
+                ("lookahead_tables", ctypes.c_uint32), ("pair_columns", ctypes.c_uint32)]
 
 
 class dfa_match_opts_t(ctypes.Structure):
@@ -48,7 +48,8 @@ class dfa_match_opts_t(ctypes.Structure):
 class dfa_plan_info_t(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint64), ("num_chunks", ctypes.c_uint64),
                 ("kernel", ctypes.c_uint32), ("lookahead", ctypes.c_uint32),
-                ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
+                ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("symbols_per_step", ctypes.c_uint32), ("raw_input", ctypes.c_uint32)]
 
 
 class dfa_result_t(ctypes.Structure):

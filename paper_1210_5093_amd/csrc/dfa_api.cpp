@@ -259,6 +259,8 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->lookahead = p.r;
     out->blocks = p.packed ? p.blocks2 : p.blocks;
     out->threads = p.packed ? p.threads2 : p.waves_per_block * 64u;
+    out->symbols_per_step = p.pairs ? 2u : 1u;
+    out->raw_input = p.packed && !p.pairs && d->dev.direct && p.lookahead != 2 && p.segments <= 1;
     return DFA_OK;
 }
 

@@ -123,19 +123,13 @@ __global__ __launch_bounds__(256) void k_b2_translate(B2Args a, const B2Seg *__r
         __syncthreads();
         const bool wide = d.layout != 1;
         uint32_t bad = 0;
-        for (uint64_t off = (uint64_t)threadIdx.x * 16; off < seg.len;
-             off += (uint64_t)blockDim.x * 16) {
+        auto convert = [&](const uint32_t (&w)[4], uint64_t off) {
             const uint64_t pos = seg.beg + off;
             const uint32_t cnt = (uint32_t)min<uint64_t>(16, seg.len - off);
-            uint8_t b[16];
-            uint32_t w[4];
-            load16(st.in, pos, st.n, w);   // pos < seg.beg + seg.len <= n
-#pragma unroll
-            for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
             uint16_t c[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const uint16_t v = lut[b[k]];
+                const uint16_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
                 const bool inside = (uint32_t)k < cnt;
                 bad |= (inside && v == kCodeInvalid) ? 1u : 0u;
                 c[k] = (v == kCodeInvalid || !inside) ? (uint16_t)0 : v;
@@ -153,11 +147,76 @@ __global__ __launch_bounds__(256) void k_b2_translate(B2Args a, const B2Seg *__r
                 uint4 o[2];
                 uint32_t *ow = reinterpret_cast<uint32_t *>(o);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) ow[q] = (uint32_t)c[2 * q] | ((uint32_t)c[2 * q + 1] << 16);
+                for (int q = 0; q < 8; ++q)
+                    ow[q] = (uint32_t)c[2 * q] | ((uint32_t)c[2 * q + 1] << 16);
                 uint4 *dst = reinterpret_cast<uint4 *>(a.codes + st.code_off + 2 * pos);
                 dst[0] = o[0];
                 dst[1] = o[1];
             }
+        };
+        // Whole rounds first: U blocks of 16 bytes per thread, all loaded
+        // before any is used (one load in flight per lane leaves the pass
+        // latency bound).  The segment start and its misalignment are the
+        // same for every lane, so these rounds take no per-lane branches.
+        constexpr int U = 4;
+        typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) const u32x4_t gu4_t;
+        const uint64_t round = (uint64_t)blockDim.x * 16 * U;
+        const uintptr_t p0 = (uintptr_t)(st.in + seg.beg);
+        const uint32_t sh = (uint32_t)(p0 & 15u);
+        const uintptr_t a0 = p0 - sh;                    // aligned base
+        // the aligned words read stay inside the string: whole rounds end at
+        // or before seg.len, and a misaligned round also reads the 16 bytes
+        // after its last block (up to byte seg.beg + end + sh + 15 < n)
+        const uint64_t avail = st.n - seg.beg;
+        uint64_t whole = seg.len / round * round;
+        if (sh != 0)
+            while (whole > 0 && whole + 16 > avail) whole -= round;
+        uint64_t base = 0;
+        for (; base < whole; base += round) {
+            uint32_t w[U][4];
+            if (sh == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t off = base + ((uint64_t)u * blockDim.x + threadIdx.x) * 16;
+                    const u32x4_t v = *(gu4_t *)(a0 + off);
+                    w[u][0] = v.x; w[u][1] = v.y; w[u][2] = v.z; w[u][3] = v.w;
+                }
+            } else {
+                u32x4_t v0[U], v1[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t off = base + ((uint64_t)u * blockDim.x + threadIdx.x) * 16;
+                    v0[u] = *(gu4_t *)(a0 + off);
+                    v1[u] = *(gu4_t *)(a0 + off + 16);
+                }
+                const uint32_t r = sh & 3u, q0 = sh >> 2;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t x[8] = {v0[u].x, v0[u].y, v0[u].z, v0[u].w,
+                                           v1[u].x, v1[u].y, v1[u].z, v1[u].w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // words q0 + q and q0 + q + 1 of x, selected without
+                        // dynamic register indexing
+                        uint32_t lo = x[q], hi = x[q + 1];
+                        if (q0 == 1) { lo = x[q + 1]; hi = x[q + 2]; }
+                        if (q0 == 2) { lo = x[q + 2]; hi = x[q + 3]; }
+                        if (q0 == 3) { lo = x[q + 3]; hi = x[q + 4]; }
+                        w[u][q] = __builtin_amdgcn_alignbyte(hi, lo, r);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                convert(w[u], base + ((uint64_t)u * blockDim.x + threadIdx.x) * 16);
+        }
+        // the rest: one block at a time
+        for (uint64_t off = base + (uint64_t)threadIdx.x * 16; off < seg.len;
+             off += (uint64_t)blockDim.x * 16) {
+            uint32_t w[4];
+            load16(st.in, seg.beg + off, st.n, w);   // seg.beg + off < n
+            convert(w, off);
         }
         if (bad) atomicOr(&a.str_bad[seg.str], 1u);
     }

@@ -306,6 +306,73 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     }
     if (stab.empty()) stab.assign(8, 0);
 
+    // ---- two-symbol steps --------------------------------------------------
+    // delta2(s, c1 c2) = delta(delta(s, c1), c2) halves the lookups of a walk.
+    // Pair columns are deduplicated; the table is laid out as layout 1 (rows
+    // of an odd number of dwords, one-byte codes 2 * column) and exists when
+    // there are at most 127 columns and its entries fit 16 bits.
+    uint32_t pairs = 0, rowbytes2 = 0, abs_off2 = 0, npair = 0;
+    std::vector<uint16_t> stab2;
+    std::vector<uint8_t> pcode(256, 0xFF);
+    {
+        const uint32_t Kc = (uint32_t)class_sym.size();
+        if (layout != 0 && Kc >= 1 && Kc <= 63) {
+            std::unordered_map<std::string, uint32_t> pid;
+            std::vector<std::vector<uint32_t>> pcols;
+            std::vector<uint8_t> pc((size_t)Kc * (Kc + 1), 0);
+            std::string key(nq * sizeof(uint32_t), '\0');
+            std::vector<uint32_t> colv(nq);
+            bool ok = true;
+            for (uint32_t c1 = 0; c1 < Kc && ok; ++c1)
+                for (uint32_t c2 = 0; c2 <= Kc && ok; ++c2) {
+                    for (uint32_t q = 0; q < nq; ++q) {
+                        uint32_t t = delta[(uint64_t)q * nsym + class_sym[c1]];
+                        if (c2 < Kc) t = delta[(uint64_t)t * nsym + class_sym[c2]];
+                        colv[q] = t;
+                    }
+                    std::memcpy(&key[0], colv.data(), key.size());
+                    auto it = pid.find(key);
+                    uint32_t id;
+                    if (it == pid.end()) {
+                        id = (uint32_t)pcols.size();
+                        if (id >= 127) { ok = false; break; }
+                        pid.emplace(key, id);
+                        pcols.push_back(colv);
+                    } else {
+                        id = it->second;
+                    }
+                    pc[(size_t)c1 * (Kc + 1) + c2] = (uint8_t)(2 * id);
+                }
+            uint32_t R2 = ok ? (2 * (uint32_t)pcols.size() + 3) / 4 * 4 : 0;
+            if (ok && (R2 / 4) % 2 == 0) R2 += 4;
+            const uint64_t img = align_up((uint64_t)nq * R2, 16);
+            const uint64_t bits_bytes = align_up(((uint64_t)nq * (R2 / 4) + 31) / 32 * 4, 16);
+            if (ok && (uint64_t)(nq - 1) * R2 <= 0xFFFF && img + bits_bytes + 16 <= (uint64_t)lds) {
+                pairs = 1;
+                npair = (uint32_t)pcols.size();
+                rowbytes2 = R2;
+                stab2.assign(img / 2, 0);
+                for (uint32_t q = 0; q < nq; ++q)
+                    for (size_t c = 0; c < pcols.size(); ++c)
+                        stab2[(size_t)q * (R2 / 2) + c] = (uint16_t)(R2 * pcols[c][q]);
+                abs_off2 = (uint32_t)img;
+                std::vector<uint32_t> bits(bits_bytes / 4, 0);
+                const uint32_t unit = R2 / 4;
+                for (uint32_t q = 0; q < nq; ++q)
+                    if (absorbing[q]) bits[(q * unit) >> 5] |= 1u << ((q * unit) & 31);
+                for (uint32_t w : bits) {
+                    stab2.push_back((uint16_t)(w & 0xFFFF));
+                    stab2.push_back((uint16_t)(w >> 16));
+                }
+                for (int b = 0; b < 256; ++b)
+                    if (byte_class[b] >= 0) pcode[b] = (uint8_t)byte_class[b];
+                pcode.insert(pcode.end(), pc.begin(), pc.end());
+            }
+        }
+    }
+    if (stab2.empty()) stab2.assign(8, 0);
+    pcode.resize(align_up(pcode.size(), 16), 0);
+
     std::vector<uint32_t> accept_bits((nq + 31) / 32, 0);
     for (uint32_t k = 0; k < nacc; ++k) accept_bits[accepting[k] >> 5] |= 1u << (accepting[k] & 31);
 
@@ -332,6 +399,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     size_t i_moff = add(mset_off.data(), mset_off.size() * 4);
     size_t i_mst = add(mset_st.data(), mset_st.size() * 2);
     size_t i_stab = add(stab.data(), stab.size() * 2);
+    size_t i_stab2 = add(stab2.data(), stab2.size() * 2);
+    size_t i_pcode = add(pcode.data(), pcode.size());
     const size_t arena_bytes = align_up(at, 256);
 
     dfa *d = new (std::nothrow) dfa();
@@ -386,6 +455,12 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.abs_off = abs_off;
     v.abs_shift = abs_shift;
     v.nabs = nabs;
+    v.pairs = pairs;
+    v.stab2 = (const uint16_t *)ptr(i_stab2);
+    v.stab2_bytes = pairs ? (uint32_t)(stab2.size() * 2) : 0u;
+    v.rowbytes2 = rowbytes2;
+    v.abs_off2 = abs_off2;
+    v.pcode = (const uint8_t *)ptr(i_pcode);
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;
@@ -404,6 +479,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.device_bytes = arena_bytes;
     inf.packed_layout = direct ? 3u : layout;
     inf.lookahead_tables = r0;
+    inf.pair_columns = npair;
     *out = d;
     return DFA_OK;
 }

@@ -67,6 +67,19 @@ struct DevDFA {
     uint32_t abs_off;            // LDS byte offset of that bitmap; bit (LDS state
     uint32_t abs_shift;          //  offset >> abs_shift) is set iff the state is absorbing
     uint32_t nabs;               // number of absorbing states
+    // Two-symbol steps: a state-major table of delta2(s, c1 c2) =
+    // delta(delta(s, c1), c2) over the distinct pair columns (c2 = K stands
+    // for "no second symbol": a string's odd last byte), laid out as layout 1
+    // (entry R2 * delta2, code = 2 * pair column, rows of R2 bytes), staged
+    // with its own absorbing-state bitmap (index R2 * s / 4).  pcode holds
+    // 256 bytes byte -> class (0xFF outside Sigma), then the one-byte codes
+    // of the K x (K + 1) class pairs.
+    uint32_t pairs;              // 1 if the pair table exists
+    const uint16_t *stab2;
+    uint32_t stab2_bytes;        // multiple of 16
+    uint32_t rowbytes2;          // R2
+    uint32_t abs_off2;           // LDS byte offset of its absorbing bitmap
+    const uint8_t *pcode;
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -126,6 +139,7 @@ struct MatchPlan {
     bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
     uint32_t segments = 1;       // translate/match pipeline segments (1 .. kMaxSegments)
+    bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
     uint32_t blocks2 = 0;        // persistent grid
     uint32_t threads2 = 256;     // threads per block (more for large tables)
     uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)

@@ -327,6 +327,12 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                 (p->lookahead >= 2 ||
                  (!(force && force[0] == '1') &&
                   ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
+    // two-symbol steps halve the lookups; they need whole 32-byte chunk
+    // multiples (16-byte blocks of pair codes) and per-byte codes for the
+    // window pass.  DFA_PAIRS=0 keeps one symbol per step.
+    const char *fpairs = std::getenv("DFA_PAIRS");
+    p->pairs = p->packed && d->dev.pairs && p->lookahead != 2 &&
+               !(fpairs && fpairs[0] == '0') && (chunk_req == 0 || chunk_req % 32 == 0);
     if (p->packed) {
         // two pairs per lane when the start sets are tiny (many chunks per
         // tile: shorter tiles spread the chains over more wavefronts), four
@@ -337,8 +343,9 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
         const char *fs = std::getenv("DFA_SLOTS");
         p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 8.0 ? 2u : 4u);
+        const uint32_t staged = p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
         const uint32_t per_cu = std::max<uint32_t>(
-            1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(d->dev.stab_bytes, 1024u)));
+            1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(staged, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
         p->threads2 = 64u * std::min<uint32_t>(16u, std::max<uint32_t>(4u, (32u + per_cu - 1) / per_cu));
         p->blocks2 = (uint32_t)cus * per_cu;
@@ -366,7 +373,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // beyond the precomputed sets) reads codes before every chunk, so it keeps
     // one segment; segment starts must be whole 16-code blocks (chunk
     // lengths of 64k).
-    const bool can_split = p->packed && p->lookahead != 2 && chunk % 64 == 0;
+    const bool can_split = p->packed && !p->pairs && p->lookahead != 2 && chunk % 64 == 0;
     if (const char *fs = std::getenv("DFA_SEGMENTS")) {
         const int v = std::atoi(fs);
         if (v >= 1 && v <= (int)kMaxSegments && can_split && nch >= (uint64_t)v)

@@ -38,53 +38,174 @@ namespace dfaspec {
 
 // ---------------------------------------------------------------------------
 // Translation: code[i] = code_lut[in[i]]; per-block flag if a byte is outside
-// Sigma.  Threads take 16 input bytes at a time (grid-stride); the output is
-// 16-byte aligned.  WRITE = false only validates (direct tables).
+// Sigma.  WRITE = false only validates (direct tables).  The output is
+// 16-byte aligned.
 // ---------------------------------------------------------------------------
+constexpr int kTrU = 4;
+
+// The grid walk shared by the translation kernels: convert(tag, w, first)
+// handles the 16 input bytes at `first` (tag: std::true_type when all lie
+// before n).  Whole rounds of an aligned input load kTrU blocks per thread
+// before converting any (block u of a round is u * threads + thread, so every
+// load instruction is coalesced): with one 16-byte load in flight per lane a
+// pass is bound by memory latency well below HBM bandwidth.  The last partial
+// round and misaligned inputs go one block at a time.
+template <typename Conv>
+__device__ __forceinline__ void translate_grid(const uint8_t *__restrict__ in, uint64_t n,
+                                               Conv &convert) {
+    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t base = 0;
+    if ((reinterpret_cast<uintptr_t>(in) & 15u) == 0) {
+        for (; base + T * 16 * kTrU <= n; base += T * 16 * kTrU) {
+            uint4 v[kTrU];
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u)
+                v[u] = *reinterpret_cast<const uint4 *>(in + base + ((uint64_t)u * T + tid) * 16);
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u) {
+                const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                convert(std::true_type{}, w, base + ((uint64_t)u * T + tid) * 16);
+            }
+        }
+    }
+    for (uint64_t first = base + tid * 16; first < n; first += T * 16) {
+        uint32_t w[4];
+        load16(in, first, n, w);
+        if (first + 16 <= n) convert(std::true_type{}, w, first);
+        else convert(std::false_type{}, w, first);
+    }
+}
+
+// Bytes 0 of four words packed into one (v_perm_b32).
+__device__ __forceinline__ uint32_t pack_low_bytes(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+    return __builtin_amdgcn_perm(c1, c0, 0x0C0C0400u) | __builtin_amdgcn_perm(c3, c2, 0x04000C0Cu);
+}
+
 template <typename CodeT, bool WRITE = true>
 __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ in, uint64_t n,
                                                    const uint16_t *__restrict__ code_lut,
                                                    CodeT *__restrict__ out,
                                                    uint32_t *__restrict__ block_bad) {
+    // one-byte codes (< 256) are staged with bytes outside Sigma as 0xFF00:
+    // the low byte (the code written) is 0 and an OR of the entries flags them
+    constexpr bool kNarrow = sizeof(CodeT) == 1;
     __shared__ uint16_t lut[256];
     __shared__ uint32_t bad_any;
-    lut[threadIdx.x] = code_lut[threadIdx.x];
+    {
+        const uint16_t v = code_lut[threadIdx.x];
+        lut[threadIdx.x] = kNarrow && v == kCodeInvalid ? (uint16_t)0xFF00u : v;
+    }
     if (threadIdx.x == 0) bad_any = 0;
     __syncthreads();
     uint32_t bad = 0;
-    for (uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; first < n;
-         first += (uint64_t)gridDim.x * blockDim.x * 16) {
-        uint8_t b[16];
-        uint32_t w[4];
-        load16(in, first, n, w);
+    // WHOLE: all 16 bytes lie before n (no per-byte bounds)
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[16];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-        uint16_t c[16];
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+                if constexpr (kNarrow) {
+                    acc |= v;
+                    c[k] = v;
+                } else {
+                    const bool inv = v == kCodeInvalid;
+                    bad |= inv ? 1u : 0u;
+                    c[k] = inv ? 0u : v;
+                }
+            }
+            if constexpr (kNarrow) bad |= acc >> 8;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            uint16_t v = lut[b[k]];
-            const bool inside = first + k < n;
-            bad |= (inside && v == kCodeInvalid) ? 1u : 0u;
-            c[k] = (v == kCodeInvalid || !inside) ? (uint16_t)0 : v;
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+                const bool inside = first + k < n;
+                const bool inv = kNarrow ? (v >> 8) != 0 : v == kCodeInvalid;
+                bad |= (inside && inv) ? 1u : 0u;
+                c[k] = (inv || !inside) ? 0u : v;
+            }
         }
         if constexpr (!WRITE) {
-        } else if constexpr (sizeof(CodeT) == 1) {
+        } else if constexpr (kNarrow) {
             uint4 o;
-            uint32_t *ow = reinterpret_cast<uint32_t *>(&o);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                ow[q] = (uint32_t)c[4 * q] | ((uint32_t)c[4 * q + 1] << 8) |
-                        ((uint32_t)c[4 * q + 2] << 16) | ((uint32_t)c[4 * q + 3] << 24);
+            o.x = pack_low_bytes(c[0], c[1], c[2], c[3]);
+            o.y = pack_low_bytes(c[4], c[5], c[6], c[7]);
+            o.z = pack_low_bytes(c[8], c[9], c[10], c[11]);
+            o.w = pack_low_bytes(c[12], c[13], c[14], c[15]);
             *reinterpret_cast<uint4 *>(out + first) = o;
         } else {
             uint4 o[2];
             uint32_t *ow = reinterpret_cast<uint32_t *>(o);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) ow[q] = (uint32_t)c[2 * q] | ((uint32_t)c[2 * q + 1] << 16);
+            for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
             *reinterpret_cast<uint4 *>(out + first) = o[0];
             *reinterpret_cast<uint4 *>(out + first + 8) = o[1];
         }
-    }
+    };
+    translate_grid(in, n, convert);
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
+}
+
+
+// Two-symbol translation: code i = the pair code of bytes 2i and 2i + 1 (the
+// class alone when 2i + 1 = n); per-block flag if a byte is outside Sigma.
+// pcode: byte -> class (256 bytes), then the codes of the K x (K + 1) pairs.
+__global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restrict__ in, uint64_t n,
+                                                         const uint8_t *__restrict__ pcode,
+                                                         uint32_t K, uint8_t *__restrict__ out,
+                                                         uint32_t *__restrict__ block_bad) {
+    // pc covers every index c1 * (K + 1) + c2 with c1, c2 <= 255, so that a
+    // class 0xFF (byte outside Sigma) reads a staged value: a pair code, or 0
+    // past the K x (K + 1) codes; such blocks are flagged and their codes
+    // only need to stay valid table offsets
+    constexpr uint32_t kPc = 256u * 64u + 256u;
+    __shared__ uint8_t cls[256];
+    __shared__ __align__(16) uint8_t pc[kPc];
+    __shared__ uint32_t bad_any;
+    cls[threadIdx.x] = pcode[threadIdx.x];
+    for (uint32_t i = threadIdx.x; i < kPc / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(pc)[i] = 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < K * (K + 1); i += blockDim.x) pc[i] = pcode[256 + i];
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    const uint32_t K1 = K + 1;
+    uint32_t bad = 0;
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[8];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t c1 = cls[(w[k >> 1] >> (16 * (k & 1))) & 0xFFu];
+                const uint32_t c2 = cls[(w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu];
+                acc |= c1 | c2;
+                c[k] = pc[__umul24(c1, K1) + c2];
+            }
+            bad |= (acc & 0x80u) ? 1u : 0u;   // classes are below 64; 0xFF marks a bad byte
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
+                const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
+                const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
+                const uint32_t c1 = cls[b1];
+                const uint32_t c2 = in2 ? (uint32_t)cls[b2] : K;
+                const bool bad1 = in1 && c1 == 0xFFu, bad2 = in2 && c2 == 0xFFu;
+                bad |= (bad1 || bad2) ? 1u : 0u;
+                c[k] = (in1 && !bad1 && !bad2) ? (uint32_t)pc[c1 * K1 + c2] : 0u;
+            }
+        }
+        *reinterpret_cast<uint2 *>(out + first / 2) =
+            make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+    };
+    translate_grid(in, n, convert);
     if (bad) atomicOr(&bad_any, 1u);
     __syncthreads();
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
@@ -382,7 +503,8 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
     }
 }
 
-// L: layout (3 = a direct layout-1 table walked over the raw input);
+// L: layout (3 = a direct layout-1 table walked over the raw input, 4 = the
+// two-symbol table walked over pair codes);
 // S: slots (pairs) per lane; EXIT: early exit at absorbing states.  The
 // four-slot walk without exit is held to 64 VGPRs (8 waves per SIMD; a few
 // values spill once per tile, outside the walk).
@@ -407,8 +529,11 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     auto code_at = [&](uint64_t pos) -> uint32_t {
         return L == 3 ? 2u * (codes[pos] & 0x7Fu) : (uint32_t)codes[pos];
     };
+    // L = 4 (two-symbol steps): one code per two input bytes, chunk lengths
+    // are even (the host only picks it for multiples of 32)
+    constexpr uint32_t kSym = L == 4 ? 2u : 1u;       // symbols per code
     // full chunks start on 16-byte boundaries iff the chunk length does
-    const bool aligned_chunks = (a.chunk % kPer16) == 0;
+    const bool aligned_chunks = (a.chunk % (kPer16 * kSym)) == 0;
 
     for (uint32_t tile = t_lo + wave_id; tile < t_hi; tile += total_waves) {
         const uint32_t lo0 = a.tile_first[tile];
@@ -434,7 +559,7 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
             }
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
-            o16[j] = aligned_chunks ? (uint32_t)((uint64_t)c * a.chunk / kPer16) : 0u;
+            o16[j] = aligned_chunks ? (uint32_t)((uint64_t)c * a.chunk / (kPer16 * kSym)) : 0u;
         }
         if (aligned_chunks) {
             uint32_t live = 0;
@@ -444,18 +569,19 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
             // bounds; their end states are discarded)
             auto len_of = [&](int j) -> uint32_t {
                 const uint64_t c = ci[j] == 0xFFFFFFFFu ? 0u : ci[j];
-                return (uint32_t)min<uint64_t>(a.chunk, a.n - c * a.chunk);
+                return (uint32_t)((min<uint64_t>(a.chunk, a.n - c * a.chunk) + kSym - 1) / kSym);
             };
             walk_var<L, S, EXIT>(reinterpret_cast<const uint4 *>(codes), o16, len_of, st,
                                   a.exit_base, a.exit_shift, live);
         } else {
             // general path: per-lane code loads, chunks of any length and alignment
-            for (uint64_t t = 0; t < a.chunk; ++t) {
+            const uint64_t ncodes = (a.n + kSym - 1) / kSym;
+            for (uint64_t t = 0; t < (a.chunk + kSym - 1) / kSym; ++t) {
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
                     if (ci[j] != 0xFFFFFFFFu) {
-                        const uint64_t pos = (uint64_t)ci[j] * a.chunk + t;
-                        if (pos < a.n) st[j] = lds_ld(st[j] + code_at(pos));
+                        const uint64_t pos = (uint64_t)ci[j] * a.chunk / kSym + t;
+                        if (pos < ncodes) st[j] = lds_ld(st[j] + code_at(pos));
                     }
                 }
             }
@@ -539,7 +665,7 @@ void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint
 
 namespace {
 const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
-    static const void *const tab[3][2][2] = {
+    static const void *const tab[4][2][2] = {
         {{reinterpret_cast<const void *>(&k_match2<1, 2, false>),
           reinterpret_cast<const void *>(&k_match2<1, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<1, 4, false>),
@@ -551,7 +677,11 @@ const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
         {{reinterpret_cast<const void *>(&k_match2<3, 2, false>),
           reinterpret_cast<const void *>(&k_match2<3, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<3, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<3, 4, true>)}}};
+          reinterpret_cast<const void *>(&k_match2<3, 4, true>)}},
+        {{reinterpret_cast<const void *>(&k_match2<4, 2, false>),
+          reinterpret_cast<const void *>(&k_match2<4, 2, true>)},
+         {reinterpret_cast<const void *>(&k_match2<4, 4, false>),
+          reinterpret_cast<const void *>(&k_match2<4, 4, true>)}}};
     return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
 const void *window2_kernel(uint32_t L, uint32_t slots) {
@@ -565,10 +695,14 @@ const void *window2_kernel(uint32_t L, uint32_t slots) {
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
                   hipEvent_t ev_before_matcher) {
-    // direct tables: the matcher reads the (16-byte aligned) input itself
-    const bool direct = d->dev.direct && p.lookahead != 2 && p.segments <= 1 &&
+    // two-symbol steps (the plan checked the chunk length); else direct
+    // tables: the matcher reads the (16-byte aligned) input itself
+    const bool pairs = p.pairs && d->dev.pairs;
+    const bool direct = !pairs && d->dev.direct && p.lookahead != 2 && p.segments <= 1 &&
                         (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
-    const uint32_t L = direct ? 3u : d->dev.layout;
+    const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
+    if (pairs && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
+        return fail(DFA_E_INVAL, "two-symbol plan with segments, window pass or odd chunks");
     const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
     uint32_t cb[kMaxSegments + 1];
     for (uint32_t k = 0; k <= nseg; ++k) cb[k] = (uint32_t)((uint64_t)p.nch * k / nseg);
@@ -584,7 +718,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint64_t off = (uint64_t)cb[k] * p.chunk;
         const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
         uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
-        if (direct)
+        if (pairs)
+            hipLaunchKernelGGL(k_translate_pairs, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
+                               end - off, d->dev.pcode, d->dev.nclass, (uint8_t *)b.codes + off / 2,
+                               bad);
+        else if (direct)
             hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, ts,
                                d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad);
         else if (L == 1)
@@ -600,6 +738,13 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     }
     Match2Args a;
     a.d = d->dev;
+    if (pairs) {   // the matcher stages and indexes the pair table instead
+        a.d.stab = d->dev.stab2;
+        a.d.stab_bytes = d->dev.stab2_bytes;
+        a.d.rowbytes = d->dev.rowbytes2;
+        a.d.abs_off = d->dev.abs_off2;
+        a.d.abs_shift = 2;
+    }
     a.codes = direct ? static_cast<const void *>(d_in) : b.codes;
     a.n = p.n;
     a.chunk = p.chunk;
@@ -615,11 +760,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.bits = b.bits;
     a.W = p.bitmap_words;
     a.maps = maps;
-    a.exit_base = p.early_exit ? d->dev.abs_off : 0u;
-    a.exit_shift = d->dev.abs_shift;
+    a.exit_base = p.early_exit ? a.d.abs_off : 0u;
+    a.exit_shift = a.d.abs_shift;
     a.c_lo = 0;
     a.c_hi = p.nch;
-    const size_t lds = d->dev.stab_bytes;
+    const size_t lds = a.d.stab_bytes;
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
@@ -696,6 +841,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(2, 4, false), match2_kernel(2, 4, true),
                          match2_kernel(3, 2, false), match2_kernel(3, 2, true),
                          match2_kernel(3, 4, false), match2_kernel(3, 4, true),
+                         match2_kernel(4, 2, false), match2_kernel(4, 2, true),
+                         match2_kernel(4, 4, false), match2_kernel(4, 4, true),
                          window2_kernel(1, 2), window2_kernel(1, 4),
                          window2_kernel(2, 2), window2_kernel(2, 4)};
     int rc = DFA_OK;

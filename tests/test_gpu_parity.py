@@ -345,6 +345,12 @@ def test_layouts_reported(dfa_mod):
     assert dfa_mod.DFA.from_workload(configs.c3_protein_dfa()).info().packed_layout == 3
     assert dfa_mod.DFA.from_workload(configs.c3_byte_dfa()).info().packed_layout == 2
     assert dfa_mod.DFA.from_workload(configs.c1_dfa(1)).info().packed_layout == 2
+    # two-symbol tables: C2's 8 classes give 42 distinct pair columns; the
+    # 1297-state table would not fit 16-bit entries, 64 or 256 classes too many
+    assert dfa_mod.DFA.from_workload(configs.c2_dfa()).info().pair_columns == 42
+    assert dfa_mod.DFA.from_workload(configs.c3_protein_dfa()).info().pair_columns == 0
+    assert dfa_mod.DFA.from_workload(configs.c3_byte_dfa()).info().pair_columns == 0
+    assert dfa_mod.DFA.from_workload(configs.c1_dfa(1)).info().pair_columns == 0
 
 
 def test_table_beyond_64k_uses_first_generation_kernel(dfa_mod):
@@ -662,3 +668,73 @@ def test_direct_table_early_exit_c3_protein(dfa_mod, offset):
             b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
             assert np.array_equal(b, ps.astype(np.int64)), (ex, look)
     d.close()
+
+
+# ---------------------------------------------------------------------------
+# Two-symbol steps (a table of delta(delta(s, a), b) over pair columns; one
+# code per two input bytes): odd lengths end on a one-symbol column, chunk
+# boundaries stay exact, invalid bytes at even and odd positions are flagged.
+# DFA_PAIRS=0 gives the one-symbol path on the same inputs.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pairs", ["1", "0"])
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 4095, 4097, 1_000_001, 3 << 20])
+@pytest.mark.parametrize("look", [1, 5])
+def test_two_symbol_steps_lengths(dfa_mod, monkeypatch, pairs, n, look):
+    if pairs == "0":
+        monkeypatch.setenv("DFA_PAIRS", "0")
+    w = configs.c2_dfa()
+    x = configs.c2_input(n, seed=70 + n % 89)
+    for chunk in (0, 64, 2048):
+        check(dfa_mod, w, x, chunk=chunk, lookahead=look)
+
+
+@pytest.mark.parametrize("pos", [0, 1, 30, 31, 2047, 2048, 99_998, 99_999, 100_000])
+def test_two_symbol_steps_invalid_bytes(dfa_mod, pos):
+    w = configs.c2_dfa()
+    x = configs.c2_input(100_001).copy()
+    x[pos] = ord("J") if pos % 2 else 0xE1
+    d = dfa_mod.DFA.from_workload(w)
+    for look in (1, 4):
+        assert gpu_run(dfa_mod, d, x, chunk=2048, lookahead=look, boundaries=False)[2] & \
+            dfa_mod.FLAG_SYMBOL
+    d.close()
+
+
+@pytest.mark.parametrize("seed,contains", [(32, False), (7, False), (7, True)])
+def test_two_symbol_steps_early_exit_and_other_dfas(dfa_mod, seed, contains):
+    import torch
+    w = from_pattern(patterns.pattern_dfa(seed, contains=contains))
+    d = dfa_mod.DFA.from_workload(w)
+    assert d.info().pair_columns > 0
+    n = (5 << 20) + 7
+    x = configs.c2_input(n, seed=300 + seed)
+    probes = list(range(0, n, 1024)) + [n]
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    dev = torch.from_numpy(x).to("cuda")
+    for ex in (False, True):
+        for look in (1, 3):
+            res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=1024, lookahead=look,
+                                            boundaries=True, early_exit=ex)
+            torch.cuda.synchronize()
+            assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), (ex, look)
+            b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(b, ps.astype(np.int64)), (ex, look)
+    d.close()
+
+
+def test_two_symbol_steps_random_small_alphabets(dfa_mod):
+    """Random byte-alphabet DFAs with 2..60 distinct columns: up to 10
+    columns give at most 110 pair columns (a pair table when the states fit
+    16-bit entries), more columns too many."""
+    rng = np.random.default_rng(77)
+    for t, k in enumerate([2, 3, 4, 5, 6, 8, 10, 10, 11, 20, 60, 7]):
+        nq = int(rng.integers(2, 300))
+        w = column_dfa(500 + t, 600 + t, nq, k)
+        d = dfa_mod.DFA.from_workload(w)
+        pc = d.info().pair_columns
+        d.close()
+        x = streams.uniform_bytes(700 + t, int(rng.integers(50_000, 400_000)))
+        say(f"random dfa {t}: Q={nq} K={k} pair columns {pc}")
+        check(dfa_mod, w, x, chunk=512, lookahead=1)
+        check(dfa_mod, w, x, chunk=4096, lookahead=2)

@@ -212,6 +212,52 @@ def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int,
     return int(total)
 
 
+def merged_lookups(w, x: np.ndarray, chunk: int, lookahead: int, rounds: int,
+                   step: int = 1) -> int:
+    """Table reads of the merged walks (rounds >= 2): round k walks bytes
+    [t_k, t_{k+1}) of every chunk (t_1 = 32, x4 per round, the last round to
+    the chunk end), every walk still live; after a round that is not the last
+    one walk per distinct (chunk, state) goes on, and walks whose chunk ended
+    or that reached an absorbing state stop.  Grouping here is per chunk; the
+    kernel groups per wave-tile, so a chunk split over two tiles may keep one
+    more walk: this count is the least work the kernel does."""
+    d = w.delta.astype(np.int32)
+    nq = d.shape[0]
+    absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
+    sym = w.byte_to_symbol.astype(np.int64)
+    n = x.size
+    nch = (n + chunk - 1) // chunk
+    lens = np.minimum(chunk, n - np.arange(nch, dtype=np.int64) * chunk)
+    pcs, pss = [np.zeros(1, np.int64)], [np.array([int(w.q0)], np.int64)]
+    base = 1
+    for S in start_sets(w, x, chunk, nch, max(lookahead, 1) if lookahead else 0):
+        rr, cc = np.nonzero(S >= 0)
+        pcs.append(rr + base)
+        pss.append(S[rr, cc].astype(np.int64))
+        base += S.shape[0]
+    pc, ps = np.concatenate(pcs), np.concatenate(pss)
+    total = 0
+    t0 = 0
+    for k in range(rounds):
+        last = k + 1 == rounds
+        t1 = 32 << (2 * k)
+        end = lens[pc] if last else np.minimum(lens[pc], t1)
+        total += int(((end - t0 + step - 1) // step).clip(min=0).sum())
+        if last:
+            break
+        for t in range(t0, t1):
+            live = t < lens[pc]
+            if not live.any():
+                break
+            ps = np.where(live, d[ps, sym[x[np.where(live, pc * chunk + t, 0)]]], ps)
+        keep = (lens[pc] > t1) & ~absorbing[ps]
+        pc, ps = pc[keep], ps[keep]
+        key = np.unique(pc * nq + ps)
+        pc, ps = key // nq, key % nq
+        t0 = t1
+    return total
+
+
 def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int, step: int = 1) -> int:
     """len(c_0) + sum_{i>=1} |I_i| len(c_i) (Algorithm 3's work; I_i is the
     chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13).
@@ -652,8 +698,18 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--early-exit", action="store_true",
                     help="stop a wavefront's walks once all its pairs are absorbing")
+    ap.add_argument("--rounds", type=int, default=-1,
+                    help="walk rounds with merging (1 = none, 2..4; -1 = the autotuner's "
+                         "pick, else one)")
+    ap.add_argument("--single-step", action="store_true",
+                    help="one symbol per table lookup even where a two-symbol table exists")
+    ap.add_argument("--chunk-lanes", action="store_true",
+                    help="one chunk per lane with merged walks")
+    ap.add_argument("--interleave", action="store_true",
+                    help="chunk-interleaved code stream (else linear; direct tables: raw input)")
     ap.add_argument("--tune-only", action="store_true",
-                    help="print the autotuner's lookahead and chunk length, then exit")
+                    help="print the autotuner's lookahead, chunk length, early exit and "
+                         "rounds, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
@@ -693,11 +749,19 @@ def main() -> int:
     tuned = None
     if args.lookahead < 0:
         t0 = time.perf_counter()
-        r, c, ms, ex = dfa.dfa_autotune(d, dev_in, stream)
+        r, c, ms, ex, rounds, single, ilv, lanes = dfa.dfa_autotune(d, dev_in, stream)
         tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4), "early_exit": ex,
+                 "rounds": rounds, "single_step": single, "interleave": ilv,
+                 "chunk_lanes": lanes,
                  "tuning_s": round(time.perf_counter() - t0, 2)}
-        log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex} "
+        log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex}, "
+            f"rounds {rounds or 1}, single step {single}, interleave {ilv}, chunk lanes {lanes} "
             f"({ms:.3f} ms)")
+        if args.rounds < 0:
+            args.rounds = rounds
+        args.single_step = args.single_step or single
+        args.interleave = args.interleave or ilv
+        args.chunk_lanes = args.chunk_lanes or lanes
         # the timed run uses early exit only when asked for (--early-exit):
         # its work depends on the data, so the roofline would need the
         # smaller exact count
@@ -706,11 +770,13 @@ def main() -> int:
         if not args.chunk:
             args.chunk = c
         if args.tune_only:
-            print(r, c, int(ex), flush=True)
+            print(r, c, int(ex), rounds, int(single), int(ilv), int(lanes), flush=True)
             return 0
+    args.rounds = max(args.rounds, 0)
     chunk, nch = dfa.dfa_plan_chunks(d, nbytes, args.chunk, args.lookahead)
     opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result,
-                early_exit=args.early_exit)
+                early_exit=args.early_exit, rounds=args.rounds, single_step=args.single_step,
+                interleave=args.interleave, chunk_lanes=args.chunk_lanes)
 
     if args.calibrate_copy:
         scratch = torch.empty_like(dev_in)
@@ -743,7 +809,9 @@ def main() -> int:
 
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
-    plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead)
+    plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead, rounds=args.rounds,
+                        early_exit=args.early_exit, single_step=args.single_step,
+                        interleave=args.interleave, chunk_lanes=args.chunk_lanes)
     step = int(plan.symbols_per_step) if plan.kernel == 1 else 1
     if args.early_exit:
         lookups = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0))
@@ -752,14 +820,21 @@ def main() -> int:
     else:
         lookups = algorithmic_lookups(w, x, chunk, args.lookahead)
         reads = algorithmic_lookups(w, x, chunk, args.lookahead, step) if step > 1 else lookups
+    merged = plan.kernel == 1 and (plan.rounds > 1 or plan.chunk_lanes)
+    if merged:
+        reads = merged_lookups(w, x, chunk, args.lookahead, max(2, int(plan.rounds)), step)
     if plan.kernel == 1:
         lay = 4 if step == 2 else 3 if plan.raw_input else (2 if info.packed_layout == 2 else 1)
-        kernel = f"k_match2<{lay}>"
+        kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
+                  f"k_round<{lay}>" if merged else f"k_match2<{lay}>")
     else:
         kernel = "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
     achieved = reads / (matcher_avg_ms * 1e-3)
     traffic, traffic_src = stored_traffic(kernel, args.workload, args.lookahead, int(chunk))
+    # bytes the walk streams per input byte: raw input or one-byte codes 1,
+    # two-byte codes 2, pair codes 1/2
+    stream_bpb = 0.5 if step == 2 else (2.0 if kernel.endswith("<2>") else 1.0)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -786,6 +861,7 @@ def main() -> int:
             "chunk_bytes": int(chunk),
             "chunks": int(nch),
             "lookups_per_byte": round(lookups / nbytes, 3),
+            "rounds": int(plan.rounds) if plan.kernel == 1 else 1,
         },
         "roofline": {
             "bound": "lds",
@@ -799,13 +875,25 @@ def main() -> int:
             "traffic": traffic,
             "traffic_source": traffic_src,
             "kernel_avg_ms": round(matcher_avg_ms, 4),
-            "hbm_frac": round(nbytes / (matcher_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+            "hbm_frac": round(nbytes * stream_bpb / (matcher_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              5),
         },
         "final_state": fin,
         "accepted": acc,
         "dfa_create_ms": round(create_ms, 2),
         "call_ms_avg": round(call_ms / max(calls, 1), 4),
     }
+
+    if merged:
+        # merged walks do about one walk per chunk after the first round: the
+        # rounds stream the code bytes once, so HBM bounds them
+        rl = line["roofline"]
+        hbm_gbs = nbytes * stream_bpb / (matcher_avg_ms * 1e-3) / 1e9
+        rl.update({"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                   "lds_achieved_glookup_s": round(achieved / 1e9, 2),
+                   "lds_frac": round(achieved / LDS_LOOKUP_PEAK, 4)})
+        rl.pop("hbm_frac", None)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -105,6 +105,51 @@ typedef struct dfa_match_opts {
  * batch) for DFAs with an absorbing state; ignored otherwise. */
 #define DFA_MATCH_EARLY_EXIT 1u
 
+/* flags bit: walk one symbol per table lookup even where the DFA has a
+ * two-symbol table (dfa_info_t::pair_columns > 0).  The two-symbol table
+ * halves the lookups but needs a pass that turns byte pairs into codes; with
+ * a direct table (packed_layout 3) the one-symbol walk reads the input as it
+ * is.  Which is faster depends on how much walking is left after merging
+ * (below); dfa_autotune tries both. */
+#define DFA_MATCH_SINGLE_STEP 2u
+
+/* flags bit: interleave the packed matcher's code stream: the 16-byte code
+ * blocks of 64 consecutive chunks are stored side by side (block b of all 64
+ * contiguous), so that the walks of consecutive chunks read whole cache lines
+ * together.  Without it the stream is linear, chunk after chunk (with a
+ * direct table, packed_layout 3: the raw input itself, no stream written).
+ * Needs chunk lengths of a multiple of 32 and precomputed start sets; ignored
+ * otherwise. */
+#define DFA_MATCH_INTERLEAVE 4u
+
+/* flags bit: one chunk per lane with merged walks.  A lane walks its chunk's
+ * start states (sets of at most 128) four at a time over the first 32 code
+ * positions,
+ * keeps the distinct states reached (the walks of one chunk converge; at most
+ * 4 are kept), walks only those to the chunk's end and gives every start state
+ * the end of its group; a chunk that does not reduce that far is walked state
+ * by state.  Implies DFA_MATCH_INTERLEAVE (chunk lengths of a multiple of 32,
+ * precomputed start sets); ignored otherwise.  The maps, and every result,
+ * are unchanged. */
+#define DFA_MATCH_CHUNK_LANES 8u
+
+/* flags field bits 8..11: walk rounds of the packed matcher.  Walks of one
+ * chunk that reach the same state at the same position have the same future
+ * (delta is a function), so after each round but the last the matcher keeps
+ * one walk per distinct (chunk, state) and the others take its end state.
+ * Round 1 walks the first 32 bytes of every chunk, each later round four
+ * times as far, the last round to the chunk end.  The maps, and so every
+ * result, are unchanged; the work after a round shrinks to the number of
+ * distinct states, which for the automata measured here is about one per
+ * chunk within a few dozen bytes.
+ *   DFA_MATCH_ROUNDS(1) or 0 (the default): one round, every walk runs its
+ *                        whole chunk (Algorithm 3 as written);
+ *   DFA_MATCH_ROUNDS(2..4): that many rounds.
+ * Rounds beyond one need chunk lengths that are multiples of 32 and no early
+ * exit; otherwise a single round runs.  dfa_autotune tries them. */
+#define DFA_MATCH_ROUNDS(k) (((uint32_t)(k) & 0xFu) << 8)
+#define DFA_MATCH_ROUNDS_OF(flags) (((flags) >> 8) & 0xFu)
+
 /* ---------------------------------------------------------------------------
  * dfa_create -- compile a DFA (Q, Sigma, delta, q0, F) (Section 2.1) and keep
  * it resident on the current device.
@@ -177,9 +222,12 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * result (the method is exact); only speed differs.  Inputs beyond 256 MiB
  * are tuned on their first 256 MiB.  The choice is cached per DFA and
  * power-of-two length bucket and used by calls with lookahead
- * DFA_LOOKAHEAD_AUTO.  For a DFA with an absorbing state the best setting is
- * timed again with DFA_MATCH_EARLY_EXIT, which is kept (in best->flags) if
- * faster.
+ * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r and r + 1, a quarter
+ * to four times the chunk) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
+ * interleaved codes (one and two rounds) and one chunk per lane, then the best
+ * with DFA_MATCH_SINGLE_STEP where a two-symbol table exists, and for a DFA
+ * with an absorbing state with DFA_MATCH_EARLY_EXIT; whichever is faster is
+ * kept (in best->flags).
  *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
  *   fastest candidate's time per call (may be NULL).  Synchronises `stream`. */
 int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
@@ -214,6 +262,9 @@ typedef struct dfa_plan_info {
     uint32_t raw_input;       /* 1: the packed matcher reads the input bytes themselves
                                  (direct table: only a validation pass runs first) when
                                  the input is 16-byte aligned */
+    uint32_t rounds;          /* walk rounds with merging (DFA_MATCH_ROUNDS); 1 = none */
+    uint32_t interleaved;     /* 1: chunk-interleaved code stream (DFA_MATCH_INTERLEAVE) */
+    uint32_t chunk_lanes;     /* 1: one chunk per lane with merged walks (DFA_MATCH_CHUNK_LANES) */
 } dfa_plan_info_t;
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 

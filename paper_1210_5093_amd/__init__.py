@@ -49,7 +49,9 @@ class dfa_plan_info_t(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint64), ("num_chunks", ctypes.c_uint64),
                 ("kernel", ctypes.c_uint32), ("lookahead", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("symbols_per_step", ctypes.c_uint32), ("raw_input", ctypes.c_uint32)]
+                ("symbols_per_step", ctypes.c_uint32), ("raw_input", ctypes.c_uint32),
+                ("rounds", ctypes.c_uint32), ("interleaved", ctypes.c_uint32),
+                ("chunk_lanes", ctypes.c_uint32)]
 
 
 class dfa_result_t(ctypes.Structure):
@@ -181,10 +183,23 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 MATCH_EARLY_EXIT = 1
+MATCH_SINGLE_STEP = 2
+MATCH_INTERLEAVE = 4
+MATCH_CHUNK_LANES = 8
 
 
-def _opts(chunk_len: int = 0, lookahead: int = 1, early_exit: bool = False) -> dfa_match_opts_t:
-    return dfa_match_opts_t(int(chunk_len), int(lookahead), MATCH_EARLY_EXIT if early_exit else 0)
+def match_rounds(k: int) -> int:
+    """flags bits of DFA_MATCH_ROUNDS(k): walk rounds with merging (0 = planner)."""
+    return (int(k) & 0xF) << 8
+
+
+def _opts(chunk_len: int = 0, lookahead: int = 1, early_exit: bool = False,
+          rounds: int = 0, single_step: bool = False, interleave: bool = False,
+          chunk_lanes: bool = False) -> dfa_match_opts_t:
+    flags = ((MATCH_EARLY_EXIT if early_exit else 0) | match_rounds(rounds) |
+             (MATCH_SINGLE_STEP if single_step else 0) | (MATCH_INTERLEAVE if interleave else 0) |
+             (MATCH_CHUNK_LANES if chunk_lanes else 0))
+    return dfa_match_opts_t(int(chunk_len), int(lookahead), flags)
 
 
 class DFA:
@@ -285,17 +300,24 @@ def dfa_lookahead_set(d: DFA, lookahead_bytes) -> List[int]:
     return out[:cnt.value].tolist()
 
 
-def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1) -> dfa_plan_info_t:
+def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1, rounds: int = 0,
+             early_exit: bool = False, single_step: bool = False,
+             interleave: bool = False, chunk_lanes: bool = False) -> dfa_plan_info_t:
     out = dfa_plan_info_t()
-    o = _opts(chunk_len, lookahead)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
     _check(lib().dfa_plan(d.handle, int(n), ctypes.byref(o), ctypes.byref(out)))
     return out
 
 
 def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
                  lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
-                 bound_out=None, early_exit: bool = False):
+                 bound_out=None, early_exit: bool = False, rounds: int = 0,
+                 single_step: bool = False, interleave: bool = False, chunk_lanes: bool = False):
     """Test with options; optionally the state at every chunk boundary.
+    rounds: walk rounds with merging (DFA_MATCH_ROUNDS; 0 = the planner's);
+    single_step: one symbol per lookup even with a two-symbol table;
+    interleave: chunk-interleaved code stream (else linear; direct tables: the raw input);
+    chunk_lanes: one chunk per lane with merged walks.
     Returns (result tensor, boundaries tensor or None)."""
     import torch
     result = _result_tensor(result)
@@ -306,7 +328,7 @@ def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 
         bnd = bound_out if bound_out is not None else torch.empty(
             nch + 1, dtype=torch.int32, device="cuda")
         assert bnd.numel() >= nch + 1
-    o = _opts(chunk_len, lookahead, early_exit)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
     _check(lib().dfa_match_ex(d.handle, d_input.data_ptr() if n else None, n,
                               DFA_Q0 if start is None else int(start), ctypes.byref(o),
                               _stream_handle(stream), result.data_ptr(),
@@ -341,14 +363,17 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
     return float(m.value), float(c.value), int(k.value)
 
 
-def dfa_autotune(d: DFA, d_input, stream=None) -> Tuple[int, int, float, bool]:
-    """Tune on a device input: (lookahead r, chunk length, ms per call, early exit)."""
+def dfa_autotune(d: DFA, d_input, stream=None):
+    """Tune on a device input: (lookahead r, chunk length, ms per call, early exit,
+    walk rounds (0 = one), one symbol per lookup, interleaved codes, chunk lanes)."""
     o = dfa_match_opts_t()
     ms = ctypes.c_double()
     n = int(d_input.numel())
     _check(lib().dfa_autotune(d.handle, d_input.data_ptr() if n else None, n,
                               _stream_handle(stream), ctypes.byref(o), ctypes.byref(ms)))
-    return int(o.lookahead), int(o.chunk_len), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT)
+    return (int(o.lookahead), int(o.chunk_len), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT),
+            (int(o.flags) >> 8) & 0xF, bool(o.flags & MATCH_SINGLE_STEP),
+            bool(o.flags & MATCH_INTERLEAVE), bool(o.flags & MATCH_CHUNK_LANES))
 
 
 def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None

@@ -118,8 +118,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     uint64_t chunk = opts->chunk_len ? opts->chunk_len : env_chunk();
     uint32_t look = opts->lookahead;
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, look, &p);
-    p.early_exit = p.packed && (opts->flags & DFA_MATCH_EARLY_EXIT) && d->dev.nabs > 0;
+    int rc = plan_match(d, len, chunk, look, &p, opts->flags);
     if (rc) return rc;
     Workspace *ws = workspace_for(s);
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
@@ -128,9 +127,13 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     const size_t sz_bytes = a256(p.msize_entries * 2);
     size_t need = map_bytes + 2 * sz_bytes;
     size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0,
-           bits_off = 0, mem_off = 0, cset_off = 0;
+           bits_off = 0, mem_off = 0, cset_off = 0, round_off = 0;
     if (p.packed && len) {
-        need += a256(((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64);
+        uint64_t code_stream = ((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64;
+        if (p.ilv_nblk)   // whole groups of 64 chunks of ilv_nblk blocks each
+            code_stream = std::max<uint64_t>(
+                code_stream, ((uint64_t)p.nch + 63) / 64 * 64 * p.ilv_nblk * 16 + 64);
+        need += a256(code_stream);
         bad_off = need;
         need += a256((uint64_t)p.tblocks * 4 * kMaxSegments);
         bsum_off = need;
@@ -148,6 +151,16 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
             need += a256((uint64_t)p.nch * p.bitmap_words * 4);
             mem_off = need;
             need += a256(((uint64_t)p.nch * p.stride + 1) * 2);
+        }
+        if (p.rounds > 1) {
+            // per round: outcomes (4 B per walk or place); rounds >= 1: walk
+            // lists of kRegions regions (8 B per place)
+            const uint64_t walks = p.max_tiles * (uint64_t)match2_tile_pairs(p.slots);
+            const uint64_t places = (uint64_t)kRegions * round_region_cap(p);
+            round_off = need;
+            need += a256((uint64_t)kMaxRounds * kRegions * 4);
+            for (uint32_t k = 0; k < p.rounds; ++k)
+                need += k ? a256(places * 4) + a256(places * 8) : a256(walks * 4);
         }
     }
     rc = ensure(&ws->buf, &ws->bytes, need + 256);
@@ -178,6 +191,21 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         if (p.lookahead == 2) {
             pb.bits = (uint32_t *)(base + bits_off);
             pb.members = (uint16_t *)(base + mem_off);
+        }
+        if (p.rounds > 1) {
+            const uint64_t walks = p.max_tiles * (uint64_t)match2_tile_pairs(p.slots);
+            const uint64_t places = (uint64_t)kRegions * round_region_cap(p);
+            size_t at = round_off;
+            pb.cnt = (uint32_t *)(base + at);
+            at += a256((uint64_t)kMaxRounds * kRegions * 4);
+            for (uint32_t k = 0; k < p.rounds; ++k) {
+                pb.lo[k] = (uint32_t *)(base + at);
+                at += a256((k ? places : walks) * 4);
+                if (k) {
+                    pb.list[k] = (uint2 *)(base + at);
+                    at += a256(places * 8);
+                }
+            }
         }
         if (p.segments > 1) {
             if (!ws->aux) {
@@ -238,7 +266,7 @@ extern "C" int dfa_plan_chunks(const dfa_t *d, size_t len, const dfa_match_opts_
     const dfa_match_opts_t o = resolve_opts(d, len, opts_in);
     uint64_t chunk = o.chunk_len ? o.chunk_len : env_chunk();
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, o.lookahead, &p);
+    int rc = plan_match(d, len, chunk, o.lookahead, &p, o.flags);
     if (rc) return rc;
     if (chunk_len) *chunk_len = p.chunk;
     if (num_chunks) *num_chunks = p.nch;
@@ -251,7 +279,7 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     const dfa_match_opts_t o = resolve_opts(d, len, opts_in);
     uint64_t chunk = o.chunk_len ? o.chunk_len : env_chunk();
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, o.lookahead, &p);
+    int rc = plan_match(d, len, chunk, o.lookahead, &p, o.flags);
     if (rc) return rc;
     out->chunk_len = p.chunk;
     out->num_chunks = p.nch;
@@ -260,7 +288,11 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->blocks = p.packed ? p.blocks2 : p.blocks;
     out->threads = p.packed ? p.threads2 : p.waves_per_block * 64u;
     out->symbols_per_step = p.pairs ? 2u : 1u;
-    out->raw_input = p.packed && !p.pairs && d->dev.direct && p.lookahead != 2 && p.segments <= 1;
+    out->rounds = p.rounds;
+    out->interleaved = p.ilv_nblk ? 1u : 0u;
+    out->chunk_lanes = p.chunk_lanes ? 1u : 0u;
+    out->raw_input = p.packed && !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+                     p.segments <= 1;
     return DFA_OK;
 }
 
@@ -361,6 +393,63 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
             }
         }
         if (rc) break;
+    }
+    auto time_opts = [&](const dfa_match_opts_t &o) -> double {
+        double t_best = 1e30;
+        for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+            if (rep > 0) (void)hipEventRecord(a, s);
+            rc = run_match(d, d_input, n, DFA_Q0, &o, s, res, nullptr);
+            if (rep > 0) {
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t_best = std::min<double>(t_best, ms);
+            }
+        }
+        return t_best;
+    };
+    auto consider = [&](const dfa_match_opts_t &o) {
+        const double t = time_opts(o);
+        if (rc == DFA_OK && t < pick_ms) {
+            pick_ms = t;
+            pick = o;
+        }
+    };
+    // the ways of walking that change which chunk length is best (merged
+    // rounds, interleaved codes, one chunk per lane), each at the best r and
+    // the next, around the best chunk length
+    if (rc == DFA_OK && d->dev.layout != 0) {
+        const dfa_match_opts_t base = pick;
+        uint64_t c0 = base.chunk_len;
+        if (c0 == 0) {
+            MatchPlan p0;
+            if (plan_match(d, n, 0, base.lookahead, &p0, 0) == DFA_OK) c0 = p0.chunk;
+        }
+        const uint32_t variants[] = {DFA_MATCH_ROUNDS(2), DFA_MATCH_ROUNDS(3), DFA_MATCH_ROUNDS(4),
+                                     DFA_MATCH_INTERLEAVE, DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2),
+                                     DFA_MATCH_CHUNK_LANES};
+        for (uint32_t r : {base.lookahead, std::min(base.lookahead + 1, rmax)}) {
+            for (uint32_t v : variants) {
+                for (int sh = -2; sh <= 2 && rc == DFA_OK; ++sh) {
+                    const uint64_t c = sh < 0 ? c0 >> (-sh) : c0 << sh;
+                    if (c < 256 || c % 32 != 0 || c > (1u << 20)) continue;
+                    const uint64_t nch = (n + c - 1) / c;
+                    if (nch > (1u << 20) || nch * per_chunk > (1ull << 30)) continue;
+                    dfa_match_opts_t o{};
+                    o.chunk_len = c;
+                    o.lookahead = r;
+                    o.flags = v;
+                    consider(o);
+                }
+            }
+            if (r == rmax) break;
+        }
+    }
+    if (rc == DFA_OK && d->dev.pairs) {
+        dfa_match_opts_t o = pick;
+        o.flags |= DFA_MATCH_SINGLE_STEP;
+        consider(o);
     }
     if (rc == DFA_OK && d->dev.nabs > 0 && d->dev.layout != 0) {
         // the best setting again with early exit at absorbing states

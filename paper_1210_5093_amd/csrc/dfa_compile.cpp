@@ -314,6 +314,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     uint32_t pairs = 0, rowbytes2 = 0, abs_off2 = 0, npair = 0;
     std::vector<uint16_t> stab2;
     std::vector<uint8_t> pcode(256, 0xFF);
+    std::vector<uint8_t> pcode2;   // direct tables: pair codes indexed by the bytes
     {
         const uint32_t Kc = (uint32_t)class_sym.size();
         if (layout != 0 && Kc >= 1 && Kc <= 63) {
@@ -367,11 +368,25 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
                 for (int b = 0; b < 256; ++b)
                     if (byte_class[b] >= 0) pcode[b] = (uint8_t)byte_class[b];
                 pcode.insert(pcode.end(), pc.begin(), pc.end());
+                if (direct) {
+                    // byte pairs below 128 -> code at b1 + 256 * b2, a lone
+                    // last byte at 32768 + b; 0xFF (odd) for bytes outside Sigma
+                    pcode2.assign(32768 + 128, 0xFF);
+                    for (int b1 = 0; b1 < 128; ++b1) {
+                        if (byte_class[b1] < 0) continue;
+                        pcode2[32768 + b1] = pc[(size_t)byte_class[b1] * (Kc + 1) + Kc];
+                        for (int b2 = 0; b2 < 128; ++b2)
+                            if (byte_class[b2] >= 0)
+                                pcode2[(size_t)b1 + 256 * b2] =
+                                    pc[(size_t)byte_class[b1] * (Kc + 1) + byte_class[b2]];
+                    }
+                }
             }
         }
     }
     if (stab2.empty()) stab2.assign(8, 0);
     pcode.resize(align_up(pcode.size(), 16), 0);
+    if (pcode2.empty()) pcode2.assign(16, 0);
 
     std::vector<uint32_t> accept_bits((nq + 31) / 32, 0);
     for (uint32_t k = 0; k < nacc; ++k) accept_bits[accepting[k] >> 5] |= 1u << (accepting[k] & 31);
@@ -401,6 +416,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     size_t i_stab = add(stab.data(), stab.size() * 2);
     size_t i_stab2 = add(stab2.data(), stab2.size() * 2);
     size_t i_pcode = add(pcode.data(), pcode.size());
+    size_t i_pcode2 = add(pcode2.data(), pcode2.size());
     const size_t arena_bytes = align_up(at, 256);
 
     dfa *d = new (std::nothrow) dfa();
@@ -461,6 +477,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.rowbytes2 = rowbytes2;
     v.abs_off2 = abs_off2;
     v.pcode = (const uint8_t *)ptr(i_pcode);
+    v.pcode2 = pcode2.size() > 16 ? (const uint8_t *)ptr(i_pcode2) : nullptr;
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;

@@ -25,6 +25,9 @@ constexpr uint32_t kMaxStates = 32767;
 constexpr uint32_t kMaxMsetLevel = 8;   // precomputed multi-symbol sets up to this r
 constexpr uint16_t kCodeInvalid = 0xFFFF;
 constexpr uint32_t kMaxSegments = 4;      // translate/match pipeline segments
+constexpr uint32_t kMaxRounds = 4;        // walk rounds with merging (DFA_MATCH_ROUNDS)
+constexpr uint32_t kRound1Bytes = 32;     // bytes of the first round; x4 per later round
+constexpr uint32_t kRegions = 64;         // regions (counters) of a round's walk list
 
 // Device-resident compiled DFA, passed by value to kernels.
 struct DevDFA {
@@ -80,6 +83,9 @@ struct DevDFA {
     uint32_t rowbytes2;          // R2
     uint32_t abs_off2;           // LDS byte offset of its absorbing bitmap
     const uint8_t *pcode;
+    const uint8_t *pcode2;       // direct tables only (else NULL): 32768 + 128 bytes, the
+                                 // pair code of bytes b1, b2 < 128 at b1 + 256 * b2 and of a
+                                 // lone last byte at 32768 + b; 0xFF for bytes outside Sigma
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -125,7 +131,8 @@ struct MatchPlan {
     uint32_t r = 1;              // reverse-lookahead symbols (mode 2: r >= 2)
     uint32_t bitmap_words = 0;   // mode 2: words per chunk bitmap
     uint32_t stride = 0;         // map entries per chunk (>= largest set)
-    uint32_t group = 0;          // maps combined per compose step
+    uint32_t group = 0;          // largest fan-in of a compose step (LDS bound)
+    uint32_t group_l[kMaxLevels] = {};  // fan-in from level l to level l + 1
     uint32_t levels = 0;         // compose levels above level 0
     uint32_t level_count[kMaxLevels] = {};
     uint64_t level_off[kMaxLevels] = {};  // entry offsets of each level's maps
@@ -140,6 +147,10 @@ struct MatchPlan {
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
     uint32_t segments = 1;       // translate/match pipeline segments (1 .. kMaxSegments)
     bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
+    uint32_t rounds = 1;         // walk rounds (> 1: merged walks, chunk % 32 == 0)
+    bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)
+    uint32_t ilv_nblk = 0;       // chunk-interleaved code stream: 16-byte code blocks per
+                                 // chunk (0: linear stream, or the raw input)
     uint32_t blocks2 = 0;        // persistent grid
     uint32_t threads2 = 256;     // threads per block (more for large tables)
     uint32_t tblocks = 0;        // translation blocks (4 KiB of input each)
@@ -147,7 +158,9 @@ struct MatchPlan {
     uint64_t max_tiles = 0;      // upper bound on wave-tiles of pairs
 };
 
-int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p);
+// flags: DFA_MATCH_* bits (early exit, walk rounds)
+int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p,
+               uint32_t flags = 0);
 // ev_after_match (may be null) is recorded right after the matcher kernel.
 int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                  uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,
@@ -163,6 +176,12 @@ struct PackedBufs {
     uint32_t *cset = nullptr;        // precomputed-set id per chunk (r >= 2)
     uint32_t *bits = nullptr;        // r >= 2: start-set bitmaps
     uint16_t *members = nullptr;     // r >= 2: sorted start sets, indexed by pair
+    // merged walks (MatchPlan::rounds > 1): per round k the walks' outcomes
+    // lo[k] (kDone | end state, or the walk's index in list[k + 1]), the
+    // walk lists of rounds >= 1 ({chunk, state}) and their counters
+    uint32_t *lo[kMaxRounds] = {};
+    uint2 *list[kMaxRounds] = {};
+    uint32_t *cnt = nullptr;         // [kMaxRounds][kRegions]
     // segmented pipeline (MatchPlan::segments > 1): translation runs on `aux`,
     // segment by segment, while the matcher works on the previous segment
     hipStream_t aux = nullptr;
@@ -240,6 +259,8 @@ int timing_end(hipStream_t s, hipEvent_t ev[4]);
 int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
                      uint32_t *tile_first, uint32_t tile, hipStream_t s);
 uint32_t match2_tile_pairs(uint32_t slots);
+uint32_t round_region_cap(const MatchPlan &p);   // places per region of a walk list
+size_t round_lds_extra();                         // LDS the round kernels add after the table
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();
 size_t tree_lds_bytes(uint32_t G, uint32_t stride);   // LDS of k_compose_tree

@@ -81,6 +81,33 @@ __global__ __launch_bounds__(256) void k_compose(const uint16_t *__restrict__ in
 // t's entries start at first[t] - first[group start]) or strided (`stride_in`
 // entries per map, domain sizes in in_msize); every domain holds at most
 // stride_in entries.  Output maps are strided.
+// The result record from the top map's single entry (chunk 0's domain is the
+// start state): the final state, its accept bit, and the flags.
+struct FinalArgs {
+    const uint32_t *accept_bits;
+    uint32_t nq;
+    uint32_t nch;
+    uint32_t *result;        // NULL: not the top level
+    uint32_t *boundaries;    // optional: boundaries[nch] = final state
+};
+
+__device__ __forceinline__ void write_result(const FinalArgs &fa, uint32_t v, bool symbol) {
+    uint32_t flags = 0, fin = 0xFFFFFFFFu, acc = 0;
+    if (symbol) {
+        flags |= DFA_FLAG_SYMBOL;
+    } else if (!(v & kTerm) || (v & 0x7FFFu) >= fa.nq) {
+        flags |= DFA_FLAG_SPECULATION;
+    } else {
+        fin = v & 0x7FFFu;
+        acc = (fa.accept_bits[fin >> 5] >> (fin & 31)) & 1u;
+    }
+    fa.result[0] = fin;
+    fa.result[1] = acc;
+    fa.result[2] = flags;
+    fa.result[3] = fa.nch;
+    if (fa.boundaries) fa.boundaries[fa.nch] = fin;
+}
+
 __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restrict__ in_maps,
                                                        const uint32_t *__restrict__ first,
                                                        const uint16_t *__restrict__ in_msize,
@@ -88,7 +115,8 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
                                                        uint32_t G, uint32_t emax,
                                                        uint16_t *__restrict__ out_maps,
                                                        uint32_t stride_out,
-                                                       uint16_t *__restrict__ out_msize) {
+                                                       uint16_t *__restrict__ out_msize,
+                                                       FinalArgs fa) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t flag;
     uint32_t *off = reinterpret_cast<uint32_t *>(smem);                      // [G + 1]
@@ -134,7 +162,10 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
     }
     const uint32_t m0 = dom[0];
     for (uint32_t p = threadIdx.x; p < m0; p += T) out_maps[(size_t)g * stride_out + p] = sm[p];
-    if (threadIdx.x == 0) out_msize[g] = (uint16_t)(m0 | (flag ? kFlagSymbol : 0));
+    if (threadIdx.x == 0) {
+        out_msize[g] = (uint16_t)(m0 | (flag ? kFlagSymbol : 0));
+        if (fa.result) write_result(fa, sm[0], flag != 0);
+    }
 }
 
 // Down-sweep: the value at the start of group g (bv_up[g], or position 0 at
@@ -193,21 +224,8 @@ __global__ void k_finalize(DevDFA d, const uint16_t *__restrict__ top_map,
                            const uint16_t *__restrict__ top_msize, uint32_t nch,
                            uint32_t *__restrict__ result, uint32_t *__restrict__ boundaries) {
     if (threadIdx.x != 0) return;
-    const uint32_t v = top_map[0];
-    uint32_t flags = 0, fin = 0xFFFFFFFFu, acc = 0;
-    if (top_msize[0] & kFlagSymbol) {
-        flags |= DFA_FLAG_SYMBOL;
-    } else if (!(v & kTerm) || (v & 0x7FFFu) >= d.nq) {
-        flags |= DFA_FLAG_SPECULATION;
-    } else {
-        fin = v & 0x7FFFu;
-        acc = (d.accept_bits[fin >> 5] >> (fin & 31)) & 1u;
-    }
-    result[0] = fin;
-    result[1] = acc;
-    result[2] = flags;
-    result[3] = nch;
-    if (boundaries) boundaries[nch] = fin;
+    write_result(FinalArgs{d.accept_bits, d.nq, nch, result, boundaries}, top_map[0],
+                 (top_msize[0] & kFlagSymbol) != 0);
 }
 
 __global__ void k_empty(DevDFA d, uint32_t start, uint32_t *__restrict__ result,
@@ -285,7 +303,8 @@ size_t tree_lds_bytes(uint32_t G, uint32_t stride) {
 int device_lds_bytes() { return props().lds; }
 int device_cu_count() { return props().cus; }
 
-int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p) {
+int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p,
+               uint32_t flags) {
     *p = MatchPlan();
     p->n = n;
     // r >= 2 needs the packed matcher (bitmaps); without a packed layout the
@@ -331,7 +350,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // multiples (16-byte blocks of pair codes) and per-byte codes for the
     // window pass.  DFA_PAIRS=0 keeps one symbol per step.
     const char *fpairs = std::getenv("DFA_PAIRS");
-    p->pairs = p->packed && d->dev.pairs && p->lookahead != 2 &&
+    p->pairs = p->packed && d->dev.pairs && p->lookahead != 2 && !(flags & DFA_MATCH_SINGLE_STEP) &&
                !(fpairs && fpairs[0] == '0') && (chunk_req == 0 || chunk_req % 32 == 0);
     if (p->packed) {
         // two pairs per lane when the start sets are tiny (many chunks per
@@ -350,7 +369,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         p->threads2 = 64u * std::min<uint32_t>(16u, std::max<uint32_t>(4u, (32u + per_cu - 1) / per_cu));
         p->blocks2 = (uint32_t)cus * per_cu;
         p->code_bytes = d->dev.layout == 1 ? 1u : 2u;
-        p->tblocks = (uint32_t)std::min<uint64_t>((n + 4095) / 4096, (uint64_t)cus * 8u);
+        // translation grid: 8 blocks per CU; 4 with the 33 KB pair-code table
+        // of direct tables (each block stages it)
+        const uint32_t tpc = p->pairs && d->dev.pcode2 ? 4u : 8u;
+        p->tblocks = (uint32_t)std::min<uint64_t>((n + 4095) / 4096, (uint64_t)cus * tpc);
         if (chunk_req == 0) {
             // about six wave-tiles of pairs per resident wavefront
             const double mean = std::max(1.0, p->lookahead == 0 ? (double)d->setmax_host[0]
@@ -381,10 +403,51 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     }
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
+    p->early_exit = p->packed && (flags & DFA_MATCH_EARLY_EXIT) && d->dev.nabs > 0;
+    // chunk-interleaved codes: the packed matcher's chunks are whole blocks
+    // of 64 consecutive chunks' code streams; the window pass reads codes
+    // across chunk ends, so it keeps the linear stream
+    if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) && p->segments == 1 &&
+        p->lookahead != 2 && chunk % 32 == 0) {
+        const uint64_t bytes_per_chunk = p->pairs ? chunk / 2 : chunk * p->code_bytes;
+        p->ilv_nblk = (uint32_t)(bytes_per_chunk / 16);
+    }
+    // one chunk per lane (merged walks): interleaved codes and precomputed
+    // sets; a lane walks every start state over the prefix, so sets are
+    // bounded (128) to keep that serial part short
+    {
+        uint32_t set_bound = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
+        if (p->lookahead == 3) set_bound = d->mset_max[std::min(p->r, d->dev.r0)];
+        p->chunk_lanes = (flags & DFA_MATCH_CHUNK_LANES) && p->ilv_nblk && !p->early_exit &&
+                         p->lookahead != 2 && set_bound <= 128;
+    }
+    // merged walks: two rounds unless asked otherwise; the last round must
+    // start inside a chunk
+    {
+        const uint32_t req = DFA_MATCH_ROUNDS_OF(flags);
+        uint32_t rounds = std::min<uint32_t>(req ? req : 1u, kMaxRounds);
+        if (!p->packed || p->segments > 1 || p->early_exit || chunk % 32 != 0 || p->chunk_lanes)
+            rounds = 1;
+        while (rounds > 1 && ((uint64_t)kRound1Bytes << (2 * (rounds - 2))) >= chunk) --rounds;
+        p->rounds = rounds;
+    }
     // compose fan-in: G maps of `stride` entries staged in LDS for the tree
     // composition
     const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);
     p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(1024, stage / (2ull * p->stride + 8)));
+    // The first level takes a smaller fan-in when that spreads its groups
+    // over at least two workgroups per CU without adding a level (131072
+    // chunks: 512 groups of 256, then one group of 512).
+    auto count_levels = [&](uint64_t g0) {
+        uint32_t lv = 0;
+        for (uint64_t c = nch; c > 1; c = (c + (lv == 0 ? g0 : p->group) - 1) / (lv == 0 ? g0 : p->group))
+            ++lv;
+        return lv;
+    };
+    uint64_t g0 = p->group;
+    const uint32_t lv_max = count_levels(g0);
+    while (g0 > 64 && (nch + g0 - 1) / g0 < 2ull * (uint64_t)cus && count_levels(g0 / 2) == lv_max)
+        g0 /= 2;
     uint64_t cnt = nch, moff = 0, soff = 0;
     uint32_t L = 0;
     p->level_count[0] = (uint32_t)cnt;
@@ -394,7 +457,8 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     soff += cnt;
     while (cnt > 1) {
         if (L + 1 >= kMaxLevels) return fail(DFA_E_TOOBIG, "too many compose levels");
-        cnt = (cnt + p->group - 1) / p->group;
+        p->group_l[L] = (uint32_t)(L == 0 ? g0 : p->group);
+        cnt = (cnt + p->group_l[L] - 1) / p->group_l[L];
         ++L;
         p->level_count[L] = (uint32_t)cnt;
         p->level_off[L] = moff;
@@ -451,22 +515,27 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
                    uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
                    uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s) {
     hipError_t e;
-    const uint32_t emax = p.group * p.stride;
-    const size_t lds = tree_lds_bytes(p.group, p.stride);
     for (uint32_t l = 0; l < p.levels; ++l) {
-        // level 0 of the packed matcher is pair-indexed; every other level strided
+        // level 0 of the packed matcher is pair-indexed; every other level
+        // strided.  The last level (one group) also writes the result.
+        const uint32_t G = p.group_l[l];
         const uint32_t *first = (l == 0 && pb) ? pb->first : nullptr;
-        hipLaunchKernelGGL(k_compose_tree, dim3(p.level_count[l + 1]), dim3(1024), lds, s,
-                           maps + p.level_off[l], first, msize + p.msize_off[l], p.level_count[l],
-                           p.stride, p.group, emax, maps + p.level_off[l + 1], p.stride,
-                           msize + p.msize_off[l + 1]);
+        const bool top = l + 1 == p.levels;
+        FinalArgs fa{d->dev.accept_bits, d->dev.nq, p.nch, top ? d_result : nullptr,
+                     top ? d_boundaries : nullptr};
+        hipLaunchKernelGGL(k_compose_tree, dim3(p.level_count[l + 1]), dim3(1024),
+                           tree_lds_bytes(G, p.stride), s, maps + p.level_off[l], first,
+                           msize + p.msize_off[l], p.level_count[l], p.stride, G, G * p.stride,
+                           maps + p.level_off[l + 1], p.stride, msize + p.msize_off[l + 1], fa);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "k_compose_tree launch");
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d->dev, maps + p.level_off[p.levels],
-                       msize + p.msize_off[p.levels], p.nch, d_result, d_boundaries);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "k_finalize launch");
+    if (p.levels == 0) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d->dev, maps, msize, p.nch,
+                           d_result, d_boundaries);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "k_finalize launch");
+    }
     if (d_boundaries) {
         // bvals reuses the msize offsets (one value per map at every level)
         for (int l = (int)p.levels; l >= 1; --l) {
@@ -479,8 +548,8 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
             const uint32_t n_up = p.level_count[l];
             const uint16_t *up = (l == (int)p.levels) ? nullptr : bvals + p.msize_off[l];
             hipLaunchKernelGGL(k_down, dim3((n_up + 255) / 256), dim3(256), 0, s,
-                               maps + p.level_off[l - 1], p.level_count[l - 1], p.stride, p.group,
-                               up, n_up, bvals + p.msize_off[l - 1]);
+                               maps + p.level_off[l - 1], p.level_count[l - 1], p.stride,
+                               p.group_l[l - 1], up, n_up, bvals + p.msize_off[l - 1]);
         }
         if (p.levels == 0) {
             hipLaunchKernelGGL(k_down, dim3(1), dim3(256), 0, s, maps, 1u, p.stride, 1u,

@@ -23,8 +23,8 @@
 // The table sits at LDS address 0 (the kernel has no static LDS), so stored
 // table entries are LDS addresses themselves.
 //
-// Kernels: k_translate (bytes -> codes, invalid-byte flags), k_chunkinfo
-// (lookahead class and |I| per chunk), k_scan (exclusive prefix of set
+// Kernels: k_translate (bytes -> codes, invalid-byte flags), k_scan
+// (lookahead class or set and |I| per chunk, exclusive prefix of the set
 // sizes = first pair of each chunk), k_match2 (persistent tiles of pairs).
 // The sparse maps it writes have the same form as the one-chunk-per-wave
 // matcher's, so the combination kernels are shared.
@@ -43,16 +43,46 @@ namespace dfaspec {
 // ---------------------------------------------------------------------------
 constexpr int kTrU = 4;
 
-// The grid walk shared by the translation kernels: convert(tag, w, first)
-// handles the 16 input bytes at `first` (tag: std::true_type when all lie
-// before n).  Whole rounds of an aligned input load kTrU blocks per thread
+// Chunk-interleaved code stream: with chunks of nblk 16-byte code blocks,
+// block b of chunk c is unit ((c / 64) * nblk + b) * 64 + c % 64, so that the
+// walks of 64 consecutive chunks read one contiguous KiB per block.  nblk = 0:
+// the linear stream (unit c * nblk + b, i.e. the byte offset itself).
+struct Ilv {
+    uint32_t nblk;     // 16-byte code blocks per chunk; 0 = linear
+    uint32_t nch;
+    uint64_t chunk;    // input bytes per chunk
+};
+
+// Where byte `ob` of the linear code stream goes (a store never crosses a
+// 16-byte unit): the linear stream itself, or its interleaved place for the
+// chunk c the grid is converting.
+struct LinearSink {
+    uint8_t *out;
+    __device__ __forceinline__ uint8_t *at(uint64_t ob) const { return out + ob; }
+};
+struct IlvSink {
+    uint8_t *out;
+    uint32_t nblk;
+    uint32_t c;
+    uint64_t base;           // linear offset of chunk c's first code byte
+    __device__ __forceinline__ uint8_t *at(uint64_t ob) const {
+        const uint32_t b = (uint32_t)((ob - base) >> 4);
+        const uint64_t unit = ((uint64_t)(c >> 6) * nblk + b) * 64u + (c & 63u);
+        return out + unit * 16u + (ob & 15u);
+    }
+};
+
+// The grid walk shared by the translation kernels: convert(tag, w, first,
+// sink) handles the 16 input bytes at `first` (tag: std::true_type when all
+// lie before n) and stores its codes through the sink.  Whole rounds of an aligned input load kTrU blocks per thread
 // before converting any (block u of a round is u * threads + thread, so every
 // load instruction is coalesced): with one 16-byte load in flight per lane a
 // pass is bound by memory latency well below HBM bandwidth.  The last partial
 // round and misaligned inputs go one block at a time.
 template <typename Conv>
 __device__ __forceinline__ void translate_grid(const uint8_t *__restrict__ in, uint64_t n,
-                                               Conv &convert) {
+                                               uint8_t *out, Conv &convert) {
+    const LinearSink sink{out};
     const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t base = 0;
@@ -65,15 +95,56 @@ __device__ __forceinline__ void translate_grid(const uint8_t *__restrict__ in, u
 #pragma unroll
             for (int u = 0; u < kTrU; ++u) {
                 const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-                convert(std::true_type{}, w, base + ((uint64_t)u * T + tid) * 16);
+                convert(std::true_type{}, w, base + ((uint64_t)u * T + tid) * 16, sink);
             }
         }
     }
     for (uint64_t first = base + tid * 16; first < n; first += T * 16) {
         uint32_t w[4];
         load16(in, first, n, w);
-        if (first + 16 <= n) convert(std::true_type{}, w, first);
-        else convert(std::false_type{}, w, first);
+        if (first + 16 <= n) convert(std::true_type{}, w, first, sink);
+        else convert(std::false_type{}, w, first, sink);
+    }
+}
+
+// Grid walk of the interleaved translation.  A wave takes 64 / PIECES
+// consecutive chunks (lane l: chunk l / PIECES, piece l % PIECES) and goes
+// through their code blocks a quad (4 blocks, PIECES 16-byte input pieces per
+// chunk) at a time, kTrU quads in flight, so that loads are contiguous per
+// chunk and every block's stores of the wave are contiguous too.
+template <int PIECES, typename Conv>
+__device__ __forceinline__ void translate_ilv_grid(const uint8_t *__restrict__ in, uint64_t n,
+                                                   uint8_t *out, const Ilv &v,
+                                                   uint64_t code_bytes_per_chunk, Conv &convert) {
+    constexpr uint32_t kCpw = 64 / PIECES;
+    const uint32_t nquad = (v.nblk + 3) / 4;
+    const uint32_t nsg = (v.nch + kCpw - 1) / kCpw;
+    const uint64_t span = (uint64_t)PIECES * 16u;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t cc = lane / PIECES, k = lane % PIECES;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t sg = wave; sg < nsg; sg += nwaves) {
+        const uint32_t c = sg * kCpw + cc;
+        const bool live = c < v.nch;
+        const uint64_t c0 = (uint64_t)c * v.chunk;
+        const uint64_t end = live ? min<uint64_t>(c0 + v.chunk, n) : 0u;
+        const IlvSink sink{out, v.nblk, c, (uint64_t)c * code_bytes_per_chunk};
+        for (uint32_t q0 = 0; q0 < nquad; q0 += kTrU) {
+            uint32_t w[kTrU][4];
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u) {
+                const uint64_t first = c0 + (uint64_t)(q0 + u) * span + 16u * k;
+                if (first < end) load16(in, first, n, w[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u) {
+                const uint64_t first = c0 + (uint64_t)(q0 + u) * span + 16u * k;
+                if (first >= end) continue;
+                if (first + 16 <= n) convert(std::true_type{}, w[u], first, sink);
+                else convert(std::false_type{}, w[u], first, sink);
+            }
+        }
     }
 }
 
@@ -86,7 +157,7 @@ template <typename CodeT, bool WRITE = true>
 __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ in, uint64_t n,
                                                    const uint16_t *__restrict__ code_lut,
                                                    CodeT *__restrict__ out,
-                                                   uint32_t *__restrict__ block_bad) {
+                                                   uint32_t *__restrict__ block_bad, Ilv ilv) {
     // one-byte codes (< 256) are staged with bytes outside Sigma as 0xFF00:
     // the low byte (the code written) is 0 and an OR of the entries flags them
     constexpr bool kNarrow = sizeof(CodeT) == 1;
@@ -100,7 +171,7 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
     __syncthreads();
     uint32_t bad = 0;
     // WHOLE: all 16 bytes lie before n (no per-byte bounds)
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) {
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
         constexpr bool WHOLE = decltype(whole_tag)::value;
         uint32_t c[16];
         if constexpr (WHOLE) {
@@ -135,17 +206,21 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
             o.y = pack_low_bytes(c[4], c[5], c[6], c[7]);
             o.z = pack_low_bytes(c[8], c[9], c[10], c[11]);
             o.w = pack_low_bytes(c[12], c[13], c[14], c[15]);
-            *reinterpret_cast<uint4 *>(out + first) = o;
+            *reinterpret_cast<uint4 *>(sink.at(first)) = o;
         } else {
             uint4 o[2];
             uint32_t *ow = reinterpret_cast<uint32_t *>(o);
 #pragma unroll
             for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
-            *reinterpret_cast<uint4 *>(out + first) = o[0];
-            *reinterpret_cast<uint4 *>(out + first + 8) = o[1];
+            *reinterpret_cast<uint4 *>(sink.at(2 * first)) = o[0];
+            *reinterpret_cast<uint4 *>(sink.at(2 * first + 16)) = o[1];
         }
     };
-    translate_grid(in, n, convert);
+    uint8_t *ob = reinterpret_cast<uint8_t *>(out);
+    if (WRITE && ilv.nblk)
+        translate_ilv_grid<kNarrow ? 4 : 2>(in, n, ob, ilv, (uint64_t)ilv.nblk * 16u, convert);
+    else
+        translate_grid(in, n, ob, convert);
     if (bad) atomicOr(&bad_any, 1u);
     __syncthreads();
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
@@ -158,7 +233,7 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
 __global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restrict__ in, uint64_t n,
                                                          const uint8_t *__restrict__ pcode,
                                                          uint32_t K, uint8_t *__restrict__ out,
-                                                         uint32_t *__restrict__ block_bad) {
+                                                         uint32_t *__restrict__ block_bad, Ilv ilv) {
     // pc covers every index c1 * (K + 1) + c2 with c1, c2 <= 255, so that a
     // class 0xFF (byte outside Sigma) reads a staged value: a pair code, or 0
     // past the K x (K + 1) codes; such blocks are flagged and their codes
@@ -176,7 +251,7 @@ __global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restri
     __syncthreads();
     const uint32_t K1 = K + 1;
     uint32_t bad = 0;
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) {
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
         constexpr bool WHOLE = decltype(whole_tag)::value;
         uint32_t c[8];
         if constexpr (WHOLE) {
@@ -202,33 +277,75 @@ __global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restri
                 c[k] = (in1 && !bad1 && !bad2) ? (uint32_t)pc[c1 * K1 + c2] : 0u;
             }
         }
-        *reinterpret_cast<uint2 *>(out + first / 2) =
+        *reinterpret_cast<uint2 *>(sink.at(first / 2)) =
             make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
     };
-    translate_grid(in, n, convert);
+    if (ilv.nblk) translate_ilv_grid<8>(in, n, out, ilv, (uint64_t)ilv.nblk * 16u, convert);
+    else translate_grid(in, n, out, convert);
     if (bad) atomicOr(&bad_any, 1u);
     __syncthreads();
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
 }
 
-// Lookahead class and set size of every chunk (chunk 0: the start state).
-__global__ void k_chunkinfo(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
-                            uint32_t nch, uint32_t mode, uint16_t *__restrict__ msize,
-                            uint16_t *__restrict__ ccls) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nch) return;
-    uint32_t m = 1, cls = 0;
-    if (i > 0) {
-        const uint32_t e = d.lut[in[(uint64_t)i * chunk - 1]];
-        if (e == kLutInvalid) {
-            m = 0;
-        } else {
-            cls = e >> 24;
-            m = d.set_off[mode][cls + 1] - d.set_off[mode][cls];
+// Two-symbol translation for direct tables (every byte of Sigma below 128):
+// one LDS lookup per pair, pc2[b1 + 256 * b2] (a lone last byte: pc2[32768 +
+// b]).  Entries of bytes outside Sigma are 0xFF (odd, unlike every code); a
+// block whose OR of entries is odd or that holds a byte >= 128 is redone on
+// the checked path, which writes 0 for such pairs.
+__global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *__restrict__ in,
+                                                                uint64_t n,
+                                                                const uint8_t *__restrict__ pcode2,
+                                                                uint8_t *__restrict__ out,
+                                                                uint32_t *__restrict__ block_bad,
+                                                                Ilv ilv) {
+    constexpr uint32_t kPc2 = 32768u + 128u;
+    __shared__ __align__(16) uint8_t pc2[kPc2];
+    __shared__ uint32_t bad_any;
+    for (uint32_t i = threadIdx.x; i < kPc2 / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(pc2)[i] = reinterpret_cast<const uint4 *>(pcode2)[i];
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    auto checked = [&](const uint32_t (&w)[4], uint64_t first, uint32_t (&c)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
+            const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
+            const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
+            uint32_t v = 0xFFu;
+            if (in2) {
+                if (b1 < 128u && b2 < 128u) v = pc2[b1 + 256u * b2];
+            } else if (b1 < 128u) {
+                v = pc2[32768u + b1];
+            }
+            const bool inv = in1 && (v & 1u);
+            bad |= inv ? 1u : 0u;
+            c[k] = (!in1 || inv) ? 0u : v;
         }
-    }
-    msize[i] = (uint16_t)m;
-    ccls[i] = (uint16_t)cls;
+    };
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[8];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                c[k] = pc2[(w[k >> 1] >> (16 * (k & 1))) & 0x7F7Fu];
+                acc |= c[k];
+            }
+            const uint32_t high = (w[0] | w[1] | w[2] | w[3]) & 0x80808080u;
+            if ((acc & 1u) || high) checked(w, first, c);
+        } else {
+            checked(w, first, c);
+        }
+        *reinterpret_cast<uint2 *>(sink.at(first / 2)) =
+            make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+    };
+    if (ilv.nblk) translate_ilv_grid<8>(in, n, out, ilv, (uint64_t)ilv.nblk * 16u, convert);
+    else translate_grid(in, n, out, convert);
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
 }
 
 // Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
@@ -242,26 +359,9 @@ __global__ void k_chunkinfo(DevDFA d, const uint8_t *__restrict__ in, uint64_t c
 // state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
 // lays out the start sets as sorted member lists.
 //
-// r <= r0: the start set of chunk i >= 1 is the precomputed I_{c_1..c_k} of
-// its k = min(r, p) lookahead bytes (Eq. 13).
-__global__ void k_chunkinfo_m(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
-                              uint32_t nch, uint32_t r, uint16_t *__restrict__ msize,
-                              uint32_t *__restrict__ cset) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nch) return;
-    uint32_t m = 1, id = 0;
-    if (i > 0) {
-        const uint64_t p = (uint64_t)i * chunk;
-        const uint32_t k = (uint32_t)min<uint64_t>(r, p);
-        bool bad = false;
-        id = class_string_id(d, in, p - k, k, &bad);
-        m = bad ? 0u : mset_end(d, k, id) - mset_begin(d, k, id);
-    }
-    msize[i] = (uint16_t)m;
-    cset[i] = id;
-}
-
-// r > r0: window pairs start from the precomputed set of the window's first
+// For r <= r0 the start set of chunk i >= 1 is the precomputed I_{c_1..c_k}
+// of its k = min(r, p) lookahead bytes (chunk_info, in the scan's first
+// phase).  r > r0: window pairs start from the precomputed set of the window's first
 // k0 = min(r', r0) bytes; cset holds that set's id.  Clears the bitmaps.
 __global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
                               uint32_t nch, uint32_t r, uint32_t W,
@@ -340,13 +440,90 @@ __global__ __launch_bounds__(1024) void k_scan_sums(ScanSrc q, uint32_t *__restr
     if (threadIdx.x == blockDim.x - 1) bsum[blockIdx.x] = inc;
 }
 
+// The first phase fused with the per-chunk lookahead information of modes
+// 0, 1 (class sets: ccls) and 3 (precomputed multi-symbol sets: cset): the
+// sizes it sums are computed here and written to msize for the later phases.
+struct InfoSrc {
+    DevDFA d;
+    const uint8_t *in;
+    uint64_t chunk;
+    uint32_t mode;
+    uint32_t r;
+    uint16_t *ccls;
+    uint32_t *cset;
+};
+
+__device__ __forceinline__ uint32_t chunk_info(const InfoSrc &f, uint64_t i) {
+    uint32_t m = 1, id = 0;
+    if (i > 0) {
+        const uint64_t p = i * f.chunk;
+        if (f.mode == 3) {
+            const uint32_t k = (uint32_t)min<uint64_t>(f.r, p);
+            bool bad = false;
+            if (k <= 8 && p >= 8 && ((reinterpret_cast<uintptr_t>(f.in) + p) & 7u) == 0) {
+                // the 8 bytes before p in one aligned load; the k class
+                // lookups are independent
+                const uint64_t wv = *reinterpret_cast<const uint64_t *>(f.in + p - 8);
+                uint32_t cls[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cls[j] = f.d.lut[(uint32_t)(wv >> (8 * j)) & 0xFFu];
+                for (uint32_t j = 8 - k; j < 8; ++j) {
+                    if (cls[j] == kLutInvalid) { bad = true; id = 0; break; }
+                    id = id * f.d.nclass + (cls[j] >> 24);
+                }
+            } else {
+                id = class_string_id(f.d, f.in, p - k, k, &bad);
+            }
+            m = bad ? 0u : mset_end(f.d, k, id) - mset_begin(f.d, k, id);
+        } else {
+            const uint32_t e = f.d.lut[f.in[p - 1]];
+            if (e == kLutInvalid) {
+                m = 0;
+            } else {
+                id = e >> 24;
+                m = f.d.set_off[f.mode][id + 1] - f.d.set_off[f.mode][id];
+            }
+        }
+    }
+    if (f.mode == 3) f.cset[i] = id;
+    else f.ccls[i] = (uint16_t)id;
+    return m;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums_info(ScanSrc q, InfoSrc f,
+                                                         uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint16_t ms[kScanBlock];
+    // the block's chunks are computed strided over the threads (independent,
+    // coalesced), then summed in consecutive runs for the scan
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanItems; ++k) {
+        const uint32_t t = k * kScanThreads + threadIdx.x;
+        uint32_t m = 0;
+        if (b0 + t < q.nch) {
+            m = chunk_info(f, b0 + t);
+            q.msize[b0 + t] = (uint16_t)m;
+        }
+        ms[t] = (uint16_t)m;
+    }
+    __syncthreads();
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanItems; ++k) v += ms[threadIdx.x * kScanItems + k];
+    const uint32_t inc = block_inclusive_scan(v, part);
+    if (threadIdx.x == blockDim.x - 1) bsum[blockIdx.x] = inc;
+}
+
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ bsum, uint32_t nb,
                                                    uint16_t *__restrict__ msize, uint32_t nch,
                                                    const uint32_t *__restrict__ block_bad,
-                                                   uint32_t nbad, uint32_t *__restrict__ first) {
+                                                   uint32_t nbad, uint32_t *__restrict__ first,
+                                                   uint32_t *__restrict__ zero, uint32_t nzero) {
     __shared__ uint32_t part[kScanThreads];
     __shared__ uint32_t bad_any;
     const uint32_t t = threadIdx.x, T = blockDim.x;
+    if (t < nzero) zero[t] = 0;   // counters of the merged-walk rounds
     if (t == 0) bad_any = 0;
     uint32_t bad = 0;
     for (uint32_t b = t; b < nbad; b += T) bad |= block_bad[b];
@@ -435,7 +612,17 @@ struct Match2Args {
     uint32_t exit_base;      // early exit: LDS byte offset of the absorbing bitmap (0 = off)
     uint32_t exit_shift;
     uint32_t c_lo, c_hi;     // this launch walks the pairs of chunks [c_lo, c_hi)
+    uint32_t tile;           // pairs per wave-tile (64 * slots)
+    uint32_t ilv_nblk;       // chunk-interleaved codes: 16-byte blocks per chunk; 0 = linear
 };
+
+// First 16-byte unit of block b of chunk c in the code stream, and the
+// distance between a chunk's consecutive blocks.
+__device__ __forceinline__ uint32_t code_unit(const Match2Args &a, uint32_t c, uint32_t b,
+                                              uint32_t per_chunk_linear) {
+    if (a.ilv_nblk) return ((c >> 6) * a.ilv_nblk + b) * 64u + (c & 63u);
+    return c * per_chunk_linear + b;
+}
 
 template <int L>
 __device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
@@ -443,6 +630,39 @@ __device__ __forceinline__ void stage_table(const DevDFA &d, uint8_t *smem) {
     uint4 *dst = reinterpret_cast<uint4 *>(smem);
     for (uint32_t i = threadIdx.x; i < d.stab_bytes / 16; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
+}
+
+// Map entry of a walk of chunk c that ended in state e: kTerm | e for the
+// last chunk or an absorbing e, else e's position in chunk c + 1's start set.
+__device__ __forceinline__ uint16_t map_entry(const Match2Args &a, uint32_t c, uint32_t e) {
+    if (c + 1 == a.nch) return (uint16_t)(kTerm | e);
+    if (a.mode == 2) {
+        const uint16_t ab = a.d.pos[1][e];   // class-0 row: kTerm|e iff absorbing
+        return ab == (uint16_t)(kTerm | e)
+                   ? ab
+                   : (uint16_t)member_rank(a.members, a.first[c + 1], a.first[c + 2], e);
+    }
+    if (a.mode == 3) {
+        const uint16_t ab = a.d.pos[1][e];
+        const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)(c + 1) * a.chunk);
+        const uint32_t id = a.cset[c + 1];
+        return ab == (uint16_t)(kTerm | e)
+                   ? ab
+                   : (uint16_t)member_rank(a.d.mset_st + a.d.mst[k], mset_begin(a.d, k, id),
+                                           mset_end(a.d, k, id), e);
+    }
+    return a.d.pos[a.mode][(size_t)a.ccls[c + 1] * a.d.nq + e];
+}
+
+// Start state of pair P (chunk c >= 0 of the pair numbering).
+__device__ __forceinline__ uint32_t pair_start(const Match2Args &a, uint32_t c, uint32_t P) {
+    if (c == 0) return a.start;
+    if (a.mode == 2) return a.members[P];
+    if (a.mode == 3) {
+        const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)c * a.chunk);
+        return a.d.mset_st[a.d.mst[k] + mset_begin(a.d, k, a.cset[c]) + (P - a.first[c])];
+    }
+    return a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
 }
 
 // Window pass: pair P of chunk c starts at the (P - first[c])-th state of
@@ -544,22 +764,10 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
             const uint32_t P = tile * kTile + j * kWave2 + lane;
             const bool valid = P >= p_lo && P < p_hi;
             const uint32_t c = valid ? owner_chunk(a.first, lo0, hi0, P) : 0u;
-            uint32_t s = 0;
-            if (valid) {
-                if (c == 0) {
-                    s = a.start;
-                } else if (a.mode == 2) {
-                    s = a.members[P];
-                } else if (a.mode == 3) {
-                    const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)c * a.chunk);
-                    s = a.d.mset_st[a.d.mst[k] + mset_begin(a.d, k, a.cset[c]) + (P - a.first[c])];
-                } else {
-                    s = a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
-                }
-            }
+            const uint32_t s = valid ? pair_start(a, c, P) : 0u;
             st[j] = R * s;
             ci[j] = valid ? c : 0xFFFFFFFFu;
-            o16[j] = aligned_chunks ? (uint32_t)((uint64_t)c * a.chunk / (kPer16 * kSym)) : 0u;
+            o16[j] = aligned_chunks ? code_unit(a, c, 0u, (uint32_t)(a.chunk / (kPer16 * kSym))) : 0u;
         }
         if (aligned_chunks) {
             uint32_t live = 0;
@@ -572,7 +780,7 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
                 return (uint32_t)((min<uint64_t>(a.chunk, a.n - c * a.chunk) + kSym - 1) / kSym);
             };
             walk_var<L, S, EXIT>(reinterpret_cast<const uint4 *>(codes), o16, len_of, st,
-                                  a.exit_base, a.exit_shift, live);
+                                  a.exit_base, a.exit_shift, live, a.ilv_nblk ? 64u : 1u);
         } else {
             // general path: per-lane code loads, chunks of any length and alignment
             const uint64_t ncodes = (a.n + kSym - 1) / kSym;
@@ -589,29 +797,385 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             if (ci[j] != 0xFFFFFFFFu) {
-                const uint32_t e = st[j] / R;
-                const uint32_t c = ci[j];
                 const uint32_t P = tile * kTile + j * kWave2 + lane;
-                uint16_t v;
-                if (c + 1 == a.nch) {
-                    v = (uint16_t)(kTerm | e);
-                } else if (a.mode == 2) {
-                    const uint16_t ab = a.d.pos[1][e];   // class-0 row: kTerm|e iff absorbing
-                    v = ab == (uint16_t)(kTerm | e)
-                            ? ab
-                            : (uint16_t)member_rank(a.members, a.first[c + 1], a.first[c + 2], e);
-                } else if (a.mode == 3) {
-                    const uint16_t ab = a.d.pos[1][e];
-                    const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)(c + 1) * a.chunk);
-                    const uint32_t id = a.cset[c + 1];
-                    v = ab == (uint16_t)(kTerm | e)
-                            ? ab
-                            : (uint16_t)member_rank(a.d.mset_st + a.d.mst[k], mset_begin(a.d, k, id),
-                                                    mset_end(a.d, k, id), e);
+                a.maps[P] = map_entry(a, ci[j], st[j] / R);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Merged walks.  delta is a function, so two walks of one chunk that are in
+// the same state at the same position stay together to the chunk's end.  The
+// walk runs in rounds over byte ranges [t0, t1) of every chunk; after a round
+// that is not the last, the walks of each wave-tile are grouped by (chunk,
+// state), one walk per group (the leader) goes on into the next round's
+// list, and every walk records its leader's index there.  A walk whose chunk
+// ends within the round, or that reached an absorbing state, is done and
+// records kDone | its end state.  Walks of one chunk split over two tiles may
+// keep two leaders; the result is exact either way.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDone = 0x80000000u;     // outcome: the walk ended (low bits: state)
+constexpr uint32_t kMapped = 0x40000000u;   // with kDone: low 16 bits are the map entry
+
+// A round's list is split into kRegions regions of `cap` places, each with
+// its own counter: tile t appends its leaders to region t % kRegions (one
+// atomic add per tile, spread over kRegions addresses), and the next round
+// numbers the walks densely across the regions.
+struct RoundArgs {
+    uint32_t t0, t1;           // chunk bytes of this round
+    uint32_t first_round;      // walks are the pairs (start states from the sets)
+    uint32_t last_round;       // walks run to the chunk end; no grouping
+    uint32_t cap;              // places per region
+    const uint32_t *in_cnt;    // later rounds: [kRegions] walks per region of in_list
+    const uint2 *in_list;      // later rounds: {chunk, state} per place
+    uint32_t *out_lo;          // per walk (pair, or place of in_list): kDone | end
+                               //  state, or the place of its leader in out_list
+    uint2 *out_list;           // the next round's walks
+    uint32_t *out_cnt;         // [kRegions] its counters (zero before the first round)
+};
+
+template <int L, int S>
+__global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, RoundArgs m) {
+    constexpr uint32_t kTile = kWave2 * S;
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table<L>(a.d, smem);
+    using CodeT = typename std::conditional<L != 2, uint8_t, uint16_t>::type;
+    constexpr uint32_t kPer16 = 16 / sizeof(CodeT);
+    constexpr uint32_t kSym = L == 4 ? 2u : 1u;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t lane = threadIdx.x & (kWave2 - 1);
+    const uint32_t waves = blockDim.x / kWave2;
+    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    const uint32_t total_waves = gridDim.x * waves;
+    // later rounds: exclusive prefix of the regions' counts, in LDS after the
+    // staged table (the kernel has no static LDS: the table stays at address 0)
+    uint32_t *region_pre = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes);
+    if (!m.first_round) {
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (uint32_t g = 0; g < kRegions; ++g) {
+                region_pre[g] = acc;
+                acc += m.in_cnt[g];
+            }
+            region_pre[kRegions] = acc;
+        }
+        __syncthreads();
+    }
+    const uint32_t total = m.first_round ? a.first[a.nch] : region_pre[kRegions];
+    const uint32_t ntiles = (total + kTile - 1) / kTile;
+    const uint32_t R = L != 2 ? a.d.rowbytes : 2u;
+    const uint4 *codes16 = reinterpret_cast<const uint4 *>(a.codes);
+    const uint64_t lanes_lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // place of dense walk w of a later round: region by binary search
+    auto place_of = [&](uint32_t w) -> uint32_t {
+        uint32_t lo = 0, hi = kRegions;
+        while (hi > lo + 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (region_pre[mid] <= w) lo = mid; else hi = mid;
+        }
+        return lo * m.cap + (w - region_pre[lo]);
+    };
+
+    for (uint32_t tile = wave_id; tile < ntiles; tile += total_waves) {
+        uint32_t st[S], ci[S], o16[S];
+        const uint32_t lo0 = m.first_round ? a.tile_first[tile] : 0u;
+        const uint32_t hi0 = m.first_round ? (tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch) : 0u;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const uint32_t w = tile * kTile + j * kWave2 + lane;
+            const bool valid = w < total;
+            uint32_t c = 0, s0 = 0;
+            if (valid) {
+                if (m.first_round) {
+                    c = owner_chunk(a.first, lo0, hi0, w);
+                    s0 = pair_start(a, c, w);
                 } else {
-                    v = a.d.pos[a.mode][(size_t)a.ccls[c + 1] * a.d.nq + e];
+                    const uint2 rec = m.in_list[place_of(w)];
+                    c = rec.x;
+                    s0 = rec.y;
                 }
-                a.maps[P] = v;
+            }
+            st[j] = R * s0;
+            ci[j] = valid ? c : kNone;
+            o16[j] = code_unit(a, c, m.t0 / (kSym * kPer16), (uint32_t)(a.chunk / (kSym * kPer16)));
+        }
+        uint32_t live = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) live |= (ci[j] != kNone ? 1u : 0u) << j;
+        // codes of [t0, min(t1, chunk length)); walks past the list's end
+        // shadow chunk 0 (their loads stay in bounds; results discarded)
+        auto len_of = [&](int j) -> uint32_t {
+            const uint64_t c = ci[j] == kNone ? 0u : ci[j];
+            const uint64_t len = min<uint64_t>(a.chunk, a.n - c * a.chunk);
+            const uint64_t end = m.last_round ? len : min<uint64_t>(len, m.t1);
+            return end > m.t0 ? (uint32_t)((end - m.t0 + kSym - 1) / kSym) : 0u;
+        };
+        walk_var<L, S, false>(codes16, o16, len_of, st, 0u, 0u, live, a.ilv_nblk ? 64u : 1u);
+
+        // end states; done = the chunk ended or the state is absorbing
+        uint32_t e[S];
+        bool act[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            e[j] = st[j] / R;
+            bool done = true;
+            if (ci[j] != kNone && !m.last_round) {
+                const uint64_t len = min<uint64_t>(a.chunk, a.n - (uint64_t)ci[j] * a.chunk);
+                const uint32_t idx = st[j] >> a.d.abs_shift;
+                const bool absorbed = (lds_ld32(a.d.abs_off + ((idx >> 5) << 2)) >> (idx & 31)) & 1u;
+                done = len <= m.t1 || absorbed;
+            }
+            act[j] = ci[j] != kNone && !done;
+        }
+        uint32_t lead[S];      // tile position of the walk's leader
+        bool is_lead[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) { lead[j] = kNone; is_lead[j] = false; }
+        if (!m.last_round) {
+            // group the active walks by (chunk, state): one pass per distinct
+            // key, taking the first unresolved lane's key (at most 64 passes
+            // per slot; each removes at least that lane)
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                uint64_t todo = __ballot(act[j]);
+                while (todo) {
+                    const uint32_t l0 = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+                    const uint32_t kc = __builtin_amdgcn_readlane(ci[j], l0);
+                    const uint32_t ke = __builtin_amdgcn_readlane(e[j], l0);
+                    uint32_t q = (uint32_t)j * kWave2 + l0;
+                    // a leader with this key in an earlier slot?
+#pragma unroll
+                    for (int jj = 0; jj < j; ++jj) {
+                        const uint64_t mm = __ballot(is_lead[jj] && ci[jj] == kc && e[jj] == ke);
+                        if (mm && q == (uint32_t)j * kWave2 + l0)
+                            q = (uint32_t)jj * kWave2 + (uint32_t)__ffsll((unsigned long long)mm) - 1u;
+                    }
+                    const uint64_t mine = __ballot(act[j] && ci[j] == kc && e[j] == ke) & todo;
+                    if ((mine >> lane) & 1ull) lead[j] = q;
+                    if (lane == l0 && q == (uint32_t)j * kWave2 + l0) is_lead[j] = true;
+                    todo &= ~mine;
+                }
+            }
+        }
+        // leaders take consecutive places in the next list
+        uint32_t nlead = 0, myidx[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const uint64_t lm = __ballot(is_lead[j]);
+            myidx[j] = nlead + (uint32_t)__popcll(lm & lanes_lt);
+            nlead += (uint32_t)__popcll(lm);
+        }
+        uint32_t base = 0;
+        if (nlead) {
+            const uint32_t g = tile % kRegions;
+            if (lane == 0) base = g * m.cap + atomicAdd(m.out_cnt + g, nlead);
+            base = __shfl(base, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            myidx[j] += base;
+            if (is_lead[j]) m.out_list[myidx[j]] = make_uint2(ci[j], e[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            // the leader's list index, from its slot and lane
+            uint32_t li = 0;
+            const uint32_t ql = lead[j] == kNone ? 0u : lead[j];
+#pragma unroll
+            for (int jj = 0; jj < S; ++jj) {
+                const uint32_t v = __shfl(myidx[jj], (int)(ql & (kWave2 - 1)));
+                if ((ql >> 6) == (uint32_t)jj) li = v;
+            }
+            if (ci[j] != kNone) {
+                const uint32_t w = tile * kTile + j * kWave2 + lane;
+                // the last round stores the map entry itself (one per leader;
+                // the walks that follow it take it as it is)
+                const uint32_t done = m.last_round ? (kDone | kMapped | map_entry(a, ci[j], e[j]))
+                                                   : (kDone | e[j]);
+                m.out_lo[m.first_round ? w : place_of(w)] = act[j] ? li : done;
+            }
+        }
+    }
+}
+
+// Map entries of merged walks: pair P follows its leaders round by round to
+// the walk that ran to the end (which stored the map entry), or to its own
+// end state if its walk stopped early.
+struct MergeMapArgs {
+    const uint32_t *lo[kMaxRounds];
+    uint32_t rounds;
+};
+
+__global__ __launch_bounds__(256) void k_merge_maps(Match2Args a, MergeMapArgs mm) {
+    const uint32_t total = a.first[a.nch];
+    const uint32_t P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= total) return;
+    uint32_t v = mm.lo[0][P];
+    for (uint32_t k = 1; k < mm.rounds && !(v & kDone); ++k) v = mm.lo[k][v];
+    if ((v & (kDone | kMapped)) == (kDone | kMapped)) {
+        a.maps[P] = (uint16_t)(v & 0xFFFFu);
+        return;
+    }
+    // a walk that stopped before the last round: its end state
+    const uint32_t e = (v & kDone) ? (v & 0x7FFFu) : 0xFFFFu;   // 0xFFFF: not reached
+    const uint32_t tile = P / a.tile;
+    const uint32_t ntiles = (total + a.tile - 1) / a.tile;
+    const uint32_t lo0 = a.tile_first[tile];
+    const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
+    const uint32_t c = owner_chunk(a.first, lo0, hi0, P);
+    a.maps[P] = e < a.d.nq ? map_entry(a, c, e) : kBadPos;
+}
+
+// ---------------------------------------------------------------------------
+// One chunk per lane with merged walks (interleaved code streams).  The lane
+// walks its chunk's start states four at a time over the first `prefix`
+// codes and keeps the distinct states reached (at most kCwDistinct; each
+// pair's map entry temporarily holds the index of its state); since the
+// walks of one chunk converge, it then walks only those to the chunk's end,
+// four chains (or fewer) in step, and rewrites every pair's map entry from
+// its state's end.  A chunk whose
+// states do not reduce that far is walked state by state to the end.  The
+// 64 lanes of a wave hold 64 consecutive chunks, whose code blocks sit side
+// by side in the interleaved stream, so each block load is one contiguous
+// KiB.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCwDistinct = 4;
+
+// Walk NS chains of one chunk over ncodes codes (whole 16-byte blocks from
+// unit u0 on, `stride` units apart; the last block may be partial).  A lane
+// walks one chunk, so one block lasts only 16 (or 8) steps: kCwAhead blocks
+// are loaded ahead to cover the memory latency.
+constexpr int kCwAhead = 4;
+
+template <int L, int NS>
+__device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16, uint32_t u0,
+                                               uint32_t stride, uint32_t ncodes,
+                                               uint32_t (&st)[NS]) {
+    constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
+    const uint32_t whole = ncodes / kPer16;
+    uint4 ring[kCwAhead];
+#pragma unroll
+    for (int k = 0; k < kCwAhead; ++k)
+        ring[k] = (uint32_t)k < whole ? codes16[(size_t)u0 + (size_t)k * stride] : make_uint4(0, 0, 0, 0);
+    for (uint32_t b = 0; b < whole; ++b) {
+        const uint4 cur = ring[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kCwAhead; ++k) ring[k] = ring[k + 1];
+        if (b + kCwAhead < whole) ring[kCwAhead - 1] = codes16[(size_t)u0 + (size_t)(b + kCwAhead) * stride];
+        const uint32_t w4[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t w = w4[q];
+            if constexpr (L != 2) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<1, 0>(st[j], w));
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<1, 1>(st[j], w));
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<1, 2>(st[j], w));
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<1, 3>(st[j], w));
+            } else {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 0>(st[j], w));
+#pragma unroll
+                for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 1>(st[j], w));
+            }
+        }
+    }
+    const uint32_t rest = ncodes - whole * kPer16;
+    if (rest) {
+        const uint4 v = codes16[(size_t)u0 + (size_t)whole * stride];
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        for (uint32_t t = 0; t < rest; ++t) {
+            const uint32_t w = w4[t / (kPer16 / 4)];
+            const uint32_t code = L == 2 ? (w >> (16 * (t & 1))) & 0xFFFFu : (w >> (8 * (t & 3))) & 0xFFu;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) st[j] = lds_ld(st[j] + code);
+        }
+    }
+}
+
+struct ChunkWalkArgs {
+    uint32_t prefix;          // codes walked by every start state (multiple of 16)
+};
+
+template <int L>
+__global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs cw) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table<L>(a.d, smem);
+    constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
+    constexpr uint32_t kSym = L == 4 ? 2u : 1u;
+    const uint32_t R = L != 2 ? a.d.rowbytes : 2u;
+    const uint4 *codes16 = reinterpret_cast<const uint4 *>(a.codes);
+    const uint32_t per_chunk = (uint32_t)(a.chunk / (kPer16 * kSym));   // blocks per chunk
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nch;
+         c += gridDim.x * blockDim.x) {
+        const uint32_t P0 = a.first[c];
+        const uint32_t m = a.first[c + 1] - P0;
+        if (m == 0) continue;
+        const uint64_t len = min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk);
+        const uint32_t ncodes = (uint32_t)((len + kSym - 1) / kSym);
+        const uint32_t u0 = code_unit(a, c, 0u, per_chunk);
+        const uint32_t pre = min(cw.prefix, ncodes);
+        // phase 1: every start state over the prefix, four at a time
+        uint32_t dst[kCwDistinct];
+        uint32_t nd = 0;
+        bool spill = false;
+        for (uint32_t b0 = 0; b0 < m && !spill; b0 += 4) {
+            uint32_t st[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                st[j] = R * (b0 + j < m ? pair_start(a, c, P0 + b0 + j) : pair_start(a, c, P0));
+            walk_one_chunk<L, 4>(codes16, u0, 64u, pre, st);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (b0 + j >= m) break;
+                uint32_t idx = kCwDistinct;
+                for (uint32_t t = 0; t < nd; ++t)
+                    if (dst[t] == st[j]) idx = t;
+                if (idx == kCwDistinct) {
+                    if (nd == kCwDistinct) { spill = true; break; }
+                    dst[nd] = st[j];
+                    idx = nd++;
+                }
+                a.maps[P0 + b0 + j] = (uint16_t)idx;
+            }
+        }
+        if (!spill) {
+            // phase 2: the distinct states to the chunk's end
+            const uint32_t rest = ncodes - pre;
+            const uint32_t ur = u0 + (pre / kPer16) * 64u;   // pre is whole blocks
+            if (rest) {
+                if (nd == 1) {
+                    uint32_t st[1] = {dst[0]};
+                    walk_one_chunk<L, 1>(codes16, ur, 64u, rest, st);
+                    dst[0] = st[0];
+                } else if (nd == 2) {
+                    uint32_t st[2] = {dst[0], dst[1]};
+                    walk_one_chunk<L, 2>(codes16, ur, 64u, rest, st);
+                    dst[0] = st[0]; dst[1] = st[1];
+                } else {
+                    uint32_t st[4] = {dst[0], dst[1], nd > 2 ? dst[2] : dst[0], nd > 3 ? dst[3] : dst[0]};
+                    walk_one_chunk<L, 4>(codes16, ur, 64u, rest, st);
+                    dst[0] = st[0]; dst[1] = st[1]; dst[2] = st[2]; dst[3] = st[3];
+                }
+            }
+            uint16_t v[kCwDistinct];
+            for (uint32_t t = 0; t < nd; ++t) v[t] = map_entry(a, c, dst[t] / R);
+            for (uint32_t k = 0; k < m; ++k) a.maps[P0 + k] = v[a.maps[P0 + k] & 3u];
+        } else {
+            // the states did not reduce: every start state to the end
+            for (uint32_t b0 = 0; b0 < m; b0 += 4) {
+                uint32_t st[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    st[j] = R * (b0 + j < m ? pair_start(a, c, P0 + b0 + j) : pair_start(a, c, P0));
+                walk_one_chunk<L, 4>(codes16, u0, 64u, ncodes, st);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (b0 + j < m) a.maps[P0 + b0 + j] = map_entry(a, c, st[j] / R);
             }
         }
     }
@@ -651,13 +1215,17 @@ __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__re
 namespace {
 template <int SRC>
 void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint16_t *flag_msize,
-                 uint32_t start, hipStream_t s) {
+                 uint32_t start, hipStream_t s, const InfoSrc *info = nullptr) {
     const uint32_t nsb = (p.nch + kScanBlock - 1) / kScanBlock;
     ScanSrc qq = q;
     qq.tile = kWave2 * p.slots;
-    hipLaunchKernelGGL(k_scan_sums<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, qq, b.bsum);
+    if (info)
+        hipLaunchKernelGGL(k_scan_sums_info, dim3(nsb), dim3(kScanThreads), 0, s, qq, *info, b.bsum);
+    else
+        hipLaunchKernelGGL(k_scan_sums<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, qq, b.bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, b.bsum, nsb, flag_msize,
-                       p.nch, b.block_bad, flag_msize ? p.tblocks : 0u, b.first);
+                       p.nch, b.block_bad, flag_msize ? p.tblocks : 0u, b.first, b.cnt,
+                       b.cnt ? kMaxRounds * kRegions : 0u);
     hipLaunchKernelGGL(k_scan_apply<SRC>, dim3(nsb), dim3(kScanThreads), 0, s, qq, b.bsum, b.first,
                        b.tile_first, b.members, start);
 }
@@ -684,6 +1252,20 @@ const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
           reinterpret_cast<const void *>(&k_match2<4, 4, true>)}}};
     return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
+const void *chunk_walk_kernel(uint32_t L) {
+    static const void *const tab[4] = {
+        reinterpret_cast<const void *>(&k_chunk_walk<1>), reinterpret_cast<const void *>(&k_chunk_walk<2>),
+        reinterpret_cast<const void *>(&k_chunk_walk<1>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
+    return tab[L - 1];
+}
+const void *round_kernel(uint32_t L, uint32_t slots) {
+    static const void *const tab[4][2] = {
+        {reinterpret_cast<const void *>(&k_round<1, 2>), reinterpret_cast<const void *>(&k_round<1, 4>)},
+        {reinterpret_cast<const void *>(&k_round<2, 2>), reinterpret_cast<const void *>(&k_round<2, 4>)},
+        {reinterpret_cast<const void *>(&k_round<3, 2>), reinterpret_cast<const void *>(&k_round<3, 4>)},
+        {reinterpret_cast<const void *>(&k_round<4, 2>), reinterpret_cast<const void *>(&k_round<4, 4>)}};
+    return tab[L - 1][slots >= 4 ? 1 : 0];
+}
 const void *window2_kernel(uint32_t L, uint32_t slots) {
     static const void *const tab[2][2] = {
         {reinterpret_cast<const void *>(&k_window2<1, 2>), reinterpret_cast<const void *>(&k_window2<1, 4>)},
@@ -698,8 +1280,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     // two-symbol steps (the plan checked the chunk length); else direct
     // tables: the matcher reads the (16-byte aligned) input itself
     const bool pairs = p.pairs && d->dev.pairs;
-    const bool direct = !pairs && d->dev.direct && p.lookahead != 2 && p.segments <= 1 &&
-                        (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+    const bool direct = !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+                        p.segments <= 1 && (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+    const Ilv ilv{p.ilv_nblk, p.nch, p.chunk};
+    if (p.ilv_nblk && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
+        return fail(DFA_E_INVAL, "interleaved codes with segments, window pass or odd chunks");
     const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
     if (pairs && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
         return fail(DFA_E_INVAL, "two-symbol plan with segments, window pass or odd chunks");
@@ -718,19 +1303,23 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint64_t off = (uint64_t)cb[k] * p.chunk;
         const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
         uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
-        if (pairs)
+        if (pairs && d->dev.pcode2)
+            hipLaunchKernelGGL(k_translate_pairs_direct, dim3(p.tblocks), dim3(256), 0, ts,
+                               d_in + off, end - off, d->dev.pcode2, (uint8_t *)b.codes + off / 2,
+                               bad, ilv);
+        else if (pairs)
             hipLaunchKernelGGL(k_translate_pairs, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
                                end - off, d->dev.pcode, d->dev.nclass, (uint8_t *)b.codes + off / 2,
-                               bad);
+                               bad, ilv);
         else if (direct)
             hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, ts,
-                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad);
+                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad, ilv);
         else if (L == 1)
             hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad);
+                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad, ilv);
         else
             hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad);
+                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad, ilv);
         if (nseg > 1) {
             hipError_t fe = hipEventRecord(b.ev_seg[k], ts);
             if (fe != hipSuccess) return hip_fail(fe, "hipEventRecord (segment)");
@@ -764,6 +1353,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.exit_shift = a.d.abs_shift;
     a.c_lo = 0;
     a.c_hi = p.nch;
+    a.tile = kWave2 * p.slots;
+    a.ilv_nblk = p.ilv_nblk;
     const size_t lds = a.d.stab_bytes;
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     if (p.lookahead == 2) {
@@ -776,17 +1367,60 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         hipError_t we = hipLaunchKernel(wf, dim3(p.blocks2), dim3(p.threads2), wargs, lds, s);
         if (we != hipSuccess) return hip_fail(we, "k_window2 launch");
         launch_scan<1>(p, q, b, msize, start, s);
-    } else if (p.lookahead == 3) {
-        hipLaunchKernelGGL(k_chunkinfo_m, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
-                           p.chunk, p.nch, p.r, msize, b.cset);
-        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s);
     } else {
-        hipLaunchKernelGGL(k_chunkinfo, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
-                           p.chunk, p.nch, p.lookahead, msize, b.ccls);
-        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s);
+        // lookahead sets and sizes computed inside the scan's first phase
+        const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset};
+        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s, &info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
+    if (p.chunk_lanes) {
+        if (!p.ilv_nblk || L == 3 || p.lookahead == 2)
+            return fail(DFA_E_INVAL, "chunk lanes need interleaved codes and precomputed sets");
+        if (ev_before_matcher) {
+            e = hipEventRecord(ev_before_matcher, s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        ChunkWalkArgs cw{kRound1Bytes};
+        void *cargs[] = {&a, &cw};
+        const uint32_t blocks = std::max<uint32_t>(
+            1u, std::min<uint32_t>((p.nch + 255) / 256, p.blocks2 * (p.threads2 / 256)));
+        e = hipLaunchKernel(chunk_walk_kernel(L), dim3(blocks), dim3(256), cargs, lds, s);
+        return e == hipSuccess ? DFA_OK : hip_fail(e, "k_chunk_walk launch");
+    }
+    if (p.rounds > 1) {
+        if (nseg > 1 || p.early_exit || p.chunk % 32 != 0 || !b.cnt)
+            return fail(DFA_E_INVAL, "merged walks need one segment, no early exit, chunks of 32k");
+        if (ev_before_matcher) {
+            e = hipEventRecord(ev_before_matcher, s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        const void *rf = round_kernel(L, p.slots);
+        for (uint32_t k = 0; k < p.rounds; ++k) {
+            RoundArgs m;
+            m.t0 = k == 0 ? 0u : kRound1Bytes << (2 * (k - 1));
+            m.t1 = kRound1Bytes << (2 * k);
+            m.first_round = k == 0;
+            m.last_round = k + 1 == p.rounds;
+            m.cap = round_region_cap(p);
+            m.in_cnt = k ? b.cnt + (size_t)k * kRegions : nullptr;
+            m.in_list = k ? b.list[k] : nullptr;
+            m.out_lo = b.lo[k];
+            m.out_list = m.last_round ? nullptr : b.list[k + 1];
+            m.out_cnt = m.last_round ? nullptr : b.cnt + (size_t)(k + 1) * kRegions;
+            void *rargs[] = {&a, &m};
+            e = hipLaunchKernel(rf, dim3(p.blocks2), dim3(p.threads2), rargs,
+                                lds + round_lds_extra(), s);
+            if (e != hipSuccess) return hip_fail(e, "k_round launch");
+        }
+        MergeMapArgs mm{};
+        for (uint32_t k = 0; k < p.rounds; ++k) mm.lo[k] = b.lo[k];
+        mm.rounds = p.rounds;
+        const uint64_t bound = (uint64_t)p.max_tiles * kWave2 * p.slots;
+        hipLaunchKernelGGL(k_merge_maps, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s, a, mm);
+        e = hipGetLastError();
+        return e == hipSuccess ? DFA_OK : hip_fail(e, "k_merge_maps launch");
+    }
     const void *fn = match2_kernel(L, p.slots, p.early_exit);
     for (uint32_t k = 0; k < nseg; ++k) {
         if (nseg > 1) {
@@ -816,7 +1450,8 @@ int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *fi
     ScanSrc q{msize, nullptr, 0, nch, tile};
     hipLaunchKernelGGL(k_scan_sums<0>, dim3(nsb), dim3(kScanThreads), 0, s, q, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, bsum, nsb,
-                       (uint16_t *)nullptr, nch, (const uint32_t *)nullptr, 0u, first);
+                       (uint16_t *)nullptr, nch, (const uint32_t *)nullptr, 0u, first,
+                       (uint32_t *)nullptr, 0u);
     hipLaunchKernelGGL(k_scan_apply<0>, dim3(nsb), dim3(kScanThreads), 0, s, q, bsum, first,
                        tile_first, (uint16_t *)nullptr, 0u);
     hipError_t e = hipGetLastError();
@@ -826,7 +1461,7 @@ int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *fi
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                  const uint16_t *bv_up, uint16_t *bv0, hipStream_t s) {
     const uint32_t n_up = p.levels >= 1 ? p.level_count[1] : 1u;
-    const uint32_t G = p.levels >= 1 ? p.group : 1u;
+    const uint32_t G = p.levels >= 1 ? p.group_l[0] : 1u;
     hipLaunchKernelGGL(k_down0, dim3((n_up + 255) / 256), dim3(256), 0, s, maps0, first, p.nch, G,
                        bv_up, n_up, bv0);
     hipError_t e = hipGetLastError();
@@ -843,6 +1478,10 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(3, 4, false), match2_kernel(3, 4, true),
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
+                         chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(4),
+                         round_kernel(1, 2), round_kernel(1, 4), round_kernel(2, 2),
+                         round_kernel(2, 4), round_kernel(3, 2), round_kernel(3, 4),
+                         round_kernel(4, 2), round_kernel(4, 4),
                          window2_kernel(1, 2), window2_kernel(1, 4),
                          window2_kernel(2, 2), window2_kernel(2, 4)};
     int rc = DFA_OK;
@@ -852,6 +1491,12 @@ int set_match2_lds_limit(int lds) {
 }
 
 uint32_t match2_tile_pairs(uint32_t slots) { return kWave2 * slots; }
+size_t round_lds_extra() { return (4u * (kRegions + 1) + 15u) / 16u * 16u; }
+uint32_t round_region_cap(const MatchPlan &p) {
+    // a region receives the leaders of every kRegions-th tile, at most a
+    // tile's walks each
+    return (uint32_t)(((p.max_tiles + kRegions - 1) / kRegions) * kWave2 * p.slots);
+}
 uint32_t match2_scan_blocks(uint32_t nch) { return (nch + kScanBlock - 1) / kScanBlock; }
 
 }  // namespace dfaspec

@@ -98,7 +98,9 @@ __device__ __forceinline__ uint32_t member_rank(const uint16_t *__restrict__ mem
 
 // Walk KS pairs per lane.  Fast path: every pair of the tile has a full,
 // 16-byte-aligned chunk (o16 = its first code's offset in 16-byte units),
-// read as uint4 blocks with one block of prefetch.
+// read as uint4 blocks with one block of prefetch; consecutive blocks of a
+// chunk are `stride` units apart (1 in a linear code stream, 64 in the
+// chunk-interleaved one).
 // The 16 input bytes at in[pos ..] (zero at and past n), read as whole
 // aligned words: one 16-byte load when in + pos is 16-byte aligned, two
 // loads and a byte funnel shift when it is not (then only while the second
@@ -181,7 +183,8 @@ template <int L, int S, bool EXIT = false, int PF = 1>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
                                           const uint32_t (&o16)[S], uint32_t blocks,
                                           uint32_t (&st)[S], uint32_t exit_base = 0,
-                                          uint32_t exit_shift = 0, uint32_t live = 0) {
+                                          uint32_t exit_shift = 0, uint32_t live = 0,
+                                          uint32_t stride = 1) {
     // PF blocks of prefetch: cur is block b - 1, ahead[k] is block b - 1 + k + 1
     uint4 cur[S], ahead[PF][S];
 #pragma unroll
@@ -190,13 +193,14 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
     for (int k = 0; k + 1 < PF; ++k)
 #pragma unroll
         for (int j = 0; j < S; ++j)
-            if ((uint32_t)(k + 1) < blocks) ahead[k][j] = codes16[(size_t)o16[j] + k + 1];
+            if ((uint32_t)(k + 1) < blocks)
+                ahead[k][j] = codes16[(size_t)o16[j] + (size_t)(k + 1) * stride];
     for (uint32_t b = 1; ; ++b) {
         const bool more = b < blocks;
         const uint32_t far = b + PF - 1;
         if (far < blocks) {
 #pragma unroll
-            for (int j = 0; j < S; ++j) ahead[PF - 1][j] = codes16[(size_t)o16[j] + far];
+            for (int j = 0; j < S; ++j) ahead[PF - 1][j] = codes16[(size_t)o16[j] + (size_t)far * stride];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -237,7 +241,8 @@ template <int L, int S, bool EXIT = false, typename LenFn>
 __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
                                          const uint32_t (&o16)[S], LenFn len_of,
                                          uint32_t (&st)[S], uint32_t exit_base = 0,
-                                         uint32_t exit_shift = 0, uint32_t live = 0) {
+                                         uint32_t exit_shift = 0, uint32_t live = 0,
+                                         uint32_t stride = 1) {
     constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
     uint32_t common = 0xFFFFFFFFu, most = 0;
 #pragma unroll
@@ -246,7 +251,8 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
         common = min(common, len / kPer16);
         most = max(most, (len + kPer16 - 1) / kPer16);
     }
-    if (common > 0) walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live);
+    if (common > 0)
+        walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live, stride);
     for (uint32_t b = common; b < most; ++b) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -255,7 +261,8 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
             const uint32_t cnt = min(kPer16, len - b * kPer16);
             uint32_t w[4];
             if (L == 3 && cnt < kPer16) {
-                const uint8_t *p = reinterpret_cast<const uint8_t *>(codes16 + o16[j] + b);
+                const uint8_t *p =
+                    reinterpret_cast<const uint8_t *>(codes16 + o16[j] + (size_t)b * stride);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     uint32_t v = 0;
@@ -265,7 +272,7 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
                     w[q] = word_codes<L>(v);
                 }
             } else {
-                const uint4 v = codes16[(size_t)o16[j] + b];
+                const uint4 v = codes16[(size_t)o16[j] + (size_t)b * stride];
                 w[0] = word_codes<L>(v.x); w[1] = word_codes<L>(v.y);
                 w[2] = word_codes<L>(v.z); w[3] = word_codes<L>(v.w);
             }

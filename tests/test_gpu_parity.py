@@ -688,11 +688,14 @@ def test_two_symbol_steps_lengths(dfa_mod, monkeypatch, pairs, n, look):
         check(dfa_mod, w, x, chunk=chunk, lookahead=look)
 
 
+@pytest.mark.parametrize("byte", [ord("J"), ord("0"), 0x80, 0xC1, 0xE1])
 @pytest.mark.parametrize("pos", [0, 1, 30, 31, 2047, 2048, 99_998, 99_999, 100_000])
-def test_two_symbol_steps_invalid_bytes(dfa_mod, pos):
+def test_two_symbol_steps_invalid_bytes(dfa_mod, byte, pos):
+    """Bytes outside Sigma below and above 128 (0xC1 & 0x7F is 'A'), on
+    either side of a pair and as a lone last byte."""
     w = configs.c2_dfa()
     x = configs.c2_input(100_001).copy()
-    x[pos] = ord("J") if pos % 2 else 0xE1
+    x[pos] = byte
     d = dfa_mod.DFA.from_workload(w)
     for look in (1, 4):
         assert gpu_run(dfa_mod, d, x, chunk=2048, lookahead=look, boundaries=False)[2] & \
@@ -738,3 +741,170 @@ def test_two_symbol_steps_random_small_alphabets(dfa_mod):
         say(f"random dfa {t}: Q={nq} K={k} pair columns {pc}")
         check(dfa_mod, w, x, chunk=512, lookahead=1)
         check(dfa_mod, w, x, chunk=4096, lookahead=2)
+
+
+# ---------------------------------------------------------------------------
+# Merged walks (DFA_MATCH_ROUNDS): after each round but the last, walks of a
+# chunk in the same state continue as one.  Every boundary state must equal
+# the oracle's for any round count, chunk length (32 bytes up, ragged last
+# chunk), lookahead mode (0: all states, 1, precomputed 3, window 12) and
+# table kind (class codes, direct rows, two-symbol steps, class-major).
+# ---------------------------------------------------------------------------
+def merged_cases():
+    return [
+        ("c2", lambda: (configs.c2_dfa(), configs.c2_input((3 << 20) + 5, seed=61))),
+        ("c3p", lambda: (configs.c3_protein_dfa(), configs.c3_protein_input((2 << 20) + 17))),
+        ("c3b", lambda: (configs.c3_byte_dfa(), configs.c3_byte_input((2 << 20) + 9))),
+        ("c1", lambda: (configs.c1_dfa(2), configs.c1_input((1 << 20) + 3))),
+        ("anchored", lambda: (from_pattern(patterns.pattern_dfa(32, contains=False)),
+                              configs.c2_input((2 << 20) + 1, seed=62))),
+        ("cols6", lambda: (column_dfa(91, 92, 150, 6), streams.uniform_bytes(93, (1 << 20) + 31))),
+    ]
+
+
+@pytest.mark.parametrize("case", [c[0] for c in merged_cases()])
+@pytest.mark.parametrize("rounds", [1, 2, 3, 4])
+def test_merged_rounds_match_oracle(dfa_mod, case, rounds):
+    w, x = dict(merged_cases())[case]()
+    n = x.size
+    d = dfa_mod.DFA.from_workload(w)
+    for chunk in (32, 96, 2048, 65536):
+        for look in (1, 3):
+            plan = dfa_mod.dfa_plan(d, n, chunk, look, rounds=rounds)
+            say(f"{case}: rounds {rounds} (plan {plan.rounds}) chunk {chunk} r {look} "
+                f"kernel {plan.kernel} sym/step {plan.symbols_per_step}")
+            if plan.kernel == 1:
+                # the last round must start inside a chunk
+                want = rounds
+                while want > 1 and 32 << (2 * (want - 2)) >= chunk:
+                    want -= 1
+                assert plan.rounds == want
+            fin, acc, flags, nch, b = gpu_run(dfa_mod, d, x, chunk, look)
+            # gpu_run uses the default (planner) rounds; run the requested ones
+            # on the interleaved and the linear code stream
+            import torch
+            probes = [min(i * plan.chunk_len, n) for i in range(plan.num_chunks + 1)]
+            ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+            assert (fin, acc) == (ofin, oracle.accepts(ofin, w.accepting))
+            for ilv in (False, True):
+                res, bnd = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=chunk, lookahead=look,
+                                                boundaries=True, rounds=rounds, interleave=ilv)
+                torch.cuda.synchronize()
+                assert dfa_mod.result_tuple(res)[:3] == \
+                    (ofin, oracle.accepts(ofin, w.accepting), 0), ilv
+                bb = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+                bad = np.nonzero(bb != ps)[0]
+                assert bad.size == 0, f"interleave {ilv} chunks {bad[:8]}: {bb[bad[:8]]} vs {ps[bad[:8]]}"
+    d.close()
+
+
+@pytest.mark.parametrize("rounds", [2, 4])
+def test_merged_rounds_all_states_and_window(dfa_mod, rounds):
+    """Lookahead 0 (every non-absorbing state starts each chunk) and 12 (the
+    window pass beyond the precomputed sets)."""
+    w = configs.c2_dfa()
+    x = configs.c2_input((1 << 20) + 7, seed=63)
+    for look in (0, 12):
+        for chunk in (64, 4096):
+            import torch
+            d = dfa_mod.DFA.from_workload(w)
+            res, bnd = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=chunk, lookahead=look,
+                                            boundaries=True, rounds=rounds)
+            torch.cuda.synchronize()
+            n = x.size
+            used, nch = dfa_mod.dfa_plan_chunks(d, n, chunk, look)
+            probes = [min(i * used, n) for i in range(nch + 1)]
+            ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+            assert dfa_mod.result_tuple(res)[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+            assert np.array_equal(bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF,
+                                  ps.astype(np.int64))
+            d.close()
+
+
+@pytest.mark.parametrize("pos", [0, 31, 32, 33, 127, 128, 129, 4095, 77_777])
+def test_merged_rounds_invalid_bytes(dfa_mod, pos):
+    w = configs.c2_dfa()
+    x = configs.c2_input(100_003, seed=64).copy()
+    x[pos] = 0xC1
+    d = dfa_mod.DFA.from_workload(w)
+    import torch
+    for rounds in (2, 3):
+        res, _ = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=4096, lookahead=3, rounds=rounds)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()
+
+
+@pytest.mark.parametrize("case", ["c2", "c3b", "c1", "cols6"])
+@pytest.mark.parametrize("single", [False, True])
+def test_interleaved_codes_ragged(dfa_mod, case, single):
+    """Chunk-interleaved code streams: chunk counts around multiples of 64
+    (partial last group), ragged last chunk, one- and two-symbol codes."""
+    import torch
+    w, _ = dict(merged_cases())[case]()
+    d = dfa_mod.DFA.from_workload(w)
+    rng = np.random.default_rng(5)
+    for nch, chunk in ((1, 64), (63, 64), (64, 96), (65, 128), (129, 2048), (200, 4096)):
+        n = int((nch - 1) * chunk + rng.integers(1, chunk + 1))
+        x = (configs.c2_input(n, seed=n % 97) if case == "c2" else
+             streams.uniform_bytes(70 + nch, n) if case != "cols6" else
+             streams.uniform_bytes(93, n))
+        plan = dfa_mod.dfa_plan(d, n, chunk, 1, single_step=single, interleave=True)
+        assert plan.kernel == 1 and plan.interleaved == 1 and plan.num_chunks == nch
+        probes = [min(i * chunk, n) for i in range(nch + 1)]
+        ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+        for rounds in (1, 2):
+            res, bnd = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=chunk, lookahead=1,
+                                            boundaries=True, rounds=rounds, single_step=single,
+                                            interleave=True)
+            torch.cuda.synchronize()
+            assert dfa_mod.result_tuple(res)[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+            assert np.array_equal(bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF,
+                                  ps.astype(np.int64)), (nch, chunk, rounds)
+    d.close()
+
+
+@pytest.mark.parametrize("case", [c[0] for c in merged_cases()])
+def test_chunk_lanes_match_oracle(dfa_mod, case):
+    """One chunk per lane with merged walks (DFA_MATCH_CHUNK_LANES): every
+    boundary state equals the oracle's; sets too large for it fall back."""
+    import torch
+    w, x = dict(merged_cases())[case]()
+    n = x.size
+    d = dfa_mod.DFA.from_workload(w)
+    used = 0
+    for chunk in (32, 96, 512, 2048, 65536):
+        for look in (1, 3, 5, 6):
+            for single in (False, True):
+                plan = dfa_mod.dfa_plan(d, n, chunk, look, chunk_lanes=True, single_step=single)
+                used += plan.chunk_lanes
+                res, bnd = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=chunk, lookahead=look,
+                                                boundaries=True, chunk_lanes=True,
+                                                single_step=single)
+                torch.cuda.synchronize()
+                probes = [min(i * plan.chunk_len, n) for i in range(plan.num_chunks + 1)]
+                ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+                assert dfa_mod.result_tuple(res)[:3] == \
+                    (ofin, oracle.accepts(ofin, w.accepting), 0), (chunk, look, single)
+                bb = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+                bad = np.nonzero(bb != ps)[0]
+                assert bad.size == 0, (chunk, look, single, bad[:8])
+    say(f"{case}: chunk lanes used in {used} settings")
+    if case in ("c2", "c3p", "anchored", "c1"):
+        assert used > 0
+    d.close()
+
+
+@pytest.mark.parametrize("pos", [0, 31, 32, 33, 1023, 100_000])
+def test_chunk_lanes_invalid_bytes(dfa_mod, pos):
+    import torch
+    w = configs.c2_dfa()
+    x = configs.c2_input(200_001, seed=66).copy()
+    x[pos] = 0xC1
+    d = dfa_mod.DFA.from_workload(w)
+    for single in (False, True):
+        res, _ = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=1024, lookahead=5, chunk_lanes=True,
+                                      single_step=single)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()

@@ -148,6 +148,56 @@ __device__ __forceinline__ void translate_ilv_grid(const uint8_t *__restrict__ i
     }
 }
 
+// Interleaved grid walk of the two-symbol translations: a thread item is 32
+// input bytes (two pieces, 16 codes) stored as one 16-byte unit, so that
+// every store instruction writes whole lines.  conv(tag, w, first) returns the
+// 8 codes of the piece at `first` (tag: all 16 bytes before n).
+template <typename Conv>
+__device__ __forceinline__ uint2 pair_piece(Conv &conv, const uint32_t (&w)[4], uint64_t first,
+                                            uint64_t n) {
+    if (first >= n) return make_uint2(0u, 0u);
+    if (first + 16 <= n) return conv(std::true_type{}, w, first);
+    return conv(std::false_type{}, w, first);
+}
+
+// Interleaved: a wave takes 16 consecutive chunks, 4 lanes per chunk (32
+// input bytes each: one code block), kTrU blocks per lane in flight.
+template <typename Conv>
+__device__ __forceinline__ void pairs_grid_ilv(const uint8_t *__restrict__ in, uint64_t n,
+                                               uint8_t *out, const Ilv &v, Conv &conv) {
+    const uint32_t nsg = (v.nch + 15) / 16;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t cc = lane >> 2, k = lane & 3u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t sg = wave; sg < nsg; sg += nwaves) {
+        const uint32_t c = sg * 16 + cc;
+        const uint64_t c0 = (uint64_t)c * v.chunk;
+        const uint64_t end = c < v.nch ? min<uint64_t>(c0 + v.chunk, n) : 0u;
+        for (uint32_t b0 = 0; b0 < v.nblk; b0 += 4 * kTrU) {
+            uint32_t w[kTrU][2][4];
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u) {
+                const uint64_t first = c0 + (uint64_t)(b0 + 4 * u + k) * 32;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (first + 16 * h < end) load16(in, first + 16 * h, n, w[u][h]);
+            }
+#pragma unroll
+            for (int u = 0; u < kTrU; ++u) {
+                const uint32_t b = b0 + 4 * u + k;
+                const uint64_t first = c0 + (uint64_t)b * 32;
+                if (first >= end) continue;
+                const uint2 lo = pair_piece(conv, w[u][0], first, n);
+                const uint2 hi = first + 16 < end ? pair_piece(conv, w[u][1], first + 16, n)
+                                                  : make_uint2(0u, 0u);
+                const uint64_t unit = ((uint64_t)(c >> 6) * v.nblk + b) * 64u + (c & 63u);
+                *reinterpret_cast<uint4 *>(out + unit * 16u) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            }
+        }
+    }
+}
+
 // Bytes 0 of four words packed into one (v_perm_b32).
 __device__ __forceinline__ uint32_t pack_low_bytes(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
     return __builtin_amdgcn_perm(c1, c0, 0x0C0C0400u) | __builtin_amdgcn_perm(c3, c2, 0x04000C0Cu);
@@ -251,7 +301,7 @@ __global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restri
     __syncthreads();
     const uint32_t K1 = K + 1;
     uint32_t bad = 0;
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
         constexpr bool WHOLE = decltype(whole_tag)::value;
         uint32_t c[8];
         if constexpr (WHOLE) {
@@ -277,11 +327,16 @@ __global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restri
                 c[k] = (in1 && !bad1 && !bad2) ? (uint32_t)pc[c1 * K1 + c2] : 0u;
             }
         }
-        *reinterpret_cast<uint2 *>(sink.at(first / 2)) =
-            make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
     };
-    if (ilv.nblk) translate_ilv_grid<8>(in, n, out, ilv, (uint64_t)ilv.nblk * 16u, convert);
-    else translate_grid(in, n, out, convert);
+    if (ilv.nblk) {
+        pairs_grid_ilv(in, n, out, ilv, convert);
+    } else {
+        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
+        };
+        translate_grid(in, n, out, store8);
+    }
     if (bad) atomicOr(&bad_any, 1u);
     __syncthreads();
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
@@ -323,7 +378,7 @@ __global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *_
             c[k] = (!in1 || inv) ? 0u : v;
         }
     };
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
         constexpr bool WHOLE = decltype(whole_tag)::value;
         uint32_t c[8];
         if constexpr (WHOLE) {
@@ -338,11 +393,16 @@ __global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *_
         } else {
             checked(w, first, c);
         }
-        *reinterpret_cast<uint2 *>(sink.at(first / 2)) =
-            make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
     };
-    if (ilv.nblk) translate_ilv_grid<8>(in, n, out, ilv, (uint64_t)ilv.nblk * 16u, convert);
-    else translate_grid(in, n, out, convert);
+    if (ilv.nblk) {
+        pairs_grid_ilv(in, n, out, ilv, convert);
+    } else {
+        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
+        };
+        translate_grid(in, n, out, store8);
+    }
     if (bad) atomicOr(&bad_any, 1u);
     __syncthreads();
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
@@ -390,7 +450,7 @@ __global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t
 // msize and the sorted member lists to members[first[i] ..]).  Phase 2 folds
 // the translation flags into the flag bit of chunk 0's size, from where the
 // compose levels carry it up.
-constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanThreads = 256;    // enough blocks to spread the first phase
 constexpr uint32_t kScanItems = 4;
 constexpr uint32_t kScanBlock = kScanThreads * kScanItems;   // chunks per scan block
 
@@ -523,7 +583,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ bsum, 
     __shared__ uint32_t part[kScanThreads];
     __shared__ uint32_t bad_any;
     const uint32_t t = threadIdx.x, T = blockDim.x;
-    if (t < nzero) zero[t] = 0;   // counters of the merged-walk rounds
+    for (uint32_t i = t; i < nzero; i += T) zero[i] = 0;   // counters of the merged-walk rounds
     if (t == 0) bad_any = 0;
     uint32_t bad = 0;
     for (uint32_t b = t; b < nbad; b += T) bad |= block_bad[b];

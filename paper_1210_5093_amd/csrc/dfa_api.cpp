@@ -207,7 +207,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
                 }
             }
         }
-        if (p.segments > 1) {
+        if (p.fork) {
             if (!ws->aux) {
                 // non-blocking, default priority
                 e = hipStreamCreateWithFlags(&ws->aux, hipStreamNonBlocking);

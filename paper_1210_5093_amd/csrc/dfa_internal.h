@@ -146,6 +146,8 @@ struct MatchPlan {
     bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
     uint32_t segments = 1;       // translate/match pipeline segments (1 .. kMaxSegments)
+    bool fork = false;           // translation on a second stream, beside the lookahead
+                                 // scan (and the matcher, when that reads the raw input)
     bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
     uint32_t rounds = 1;         // walk rounds (> 1: merged walks, chunk % 32 == 0)
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)
@@ -182,8 +184,8 @@ struct PackedBufs {
     uint32_t *lo[kMaxRounds] = {};
     uint2 *list[kMaxRounds] = {};
     uint32_t *cnt = nullptr;         // [kMaxRounds][kRegions]
-    // segmented pipeline (MatchPlan::segments > 1): translation runs on `aux`,
-    // segment by segment, while the matcher works on the previous segment
+    // translation on a second stream (MatchPlan::fork): it runs on `aux`,
+    // segment by segment, beside the scan and the matcher's earlier segments
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_seg[kMaxSegments] = {};

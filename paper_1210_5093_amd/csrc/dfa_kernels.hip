@@ -89,6 +89,8 @@ struct FinalArgs {
     uint32_t nch;
     uint32_t *result;        // NULL: not the top level
     uint32_t *boundaries;    // optional: boundaries[nch] = final state
+    const uint32_t *bad;     // translation blocks' flags (byte outside Sigma), or NULL
+    uint32_t nbad;
 };
 
 __device__ __forceinline__ void write_result(const FinalArgs &fa, uint32_t v, bool symbol) {
@@ -136,6 +138,12 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
         const uint16_t ms = in_msize[c0 + t];
         if (ms & kFlagSymbol) atomicOr(&flag, 1u);
         dom[t] = first ? (uint16_t)(off[t + 1] - off[t]) : (uint16_t)(ms & 0x7FFFu);
+    }
+    if (fa.result && fa.bad) {
+        // the top level also takes the translation pass's flags
+        uint32_t any = 0;
+        for (uint32_t b = threadIdx.x; b < fa.nbad; b += T) any |= fa.bad[b];
+        if (any) atomicOr(&flag, 1u);
     }
     const uint32_t E = off[cnt];
     for (uint32_t e = threadIdx.x; e < E; e += T) sm[e] = in_maps[base + e];
@@ -222,10 +230,14 @@ __global__ void k_bound_states(DevDFA d, const uint8_t *__restrict__ in, uint64_
 
 __global__ void k_finalize(DevDFA d, const uint16_t *__restrict__ top_map,
                            const uint16_t *__restrict__ top_msize, uint32_t nch,
-                           uint32_t *__restrict__ result, uint32_t *__restrict__ boundaries) {
+                           uint32_t *__restrict__ result, uint32_t *__restrict__ boundaries,
+                           const uint32_t *__restrict__ bad, uint32_t nbad) {
+    uint32_t any = 0;
+    for (uint32_t b = threadIdx.x; b < nbad; b += blockDim.x) any |= bad[b];
+    const bool symbol = __any(any != 0) || (top_msize[0] & kFlagSymbol) != 0;
     if (threadIdx.x != 0) return;
-    write_result(FinalArgs{d.accept_bits, d.nq, nch, result, boundaries}, top_map[0],
-                 (top_msize[0] & kFlagSymbol) != 0);
+    write_result(FinalArgs{d.accept_bits, d.nq, nch, result, boundaries, nullptr, 0u}, top_map[0],
+                 symbol);
 }
 
 __global__ void k_empty(DevDFA d, uint32_t start, uint32_t *__restrict__ result,
@@ -387,20 +399,25 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     }
     p->chunk = chunk;
     const uint64_t nch = (n + chunk - 1) / chunk;
-    // Optional pipeline: translate segment k + 1 (on a second stream) while
-    // the matcher walks segment k.  Off by default: on MI355X the matcher
-    // loses more from the smaller per-launch tile count than the overlap
-    // gains (protein-style input, 5-symbol lookahead: 836 -> 662 GB/s with two
-    // segments).  DFA_SEGMENTS=2..4 turns it on.  The window pass (lookahead
-    // beyond the precomputed sets) reads codes before every chunk, so it keeps
-    // one segment; segment starts must be whole 16-code blocks (chunk
-    // lengths of 64k).
-    const bool can_split = p->packed && !p->pairs && p->lookahead != 2 && chunk % 64 == 0;
+    // Optional: the translation pass on a second stream (DFA_FORK=1), beside
+    // the chunk-info scan (which reads the raw input, not the codes) and,
+    // for direct tables, beside the matcher.  Off by default: the join
+    // between the streams costs about as much as the overlap saves, and on
+    // one stream the translation's workgroups run the scan's first phase.
+    // Optional pipeline on top of it: translate segment k + 1 while the
+    // matcher walks segment k (DFA_SEGMENTS=2..4).  Slower on MI355X: the
+    // matcher loses more from the smaller per-launch tile count than the
+    // overlap gains.  Segment starts must be whole 16-byte code blocks
+    // (chunk lengths of 64k).  The window pass (lookahead beyond the
+    // precomputed sets) reads codes before the scan, so it keeps one stream.
+    const bool can_fork = p->packed && p->lookahead != 2;
     if (const char *fs = std::getenv("DFA_SEGMENTS")) {
         const int v = std::atoi(fs);
-        if (v >= 1 && v <= (int)kMaxSegments && can_split && nch >= (uint64_t)v)
+        if (v >= 1 && v <= (int)kMaxSegments && can_fork && chunk % 64 == 0 && nch >= (uint64_t)v)
             p->segments = (uint32_t)v;
     }
+    const char *ff = std::getenv("DFA_FORK");
+    p->fork = can_fork && (p->segments > 1 || (ff && ff[0] == '1'));
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
     p->early_exit = p->packed && (flags & DFA_MATCH_EARLY_EXIT) && d->dev.nabs > 0;
@@ -515,6 +532,10 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
                    uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
                    uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s) {
     hipError_t e;
+    // the packed path's translation flags (one word per translation block
+    // and segment) reach the result through the top level
+    const uint32_t nbad =
+        pb ? std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments)) * p.tblocks : 0u;
     for (uint32_t l = 0; l < p.levels; ++l) {
         // level 0 of the packed matcher is pair-indexed; every other level
         // strided.  The last level (one group) also writes the result.
@@ -522,7 +543,7 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
         const uint32_t *first = (l == 0 && pb) ? pb->first : nullptr;
         const bool top = l + 1 == p.levels;
         FinalArgs fa{d->dev.accept_bits, d->dev.nq, p.nch, top ? d_result : nullptr,
-                     top ? d_boundaries : nullptr};
+                     top ? d_boundaries : nullptr, pb ? pb->block_bad : nullptr, nbad};
         hipLaunchKernelGGL(k_compose_tree, dim3(p.level_count[l + 1]), dim3(1024),
                            tree_lds_bytes(G, p.stride), s, maps + p.level_off[l], first,
                            msize + p.msize_off[l], p.level_count[l], p.stride, G, G * p.stride,
@@ -532,7 +553,7 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
     }
     if (p.levels == 0) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d->dev, maps, msize, p.nch,
-                           d_result, d_boundaries);
+                           d_result, d_boundaries, pb ? pb->block_bad : nullptr, nbad);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "k_finalize launch");
     }

@@ -203,246 +203,6 @@ __device__ __forceinline__ uint32_t pack_low_bytes(uint32_t c0, uint32_t c1, uin
     return __builtin_amdgcn_perm(c1, c0, 0x0C0C0400u) | __builtin_amdgcn_perm(c3, c2, 0x04000C0Cu);
 }
 
-template <typename CodeT, bool WRITE = true>
-__global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ in, uint64_t n,
-                                                   const uint16_t *__restrict__ code_lut,
-                                                   CodeT *__restrict__ out,
-                                                   uint32_t *__restrict__ block_bad, Ilv ilv) {
-    // one-byte codes (< 256) are staged with bytes outside Sigma as 0xFF00:
-    // the low byte (the code written) is 0 and an OR of the entries flags them
-    constexpr bool kNarrow = sizeof(CodeT) == 1;
-    __shared__ uint16_t lut[256];
-    __shared__ uint32_t bad_any;
-    {
-        const uint16_t v = code_lut[threadIdx.x];
-        lut[threadIdx.x] = kNarrow && v == kCodeInvalid ? (uint16_t)0xFF00u : v;
-    }
-    if (threadIdx.x == 0) bad_any = 0;
-    __syncthreads();
-    uint32_t bad = 0;
-    // WHOLE: all 16 bytes lie before n (no per-byte bounds)
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
-        constexpr bool WHOLE = decltype(whole_tag)::value;
-        uint32_t c[16];
-        if constexpr (WHOLE) {
-            uint32_t acc = 0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-                if constexpr (kNarrow) {
-                    acc |= v;
-                    c[k] = v;
-                } else {
-                    const bool inv = v == kCodeInvalid;
-                    bad |= inv ? 1u : 0u;
-                    c[k] = inv ? 0u : v;
-                }
-            }
-            if constexpr (kNarrow) bad |= acc >> 8;
-        } else {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-                const bool inside = first + k < n;
-                const bool inv = kNarrow ? (v >> 8) != 0 : v == kCodeInvalid;
-                bad |= (inside && inv) ? 1u : 0u;
-                c[k] = (inv || !inside) ? 0u : v;
-            }
-        }
-        if constexpr (!WRITE) {
-        } else if constexpr (kNarrow) {
-            uint4 o;
-            o.x = pack_low_bytes(c[0], c[1], c[2], c[3]);
-            o.y = pack_low_bytes(c[4], c[5], c[6], c[7]);
-            o.z = pack_low_bytes(c[8], c[9], c[10], c[11]);
-            o.w = pack_low_bytes(c[12], c[13], c[14], c[15]);
-            *reinterpret_cast<uint4 *>(sink.at(first)) = o;
-        } else {
-            uint4 o[2];
-            uint32_t *ow = reinterpret_cast<uint32_t *>(o);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
-            *reinterpret_cast<uint4 *>(sink.at(2 * first)) = o[0];
-            *reinterpret_cast<uint4 *>(sink.at(2 * first + 16)) = o[1];
-        }
-    };
-    uint8_t *ob = reinterpret_cast<uint8_t *>(out);
-    if (WRITE && ilv.nblk)
-        translate_ilv_grid<kNarrow ? 4 : 2>(in, n, ob, ilv, (uint64_t)ilv.nblk * 16u, convert);
-    else
-        translate_grid(in, n, ob, convert);
-    if (bad) atomicOr(&bad_any, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
-}
-
-
-// Two-symbol translation: code i = the pair code of bytes 2i and 2i + 1 (the
-// class alone when 2i + 1 = n); per-block flag if a byte is outside Sigma.
-// pcode: byte -> class (256 bytes), then the codes of the K x (K + 1) pairs.
-__global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restrict__ in, uint64_t n,
-                                                         const uint8_t *__restrict__ pcode,
-                                                         uint32_t K, uint8_t *__restrict__ out,
-                                                         uint32_t *__restrict__ block_bad, Ilv ilv) {
-    // pc covers every index c1 * (K + 1) + c2 with c1, c2 <= 255, so that a
-    // class 0xFF (byte outside Sigma) reads a staged value: a pair code, or 0
-    // past the K x (K + 1) codes; such blocks are flagged and their codes
-    // only need to stay valid table offsets
-    constexpr uint32_t kPc = 256u * 64u + 256u;
-    __shared__ uint8_t cls[256];
-    __shared__ __align__(16) uint8_t pc[kPc];
-    __shared__ uint32_t bad_any;
-    cls[threadIdx.x] = pcode[threadIdx.x];
-    for (uint32_t i = threadIdx.x; i < kPc / 4; i += blockDim.x)
-        reinterpret_cast<uint32_t *>(pc)[i] = 0u;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < K * (K + 1); i += blockDim.x) pc[i] = pcode[256 + i];
-    if (threadIdx.x == 0) bad_any = 0;
-    __syncthreads();
-    const uint32_t K1 = K + 1;
-    uint32_t bad = 0;
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
-        constexpr bool WHOLE = decltype(whole_tag)::value;
-        uint32_t c[8];
-        if constexpr (WHOLE) {
-            uint32_t acc = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t c1 = cls[(w[k >> 1] >> (16 * (k & 1))) & 0xFFu];
-                const uint32_t c2 = cls[(w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu];
-                acc |= c1 | c2;
-                c[k] = pc[__umul24(c1, K1) + c2];
-            }
-            bad |= (acc & 0x80u) ? 1u : 0u;   // classes are below 64; 0xFF marks a bad byte
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
-                const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
-                const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
-                const uint32_t c1 = cls[b1];
-                const uint32_t c2 = in2 ? (uint32_t)cls[b2] : K;
-                const bool bad1 = in1 && c1 == 0xFFu, bad2 = in2 && c2 == 0xFFu;
-                bad |= (bad1 || bad2) ? 1u : 0u;
-                c[k] = (in1 && !bad1 && !bad2) ? (uint32_t)pc[c1 * K1 + c2] : 0u;
-            }
-        }
-        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
-    };
-    if (ilv.nblk) {
-        pairs_grid_ilv(in, n, out, ilv, convert);
-    } else {
-        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
-            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
-        };
-        translate_grid(in, n, out, store8);
-    }
-    if (bad) atomicOr(&bad_any, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
-}
-
-// Two-symbol translation for direct tables (every byte of Sigma below 128):
-// one LDS lookup per pair, pc2[b1 + 256 * b2] (a lone last byte: pc2[32768 +
-// b]).  Entries of bytes outside Sigma are 0xFF (odd, unlike every code); a
-// block whose OR of entries is odd or that holds a byte >= 128 is redone on
-// the checked path, which writes 0 for such pairs.
-__global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *__restrict__ in,
-                                                                uint64_t n,
-                                                                const uint8_t *__restrict__ pcode2,
-                                                                uint8_t *__restrict__ out,
-                                                                uint32_t *__restrict__ block_bad,
-                                                                Ilv ilv) {
-    constexpr uint32_t kPc2 = 32768u + 128u;
-    __shared__ __align__(16) uint8_t pc2[kPc2];
-    __shared__ uint32_t bad_any;
-    for (uint32_t i = threadIdx.x; i < kPc2 / 16; i += blockDim.x)
-        reinterpret_cast<uint4 *>(pc2)[i] = reinterpret_cast<const uint4 *>(pcode2)[i];
-    if (threadIdx.x == 0) bad_any = 0;
-    __syncthreads();
-    uint32_t bad = 0;
-    auto checked = [&](const uint32_t (&w)[4], uint64_t first, uint32_t (&c)[8]) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
-            const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
-            const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
-            uint32_t v = 0xFFu;
-            if (in2) {
-                if (b1 < 128u && b2 < 128u) v = pc2[b1 + 256u * b2];
-            } else if (b1 < 128u) {
-                v = pc2[32768u + b1];
-            }
-            const bool inv = in1 && (v & 1u);
-            bad |= inv ? 1u : 0u;
-            c[k] = (!in1 || inv) ? 0u : v;
-        }
-    };
-    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
-        constexpr bool WHOLE = decltype(whole_tag)::value;
-        uint32_t c[8];
-        if constexpr (WHOLE) {
-            uint32_t acc = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                c[k] = pc2[(w[k >> 1] >> (16 * (k & 1))) & 0x7F7Fu];
-                acc |= c[k];
-            }
-            const uint32_t high = (w[0] | w[1] | w[2] | w[3]) & 0x80808080u;
-            if ((acc & 1u) || high) checked(w, first, c);
-        } else {
-            checked(w, first, c);
-        }
-        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
-    };
-    if (ilv.nblk) {
-        pairs_grid_ilv(in, n, out, ilv, convert);
-    } else {
-        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
-            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
-        };
-        translate_grid(in, n, out, store8);
-    }
-    if (bad) atomicOr(&bad_any, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
-}
-
-// Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
-// the image of Q under the r' = min(r, p) bytes before it (p = i*C), minus the
-// absorbing states; the true state at p lies in it, and so does the end state
-// of every walk of chunk i-1 from its own start set.  Unlike the paper's
-// precomputed I_{sigma_1..sigma_r} tables (|Sigma|^r of them), the image is
-// computed for the actual lookahead string: the image of Q under its first
-// byte is I_{sigma_1} (a precomputed class set), so every (chunk, state of
-// I_{sigma_1}) "window pair" walks the remaining r'-1 bytes and sets its end
-// state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
-// lays out the start sets as sorted member lists.
-//
-// For r <= r0 the start set of chunk i >= 1 is the precomputed I_{c_1..c_k}
-// of its k = min(r, p) lookahead bytes (chunk_info, in the scan's first
-// phase).  r > r0: window pairs start from the precomputed set of the window's first
-// k0 = min(r', r0) bytes; cset holds that set's id.  Clears the bitmaps.
-__global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
-                              uint32_t nch, uint32_t r, uint32_t W,
-                              uint16_t *__restrict__ msize, uint32_t *__restrict__ cset,
-                              uint32_t *__restrict__ bits) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nch) return;
-    for (uint32_t k = 0; k < W; ++k) bits[(size_t)i * W + k] = 0;
-    uint32_t m = 0, id = 0;
-    if (i > 0) {
-        const uint64_t p = (uint64_t)i * chunk;
-        const uint32_t rr = (uint32_t)min<uint64_t>(r, p);
-        const uint32_t k0 = min(rr, d.r0);
-        bool bad = false;
-        id = class_string_id(d, in, p - rr, k0, &bad);
-        m = bad ? 0u : mset_end(d, k0, id) - mset_begin(d, k0, id);
-    }
-    msize[i] = (uint16_t)m;
-    cset[i] = id;
-}
-
 // Exclusive scan of the set sizes in three phases: first[i] = sum_{k<i} m_k,
 // first[nch] = number of pairs, tile_first[w] = chunk holding pair w * tile.
 // Sizes come from msize (SRC 0) or from the popcounts of the start-set
@@ -550,13 +310,13 @@ __device__ __forceinline__ uint32_t chunk_info(const InfoSrc &f, uint64_t i) {
     return m;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_sums_info(ScanSrc q, InfoSrc f,
-                                                         uint32_t *__restrict__ bsum) {
-    __shared__ uint32_t part[kScanThreads];
-    __shared__ uint16_t ms[kScanBlock];
+// The first phase for scan block sb (kScanThreads threads).
+__device__ __forceinline__ void scan_sums_block(const ScanSrc &q, const InfoSrc &f,
+                                                uint32_t *__restrict__ bsum, uint32_t sb,
+                                                uint32_t *part, uint16_t *ms) {
     // the block's chunks are computed strided over the threads (independent,
     // coalesced), then summed in consecutive runs for the scan
-    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
+    const uint64_t b0 = (uint64_t)sb * kScanBlock;
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k) {
         const uint32_t t = k * kScanThreads + threadIdx.x;
@@ -572,7 +332,33 @@ __global__ __launch_bounds__(1024) void k_scan_sums_info(ScanSrc q, InfoSrc f,
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k) v += ms[threadIdx.x * kScanItems + k];
     const uint32_t inc = block_inclusive_scan(v, part);
-    if (threadIdx.x == blockDim.x - 1) bsum[blockIdx.x] = inc;
+    if (threadIdx.x == kScanThreads - 1) bsum[sb] = inc;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums_info(ScanSrc q, InfoSrc f,
+                                                         uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint16_t ms[kScanBlock];
+    scan_sums_block(q, f, bsum, blockIdx.x, part, ms);
+}
+
+// The first phase run by the workgroups of a translation pass (256 threads)
+// before they translate: scan blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+// (nsb = 0: none).
+struct SumsArgs {
+    ScanSrc q;
+    InfoSrc f;
+    uint32_t *bsum;
+    uint32_t nsb;
+};
+
+__device__ __forceinline__ void scan_sums_in_pass(const SumsArgs &sa) {
+    if (blockIdx.x >= sa.nsb) return;
+    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint16_t ms[kScanBlock];
+    for (uint32_t sb = blockIdx.x; sb < sa.nsb; sb += gridDim.x)
+        scan_sums_block(sa.q, sa.f, sa.bsum, sb, part, ms);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ bsum, uint32_t nb,
@@ -650,6 +436,293 @@ __global__ __launch_bounds__(1024) void k_scan_apply(ScanSrc q, const uint32_t *
         }
         run += m[k];
     }
+}
+
+
+// The last two phases in one pass, for sizes from msize: workgroup b adds up
+// the totals of scan blocks 0 .. b - 1 itself (a few thousand at most), then
+// lays out its chunks as k_scan_apply does; the last workgroup writes
+// first[nch], the first clears the merged-walk round counters.
+__global__ __launch_bounds__(1024) void k_scan_finish(ScanSrc q, const uint32_t *__restrict__ btot,
+                                                      uint32_t *__restrict__ first,
+                                                      uint32_t *__restrict__ tile_first,
+                                                      uint32_t *__restrict__ zero, uint32_t nzero) {
+    __shared__ uint32_t part[kScanThreads];
+    const uint32_t t = threadIdx.x, T = blockDim.x;
+    if (blockIdx.x == 0)
+        for (uint32_t i = t; i < nzero; i += T) zero[i] = 0;
+    uint32_t acc = 0;
+    for (uint32_t j = t; j < blockIdx.x; j += T) acc += btot[j];
+    block_inclusive_scan(acc, part);
+    const uint32_t pre = part[T - 1];
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + t * kScanItems;
+    uint32_t m[kScanItems], v = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanItems; ++k) {
+        m[k] = base + k < q.nch ? scan_size<0>(q, base + k) : 0u;
+        v += m[k];
+    }
+    const uint32_t inc = block_inclusive_scan(v, part);
+    uint32_t run = pre + inc - v;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanItems; ++k) {
+        const uint64_t i = base + k;
+        if (i < q.nch) {
+            first[i] = run;
+            if (m[k]) {
+                for (uint32_t w = (run + q.tile - 1) / q.tile; w <= (run + m[k] - 1) / q.tile; ++w)
+                    tile_first[w] = (uint32_t)i;
+            }
+        }
+        run += m[k];
+    }
+    if (blockIdx.x + 1 == gridDim.x && t == T - 1) first[q.nch] = pre + inc;
+}
+
+template <typename CodeT, bool WRITE = true>
+__global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ in, uint64_t n,
+                                                   const uint16_t *__restrict__ code_lut,
+                                                   CodeT *__restrict__ out,
+                                                   uint32_t *__restrict__ block_bad, Ilv ilv,
+                                                   SumsArgs sa) {
+    scan_sums_in_pass(sa);
+    // one-byte codes (< 256) are staged with bytes outside Sigma as 0xFF00:
+    // the low byte (the code written) is 0 and an OR of the entries flags them
+    constexpr bool kNarrow = sizeof(CodeT) == 1;
+    __shared__ uint16_t lut[256];
+    __shared__ uint32_t bad_any;
+    {
+        const uint16_t v = code_lut[threadIdx.x];
+        lut[threadIdx.x] = kNarrow && v == kCodeInvalid ? (uint16_t)0xFF00u : v;
+    }
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    // WHOLE: all 16 bytes lie before n (no per-byte bounds)
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[16];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+                if constexpr (kNarrow) {
+                    acc |= v;
+                    c[k] = v;
+                } else {
+                    const bool inv = v == kCodeInvalid;
+                    bad |= inv ? 1u : 0u;
+                    c[k] = inv ? 0u : v;
+                }
+            }
+            if constexpr (kNarrow) bad |= acc >> 8;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = lut[(w[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+                const bool inside = first + k < n;
+                const bool inv = kNarrow ? (v >> 8) != 0 : v == kCodeInvalid;
+                bad |= (inside && inv) ? 1u : 0u;
+                c[k] = (inv || !inside) ? 0u : v;
+            }
+        }
+        if constexpr (!WRITE) {
+        } else if constexpr (kNarrow) {
+            uint4 o;
+            o.x = pack_low_bytes(c[0], c[1], c[2], c[3]);
+            o.y = pack_low_bytes(c[4], c[5], c[6], c[7]);
+            o.z = pack_low_bytes(c[8], c[9], c[10], c[11]);
+            o.w = pack_low_bytes(c[12], c[13], c[14], c[15]);
+            *reinterpret_cast<uint4 *>(sink.at(first)) = o;
+        } else {
+            uint4 o[2];
+            uint32_t *ow = reinterpret_cast<uint32_t *>(o);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
+            *reinterpret_cast<uint4 *>(sink.at(2 * first)) = o[0];
+            *reinterpret_cast<uint4 *>(sink.at(2 * first + 16)) = o[1];
+        }
+    };
+    uint8_t *ob = reinterpret_cast<uint8_t *>(out);
+    if (WRITE && ilv.nblk)
+        translate_ilv_grid<kNarrow ? 4 : 2>(in, n, ob, ilv, (uint64_t)ilv.nblk * 16u, convert);
+    else
+        translate_grid(in, n, ob, convert);
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
+}
+
+
+// Two-symbol translation: code i = the pair code of bytes 2i and 2i + 1 (the
+// class alone when 2i + 1 = n); per-block flag if a byte is outside Sigma.
+// pcode: byte -> class (256 bytes), then the codes of the K x (K + 1) pairs.
+__global__ __launch_bounds__(256) void k_translate_pairs(const uint8_t *__restrict__ in, uint64_t n,
+                                                         const uint8_t *__restrict__ pcode,
+                                                         uint32_t K, uint8_t *__restrict__ out,
+                                                         uint32_t *__restrict__ block_bad, Ilv ilv,
+                                                         SumsArgs sa) {
+    scan_sums_in_pass(sa);
+    // pc covers every index c1 * (K + 1) + c2 with c1, c2 <= 255, so that a
+    // class 0xFF (byte outside Sigma) reads a staged value: a pair code, or 0
+    // past the K x (K + 1) codes; such blocks are flagged and their codes
+    // only need to stay valid table offsets
+    constexpr uint32_t kPc = 256u * 64u + 256u;
+    __shared__ uint8_t cls[256];
+    __shared__ __align__(16) uint8_t pc[kPc];
+    __shared__ uint32_t bad_any;
+    cls[threadIdx.x] = pcode[threadIdx.x];
+    for (uint32_t i = threadIdx.x; i < kPc / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(pc)[i] = 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < K * (K + 1); i += blockDim.x) pc[i] = pcode[256 + i];
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    const uint32_t K1 = K + 1;
+    uint32_t bad = 0;
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[8];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t c1 = cls[(w[k >> 1] >> (16 * (k & 1))) & 0xFFu];
+                const uint32_t c2 = cls[(w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu];
+                acc |= c1 | c2;
+                c[k] = pc[__umul24(c1, K1) + c2];
+            }
+            bad |= (acc & 0x80u) ? 1u : 0u;   // classes are below 64; 0xFF marks a bad byte
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
+                const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
+                const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
+                const uint32_t c1 = cls[b1];
+                const uint32_t c2 = in2 ? (uint32_t)cls[b2] : K;
+                const bool bad1 = in1 && c1 == 0xFFu, bad2 = in2 && c2 == 0xFFu;
+                bad |= (bad1 || bad2) ? 1u : 0u;
+                c[k] = (in1 && !bad1 && !bad2) ? (uint32_t)pc[c1 * K1 + c2] : 0u;
+            }
+        }
+        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+    };
+    if (ilv.nblk) {
+        pairs_grid_ilv(in, n, out, ilv, convert);
+    } else {
+        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
+        };
+        translate_grid(in, n, out, store8);
+    }
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
+}
+
+// Two-symbol translation for direct tables (every byte of Sigma below 128):
+// one LDS lookup per pair, pc2[b1 + 256 * b2] (a lone last byte: pc2[32768 +
+// b]).  Entries of bytes outside Sigma are 0xFF (odd, unlike every code); a
+// block whose OR of entries is odd or that holds a byte >= 128 is redone on
+// the checked path, which writes 0 for such pairs.
+__global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *__restrict__ in,
+                                                                uint64_t n,
+                                                                const uint8_t *__restrict__ pcode2,
+                                                                uint8_t *__restrict__ out,
+                                                                uint32_t *__restrict__ block_bad,
+                                                                Ilv ilv, SumsArgs sa) {
+    scan_sums_in_pass(sa);
+    constexpr uint32_t kPc2 = 32768u + 128u;
+    __shared__ __align__(16) uint8_t pc2[kPc2];
+    __shared__ uint32_t bad_any;
+    for (uint32_t i = threadIdx.x; i < kPc2 / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(pc2)[i] = reinterpret_cast<const uint4 *>(pcode2)[i];
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    auto checked = [&](const uint32_t (&w)[4], uint64_t first, uint32_t (&c)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t b1 = (w[k >> 1] >> (16 * (k & 1))) & 0xFFu;
+            const uint32_t b2 = (w[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
+            const bool in1 = first + 2 * k < n, in2 = first + 2 * k + 1 < n;
+            uint32_t v = 0xFFu;
+            if (in2) {
+                if (b1 < 128u && b2 < 128u) v = pc2[b1 + 256u * b2];
+            } else if (b1 < 128u) {
+                v = pc2[32768u + b1];
+            }
+            const bool inv = in1 && (v & 1u);
+            bad |= inv ? 1u : 0u;
+            c[k] = (!in1 || inv) ? 0u : v;
+        }
+    };
+    auto convert = [&](auto whole_tag, const uint32_t (&w)[4], uint64_t first) -> uint2 {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        uint32_t c[8];
+        if constexpr (WHOLE) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                c[k] = pc2[(w[k >> 1] >> (16 * (k & 1))) & 0x7F7Fu];
+                acc |= c[k];
+            }
+            const uint32_t high = (w[0] | w[1] | w[2] | w[3]) & 0x80808080u;
+            if ((acc & 1u) || high) checked(w, first, c);
+        } else {
+            checked(w, first, c);
+        }
+        return make_uint2(pack_low_bytes(c[0], c[1], c[2], c[3]), pack_low_bytes(c[4], c[5], c[6], c[7]));
+    };
+    if (ilv.nblk) {
+        pairs_grid_ilv(in, n, out, ilv, convert);
+    } else {
+        auto store8 = [&](auto tag, const uint32_t (&w)[4], uint64_t first, const auto &sink) {
+            *reinterpret_cast<uint2 *>(sink.at(first / 2)) = convert(tag, w, first);
+        };
+        translate_grid(in, n, out, store8);
+    }
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
+}
+
+// Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
+// the image of Q under the r' = min(r, p) bytes before it (p = i*C), minus the
+// absorbing states; the true state at p lies in it, and so does the end state
+// of every walk of chunk i-1 from its own start set.  Unlike the paper's
+// precomputed I_{sigma_1..sigma_r} tables (|Sigma|^r of them), the image is
+// computed for the actual lookahead string: the image of Q under its first
+// byte is I_{sigma_1} (a precomputed class set), so every (chunk, state of
+// I_{sigma_1}) "window pair" walks the remaining r'-1 bytes and sets its end
+// state's bit in the chunk's bitmap.  A scan over the bitmaps' popcounts then
+// lays out the start sets as sorted member lists.
+//
+// For r <= r0 the start set of chunk i >= 1 is the precomputed I_{c_1..c_k}
+// of its k = min(r, p) lookahead bytes (chunk_info, in the scan's first
+// phase).  r > r0: window pairs start from the precomputed set of the window's first
+// k0 = min(r', r0) bytes; cset holds that set's id.  Clears the bitmaps.
+__global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
+                              uint32_t nch, uint32_t r, uint32_t W,
+                              uint16_t *__restrict__ msize, uint32_t *__restrict__ cset,
+                              uint32_t *__restrict__ bits) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    for (uint32_t k = 0; k < W; ++k) bits[(size_t)i * W + k] = 0;
+    uint32_t m = 0, id = 0;
+    if (i > 0) {
+        const uint64_t p = (uint64_t)i * chunk;
+        const uint32_t rr = (uint32_t)min<uint64_t>(r, p);
+        const uint32_t k0 = min(rr, d.r0);
+        bool bad = false;
+        id = class_string_id(d, in, p - rr, k0, &bad);
+        m = bad ? 0u : mset_end(d, k0, id) - mset_begin(d, k0, id);
+    }
+    msize[i] = (uint16_t)m;
+    cset[i] = id;
 }
 
 struct Match2Args {
@@ -1241,20 +1314,6 @@ __global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs 
     }
 }
 
-// Translation flags of a segmented run -> the symbol flag of chunk 0's size
-// (from where the composition carries it up).
-__global__ void k_fold_bad(const uint32_t *__restrict__ block_bad, uint32_t nbad,
-                           uint16_t *__restrict__ msize) {
-    __shared__ uint32_t any;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    uint32_t bad = 0;
-    for (uint32_t b = threadIdx.x; b < nbad; b += blockDim.x) bad |= block_bad[b];
-    if (bad) atomicOr(&any, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0 && any) msize[0] = (uint16_t)(msize[0] | kFlagSymbol);
-}
-
 // Down-sweep into pair-indexed level-0 maps: bv0[i] = value at chunk i's start.
 __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__restrict__ first,
                         uint32_t nch, uint32_t G, const uint16_t *__restrict__ bv_up,
@@ -1342,45 +1401,64 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     const bool pairs = p.pairs && d->dev.pairs;
     const bool direct = !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
                         p.segments <= 1 && (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+    const bool fork = p.fork && p.lookahead != 2;
     const Ilv ilv{p.ilv_nblk, p.nch, p.chunk};
     if (p.ilv_nblk && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
         return fail(DFA_E_INVAL, "interleaved codes with segments, window pass or odd chunks");
     const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
-    if (pairs && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
-        return fail(DFA_E_INVAL, "two-symbol plan with segments, window pass or odd chunks");
+    if (pairs && (p.chunk % 32 != 0 || p.lookahead == 2 || (p.segments > 1 && p.chunk % 64 != 0)))
+        return fail(DFA_E_INVAL, "two-symbol plan with a window pass or odd chunks");
     const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
+    if (nseg > 1 && !fork) return fail(DFA_E_INVAL, "segments without the translation stream");
     uint32_t cb[kMaxSegments + 1];
     for (uint32_t k = 0; k <= nseg; ++k) cb[k] = (uint32_t)((uint64_t)p.nch * k / nseg);
+    // fork: the translation runs on the aux stream from this point of s (so
+    // after every earlier use of the codes and flags); s waits for segment k
+    // before the matcher reads it, or (raw input) before the composition
     hipStream_t ts = s;
-    if (nseg > 1) {
-        if (!b.aux || !b.ev_fork) return fail(DFA_E_DEVICE, "segmented match without an aux stream");
+    if (fork) {
+        if (!b.aux || !b.ev_fork) return fail(DFA_E_DEVICE, "forked translation without an aux stream");
         hipError_t fe = hipEventRecord(b.ev_fork, s);
         if (fe == hipSuccess) fe = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
         if (fe != hipSuccess) return hip_fail(fe, "fork to the translation stream");
         ts = b.aux;
     }
+    auto join = [&](uint32_t k) -> int {
+        if (!fork) return DFA_OK;
+        const hipError_t je = hipStreamWaitEvent(s, b.ev_seg[k], 0);
+        return je == hipSuccess ? DFA_OK : hip_fail(je, "hipStreamWaitEvent (translation)");
+    };
+    // Scan of the start-set sizes.  On one stream with precomputed sets the
+    // translation pass's workgroups also run the scan's first phase (the
+    // lookahead sets from the raw input) before they translate, and one
+    // pass finishes the scan; else the three-phase scan runs on s.
+    ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
+    const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset};
+    const bool fused_scan = !fork && p.lookahead != 2;
+    const uint32_t nsb = match2_scan_blocks(p.nch);
     for (uint32_t k = 0; k < nseg; ++k) {
         const uint64_t off = (uint64_t)cb[k] * p.chunk;
         const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
         uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
+        const SumsArgs sa{q, info, b.bsum, fused_scan ? nsb : 0u};
         if (pairs && d->dev.pcode2)
             hipLaunchKernelGGL(k_translate_pairs_direct, dim3(p.tblocks), dim3(256), 0, ts,
                                d_in + off, end - off, d->dev.pcode2, (uint8_t *)b.codes + off / 2,
-                               bad, ilv);
+                               bad, ilv, sa);
         else if (pairs)
             hipLaunchKernelGGL(k_translate_pairs, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
                                end - off, d->dev.pcode, d->dev.nclass, (uint8_t *)b.codes + off / 2,
-                               bad, ilv);
+                               bad, ilv, sa);
         else if (direct)
             hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, ts,
-                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad, ilv);
+                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad, ilv, sa);
         else if (L == 1)
             hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad, ilv);
+                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad, ilv, sa);
         else
             hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad, ilv);
-        if (nseg > 1) {
+                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad, ilv, sa);
+        if (fork) {
             hipError_t fe = hipEventRecord(b.ev_seg[k], ts);
             if (fe != hipSuccess) return hip_fail(fe, "hipEventRecord (segment)");
         }
@@ -1416,7 +1494,6 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.tile = kWave2 * p.slots;
     a.ilv_nblk = p.ilv_nblk;
     const size_t lds = a.d.stab_bytes;
-    ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
         hipLaunchKernelGGL(k_chunkinfo_w, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
@@ -1426,17 +1503,20 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         void *wargs[] = {&a};
         hipError_t we = hipLaunchKernel(wf, dim3(p.blocks2), dim3(p.threads2), wargs, lds, s);
         if (we != hipSuccess) return hip_fail(we, "k_window2 launch");
-        launch_scan<1>(p, q, b, msize, start, s);
+        launch_scan<1>(p, q, b, nullptr, start, s);
+    } else if (fused_scan) {
+        hipLaunchKernelGGL(k_scan_finish, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum, b.first,
+                           b.tile_first, b.cnt, b.cnt ? kMaxRounds * kRegions : 0u);
     } else {
         // lookahead sets and sizes computed inside the scan's first phase
-        const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset};
-        launch_scan<0>(p, q, b, nseg > 1 ? nullptr : msize, start, s, &info);
+        launch_scan<0>(p, q, b, nullptr, start, s, &info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
     if (p.chunk_lanes) {
-        if (!p.ilv_nblk || L == 3 || p.lookahead == 2)
+        if (!p.ilv_nblk || L == 3 || p.lookahead == 2 || nseg > 1)
             return fail(DFA_E_INVAL, "chunk lanes need interleaved codes and precomputed sets");
+        if (int jr = join(0)) return jr;
         if (ev_before_matcher) {
             e = hipEventRecord(ev_before_matcher, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -1451,6 +1531,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     if (p.rounds > 1) {
         if (nseg > 1 || p.early_exit || p.chunk % 32 != 0 || !b.cnt)
             return fail(DFA_E_INVAL, "merged walks need one segment, no early exit, chunks of 32k");
+        if (!direct)
+            if (int jr = join(0)) return jr;
         if (ev_before_matcher) {
             e = hipEventRecord(ev_before_matcher, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -1479,14 +1561,14 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint64_t bound = (uint64_t)p.max_tiles * kWave2 * p.slots;
         hipLaunchKernelGGL(k_merge_maps, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s, a, mm);
         e = hipGetLastError();
-        return e == hipSuccess ? DFA_OK : hip_fail(e, "k_merge_maps launch");
+        if (e != hipSuccess) return hip_fail(e, "k_merge_maps launch");
+        return direct ? join(0) : DFA_OK;
     }
     const void *fn = match2_kernel(L, p.slots, p.early_exit);
     for (uint32_t k = 0; k < nseg; ++k) {
-        if (nseg > 1) {
-            e = hipStreamWaitEvent(s, b.ev_seg[k], 0);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent (segment)");
-        }
+        // raw input: the matcher does not read the validation pass's output
+        if (!direct)
+            if (int jr = join(k)) return jr;
         if (k == 0 && ev_before_matcher) {
             e = hipEventRecord(ev_before_matcher, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -1497,8 +1579,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         e = hipLaunchKernel(fn, dim3(p.blocks2), dim3(p.threads2), args, lds, s);
         if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
     }
-    if (nseg > 1)
-        hipLaunchKernelGGL(k_fold_bad, dim3(1), dim3(256), 0, s, b.block_bad, nseg * p.tblocks, msize);
+    if (direct)
+        if (int jr = join(nseg - 1)) return jr;
     e = hipGetLastError();
     return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
 }

@@ -549,7 +549,8 @@ def test_compose_tree_group_edges(dfa_mod, nch, look):
 # ---------------------------------------------------------------------------
 # Segmented pipeline: translation of segment k + 1 on a second stream while
 # the matcher walks segment k.  Forced segment counts, boundary states, and a
-# byte outside Sigma in the last segment (its flag is folded after the walk).
+# byte outside Sigma in the last segment (its flag reaches the result through
+# the top composition level).
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("segs", [2, 3, 4])
 @pytest.mark.parametrize("look", [1, 4])
@@ -573,6 +574,44 @@ def test_segmented_pipeline(dfa_mod, monkeypatch, segs, look):
     res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=C, lookahead=look)
     torch.cuda.synchronize()
     assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()
+
+
+@pytest.mark.parametrize("fork", ["0", "1"])
+@pytest.mark.parametrize("look,single", [(1, False), (5, False), (5, True), (3, True)])
+def test_translation_stream(dfa_mod, monkeypatch, fork, look, single):
+    """The translation (or, for direct tables, validation) pass on a second
+    stream beside the scan, or on the caller's stream (DFA_FORK=0): results,
+    boundaries, a byte outside Sigma in the middle and at the very end, and a
+    clean call after a flagged one on the same workspace."""
+    import torch
+    monkeypatch.setenv("DFA_FORK", fork)
+    w = configs.c2_dfa()
+    C = 2048
+    n = 6 * (1 << 20) + 4096 * 3
+    x = configs.c2_input(n, seed=40 + look).copy()
+    probes = list(range(0, n + 1, 32 * C))
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    d = dfa_mod.DFA.from_workload(w)
+    plan = dfa_mod.dfa_plan(d, n, C, look, single_step=single)
+    assert plan.kernel == 1 and int(plan.symbols_per_step) == (1 if single else 2)
+    dev = torch.from_numpy(x).to("cuda")
+    res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=C, lookahead=look, single_step=single,
+                                    boundaries=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
+    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(b[np.array(probes) // C], ps.astype(np.int64))
+    for pos in (n // 2 + 7, n - 1):
+        y = x.copy()
+        y[pos] = ord("#")
+        res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(y).to("cuda"), chunk_len=C,
+                                      lookahead=look, single_step=single)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL, pos
+    res, _ = dfa_mod.dfa_match_ex(d, dev, chunk_len=C, lookahead=look, single_step=single)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
     d.close()
 
 

@@ -110,6 +110,47 @@ __device__ __forceinline__ void write_result(const FinalArgs &fa, uint32_t v, bo
     if (fa.boundaries) fa.boundaries[fa.nch] = fin;
 }
 
+// Copies src[0 .. E) into LDS dst[0 .. E) (dst 4-byte aligned): 16-byte
+// loads from src's first 16-byte boundary on, four per thread in flight
+// before their LDS writes.
+__device__ __forceinline__ void stage_u16(uint16_t *dst, const uint16_t *__restrict__ src,
+                                          uint32_t E) {
+    const uint32_t T = blockDim.x, t = threadIdx.x;
+    const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(src) >> 1) & 7u);
+    const uint32_t head = min(E, (8u - mis) & 7u);
+    if (t < head) dst[t] = src[t];
+    const uint32_t n16 = (E - head) / 8u;
+    const uint4 *v = reinterpret_cast<const uint4 *>(src + head);
+    uint16_t *d = dst + head;
+    constexpr uint32_t U = 4;
+    for (uint32_t i0 = 0; i0 < n16; i0 += U * T) {
+        uint4 x[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * T + t;
+            if (i < n16) x[u] = v[i];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * T + t;
+            if (i >= n16) continue;
+            const uint32_t w[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+            if ((head & 1u) == 0) {
+                uint32_t *d32 = reinterpret_cast<uint32_t *>(d) + 4u * i;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) d32[k] = w[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    d[8u * i + 2u * k] = (uint16_t)w[k];
+                    d[8u * i + 2u * k + 1u] = (uint16_t)(w[k] >> 16);
+                }
+            }
+        }
+    }
+    for (uint32_t e = head + 8u * n16 + t; e < E; e += T) dst[e] = src[e];
+}
+
 __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restrict__ in_maps,
                                                        const uint32_t *__restrict__ first,
                                                        const uint16_t *__restrict__ in_msize,
@@ -130,14 +171,17 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
     const uint32_t W = stride_in;
     const float invW = 1.0f / (float)W;
     if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    // every global read of the group in one phase: offsets, domains, flags
+    // and the maps themselves
     const uint64_t base = first ? (uint64_t)first[c0] : (uint64_t)c0 * stride_in;
+    const uint32_t E = first ? first[c0 + cnt] - (uint32_t)base : cnt * stride_in;
     for (uint32_t t = threadIdx.x; t <= cnt; t += T)
         off[t] = first ? first[c0 + t] - (uint32_t)base : t * stride_in;
-    __syncthreads();
     for (uint32_t t = threadIdx.x; t < cnt; t += T) {
         const uint16_t ms = in_msize[c0 + t];
         if (ms & kFlagSymbol) atomicOr(&flag, 1u);
-        dom[t] = first ? (uint16_t)(off[t + 1] - off[t]) : (uint16_t)(ms & 0x7FFFu);
+        dom[t] = first ? (uint16_t)(first[c0 + t + 1] - first[c0 + t]) : (uint16_t)(ms & 0x7FFFu);
     }
     if (fa.result && fa.bad) {
         // the top level also takes the translation pass's flags
@@ -145,8 +189,7 @@ __global__ __launch_bounds__(1024) void k_compose_tree(const uint16_t *__restric
         for (uint32_t b = threadIdx.x; b < fa.nbad; b += T) any |= fa.bad[b];
         if (any) atomicOr(&flag, 1u);
     }
-    const uint32_t E = off[cnt];
-    for (uint32_t e = threadIdx.x; e < E; e += T) sm[e] = in_maps[base + e];
+    stage_u16(sm, in_maps + base, E);
     __syncthreads();
     for (uint32_t step = 1; step < cnt; step <<= 1) {
         const uint32_t na = (cnt - step + 2 * step - 1) / (2 * step);   // maps with t + step < cnt
@@ -477,6 +520,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         p->group_l[L] = (uint32_t)(L == 0 ? g0 : p->group);
         cnt = (cnt + p->group_l[L] - 1) / p->group_l[L];
         ++L;
+        moff = (moff + 7u) & ~7ull;   // levels start on 16-byte boundaries
         p->level_count[L] = (uint32_t)cnt;
         p->level_off[L] = moff;
         p->msize_off[L] = soff;

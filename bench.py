@@ -183,8 +183,8 @@ def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int,
                        step: int = 1) -> int:
     """Lookups of Algorithm 3 when every walk stops at the first absorbing
     state it reaches (the least work early exit can do; the kernel checks
-    every 64 bytes, so it does at least this much).  step = 2 counts table
-    reads of the two-symbol table (one per two symbols of a walk)."""
+    every 64 bytes, so it does at least this much).  step = k counts table
+    reads of the k-symbol table (one per k symbols of a walk)."""
     d = w.delta.astype(np.int32)
     nq = d.shape[0]
     absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
@@ -261,7 +261,7 @@ def merged_lookups(w, x: np.ndarray, chunk: int, lookahead: int, rounds: int,
 def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int, step: int = 1) -> int:
     """len(c_0) + sum_{i>=1} |I_i| len(c_i) (Algorithm 3's work; I_i is the
     chunk's start set: all states, I_sigma, or the r-symbol image of Eq. 13).
-    step = 2: table reads of the two-symbol table, ceil(len / 2) per walk."""
+    step = k: table reads of the k-symbol table, ceil(len / k) per walk."""
     n = x.size
     nch = (n + chunk - 1) // chunk
     lens = np.full(nch, chunk, dtype=np.int64)
@@ -703,6 +703,9 @@ def main() -> int:
                          "pick, else one)")
     ap.add_argument("--single-step", action="store_true",
                     help="one symbol per table lookup even where a two-symbol table exists")
+    ap.add_argument("--two-step", action="store_true",
+                    help="at most two symbols per table lookup even where a three-symbol "
+                         "table exists")
     ap.add_argument("--chunk-lanes", action="store_true",
                     help="one chunk per lane with merged walks")
     ap.add_argument("--interleave", action="store_true",
@@ -749,19 +752,20 @@ def main() -> int:
     tuned = None
     if args.lookahead < 0:
         t0 = time.perf_counter()
-        r, c, ms, ex, rounds, single, ilv, lanes = dfa.dfa_autotune(d, dev_in, stream)
+        r, c, ms, ex, rounds, single, ilv, lanes, two = dfa.dfa_autotune(d, dev_in, stream)
         tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4), "early_exit": ex,
                  "rounds": rounds, "single_step": single, "interleave": ilv,
-                 "chunk_lanes": lanes,
+                 "chunk_lanes": lanes, "two_step": two,
                  "tuning_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex}, "
-            f"rounds {rounds or 1}, single step {single}, interleave {ilv}, chunk lanes {lanes} "
-            f"({ms:.3f} ms)")
+            f"rounds {rounds or 1}, single step {single}, interleave {ilv}, chunk lanes {lanes}, "
+            f"two-step {two} ({ms:.3f} ms)")
         if args.rounds < 0:
             args.rounds = rounds
         args.single_step = args.single_step or single
         args.interleave = args.interleave or ilv
         args.chunk_lanes = args.chunk_lanes or lanes
+        args.two_step = args.two_step or two
         # the timed run uses early exit only when asked for (--early-exit):
         # its work depends on the data, so the roofline would need the
         # smaller exact count
@@ -770,13 +774,13 @@ def main() -> int:
         if not args.chunk:
             args.chunk = c
         if args.tune_only:
-            print(r, c, int(ex), rounds, int(single), int(ilv), int(lanes), flush=True)
+            print(r, c, int(ex), rounds, int(single), int(ilv), int(lanes), int(two), flush=True)
             return 0
     args.rounds = max(args.rounds, 0)
     chunk, nch = dfa.dfa_plan_chunks(d, nbytes, args.chunk, args.lookahead)
     opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result,
                 early_exit=args.early_exit, rounds=args.rounds, single_step=args.single_step,
-                interleave=args.interleave, chunk_lanes=args.chunk_lanes)
+                interleave=args.interleave, chunk_lanes=args.chunk_lanes, two_step=args.two_step)
 
     if args.calibrate_copy:
         scratch = torch.empty_like(dev_in)
@@ -818,7 +822,8 @@ def main() -> int:
     value = nbytes / (ms_per_step * 1e-3) / 1e9
     plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead, rounds=args.rounds,
                         early_exit=args.early_exit, single_step=args.single_step,
-                        interleave=args.interleave, chunk_lanes=args.chunk_lanes)
+                        interleave=args.interleave, chunk_lanes=args.chunk_lanes,
+                        two_step=args.two_step)
     step = int(plan.symbols_per_step) if plan.kernel == 1 else 1
     if args.early_exit:
         lookups = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0))
@@ -831,7 +836,8 @@ def main() -> int:
     if merged:
         reads = merged_lookups(w, x, chunk, args.lookahead, max(2, int(plan.rounds)), step)
     if plan.kernel == 1:
-        lay = 4 if step == 2 else 3 if plan.raw_input else (2 if info.packed_layout == 2 else 1)
+        lay = 5 if step == 3 else 4 if step == 2 else 3 if plan.raw_input else (
+            2 if info.packed_layout == 2 else 1)
         kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
                   f"k_round<{lay}>" if merged else f"k_match2<{lay}>")
     else:
@@ -840,8 +846,9 @@ def main() -> int:
     achieved = reads / (matcher_avg_ms * 1e-3)
     traffic, traffic_src = stored_traffic(kernel, args.workload, args.lookahead, int(chunk))
     # bytes the walk streams per input byte: raw input or one-byte codes 1,
-    # two-byte codes 2, pair codes 1/2
-    stream_bpb = 0.5 if step == 2 else (2.0 if kernel.endswith("<2>") else 1.0)
+    # two-byte codes 2, pair codes 1/2, triple codes (2 bytes) 2/3
+    stream_bpb = (2.0 / 3.0 if step == 3 else 0.5 if step == 2 else
+                  2.0 if kernel.endswith("<2>") else 1.0)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -869,6 +876,9 @@ def main() -> int:
             "chunks": int(nch),
             "lookups_per_byte": round(lookups / nbytes, 3),
             "rounds": int(plan.rounds) if plan.kernel == 1 else 1,
+            "set_max": int(plan.set_max),
+            "compose": {"levels": int(plan.levels), "group0": int(plan.group0),
+                        "group": int(plan.group)},
         },
         "roofline": {
             "bound": "lds",

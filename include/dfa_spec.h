@@ -82,6 +82,9 @@ typedef struct dfa_info {
     uint32_t pair_columns;    /* distinct two-symbol columns delta(delta(., a), b) of the
                                  table that lets the packed matcher take two symbols
                                  per lookup; 0 = no such table */
+    uint32_t triple_columns;  /* distinct three-symbol columns of the table that lets it
+                                 take three symbols per lookup (class-major, all of it
+                                 within 64 KiB); 0 = no such table */
 } dfa_info_t;
 
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
@@ -132,6 +135,16 @@ typedef struct dfa_match_opts {
  * precomputed start sets); ignored otherwise.  The maps, and every result,
  * are unchanged. */
 #define DFA_MATCH_CHUNK_LANES 8u
+
+/* flags bit: at most two symbols per table lookup even where the DFA has a
+ * three-symbol table (dfa_info_t::triple_columns > 0).  The three-symbol
+ * table cuts the walk's lookups to a third but is staged larger (up to 64
+ * KiB per workgroup) and its codes take 2 bytes per 3 symbols (pair codes: 1
+ * byte per 2); it is used for requested chunk lengths (chunk_len != 0) of a
+ * multiple of 48 with precomputed start sets, and never with merged walks or
+ * interleaved codes; the planner's own lengths keep two symbols.
+ * dfa_autotune tries both. */
+#define DFA_MATCH_TWO_STEP 16u
 
 /* flags field bits 8..11: walk rounds of the packed matcher.  Walks of one
  * chunk that reach the same state at the same position have the same future
@@ -224,8 +237,10 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * power-of-two length bucket and used by calls with lookahead
  * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r and r + 1, a quarter
  * to four times the chunk) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
- * interleaved codes (one and two rounds) and one chunk per lane, then the best
- * with DFA_MATCH_SINGLE_STEP where a two-symbol table exists, and for a DFA
+ * interleaved codes (one and two rounds) and one chunk per lane, then three-
+ * symbol steps at chunk lengths of a multiple of 48 near the best where that
+ * table exists, the best with DFA_MATCH_SINGLE_STEP where a two-symbol table
+ * exists, and for a DFA
  * with an absorbing state with DFA_MATCH_EARLY_EXIT; whichever is faster is
  * kept (in best->flags).
  *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
@@ -256,15 +271,20 @@ typedef struct dfa_plan_info {
     uint32_t lookahead;       /* effective reverse-lookahead symbols r */
     uint32_t blocks;          /* matcher grid */
     uint32_t threads;         /* threads per block */
-    uint32_t symbols_per_step;/* 2: the packed matcher walks the two-symbol table (one
-                                 lookup per two input bytes, after a pass that turns
-                                 byte pairs into codes); 1 otherwise */
+    uint32_t symbols_per_step;/* 3: the packed matcher walks the three-symbol table (one
+                                 lookup per three input bytes, after a pass that turns
+                                 byte triples into codes); 2: the two-symbol table
+                                 (likewise for byte pairs); 1 otherwise */
     uint32_t raw_input;       /* 1: the packed matcher reads the input bytes themselves
                                  (direct table: only a validation pass runs first) when
                                  the input is 16-byte aligned */
     uint32_t rounds;          /* walk rounds with merging (DFA_MATCH_ROUNDS); 1 = none */
     uint32_t interleaved;     /* 1: chunk-interleaved code stream (DFA_MATCH_INTERLEAVE) */
     uint32_t chunk_lanes;     /* 1: one chunk per lane with merged walks (DFA_MATCH_CHUNK_LANES) */
+    uint32_t set_max;         /* largest start set a chunk can have (entries per strided map) */
+    uint32_t levels;          /* composition levels (Eq. 9 applied as a tree) */
+    uint32_t group0;          /* maps composed per workgroup on the first level */
+    uint32_t group;           /* maps composed per workgroup on the later levels */
 } dfa_plan_info_t;
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 

@@ -37,7 +37,8 @@ class dfa_info_t(ctypes.Structure):
                 ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
                 ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("packed_layout", ctypes.c_uint32),
-                ("lookahead_tables", ctypes.c_uint32), ("pair_columns", ctypes.c_uint32)]
+                ("lookahead_tables", ctypes.c_uint32), ("pair_columns", ctypes.c_uint32),
+                ("triple_columns", ctypes.c_uint32)]
 
 
 class dfa_match_opts_t(ctypes.Structure):
@@ -51,7 +52,9 @@ class dfa_plan_info_t(ctypes.Structure):
                 ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("symbols_per_step", ctypes.c_uint32), ("raw_input", ctypes.c_uint32),
                 ("rounds", ctypes.c_uint32), ("interleaved", ctypes.c_uint32),
-                ("chunk_lanes", ctypes.c_uint32)]
+                ("chunk_lanes", ctypes.c_uint32), ("set_max", ctypes.c_uint32),
+                ("levels", ctypes.c_uint32), ("group0", ctypes.c_uint32),
+                ("group", ctypes.c_uint32)]
 
 
 class dfa_result_t(ctypes.Structure):
@@ -186,6 +189,7 @@ MATCH_EARLY_EXIT = 1
 MATCH_SINGLE_STEP = 2
 MATCH_INTERLEAVE = 4
 MATCH_CHUNK_LANES = 8
+MATCH_TWO_STEP = 16
 
 
 def match_rounds(k: int) -> int:
@@ -195,10 +199,10 @@ def match_rounds(k: int) -> int:
 
 def _opts(chunk_len: int = 0, lookahead: int = 1, early_exit: bool = False,
           rounds: int = 0, single_step: bool = False, interleave: bool = False,
-          chunk_lanes: bool = False) -> dfa_match_opts_t:
+          chunk_lanes: bool = False, two_step: bool = False) -> dfa_match_opts_t:
     flags = ((MATCH_EARLY_EXIT if early_exit else 0) | match_rounds(rounds) |
              (MATCH_SINGLE_STEP if single_step else 0) | (MATCH_INTERLEAVE if interleave else 0) |
-             (MATCH_CHUNK_LANES if chunk_lanes else 0))
+             (MATCH_CHUNK_LANES if chunk_lanes else 0) | (MATCH_TWO_STEP if two_step else 0))
     return dfa_match_opts_t(int(chunk_len), int(lookahead), flags)
 
 
@@ -302,9 +306,11 @@ def dfa_lookahead_set(d: DFA, lookahead_bytes) -> List[int]:
 
 def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1, rounds: int = 0,
              early_exit: bool = False, single_step: bool = False,
-             interleave: bool = False, chunk_lanes: bool = False) -> dfa_plan_info_t:
+             interleave: bool = False, chunk_lanes: bool = False,
+             two_step: bool = False) -> dfa_plan_info_t:
     out = dfa_plan_info_t()
-    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes,
+              two_step)
     _check(lib().dfa_plan(d.handle, int(n), ctypes.byref(o), ctypes.byref(out)))
     return out
 
@@ -312,10 +318,12 @@ def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1, rounds: int
 def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
                  lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
                  bound_out=None, early_exit: bool = False, rounds: int = 0,
-                 single_step: bool = False, interleave: bool = False, chunk_lanes: bool = False):
+                 single_step: bool = False, interleave: bool = False, chunk_lanes: bool = False,
+                 two_step: bool = False):
     """Test with options; optionally the state at every chunk boundary.
     rounds: walk rounds with merging (DFA_MATCH_ROUNDS; 0 = the planner's);
     single_step: one symbol per lookup even with a two-symbol table;
+    two_step: at most two symbols per lookup even with a three-symbol table;
     interleave: chunk-interleaved code stream (else linear; direct tables: the raw input);
     chunk_lanes: one chunk per lane with merged walks.
     Returns (result tensor, boundaries tensor or None)."""
@@ -328,7 +336,8 @@ def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 
         bnd = bound_out if bound_out is not None else torch.empty(
             nch + 1, dtype=torch.int32, device="cuda")
         assert bnd.numel() >= nch + 1
-    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes,
+              two_step)
     _check(lib().dfa_match_ex(d.handle, d_input.data_ptr() if n else None, n,
                               DFA_Q0 if start is None else int(start), ctypes.byref(o),
                               _stream_handle(stream), result.data_ptr(),
@@ -365,7 +374,8 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
 
 def dfa_autotune(d: DFA, d_input, stream=None):
     """Tune on a device input: (lookahead r, chunk length, ms per call, early exit,
-    walk rounds (0 = one), one symbol per lookup, interleaved codes, chunk lanes)."""
+    walk rounds (0 = one), one symbol per lookup, interleaved codes, chunk lanes,
+    at most two symbols per lookup)."""
     o = dfa_match_opts_t()
     ms = ctypes.c_double()
     n = int(d_input.numel())
@@ -373,7 +383,8 @@ def dfa_autotune(d: DFA, d_input, stream=None):
                               _stream_handle(stream), ctypes.byref(o), ctypes.byref(ms)))
     return (int(o.lookahead), int(o.chunk_len), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT),
             (int(o.flags) >> 8) & 0xF, bool(o.flags & MATCH_SINGLE_STEP),
-            bool(o.flags & MATCH_INTERLEAVE), bool(o.flags & MATCH_CHUNK_LANES))
+            bool(o.flags & MATCH_INTERLEAVE), bool(o.flags & MATCH_CHUNK_LANES),
+            bool(o.flags & MATCH_TWO_STEP))
 
 
 def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None

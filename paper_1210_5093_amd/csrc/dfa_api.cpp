@@ -287,11 +287,15 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->lookahead = p.r;
     out->blocks = p.packed ? p.blocks2 : p.blocks;
     out->threads = p.packed ? p.threads2 : p.waves_per_block * 64u;
-    out->symbols_per_step = p.pairs ? 2u : 1u;
+    out->symbols_per_step = p.triples ? 3u : p.pairs ? 2u : 1u;
     out->rounds = p.rounds;
     out->interleaved = p.ilv_nblk ? 1u : 0u;
     out->chunk_lanes = p.chunk_lanes ? 1u : 0u;
-    out->raw_input = p.packed && !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+    out->set_max = p.stride;
+    out->levels = p.levels;
+    out->group0 = p.levels ? p.group_l[0] : 0u;
+    out->group = p.levels > 1 ? p.group_l[1] : 0u;
+    out->raw_input = p.packed && !p.pairs && !p.triples && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
                      p.segments <= 1;
     return DFA_OK;
 }
@@ -444,6 +448,37 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
                 }
             }
             if (r == rmax) break;
+        }
+    }
+    // three-symbol steps: chunk lengths of a multiple of 48 around the best
+    // (3/8 .. 3 times it), at the best r and the next; then the best of all
+    // with at most two symbols per lookup
+    if (rc == DFA_OK && d->dev.triples) {
+        const dfa_match_opts_t base = pick;
+        uint64_t c0 = base.chunk_len;
+        if (c0 == 0) {
+            MatchPlan p0;
+            if (plan_match(d, n, 0, base.lookahead, &p0, 0) == DFA_OK) c0 = p0.chunk;
+        }
+        for (uint32_t r : {base.lookahead, std::min(base.lookahead + 1, rmax)}) {
+            for (uint64_t num : {3u, 6u, 12u, 24u}) {
+                const uint64_t c = (c0 * num / 8) / 48 * 48;
+                if (c < 384 || c > (1u << 20) || rc != DFA_OK) continue;
+                const uint64_t nch = (n + c - 1) / c;
+                if (nch > (1u << 20) || nch * per_chunk > (1ull << 30)) continue;
+                dfa_match_opts_t o{};
+                o.chunk_len = c;
+                o.lookahead = r;
+                consider(o);
+            }
+            if (r == rmax) break;
+        }
+        MatchPlan pp;
+        if (rc == DFA_OK && plan_match(d, n, pick.chunk_len, pick.lookahead, &pp, pick.flags) == DFA_OK &&
+            pp.triples) {
+            dfa_match_opts_t o = pick;
+            o.flags |= DFA_MATCH_TWO_STEP;
+            consider(o);
         }
     }
     if (rc == DFA_OK && d->dev.pairs) {

@@ -384,6 +384,82 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
             }
         }
     }
+    // ---- three-symbol steps ------------------------------------------------
+    // delta3(s, c1 c2 c3) = delta(delta(delta(s, c1), c2), c3) cuts a walk's
+    // lookups to a third.  Columns (distinct functions over the states) are
+    // deduplicated and stored class-major, 16-bit: column j holds 2 * delta3
+    // at byte offset j * CS, the code of a class string is that offset, and
+    // an LDS address is code + 2 * s (both 16-bit, so all columns must fit
+    // 64 KiB).  CS, the column stride, is 2 nq rounded up to an odd number of
+    // dwords, so that lanes in one state but on different columns fall into
+    // different LDS banks.  Class strings end early at a string's last byte: c2 = K or
+    // c3 = K stands for "no further symbol".  tcode holds the code of class
+    // string (c1, c2, c3) at (c1 (K + 1) + c2) (K + 1) + c3.  The staged image
+    // is the columns, then the absorbing-state bitmap (bit s).
+    uint32_t triples = 0, abs_off3 = 0, ncol3 = 0;
+    std::vector<uint16_t> stab3, tcode;
+    {
+        const uint32_t Kc = (uint32_t)class_sym.size();
+        const char *ft = std::getenv("DFA_TRIPLES");   // "0": no three-symbol table (diagnostic)
+        if (pairs && Kc >= 1 && Kc <= 15 && !(ft && ft[0] == '0')) {
+            const uint32_t K1 = Kc + 1;
+            uint32_t cs = (2u * nq + 3u) / 4u * 4u;
+            if ((cs / 4u) % 2u == 0) cs += 4u;
+            const uint32_t max_cols = 0x10000u / cs;
+            std::unordered_map<std::string, uint32_t> tid;
+            std::vector<std::vector<uint32_t>> cols;
+            std::vector<uint16_t> tc((size_t)Kc * K1 * K1, 0);
+            std::string key(nq * sizeof(uint32_t), '\0');
+            std::vector<uint32_t> colv(nq);
+            bool ok = max_cols >= 1;
+            for (uint32_t c1 = 0; c1 < Kc && ok; ++c1)
+                for (uint32_t c2 = 0; c2 <= Kc && ok; ++c2)
+                    for (uint32_t c3 = 0; c3 <= Kc && ok; ++c3) {
+                        if (c2 == Kc && c3 != Kc) continue;   // no string has a gap
+                        for (uint32_t q = 0; q < nq; ++q) {
+                            uint32_t t = delta[(uint64_t)q * nsym + class_sym[c1]];
+                            if (c2 < Kc) t = delta[(uint64_t)t * nsym + class_sym[c2]];
+                            if (c3 < Kc) t = delta[(uint64_t)t * nsym + class_sym[c3]];
+                            colv[q] = t;
+                        }
+                        std::memcpy(&key[0], colv.data(), key.size());
+                        auto it = tid.find(key);
+                        uint32_t id;
+                        if (it == tid.end()) {
+                            id = (uint32_t)cols.size();
+                            if (id >= max_cols) { ok = false; break; }
+                            tid.emplace(key, id);
+                            cols.push_back(colv);
+                        } else {
+                            id = it->second;
+                        }
+                        tc[((size_t)c1 * K1 + c2) * K1 + c3] = (uint16_t)(id * cs);
+                    }
+            const uint64_t img = align_up((uint64_t)cols.size() * cs, 16);
+            const uint64_t bits_bytes = align_up(((uint64_t)nq + 31) / 32 * 4, 16);
+            if (ok && img + bits_bytes + 16 <= (uint64_t)lds) {
+                triples = 1;
+                ncol3 = (uint32_t)cols.size();
+                stab3.assign(img / 2, 0);
+                for (size_t j = 0; j < cols.size(); ++j)
+                    for (uint32_t q = 0; q < nq; ++q)
+                        stab3[j * (cs / 2u) + q] = (uint16_t)(2u * cols[j][q]);
+                abs_off3 = (uint32_t)img;
+                std::vector<uint32_t> bits(bits_bytes / 4, 0);
+                for (uint32_t q = 0; q < nq; ++q)
+                    if (absorbing[q]) bits[q >> 5] |= 1u << (q & 31);
+                for (uint32_t w : bits) {
+                    stab3.push_back((uint16_t)(w & 0xFFFF));
+                    stab3.push_back((uint16_t)(w >> 16));
+                }
+                tcode = std::move(tc);
+                tcode.resize(align_up(tcode.size() * 2, 16) / 2, 0);
+            }
+        }
+    }
+    if (stab3.empty()) stab3.assign(8, 0);
+    if (tcode.empty()) tcode.assign(8, 0);
+
     if (stab2.empty()) stab2.assign(8, 0);
     pcode.resize(align_up(pcode.size(), 16), 0);
     if (pcode2.empty()) pcode2.assign(16, 0);
@@ -417,6 +493,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     size_t i_stab2 = add(stab2.data(), stab2.size() * 2);
     size_t i_pcode = add(pcode.data(), pcode.size());
     size_t i_pcode2 = add(pcode2.data(), pcode2.size());
+    size_t i_stab3 = add(stab3.data(), stab3.size() * 2);
+    size_t i_tcode = add(tcode.data(), tcode.size() * 2);
     const size_t arena_bytes = align_up(at, 256);
 
     dfa *d = new (std::nothrow) dfa();
@@ -478,6 +556,11 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.abs_off2 = abs_off2;
     v.pcode = (const uint8_t *)ptr(i_pcode);
     v.pcode2 = pcode2.size() > 16 ? (const uint8_t *)ptr(i_pcode2) : nullptr;
+    v.triples = triples;
+    v.stab3 = (const uint16_t *)ptr(i_stab3);
+    v.stab3_bytes = triples ? (uint32_t)(stab3.size() * 2) : 0u;
+    v.abs_off3 = abs_off3;
+    v.tcode = (const uint16_t *)ptr(i_tcode);
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;
@@ -497,6 +580,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.packed_layout = direct ? 3u : layout;
     inf.lookahead_tables = r0;
     inf.pair_columns = npair;
+    inf.triple_columns = ncol3;
     *out = d;
     return DFA_OK;
 }

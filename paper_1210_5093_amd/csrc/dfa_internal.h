@@ -86,6 +86,18 @@ struct DevDFA {
     const uint8_t *pcode2;       // direct tables only (else NULL): 32768 + 128 bytes, the
                                  // pair code of bytes b1, b2 < 128 at b1 + 256 * b2 and of a
                                  // lone last byte at 32768 + b; 0xFF for bytes outside Sigma
+    // Three-symbol steps: class-major columns of delta3(s, c1 c2 c3) over the
+    // distinct class-string functions (c2, c3 = K: no further symbol),
+    // 16-bit: entry 2 * delta3, code = column * CS (CS: 2 nq rounded up to an
+    // odd number of dwords), an LDS address is code + 2 * s; staged with an
+    // absorbing-state bitmap (bit s).  tcode:
+    // the 16-bit code of class string (c1, c2, c3) at (c1 (K+1) + c2) (K+1) + c3;
+    // pcode's first 256 bytes map bytes to classes.
+    uint32_t triples;            // 1 if the three-symbol table exists
+    const uint16_t *stab3;
+    uint32_t stab3_bytes;        // multiple of 16
+    uint32_t abs_off3;
+    const uint16_t *tcode;
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -149,6 +161,8 @@ struct MatchPlan {
     bool fork = false;           // translation on a second stream, beside the lookahead
                                  // scan (and the matcher, when that reads the raw input)
     bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
+    bool triples = false;        // three-symbol steps over the class-major triple table
+                                 // (chunk % 48 == 0; excludes pairs)
     uint32_t rounds = 1;         // walk rounds (> 1: merged walks, chunk % 32 == 0)
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)
     uint32_t ilv_nblk = 0;       // chunk-interleaved code stream: 16-byte code blocks per

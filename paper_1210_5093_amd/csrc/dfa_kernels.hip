@@ -407,6 +407,17 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     const char *fpairs = std::getenv("DFA_PAIRS");
     p->pairs = p->packed && d->dev.pairs && p->lookahead != 2 && !(flags & DFA_MATCH_SINGLE_STEP) &&
                !(fpairs && fpairs[0] == '0') && (chunk_req == 0 || chunk_req % 32 == 0);
+    // three-symbol steps cut the lookups to a third; they need chunk lengths
+    // of a multiple of 48 (16-byte blocks of eight 3-symbol codes) and one
+    // walk round over a linear stream.  The planner's own chunk lengths keep
+    // two-symbol steps (on the protein-style workload the larger table and
+    // code stream cost more than the saved lookups); a requested length of a
+    // multiple of 48 takes three, unless DFA_MATCH_TWO_STEP.
+    p->triples = p->packed && d->dev.triples && p->lookahead != 2 &&
+                 !(flags & (DFA_MATCH_SINGLE_STEP | DFA_MATCH_TWO_STEP | DFA_MATCH_INTERLEAVE |
+                            DFA_MATCH_CHUNK_LANES)) &&
+                 DFA_MATCH_ROUNDS_OF(flags) <= 1 && chunk_req != 0 && chunk_req % 48 == 0;
+    if (p->triples) p->pairs = false;
     if (p->packed) {
         // two pairs per lane when the start sets are tiny (many chunks per
         // tile: shorter tiles spread the chains over more wavefronts), four
@@ -417,7 +428,8 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
         const char *fs = std::getenv("DFA_SLOTS");
         p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 8.0 ? 2u : 4u);
-        const uint32_t staged = p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
+        const uint32_t staged = p->triples ? d->dev.stab3_bytes
+                                : p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
         const uint32_t per_cu = std::max<uint32_t>(
             1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(staged, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit

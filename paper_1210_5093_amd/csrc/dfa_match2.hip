@@ -690,6 +690,94 @@ __global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *_
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
 }
 
+// Three-symbol translation: code i is the tcode entry of the class string of
+// bytes 3i, 3i + 1, 3i + 2 (class K, "no further symbol", past the end of the
+// input); per-block flag if a byte is outside Sigma (class 0xFF).  A lane
+// turns 48 input bytes (three 16-byte loads) into 16 codes (two 16-byte
+// stores); the stream is written in whole 32-byte units, codes past the end
+// of the input are 0.  Classes are masked to 4 bits before the tcode lookup
+// (K <= 15), so every index stays inside the 4096-entry staged table.
+__global__ __launch_bounds__(256) void k_translate_triples(const uint8_t *__restrict__ in,
+                                                           uint64_t n,
+                                                           const uint8_t *__restrict__ pcode,
+                                                           const uint16_t *__restrict__ tcode,
+                                                           uint32_t K, uint16_t *__restrict__ out,
+                                                           uint32_t *__restrict__ block_bad,
+                                                           SumsArgs sa) {
+    scan_sums_in_pass(sa);
+    __shared__ uint8_t cls[256];
+    __shared__ __align__(16) uint16_t tc[4096];
+    __shared__ uint32_t bad_any;
+    const uint32_t K1 = K + 1;
+    const uint32_t ntc = K * K1 * K1;
+    cls[threadIdx.x] = pcode[threadIdx.x];
+    for (uint32_t i = threadIdx.x; i < 4096u; i += blockDim.x) tc[i] = i < ntc ? tcode[i] : 0u;
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t units = (n + 47) / 48;
+    const bool aligned = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += T) {
+        const uint64_t first = u * 48u;
+        uint32_t w[12];
+        const bool whole = first + 48u <= n;
+        if (whole && aligned) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(in + first);
+            const uint4 v0 = p[0], v1 = p[1], v2 = p[2];
+            w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+            w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+            w[8] = v2.x; w[9] = v2.y; w[10] = v2.z; w[11] = v2.w;
+        } else {
+            uint32_t (&w0)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[0]);
+            uint32_t (&w1)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[4]);
+            uint32_t (&w2)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[8]);
+            load16(in, first, n, w0);
+            load16(in, first + 16u, n, w1);
+            load16(in, first + 32u, n, w2);
+        }
+        auto byte_at = [&](uint32_t k) -> uint32_t { return (w[k >> 2] >> (8u * (k & 3u))) & 0xFFu; };
+        uint32_t c[16];
+        if (whole) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) {
+                const uint32_t a0 = cls[byte_at(3 * k)], a1 = cls[byte_at(3 * k + 1)],
+                               a2 = cls[byte_at(3 * k + 2)];
+                acc |= a0 | a1 | a2;
+                c[k] = tc[(((a0 & 15u) * K1 + (a1 & 15u)) * K1 + (a2 & 15u)) & 4095u];
+            }
+            bad |= acc >> 7;
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) {
+                uint32_t a[3];
+                bool inv = false;
+#pragma unroll
+                for (uint32_t j = 0; j < 3; ++j) {
+                    const bool inside = first + 3 * k + j < n;
+                    const uint32_t v = cls[byte_at(3 * k + j)];
+                    inv = inv || (inside && v == 0xFFu);
+                    a[j] = inside ? (v & 15u) : K;
+                }
+                bad |= inv ? 1u : 0u;
+                const bool live = first + 3 * k < n;
+                c[k] = (live && !inv) ? tc[((a[0] * K1 + a[1]) * K1 + a[2]) & 4095u] : 0u;
+            }
+        }
+        uint4 o[2];
+        uint32_t *ow = reinterpret_cast<uint32_t *>(o);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
+        uint4 *dst = reinterpret_cast<uint4 *>(out + u * 16u);
+        dst[0] = o[0];
+        dst[1] = o[1];
+    }
+    if (bad) atomicOr(&bad_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
+}
+
 // Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
 // the image of Q under the r' = min(r, p) bytes before it (p = i*C), minus the
 // absorbing states; the true state at p lies in it, and so does the end state
@@ -747,6 +835,8 @@ struct Match2Args {
     uint32_t c_lo, c_hi;     // this launch walks the pairs of chunks [c_lo, c_hi)
     uint32_t tile;           // pairs per wave-tile (64 * slots)
     uint32_t ilv_nblk;       // chunk-interleaved codes: 16-byte blocks per chunk; 0 = linear
+    uint32_t spread;         // tiles to waves: 1 = first wave of every workgroup first
+                             // (few, large workgroups per CU), 0 = workgroup by workgroup
 };
 
 // First 16-byte unit of block b of chunk c in the code stream, and the
@@ -808,7 +898,12 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
     using CodeT = typename std::conditional<L == 1, uint8_t, uint16_t>::type;
     const uint32_t lane = threadIdx.x & (kWave2 - 1);
     const uint32_t waves = blockDim.x / kWave2;
-    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    // spread: tiles go to the first wave of every workgroup, then the
+    // second, ..., so that a launch with fewer tiles than waves still keeps
+    // every CU busy when each CU holds only one or two workgroups; else
+    // consecutive tiles stay in one workgroup
+    const uint32_t wave_id = a.spread ? (threadIdx.x / kWave2) * gridDim.x + blockIdx.x
+                                      : blockIdx.x * waves + threadIdx.x / kWave2;
     const uint32_t total = a.first[a.nch];
     const uint32_t ntiles = (total + kTile - 1) / kTile;
     const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
@@ -866,25 +961,32 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     constexpr uint32_t kTile = kWave2 * S;
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
-    using CodeT = typename std::conditional<L != 2, uint8_t, uint16_t>::type;
+    using CodeT = typename std::conditional<kWideCodes<L>, uint16_t, uint8_t>::type;
     constexpr uint32_t kPer16 = 16 / sizeof(CodeT);   // codes per 16 bytes
     const uint32_t lane = threadIdx.x & (kWave2 - 1);
     const uint32_t waves = blockDim.x / kWave2;
-    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    // spread: tiles go to the first wave of every workgroup, then the
+    // second, ..., so that a launch with fewer tiles than waves still keeps
+    // every CU busy when each CU holds only one or two workgroups; else
+    // consecutive tiles stay in one workgroup
+    const uint32_t wave_id = a.spread ? (threadIdx.x / kWave2) * gridDim.x + blockIdx.x
+                                      : blockIdx.x * waves + threadIdx.x / kWave2;
     const uint32_t total_waves = gridDim.x * waves;
     const uint32_t total = a.first[a.nch];
     const uint32_t ntiles = (total + kTile - 1) / kTile;
     // pairs of chunks [c_lo, c_hi): the tiles that overlap them
     const uint32_t p_lo = a.first[a.c_lo], p_hi = a.first[a.c_hi];
     const uint32_t t_lo = p_lo / kTile, t_hi = (p_hi + kTile - 1) / kTile;
-    const uint32_t R = L != 2 ? a.d.rowbytes : 2u;
+    // class-major tables (16-bit codes) hold 2 * state; row tables R * state
+    const uint32_t R = kWideCodes<L> ? 2u : a.d.rowbytes;
     const CodeT *codes = reinterpret_cast<const CodeT *>(a.codes);
     auto code_at = [&](uint64_t pos) -> uint32_t {
         return L == 3 ? 2u * (codes[pos] & 0x7Fu) : (uint32_t)codes[pos];
     };
-    // L = 4 (two-symbol steps): one code per two input bytes, chunk lengths
-    // are even (the host only picks it for multiples of 32)
-    constexpr uint32_t kSym = L == 4 ? 2u : 1u;       // symbols per code
+    // L = 4 (two-symbol steps): one code per two input bytes; L = 5 (three-
+    // symbol steps): one per three.  Chunk lengths are multiples of the step
+    // (the host picks them for multiples of 32, resp. 48)
+    constexpr uint32_t kSym = L == 5 ? 3u : L == 4 ? 2u : 1u;   // symbols per code
     // full chunks start on 16-byte boundaries iff the chunk length does
     const bool aligned_chunks = (a.chunk % (kPer16 * kSym)) == 0;
 
@@ -979,7 +1081,12 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t lane = threadIdx.x & (kWave2 - 1);
     const uint32_t waves = blockDim.x / kWave2;
-    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    // spread: tiles go to the first wave of every workgroup, then the
+    // second, ..., so that a launch with fewer tiles than waves still keeps
+    // every CU busy when each CU holds only one or two workgroups; else
+    // consecutive tiles stay in one workgroup
+    const uint32_t wave_id = a.spread ? (threadIdx.x / kWave2) * gridDim.x + blockIdx.x
+                                      : blockIdx.x * waves + threadIdx.x / kWave2;
     const uint32_t total_waves = gridDim.x * waves;
     // later rounds: exclusive prefix of the regions' counts, in LDS after the
     // staged table (the kernel has no static LDS: the table stays at address 0)
@@ -1352,7 +1459,7 @@ void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint
 
 namespace {
 const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
-    static const void *const tab[4][2][2] = {
+    static const void *const tab[5][2][2] = {
         {{reinterpret_cast<const void *>(&k_match2<1, 2, false>),
           reinterpret_cast<const void *>(&k_match2<1, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<1, 4, false>),
@@ -1368,7 +1475,11 @@ const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
         {{reinterpret_cast<const void *>(&k_match2<4, 2, false>),
           reinterpret_cast<const void *>(&k_match2<4, 2, true>)},
          {reinterpret_cast<const void *>(&k_match2<4, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<4, 4, true>)}}};
+          reinterpret_cast<const void *>(&k_match2<4, 4, true>)}},
+        {{reinterpret_cast<const void *>(&k_match2<5, 2, false>),
+          reinterpret_cast<const void *>(&k_match2<5, 2, true>)},
+         {reinterpret_cast<const void *>(&k_match2<5, 4, false>),
+          reinterpret_cast<const void *>(&k_match2<5, 4, true>)}}};
     return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
 const void *chunk_walk_kernel(uint32_t L) {
@@ -1398,14 +1509,18 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
                   hipEvent_t ev_before_matcher) {
     // two-symbol steps (the plan checked the chunk length); else direct
     // tables: the matcher reads the (16-byte aligned) input itself
-    const bool pairs = p.pairs && d->dev.pairs;
-    const bool direct = !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+    const bool triples = p.triples && d->dev.triples;
+    const bool pairs = !triples && p.pairs && d->dev.pairs;
+    const bool direct = !triples && !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
                         p.segments <= 1 && (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
     const bool fork = p.fork && p.lookahead != 2;
     const Ilv ilv{p.ilv_nblk, p.nch, p.chunk};
     if (p.ilv_nblk && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
         return fail(DFA_E_INVAL, "interleaved codes with segments, window pass or odd chunks");
-    const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
+    const uint32_t L = triples ? 5u : pairs ? 4u : direct ? 3u : d->dev.layout;
+    if (triples && (p.chunk % 48 != 0 || p.lookahead == 2 || p.ilv_nblk || p.rounds > 1 ||
+                    p.chunk_lanes))
+        return fail(DFA_E_INVAL, "three-symbol plan with a window pass, merged walks or odd chunks");
     if (pairs && (p.chunk % 32 != 0 || p.lookahead == 2 || (p.segments > 1 && p.chunk % 64 != 0)))
         return fail(DFA_E_INVAL, "two-symbol plan with a window pass or odd chunks");
     const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
@@ -1441,7 +1556,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
         uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
         const SumsArgs sa{q, info, b.bsum, fused_scan ? nsb : 0u};
-        if (pairs && d->dev.pcode2)
+        if (triples)
+            hipLaunchKernelGGL(k_translate_triples, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
+                               end - off, d->dev.pcode, d->dev.tcode, d->dev.nclass,
+                               (uint16_t *)b.codes + off / 3, bad, sa);
+        else if (pairs && d->dev.pcode2)
             hipLaunchKernelGGL(k_translate_pairs_direct, dim3(p.tblocks), dim3(256), 0, ts,
                                d_in + off, end - off, d->dev.pcode2, (uint8_t *)b.codes + off / 2,
                                bad, ilv, sa);
@@ -1471,6 +1590,12 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         a.d.rowbytes = d->dev.rowbytes2;
         a.d.abs_off = d->dev.abs_off2;
         a.d.abs_shift = 2;
+    } else if (triples) {   // or the class-major triple table (state offset 2 * s)
+        a.d.stab = d->dev.stab3;
+        a.d.stab_bytes = d->dev.stab3_bytes;
+        a.d.rowbytes = 2;
+        a.d.abs_off = d->dev.abs_off3;
+        a.d.abs_shift = 1;
     }
     a.codes = direct ? static_cast<const void *>(d_in) : b.codes;
     a.n = p.n;
@@ -1493,6 +1618,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.c_hi = p.nch;
     a.tile = kWave2 * p.slots;
     a.ilv_nblk = p.ilv_nblk;
+    a.spread = p.threads2 >= 1024 ? 1u : 0u;
     const size_t lds = a.d.stab_bytes;
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
@@ -1620,6 +1746,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(3, 4, false), match2_kernel(3, 4, true),
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
+                         match2_kernel(5, 2, false), match2_kernel(5, 2, true),
+                         match2_kernel(5, 4, false), match2_kernel(5, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(4),
                          round_kernel(1, 2), round_kernel(1, 4), round_kernel(2, 2),
                          round_kernel(2, 4), round_kernel(3, 2), round_kernel(3, 4),

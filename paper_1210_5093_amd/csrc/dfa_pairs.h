@@ -19,11 +19,17 @@ __device__ __forceinline__ uint32_t lds_ld(uint32_t addr) {
     return *(lds_u16_t *)(size_t)addr;
 }
 
-// state_offset + selected byte (layout 1) or 16-bit word (layout 2) of w.
+// Code streams of 16-bit codes: layout 2 (one symbol per code) and the
+// three-symbol table (L = 5, class-major like layout 2); every other L reads
+// one-byte codes.
+template <int L>
+constexpr bool kWideCodes = L == 2 || L == 5;
+
+// state_offset + selected byte (one-byte codes) or 16-bit word of w.
 template <int L, int K>
 __device__ __forceinline__ uint32_t add_sel(uint32_t s, uint32_t w) {
     uint32_t r;
-    if constexpr (L != 2) {
+    if constexpr (!kWideCodes<L>) {
         if constexpr (K == 0)
             asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(s), "v"(w));
         else if constexpr (K == 1)
@@ -212,7 +218,7 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
             // slots' independent chains keep several LDS loads in flight
             step_slots<L, 0, S>(st, w);
             step_slots<L, 1, S>(st, w);
-            if constexpr (L != 2) {
+            if constexpr (!kWideCodes<L>) {
                 step_slots<L, 2, S>(st, w);
                 step_slots<L, 3, S>(st, w);
             }
@@ -243,7 +249,7 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
                                          uint32_t (&st)[S], uint32_t exit_base = 0,
                                          uint32_t exit_shift = 0, uint32_t live = 0,
                                          uint32_t stride = 1) {
-    constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
+    constexpr uint32_t kPer16 = kWideCodes<L> ? 8u : 16u;
     uint32_t common = 0xFFFFFFFFu, most = 0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -252,7 +258,10 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
         most = max(most, (len + kPer16 - 1) / kPer16);
     }
     if (common > 0)
-        walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live, stride);
+        // blocks of 16-bit codes hold half the steps: two blocks of prefetch
+        // keep the same distance ahead of the walk
+        walk_fast<L, S, EXIT, kWideCodes<L> ? 2 : 1>(codes16, o16, common, st, exit_base,
+                                                     exit_shift, live, stride);
     for (uint32_t b = common; b < most; ++b) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -278,7 +287,7 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if constexpr (L != 2) {
+                if constexpr (!kWideCodes<L>) {
                     if (4 * q + 0 < cnt) st[j] = lds_ld(add_sel<1, 0>(st[j], w[q]));
                     if (4 * q + 1 < cnt) st[j] = lds_ld(add_sel<1, 1>(st[j], w[q]));
                     if (4 * q + 2 < cnt) st[j] = lds_ld(add_sel<1, 2>(st[j], w[q]));

@@ -783,6 +783,126 @@ def test_two_symbol_steps_random_small_alphabets(dfa_mod):
 
 
 # ---------------------------------------------------------------------------
+# Three-symbol steps (class-major columns of delta(delta(delta(s, a), b), c)
+# over the distinct class-string functions; one 16-bit code per three input
+# bytes): every remainder of the length mod 3 and 48, ragged last chunks,
+# boundary states, bytes outside Sigma at each place of a code, early exit,
+# misaligned input, and DFA_MATCH_TWO_STEP on the same inputs.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 47, 48, 49, 1535, 1536, 1537, 100_003, (3 << 20) + 2])
+@pytest.mark.parametrize("look", [1, 5])
+def test_three_symbol_steps_lengths(dfa_mod, n, look):
+    w = configs.c2_dfa()
+    x = configs.c2_input(n, seed=90 + n % 97)
+    d = dfa_mod.DFA.from_workload(w)
+    assert d.info().triple_columns > 0
+    for chunk in (0, 1536, 3072):
+        plan = dfa_mod.dfa_plan(d, n, chunk, look)
+        if plan.kernel == 1:   # the planner's own lengths keep two symbols per step
+            assert plan.symbols_per_step == (2 if chunk == 0 else 3), chunk
+        check(dfa_mod, w, x, chunk=chunk, lookahead=look)
+    d.close()
+
+
+@pytest.mark.parametrize("byte", [ord("J"), 0x80, 0xC1])
+@pytest.mark.parametrize("pos", [0, 1, 2, 3, 46, 47, 48, 1535, 1536, 99_999, 100_000, 100_001,
+                                 100_002])
+def test_three_symbol_steps_invalid_bytes(dfa_mod, byte, pos):
+    """Bytes outside Sigma below and above 128 as the first, second and third
+    byte of a code, at chunk and 48-byte unit edges and in the short last code."""
+    w = configs.c2_dfa()
+    x = configs.c2_input(100_003).copy()
+    x[pos] = byte
+    d = dfa_mod.DFA.from_workload(w)
+    for look in (3, 5):
+        assert dfa_mod.dfa_plan(d, x.size, 1536, look).symbols_per_step == 3
+        assert gpu_run(dfa_mod, d, x, chunk=1536, lookahead=look, boundaries=False)[2] & \
+            dfa_mod.FLAG_SYMBOL
+    x[pos] = ord("A")
+    fin, acc, flags, _, _ = gpu_run(dfa_mod, d, x, chunk=1536, lookahead=5, boundaries=False)
+    ofin, _ = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
+    assert (fin, flags) == (ofin, 0)
+    d.close()
+
+
+@pytest.mark.parametrize("seed,contains", [(32, True), (32, False), (7, False), (7, True)])
+def test_three_symbol_steps_early_exit_and_other_dfas(dfa_mod, seed, contains):
+    import torch
+    w = from_pattern(patterns.pattern_dfa(seed, contains=contains))
+    d = dfa_mod.DFA.from_workload(w)
+    n = (5 << 20) + 7
+    x = configs.c2_input(n, seed=310 + seed)
+    probes = list(range(0, n, 1536)) + [n]
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    acc = oracle.accepts(fin, w.accepting)
+    dev = torch.from_numpy(x).to("cuda")
+    say(f"pattern {seed} contains={contains}: Q={w.num_states} "
+        f"triple columns {d.info().triple_columns}")
+    for ex in (False, True):
+        for look in (1, 3, 5):
+            if d.info().triple_columns:
+                assert dfa_mod.dfa_plan(d, n, 1536, look, early_exit=ex).symbols_per_step == 3
+            res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=1536, lookahead=look,
+                                            boundaries=True, early_exit=ex)
+            torch.cuda.synchronize()
+            assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), (ex, look)
+            b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(b, ps.astype(np.int64)), (ex, look)
+    d.close()
+
+
+@pytest.mark.parametrize("shift", [1, 5, 16])
+def test_three_symbol_steps_misaligned_input(dfa_mod, shift):
+    import torch
+    w = configs.c2_dfa()
+    n = (2 << 20) + 5
+    x = configs.c2_input(n, seed=95)
+    probes = list(range(0, n, 3072)) + [n]
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    buf = torch.from_numpy(np.concatenate([np.full(shift, 65, np.uint8), x])).to("cuda")
+    dev = buf[shift:]
+    d = dfa_mod.DFA.from_workload(w)
+    res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=3072, lookahead=5, boundaries=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
+    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(b, ps.astype(np.int64))
+    d.close()
+
+
+def test_two_step_flag_keeps_pairs(dfa_mod):
+    import torch
+    w = configs.c2_dfa()
+    n = (4 << 20) + 11
+    x = configs.c2_input(n, seed=96)
+    fin, _ = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = torch.from_numpy(x).to("cuda")
+    for two, steps in ((False, 3), (True, 2)):
+        assert dfa_mod.dfa_plan(d, n, 1536, 5, two_step=two).symbols_per_step == steps
+        res, _ = dfa_mod.dfa_match_ex(d, dev, chunk_len=1536, lookahead=5, two_step=two)
+        torch.cuda.synchronize()
+        assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
+    d.close()
+
+
+def test_three_symbol_steps_random_small_alphabets(dfa_mod):
+    """Random byte-alphabet DFAs with 2..16 distinct columns (a triple table
+    when its distinct columns fit 64 KiB, none for 16 columns or more)."""
+    rng = np.random.default_rng(78)
+    for t, k in enumerate([2, 3, 4, 5, 6, 8, 12, 16]):
+        nq = int(rng.integers(2, 200))
+        w = column_dfa(800 + t, 900 + t, nq, k)
+        d = dfa_mod.DFA.from_workload(w)
+        tc = d.info().triple_columns
+        d.close()
+        x = streams.uniform_bytes(1000 + t, int(rng.integers(50_000, 400_000)))
+        say(f"random dfa {t}: Q={nq} K={k} triple columns {tc}")
+        check(dfa_mod, w, x, chunk=1536, lookahead=2)
+        check(dfa_mod, w, x, chunk=4800, lookahead=1)
+
+
+# ---------------------------------------------------------------------------
 # Merged walks (DFA_MATCH_ROUNDS): after each round but the last, walks of a
 # chunk in the same state continue as one.  Every boundary state must equal
 # the oracle's for any round count, chunk length (32 bytes up, ragged last

@@ -358,14 +358,15 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
     // candidates: r = 1 .. r0 + 2 (capped at 10), chunk = planner and powers of two
-    // (tables without a packed layout support only r = 1; chunk counts are
-    // bounded so that no candidate's maps exceed 1 GiB)
+    // from 64 B (short chunks keep the walks short on small inputs; tables
+    // without a packed layout support only r = 1; chunk counts are bounded so
+    // that no candidate's maps exceed 1 GiB)
     std::vector<uint32_t> rs;
     const uint32_t rmax = d->dev.layout ? std::min<uint32_t>(d->dev.r0 + 2, 10) : 1u;
     for (uint32_t r = 1; r <= rmax; ++r) rs.push_back(r);
     std::vector<uint64_t> chunks = {0};
     const uint64_t per_chunk = 2ull * std::max<uint32_t>(d->setmax_host[0], 1u);
-    for (uint64_t c = 256; c <= (1u << 20) && c <= std::max<size_t>(n, 256); c *= 2) {
+    for (uint64_t c = 64; c <= (1u << 20) && c <= std::max<size_t>(n, 256); c *= 2) {
         const uint64_t nch = (n + c - 1) / c;
         if (nch <= (1u << 20) && nch * per_chunk <= (1ull << 30)) chunks.push_back(c);
     }

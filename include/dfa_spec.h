@@ -236,7 +236,8 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * are tuned on their first 256 MiB.  The choice is cached per DFA and
  * power-of-two length bucket and used by calls with lookahead
  * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r and r + 1, a quarter
- * to four times the chunk) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
+ * to four times the chunk, and 16 and 64 times it for merged rounds, which
+ * stop a walk at an absorbing state) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
  * interleaved codes (one and two rounds) and one chunk per lane, then three-
  * symbol steps at chunk lengths of a multiple of 48 near the best where that
  * table exists, the best with DFA_MATCH_SINGLE_STEP where a two-symbol table

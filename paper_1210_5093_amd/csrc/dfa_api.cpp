@@ -434,9 +434,14 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
         const uint32_t variants[] = {DFA_MATCH_ROUNDS(2), DFA_MATCH_ROUNDS(3), DFA_MATCH_ROUNDS(4),
                                      DFA_MATCH_INTERLEAVE, DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2),
                                      DFA_MATCH_CHUNK_LANES};
+        // (merged rounds stop a walk at an absorbing state, so where the
+        // input reaches one within a long chunk, lengths far above the
+        // one-round best can win: up to 64 times it)
         for (uint32_t r : {base.lookahead, std::min(base.lookahead + 1, rmax)}) {
             for (uint32_t v : variants) {
-                for (int sh = -2; sh <= 2 && rc == DFA_OK; ++sh) {
+                for (int sh : {-2, -1, 0, 1, 2, 4, 6}) {
+                    if (rc != DFA_OK) break;
+                    if (sh > 2 && !(v & 0xF00u)) continue;
                     const uint64_t c = sh < 0 ? c0 >> (-sh) : c0 << sh;
                     if (c < 256 || c % 32 != 0 || c > (1u << 20)) continue;
                     const uint64_t nch = (n + c - 1) / c;

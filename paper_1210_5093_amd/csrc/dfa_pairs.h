@@ -258,10 +258,7 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
         most = max(most, (len + kPer16 - 1) / kPer16);
     }
     if (common > 0)
-        // blocks of 16-bit codes hold half the steps: two blocks of prefetch
-        // keep the same distance ahead of the walk
-        walk_fast<L, S, EXIT, kWideCodes<L> ? 2 : 1>(codes16, o16, common, st, exit_base,
-                                                     exit_shift, live, stride);
+        walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live, stride);
     for (uint32_t b = common; b < most; ++b) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {

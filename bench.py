@@ -213,14 +213,16 @@ def early_exit_lookups(w, x: np.ndarray, chunk: int, lookahead: int, start: int,
 
 
 def merged_lookups(w, x: np.ndarray, chunk: int, lookahead: int, rounds: int,
-                   step: int = 1) -> int:
-    """Table reads of the merged walks (rounds >= 2): round k walks bytes
+                   step: int = 1):
+    """Table reads of the merged walks (rounds >= 2), and the input bytes they
+    cover (per chunk, the furthest any of its walks got): round k walks bytes
     [t_k, t_{k+1}) of every chunk (t_1 = 32, x4 per round, the last round to
     the chunk end), every walk still live; after a round that is not the last
     one walk per distinct (chunk, state) goes on, and walks whose chunk ended
-    or that reached an absorbing state stop.  Grouping here is per chunk; the
-    kernel groups per wave-tile, so a chunk split over two tiles may keep one
-    more walk: this count is the least work the kernel does."""
+    or that reached an absorbing state stop (in the last round too).  Grouping
+    here is per chunk; the kernel groups per wave-tile, so a chunk split over
+    two tiles may keep one more walk: this count is the least work the kernel
+    does."""
     d = w.delta.astype(np.int32)
     nq = d.shape[0]
     absorbing = np.all(d == np.arange(nq)[:, None], axis=1)
@@ -238,13 +240,29 @@ def merged_lookups(w, x: np.ndarray, chunk: int, lookahead: int, rounds: int,
     pc, ps = np.concatenate(pcs), np.concatenate(pss)
     total = 0
     t0 = 0
+    ext = np.zeros(nch, dtype=np.int64)
     for k in range(rounds):
         last = k + 1 == rounds
         t1 = 32 << (2 * k)
-        end = lens[pc] if last else np.minimum(lens[pc], t1)
-        total += int(((end - t0 + step - 1) // step).clip(min=0).sum())
         if last:
+            # to the chunk end or the first absorbing state, a step (of
+            # `step` symbols) at a time
+            alive = ~absorbing[ps] & (lens[pc] > t0)
+            pc, ps = pc[alive], ps[alive]
+            t = t0
+            while pc.size:
+                np.maximum.at(ext, pc, np.minimum(lens[pc], t + step))
+                total += pc.size
+                for j in range(step):
+                    inside = t + j < lens[pc]
+                    ps = np.where(inside, d[ps, sym[x[np.where(inside, pc * chunk + t + j, 0)]]], ps)
+                t += step
+                keep = (lens[pc] > t) & ~absorbing[ps]
+                pc, ps = pc[keep], ps[keep]
             break
+        end = np.minimum(lens[pc], t1)
+        total += int(((end - t0 + step - 1) // step).clip(min=0).sum())
+        np.maximum.at(ext, pc, end)
         for t in range(t0, t1):
             live = t < lens[pc]
             if not live.any():
@@ -255,7 +273,7 @@ def merged_lookups(w, x: np.ndarray, chunk: int, lookahead: int, rounds: int,
         key = np.unique(pc * nq + ps)
         pc, ps = key // nq, key % nq
         t0 = t1
-    return total
+    return total, int(ext.sum())
 
 
 def algorithmic_lookups(w, x: np.ndarray, chunk: int, lookahead: int, step: int = 1) -> int:
@@ -834,7 +852,8 @@ def main() -> int:
         reads = algorithmic_lookups(w, x, chunk, args.lookahead, step) if step > 1 else lookups
     merged = plan.kernel == 1 and (plan.rounds > 1 or plan.chunk_lanes)
     if merged:
-        reads = merged_lookups(w, x, chunk, args.lookahead, max(2, int(plan.rounds)), step)
+        reads, covered = merged_lookups(w, x, chunk, args.lookahead, max(2, int(plan.rounds)),
+                                        step)
     if plan.kernel == 1:
         lay = 5 if step == 3 else 4 if step == 2 else 3 if plan.raw_input else (
             2 if info.packed_layout == 2 else 1)
@@ -903,11 +922,14 @@ def main() -> int:
 
     if merged:
         # merged walks do about one walk per chunk after the first round: the
-        # rounds stream the code bytes once, so HBM bounds them
+        # rounds stream the code bytes they cover once (up to the chunk end,
+        # or where every walk of the chunk reached an absorbing state), so HBM
+        # bounds them
         rl = line["roofline"]
-        hbm_gbs = nbytes * stream_bpb / (matcher_avg_ms * 1e-3) / 1e9
+        hbm_gbs = covered * stream_bpb / (matcher_avg_ms * 1e-3) / 1e9
         rl.update({"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                   "bytes_covered": int(covered),
                    "lds_achieved_glookup_s": round(achieved / 1e9, 2),
                    "lds_frac": round(achieved / LDS_LOOKUP_PEAK, 4)})
         rl.pop("hbm_frac", None)

@@ -232,10 +232,10 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
 
 /* dfa_autotune -- time candidate (lookahead r, chunk length) settings on the
  * caller's device input and keep the fastest.  Every candidate gives the same
- * result (the method is exact); only speed differs.  Inputs beyond 256 MiB
- * are tuned on their first 256 MiB.  The choice is cached per DFA and
+ * result (the method is exact); only speed differs.  Inputs beyond 1 GiB
+ * are tuned on their first 1 GiB.  The choice is cached per DFA and
  * power-of-two length bucket and used by calls with lookahead
- * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r and r + 1, a quarter
+ * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r, r + 1 and r0, a quarter
  * to four times the chunk, and 16 and 64 times it for merged rounds, which
  * stop a walk at an absorbing state) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
  * interleaved codes (one and two rounds) and one chunk per lane, then three-

@@ -350,7 +350,7 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
                             dfa_match_opts_t *best, double *best_ms) {
     if (!d || (len && !d_input)) return fail(DFA_E_INVAL, "dfa_autotune: NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    const size_t n = std::min<size_t>(len, 256u << 20);
+    const size_t n = std::min<size_t>(len, 1ull << 30);
     uint32_t *res = nullptr;
     hipError_t e = hipMalloc(&res, 4 * sizeof(uint32_t));
     if (e != hipSuccess) return fail(DFA_E_NOMEM, "dfa_autotune: hipMalloc");
@@ -436,8 +436,15 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
                                      DFA_MATCH_CHUNK_LANES};
         // (merged rounds stop a walk at an absorbing state, so where the
         // input reaches one within a long chunk, lengths far above the
-        // one-round best can win: up to 64 times it)
-        for (uint32_t r : {base.lookahead, std::min(base.lookahead + 1, rmax)}) {
+        // one-round best can win: up to 64 times it).  Besides r and r + 1
+        // the largest precomputed r0 is tried: beyond it the window pass
+        // needs per-byte codes, which may change the ranking.
+        std::vector<uint32_t> vr = {base.lookahead};
+        if (base.lookahead + 1 <= rmax) vr.push_back(base.lookahead + 1);
+        if (d->dev.r0 >= 1 && d->dev.r0 <= rmax && d->dev.r0 != base.lookahead &&
+            d->dev.r0 != base.lookahead + 1)
+            vr.push_back(d->dev.r0);
+        for (uint32_t r : vr) {
             for (uint32_t v : variants) {
                 for (int sh : {-2, -1, 0, 1, 2, 4, 6}) {
                     if (rc != DFA_OK) break;
@@ -453,7 +460,6 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
                     consider(o);
                 }
             }
-            if (r == rmax) break;
         }
     }
     // three-symbol steps: chunk lengths of a multiple of 48 around the best

@@ -507,9 +507,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // composition
     const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);
     p->group = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(1024, stage / (2ull * p->stride + 8)));
-    // The first level takes a smaller fan-in when that spreads its groups
-    // over at least two workgroups per CU without adding a level (131072
-    // chunks: 512 groups of 256, then one group of 512).
+    // The first level takes a smaller fan-in when that still gives every CU
+    // a group without adding a level (131072 chunks: 256 groups of 512, then
+    // one group of 256; a smaller top group shortens the one-workgroup level
+    // more than the larger first groups lengthen theirs).
     auto count_levels = [&](uint64_t g0) {
         uint32_t lv = 0;
         for (uint64_t c = nch; c > 1; c = (c + (lv == 0 ? g0 : p->group) - 1) / (lv == 0 ? g0 : p->group))
@@ -518,7 +519,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     };
     uint64_t g0 = p->group;
     const uint32_t lv_max = count_levels(g0);
-    while (g0 > 64 && (nch + g0 - 1) / g0 < 2ull * (uint64_t)cus && count_levels(g0 / 2) == lv_max)
+    while (g0 > 64 && (nch + g0 - 1) / g0 < (uint64_t)cus && count_levels(g0 / 2) == lv_max)
         g0 /= 2;
     uint64_t cnt = nch, moff = 0, soff = 0;
     uint32_t L = 0;

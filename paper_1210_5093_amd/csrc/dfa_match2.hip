@@ -1070,7 +1070,8 @@ struct RoundArgs {
     uint32_t *out_cnt;         // [kRegions] its counters (zero before the first round)
 };
 
-template <int L, int S>
+// EXIT: the DFA has absorbing states; a wave stops once all its walks are in one.
+template <int L, int S, bool EXIT>
 __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, RoundArgs m) {
     constexpr uint32_t kTile = kWave2 * S;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1151,7 +1152,10 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
             const uint64_t end = m.last_round ? len : min<uint64_t>(len, m.t1);
             return end > m.t0 ? (uint32_t)((end - m.t0 + kSym - 1) / kSym) : 0u;
         };
-        walk_var<L, S, false>(codes16, o16, len_of, st, 0u, 0u, live, a.ilv_nblk ? 64u : 1u);
+        // a wave stops walking once all its walks are absorbing (checked every
+        // four blocks); their end states are then final
+        walk_var<L, S, EXIT>(codes16, o16, len_of, st, EXIT ? a.d.abs_off : 0u, a.d.abs_shift,
+                             live, a.ilv_nblk ? 64u : 1u);
 
         // end states; done = the chunk ended or the state is absorbing
         uint32_t e[S];
@@ -1488,13 +1492,14 @@ const void *chunk_walk_kernel(uint32_t L) {
         reinterpret_cast<const void *>(&k_chunk_walk<1>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
     return tab[L - 1];
 }
-const void *round_kernel(uint32_t L, uint32_t slots) {
-    static const void *const tab[4][2] = {
-        {reinterpret_cast<const void *>(&k_round<1, 2>), reinterpret_cast<const void *>(&k_round<1, 4>)},
-        {reinterpret_cast<const void *>(&k_round<2, 2>), reinterpret_cast<const void *>(&k_round<2, 4>)},
-        {reinterpret_cast<const void *>(&k_round<3, 2>), reinterpret_cast<const void *>(&k_round<3, 4>)},
-        {reinterpret_cast<const void *>(&k_round<4, 2>), reinterpret_cast<const void *>(&k_round<4, 4>)}};
-    return tab[L - 1][slots >= 4 ? 1 : 0];
+const void *round_kernel(uint32_t L, uint32_t slots, bool ex) {
+#define DFA_RK(l) {{reinterpret_cast<const void *>(&k_round<l, 2, false>),      \
+                    reinterpret_cast<const void *>(&k_round<l, 2, true>)},       \
+                   {reinterpret_cast<const void *>(&k_round<l, 4, false>),      \
+                    reinterpret_cast<const void *>(&k_round<l, 4, true>)}}
+    static const void *const tab[4][2][2] = {DFA_RK(1), DFA_RK(2), DFA_RK(3), DFA_RK(4)};
+#undef DFA_RK
+    return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
 const void *window2_kernel(uint32_t L, uint32_t slots) {
     static const void *const tab[2][2] = {
@@ -1663,7 +1668,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             e = hipEventRecord(ev_before_matcher, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
-        const void *rf = round_kernel(L, p.slots);
+        const void *rf = round_kernel(L, p.slots, a.d.nabs > 0);
         for (uint32_t k = 0; k < p.rounds; ++k) {
             RoundArgs m;
             m.t0 = k == 0 ? 0u : kRound1Bytes << (2 * (k - 1));
@@ -1749,9 +1754,14 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(5, 2, false), match2_kernel(5, 2, true),
                          match2_kernel(5, 4, false), match2_kernel(5, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(4),
-                         round_kernel(1, 2), round_kernel(1, 4), round_kernel(2, 2),
-                         round_kernel(2, 4), round_kernel(3, 2), round_kernel(3, 4),
-                         round_kernel(4, 2), round_kernel(4, 4),
+                         round_kernel(1, 2, false), round_kernel(1, 4, false),
+                         round_kernel(2, 2, false), round_kernel(2, 4, false),
+                         round_kernel(3, 2, false), round_kernel(3, 4, false),
+                         round_kernel(4, 2, false), round_kernel(4, 4, false),
+                         round_kernel(1, 2, true), round_kernel(1, 4, true),
+                         round_kernel(2, 2, true), round_kernel(2, 4, true),
+                         round_kernel(3, 2, true), round_kernel(3, 4, true),
+                         round_kernel(4, 2, true), round_kernel(4, 4, true),
                          window2_kernel(1, 2), window2_kernel(1, 4),
                          window2_kernel(2, 2), window2_kernel(2, 4)};
     int rc = DFA_OK;

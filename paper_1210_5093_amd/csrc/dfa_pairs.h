@@ -184,7 +184,7 @@ __device__ __forceinline__ void step_slots(uint32_t (&st)[S], const uint32_t (&w
 
 // With EXIT the walk stops early (every 4 blocks it checks) once
 // every live slot of the wavefront is absorbing: the rest of the chunk cannot
-// change those states.
+// change those states.  exit_base = 0 (no absorbing state) skips the check.
 template <int L, int S, bool EXIT = false, int PF = 1>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
                                           const uint32_t (&o16)[S], uint32_t blocks,
@@ -225,7 +225,7 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
         }
         if (!more) break;
         if constexpr (EXIT)
-            if ((b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
+            if (exit_base && (b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             cur[j] = ahead[0][j];

@@ -741,7 +741,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the matcher on a single MI355X "
+        print("bench.py measures one GPU only: the matcher runs on a single MI355X "
               "(no multi-GPU path); use --gpus 1", file=sys.stderr)
         return 2
 

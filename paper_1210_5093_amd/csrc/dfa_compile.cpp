@@ -156,7 +156,8 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     // Level k holds I_{c_1..c_k} for every class string: level 1 is I_c, and
     // level k is delta(level k-1, c_k) without absorbing states (absorbing
     // states stay absorbing, so this is the exact image of Q).  Levels are
-    // added while they fit a budget of 512K states and 256K sets (a few ms).
+    // added while they fit a budget of 2M states and 256K sets (a few ms;
+    // 8 classes reach six symbols).
     std::vector<uint32_t> mset_off;
     std::vector<uint16_t> mset_st;
     uint32_t moff[kMaxMsetLevel + 1] = {0}, mst[kMaxMsetLevel + 1] = {0};
@@ -198,7 +199,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
                         }
                         std::sort(cur_st.begin() + base, cur_st.end());
                         cur_off.push_back((uint32_t)cur_st.size());
-                        if (mset_st.size() + cur_st.size() > (1u << 19)) { over = true; break; }
+                        if (mset_st.size() + cur_st.size() > (1u << 21)) { over = true; break; }
                     }
                 }
                 if (over) break;

@@ -156,6 +156,34 @@ def test_c2_full_size_bench_configuration(dfa_mod):
     check(dfa_mod, w, x)
 
 
+@pytest.mark.parametrize("look,chunk,kw", [
+    (6, 1024, {"interleave": True}),     # the autotuner's setting on the box
+    (6, 1024, {}),
+    (5, 2048, {}),
+    (5, 2048, {"interleave": True, "rounds": 2}),
+    (5, 1536, {}),                        # three-symbol steps
+    (6, 1024, {"chunk_lanes": True}),
+])
+def test_c2_full_size_tuned_settings(dfa_mod, look, chunk, kw):
+    """256 MiB in the settings the autotuner chooses between on the bench
+    workload: final state, accept and the state at every chunk boundary."""
+    import torch
+    w = configs.c2_dfa()
+    x = configs.c2_input()
+    n = x.size
+    probes = list(range(0, n, chunk)) + [n]
+    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = torch.from_numpy(x).to("cuda")
+    say("C2 full", look, chunk, kw)
+    res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=chunk, lookahead=look, boundaries=True, **kw)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res) == (fin, oracle.accepts(fin, w.accepting), 0, len(probes) - 1)
+    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(b, ps.astype(np.int64))
+    d.close()
+
+
 def test_c2_ablation_all_states(dfa_mod):
     w = configs.c2_dfa()
     x = configs.c2_input(1 << 20)

@@ -119,16 +119,62 @@ def test_contains_language_has_one_accepting_sink():
 
 
 def test_recorded_c2_seed_search():
-    first, lo, hi = configs.C2_SEARCH
-    d = patterns.search_pattern_dfa(first, lo, hi)
+    d = configs.pattern_search(configs.C2_SEARCH)
     assert d.seed == configs.C2_PATTERN_SEED
-    assert lo <= configs.c2_dfa().num_states <= hi
+    assert configs.C2_SEARCH[1] <= configs.c2_dfa().num_states <= configs.C2_SEARCH[2]
 
 
-@pytest.mark.slow
+def _first_hit(args):
+    first, lo, hi, tries, n = args
+    try:
+        return configs.pattern_search((first, lo, hi, tries, n)).seed
+    except RuntimeError:
+        return None
+
+
 def test_recorded_c3_seed_search():
-    first, lo, hi = configs.C3_SEARCH
-    assert patterns.search_pattern_dfa(first, lo, hi).seed == configs.C3_PATTERN_SEED
+    """The whole C3 search (seeds 3 .. 67824), split into ranges over a
+    process pool: the first hit of the lowest range with one is the search's."""
+    from concurrent.futures import ProcessPoolExecutor
+    first, lo, hi, _, n = configs.C3_SEARCH
+    end = configs.C3_PATTERN_SEED + 1
+    step = (end - first + 31) // 32
+    ranges = [(a, lo, hi, min(step, end - a), n) for a in range(first, end, step)]
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        hits = [h for h in ex.map(_first_hit, ranges) if h is not None]
+    assert hits and hits[0] == configs.C3_PATTERN_SEED
+
+
+def test_recorded_seeds_are_rare_in_their_inputs():
+    """Expected occurrences of the pattern in the configured input length stay
+    below the search's threshold, and the early-sink seeds are far above it."""
+    wts = streams.AMINO_WEIGHTS
+    for seed, n in [(configs.C2_PATTERN_SEED, configs.C2_BYTES),
+                    (configs.C3_PATTERN_SEED, configs.C3_BYTES)]:
+        assert n * patterns.occurrence_bound(patterns.random_pattern(seed), wts) <= 0.05
+    for seed, n in [(configs.C2_EARLY_SINK_SEED, configs.C2_BYTES),
+                    (configs.C3_EARLY_SINK_SEED, configs.C3_BYTES)]:
+        assert n * patterns.occurrence_bound(patterns.random_pattern(seed), wts) > 1
+
+
+def test_occurrence_bound_matches_counts():
+    """The union bound against counted occurrences of short patterns in a
+    residue stream: equal for a single-residue pattern, an upper bound (and
+    within a factor of ~2) for a two-element one."""
+    x = streams.residues(4, 1 << 20)
+    text = x.tobytes().decode("ascii")
+    import re
+    wts = streams.AMINO_WEIGHTS
+    one = patterns.Pattern((patterns.Element("res", (3,), 1, 1),))
+    cnt = text.count(patterns.AMINO[3])
+    exp = x.size * patterns.occurrence_bound(one, wts)
+    assert abs(cnt - exp) < 5 * exp ** 0.5
+    two = patterns.Pattern((patterns.Element("set", (0, 5), 1, 1),
+                            patterns.Element("res", (9,), 1, 2)))
+    starts = len(re.findall("(?=[%s%s]%s)" % (patterns.AMINO[0], patterns.AMINO[5],
+                                              patterns.AMINO[9]), text))
+    bound = x.size * patterns.occurrence_bound(two, wts)
+    assert starts <= bound and bound < 2.2 * starts
 
 
 def test_c3_protein_size_and_c3_byte_columns():

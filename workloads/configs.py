@@ -5,9 +5,12 @@ C1 plain:    one random complete DFA, 16 states over the 256-byte alphabet,
              bytes from stream seed 2.
 C2 protein:  minimal DFA for Sigma* P Sigma* of a seeded PROSITE-like pattern
              P over the 20 amino-acid letters, 270..330 states (seed search
-             from 3); 256 MiB of residues from stream seed 4.
-C3 large:    (i) protein DFA with 1288 states (seed search from 3; the first
-             seed within +2% is used when no exact hit is found) and
+             from 3 among patterns expected to occur at most 0.05 times in
+             the 256 MiB input, so that the walk never reaches the accepting
+             sink); 256 MiB of residues from stream seed 4.
+C3 large:    (i) protein DFA with 1288 states (seed search from 3 among
+             patterns expected at most 0.05 times in 10 GiB; the first seed
+             within +2% is used when no exact hit is found) and
              (ii) a 512-state byte DFA built from 64 distinct random columns
              (columns seed 5, byte->column map seed 6); 10 GiB inputs
              (residues, stream seed 10; uniform bytes, stream seed 11);
@@ -28,12 +31,6 @@ from . import patterns, streams
 MiB = 1 << 20
 GiB = 1 << 30
 
-# Recorded results of patterns.search_pattern_dfa(first_seed, lo, hi).
-C2_SEARCH = (3, 270, 330)
-C2_PATTERN_SEED = 32          # 284 states
-C3_SEARCH = (3, 1288, 1313)
-C3_PATTERN_SEED = 5825        # 1297 states (first seed within +2% of 1288)
-
 C1_INPUT_SEED = 2
 C2_INPUT_SEED = 4
 C3_PROTEIN_INPUT_SEED = 10
@@ -44,6 +41,20 @@ C2_BYTES = 256 * MiB
 C3_BYTES = 10 * GiB
 C3_CHUNKS = [4096 << k for k in range(9)]   # 4 KiB .. 1 MiB
 
+# Recorded results of patterns.search_pattern_dfa(first_seed, lo, hi,
+# max_tries=..., rare_in=n, weights=AMINO_WEIGHTS): (first seed, lo, hi,
+# seeds tried, input bytes n).
+C2_SEARCH = (3, 270, 330, 20000, C2_BYTES)
+C2_PATTERN_SEED = 220         # 301 states, 8 classes
+C3_SEARCH = (3, 1288, 1313, 200000, C3_BYTES)
+C3_PATTERN_SEED = 67824       # 1298 states, 13 classes (no exact 1288 among
+                              # 200000 seeds; the first within +2%)
+# Seeds of the earlier size-only searches: their patterns occur every few
+# hundred (C3) or few million (C2) residues, so walks reach the accepting
+# sink early; they stay as test cases for stops at absorbing states.
+C2_EARLY_SINK_SEED = 32       # 284 states, sink reached ~14.6 MB into the C2 input
+C3_EARLY_SINK_SEED = 5825     # 1297 states, sink reached within 4 KiB
+
 
 def c1_dfa(seed: int = 1) -> DFA:
     return random_dfa(seed, 16, 256, 4, name=f"C1 random 16x256 seed {seed}")
@@ -53,9 +64,9 @@ def c1_input(n: int = C1_BYTES, seed: int = C1_INPUT_SEED, first: int = 0) -> np
     return streams.uniform_bytes(seed, n, first)
 
 
-def c2_dfa() -> DFA:
-    d = from_pattern(patterns.pattern_dfa(C2_PATTERN_SEED))
-    d.name = f"C2 prosite-like seed {C2_PATTERN_SEED} Q={d.num_states}"
+def c2_dfa(seed: int = C2_PATTERN_SEED) -> DFA:
+    d = from_pattern(patterns.pattern_dfa(seed))
+    d.name = f"C2 prosite-like seed {seed} Q={d.num_states}"
     return d
 
 
@@ -63,10 +74,17 @@ def c2_input(n: int = C2_BYTES, seed: int = C2_INPUT_SEED, first: int = 0, out=N
     return streams.residues(seed, n, first, out=out)
 
 
-def c3_protein_dfa() -> DFA:
-    d = from_pattern(patterns.pattern_dfa(C3_PATTERN_SEED))
-    d.name = f"C3 prosite-like seed {C3_PATTERN_SEED} Q={d.num_states}"
+def c3_protein_dfa(seed: int = C3_PATTERN_SEED) -> DFA:
+    d = from_pattern(patterns.pattern_dfa(seed))
+    d.name = f"C3 prosite-like seed {seed} Q={d.num_states}"
     return d
+
+
+def pattern_search(spec) -> "patterns.PatternDFA":
+    """Re-run a recorded seed search (C2_SEARCH or C3_SEARCH)."""
+    first, lo, hi, tries, n = spec
+    return patterns.search_pattern_dfa(first, lo, hi, max_tries=tries, rare_in=n,
+                                       weights=tuple(streams.AMINO_WEIGHTS))
 
 
 def c3_byte_dfa() -> DFA:

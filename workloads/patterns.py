@@ -372,12 +372,38 @@ def pattern_dfa(seed: int, contains: bool = True, max_states: int = 20000,
                       np.nonzero(macc)[0].astype(np.uint32), 0, amino_byte_map())
 
 
+def occurrence_bound(p: Pattern, weights: Sequence[float]) -> float:
+    """Union bound on the probability that an occurrence of P starts at a given
+    position of an i.i.d. residue stream with letter weights ``weights``:
+    prod over elements of sum_{k=lo..hi} q_e^k, q_e = probability of one of the
+    element's allowed residues (every combination of repeat counts is counted
+    once)."""
+    w = np.asarray(weights, dtype=float)
+    q = w / w.sum()
+    u = 1.0
+    for e in p.elements:
+        qe = float(q[list(e.allowed())].sum())
+        u *= sum(qe ** k for k in range(e.lo, e.hi + 1))
+    return u
+
+
 @functools.lru_cache(maxsize=None)
 def search_pattern_dfa(first_seed: int, lo: int, hi: int, contains: bool = True,
                        n_elements: Optional[Tuple[int, int]] = None,
-                       max_tries: int = 20000) -> PatternDFA:
-    """First seed s = first_seed, first_seed+1, ... whose minimal DFA has lo <= #Q <= hi."""
+                       max_tries: int = 20000, rare_in: Optional[int] = None,
+                       weights: Optional[Tuple[float, ...]] = None,
+                       expected_max: float = 0.05) -> PatternDFA:
+    """First seed s = first_seed, first_seed+1, ... whose minimal DFA has lo <= #Q <= hi.
+
+    With ``rare_in = n`` only patterns whose expected number of occurrences in
+    n residues drawn i.i.d. from ``weights`` is at most ``expected_max`` (by
+    ``occurrence_bound``) qualify, so that a walk over such an input almost
+    surely never reaches the accepting sink of Sigma* P Sigma*; the cheap test
+    runs before the DFA is built."""
     for s in range(first_seed, first_seed + max_tries):
+        if rare_in is not None:
+            if rare_in * occurrence_bound(random_pattern(s, n_elements), weights) > expected_max:
+                continue
         try:
             d = pattern_dfa(s, contains, max_states=max(4 * hi, 64), n_elements=n_elements)
         except TooLarge:

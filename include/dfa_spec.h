@@ -82,9 +82,6 @@ typedef struct dfa_info {
     uint32_t pair_columns;    /* distinct two-symbol columns delta(delta(., a), b) of the
                                  table that lets the packed matcher take two symbols
                                  per lookup; 0 = no such table */
-    uint32_t triple_columns;  /* distinct three-symbol columns of the table that lets it
-                                 take three symbols per lookup (class-major, all of it
-                                 within 64 KiB); 0 = no such table */
 } dfa_info_t;
 
 /* Options for dfa_match_ex.  Zero-initialised means "library defaults". */
@@ -136,16 +133,6 @@ typedef struct dfa_match_opts {
  * are unchanged. */
 #define DFA_MATCH_CHUNK_LANES 8u
 
-/* flags bit: at most two symbols per table lookup even where the DFA has a
- * three-symbol table (dfa_info_t::triple_columns > 0).  The three-symbol
- * table cuts the walk's lookups to a third but is staged larger (up to 64
- * KiB per workgroup) and its codes take 2 bytes per 3 symbols (pair codes: 1
- * byte per 2); it is used for requested chunk lengths (chunk_len != 0) of a
- * multiple of 48 with precomputed start sets, and never with merged walks or
- * interleaved codes; the planner's own lengths keep two symbols.
- * dfa_autotune tries both. */
-#define DFA_MATCH_TWO_STEP 16u
-
 /* flags field bits 8..11: walk rounds of the packed matcher.  Walks of one
  * chunk that reach the same state at the same position have the same future
  * (delta is a function), so after each round but the last the matcher keeps
@@ -179,7 +166,13 @@ typedef struct dfa_match_opts {
  *                   be 256).
  *   out:            receives the handle (owned by the caller; dfa_destroy).
  * All inputs are copied.  Returns DFA_E_INVAL on an invalid automaton,
- * DFA_E_TOOBIG if the compressed table cannot be staged in LDS. */
+ * DFA_E_TOOBIG if the compressed table cannot be staged in LDS.
+ * Fault injection (tests of the speculation check only): when the environment
+ * variable DFA_DROP_STATE holds a state id s at dfa_create time, s is left
+ * out of every one-symbol and precomputed multi-symbol initial-state set; a
+ * match whose true state at a chunk boundary is s then reports
+ * DFA_FLAG_SPECULATION (DFA_E_SPECULATION from dfa_match) instead of a
+ * state. */
 int dfa_create(const uint32_t *delta, uint32_t num_states, uint32_t num_symbols,
                uint32_t q0, const uint32_t *accepting, uint32_t num_accepting,
                const uint8_t *byte_to_symbol, dfa_t **out);
@@ -205,12 +198,16 @@ int dfa_match(const dfa_t *d, const uint8_t *input, size_t len, uint32_t start_s
               uint32_t *final_state, int *accepted);
 
 /* dfa_match_async -- the same test on device-resident input, enqueued on
- * `stream`; nothing is waited for.
+ * `stream`.
  *   d_input:  device, len bytes; must stay valid until the stream passes
  *             this call.
  *   d_result: device, one dfa_result_t (4 x uint32), written on the stream.
  * Errors in the input (bytes outside Sigma) are reported in d_result->flags,
- * not by the return code. */
+ * not by the return code.  The library keeps one scratch workspace per
+ * (device, stream); a call that needs more than the stream's workspace holds
+ * (the first call, or a larger input) waits for `stream` (never for other
+ * streams) before it releases the old workspace, and allocates a larger one.
+ * Calls that fit return without waiting. */
 int dfa_match_async(const dfa_t *d, const uint8_t *d_input, size_t len,
                     uint32_t start_state, void *stream, uint32_t *d_result);
 
@@ -226,6 +223,27 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
                  const dfa_match_opts_t *opts, void *stream, uint32_t *d_result,
                  uint32_t *d_boundaries);
 
+/* dfa_match_maps -- dfa_match_ex on the packed-pair matcher that also
+ * returns the level-0 state maps: for every (chunk i, start state q) pair the
+ * end state delta*(q, c_i) of its walk (Section 4.1's L_i[j], over the
+ * chunk's initial-state set, Eq. 11 / Eq. 13), in the caller's numbering.
+ * For tests and diagnostics: every entry of the maps the composition reads
+ * can be checked against a direct walk.
+ *   d_first:      device, num_chunks + 1 uint32: first pair of each chunk;
+ *                 d_first[num_chunks] = number of pairs.
+ *   d_pair_start, d_pair_end: device, max_pairs uint16 each: pair P's start
+ *                 state and end state (0xFFFF: the end state is in no state
+ *                 of the next chunk's set, an invariant violation that also
+ *                 sets DFA_FLAG_SPECULATION).  Pairs >= max_pairs are not
+ *                 written; the caller compares d_first[num_chunks] with
+ *                 max_pairs (at most num_chunks * dfa_plan()'s set_max).
+ * Returns DFA_E_INVAL when the plan does not use the packed-pair matcher
+ * (dfa_plan's kernel 0) or len is 0. */
+int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t start_state,
+                   const dfa_match_opts_t *opts, void *stream, uint32_t *d_result,
+                   uint32_t *d_first, uint16_t *d_pair_start, uint16_t *d_pair_end,
+                   uint64_t max_pairs);
+
 /* lookahead value meaning "use what dfa_autotune chose for this DFA and a
  * length of this order (one symbol if it was never tuned)". */
 #define DFA_LOOKAHEAD_AUTO 0xFFFFFFFFu
@@ -238,12 +256,10 @@ int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t st
  * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r, r + 1 and r0, a quarter
  * to four times the chunk, and 16 and 64 times it for merged rounds, which
  * stop a walk at an absorbing state) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
- * interleaved codes (one and two rounds) and one chunk per lane, then three-
- * symbol steps at chunk lengths of a multiple of 48 near the best where that
- * table exists, the best with DFA_MATCH_SINGLE_STEP where a two-symbol table
- * exists, and for a DFA
- * with an absorbing state with DFA_MATCH_EARLY_EXIT; whichever is faster is
- * kept (in best->flags).
+ * interleaved codes (one and two rounds) and one chunk per lane, then the
+ * best with DFA_MATCH_SINGLE_STEP where a two-symbol table exists, and for a
+ * DFA with an absorbing state with DFA_MATCH_EARLY_EXIT; whichever is faster
+ * is kept (in best->flags).
  *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
  *   fastest candidate's time per call (may be NULL).  Synchronises `stream`. */
 int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
@@ -272,10 +288,9 @@ typedef struct dfa_plan_info {
     uint32_t lookahead;       /* effective reverse-lookahead symbols r */
     uint32_t blocks;          /* matcher grid */
     uint32_t threads;         /* threads per block */
-    uint32_t symbols_per_step;/* 3: the packed matcher walks the three-symbol table (one
-                                 lookup per three input bytes, after a pass that turns
-                                 byte triples into codes); 2: the two-symbol table
-                                 (likewise for byte pairs); 1 otherwise */
+    uint32_t symbols_per_step;/* 2: the packed matcher walks the two-symbol table (one
+                                 lookup per two input bytes, after a pass that turns
+                                 byte pairs into codes); 1 otherwise */
     uint32_t raw_input;       /* 1: the packed matcher reads the input bytes themselves
                                  (direct table: only a validation pass runs first) when
                                  the input is 16-byte aligned */
@@ -352,7 +367,15 @@ int dfa_match_batch(const dfa_t *const *dfas, const uint8_t *const *d_inputs,
  *   dfa_server_create:   opts may be NULL (defaults below).
  *   dfa_server_register: the DFA must outlive the server; *id receives its id.
  *   dfa_server_submit:   d_input (device) must stay valid until the ticket is
- *                        done; DFA_E_TOOBIG if one request exceeds the budget.
+ *                        done, and its contents must be complete when the
+ *                        call is made (the server's streams do not wait for
+ *                        the caller's); DFA_E_TOOBIG if one request exceeds
+ *                        the budget or, alone in a batch, a slot's arena.
+ *   dfa_server_submit_after: the same for an input still being produced on
+ *                        `producer_stream` (a kernel or copy enqueued before
+ *                        the call): an event recorded on that stream at
+ *                        submit time is waited for on the server's stream
+ *                        before the request's batch reads the input.
  *   dfa_server_poll:     DFA_OK and the record once done (the ticket is then
  *                        released), DFA_E_NOTREADY before.
  *   dfa_server_wait:     blocks until the ticket is done.
@@ -378,6 +401,8 @@ int dfa_server_create(const dfa_server_opts_t *opts, dfa_server_t **out);
 int dfa_server_register(dfa_server_t *srv, const dfa_t *d, uint32_t *id);
 int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
                       uint64_t *ticket);
+int dfa_server_submit_after(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
+                            void *producer_stream, uint64_t *ticket);
 int dfa_server_poll(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
 int dfa_server_wait(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out);
 int dfa_server_stats(dfa_server_t *srv, dfa_server_stats_t *out);

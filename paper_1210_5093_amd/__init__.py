@@ -37,8 +37,7 @@ class dfa_info_t(ctypes.Structure):
                 ("imax", ctypes.c_uint32), ("q0", ctypes.c_uint32),
                 ("mean_iset", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("packed_layout", ctypes.c_uint32),
-                ("lookahead_tables", ctypes.c_uint32), ("pair_columns", ctypes.c_uint32),
-                ("triple_columns", ctypes.c_uint32)]
+                ("lookahead_tables", ctypes.c_uint32), ("pair_columns", ctypes.c_uint32)]
 
 
 class dfa_match_opts_t(ctypes.Structure):
@@ -113,6 +112,9 @@ def lib() -> ctypes.CDLL:
     L.dfa_match_ex.restype = I
     L.dfa_match_ex.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(dfa_match_opts_t), P,
                                P, P]
+    L.dfa_match_maps.restype = I
+    L.dfa_match_maps.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(dfa_match_opts_t), P,
+                                 P, P, P, P, U64]
     L.dfa_plan_chunks.restype = I
     L.dfa_plan_chunks.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(dfa_match_opts_t),
                                   ctypes.POINTER(U64), ctypes.POINTER(U64)]
@@ -147,6 +149,8 @@ def lib() -> ctypes.CDLL:
     L.dfa_server_register.argtypes = [P, P, ctypes.POINTER(U32)]
     L.dfa_server_submit.restype = I
     L.dfa_server_submit.argtypes = [P, U32, P, ctypes.c_size_t, ctypes.POINTER(U64)]
+    L.dfa_server_submit_after.restype = I
+    L.dfa_server_submit_after.argtypes = [P, U32, P, ctypes.c_size_t, P, ctypes.POINTER(U64)]
     L.dfa_server_poll.restype = I
     L.dfa_server_poll.argtypes = [P, U64, ctypes.POINTER(dfa_result_t)]
     L.dfa_server_wait.restype = I
@@ -189,7 +193,6 @@ MATCH_EARLY_EXIT = 1
 MATCH_SINGLE_STEP = 2
 MATCH_INTERLEAVE = 4
 MATCH_CHUNK_LANES = 8
-MATCH_TWO_STEP = 16
 
 
 def match_rounds(k: int) -> int:
@@ -199,10 +202,10 @@ def match_rounds(k: int) -> int:
 
 def _opts(chunk_len: int = 0, lookahead: int = 1, early_exit: bool = False,
           rounds: int = 0, single_step: bool = False, interleave: bool = False,
-          chunk_lanes: bool = False, two_step: bool = False) -> dfa_match_opts_t:
+          chunk_lanes: bool = False) -> dfa_match_opts_t:
     flags = ((MATCH_EARLY_EXIT if early_exit else 0) | match_rounds(rounds) |
              (MATCH_SINGLE_STEP if single_step else 0) | (MATCH_INTERLEAVE if interleave else 0) |
-             (MATCH_CHUNK_LANES if chunk_lanes else 0) | (MATCH_TWO_STEP if two_step else 0))
+             (MATCH_CHUNK_LANES if chunk_lanes else 0))
     return dfa_match_opts_t(int(chunk_len), int(lookahead), flags)
 
 
@@ -306,11 +309,9 @@ def dfa_lookahead_set(d: DFA, lookahead_bytes) -> List[int]:
 
 def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1, rounds: int = 0,
              early_exit: bool = False, single_step: bool = False,
-             interleave: bool = False, chunk_lanes: bool = False,
-             two_step: bool = False) -> dfa_plan_info_t:
+             interleave: bool = False, chunk_lanes: bool = False) -> dfa_plan_info_t:
     out = dfa_plan_info_t()
-    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes,
-              two_step)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
     _check(lib().dfa_plan(d.handle, int(n), ctypes.byref(o), ctypes.byref(out)))
     return out
 
@@ -318,12 +319,10 @@ def dfa_plan(d: DFA, n: int, chunk_len: int = 0, lookahead: int = 1, rounds: int
 def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
                  lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
                  bound_out=None, early_exit: bool = False, rounds: int = 0,
-                 single_step: bool = False, interleave: bool = False, chunk_lanes: bool = False,
-                 two_step: bool = False):
+                 single_step: bool = False, interleave: bool = False, chunk_lanes: bool = False):
     """Test with options; optionally the state at every chunk boundary.
     rounds: walk rounds with merging (DFA_MATCH_ROUNDS; 0 = the planner's);
     single_step: one symbol per lookup even with a two-symbol table;
-    two_step: at most two symbols per lookup even with a three-symbol table;
     interleave: chunk-interleaved code stream (else linear; direct tables: the raw input);
     chunk_lanes: one chunk per lane with merged walks.
     Returns (result tensor, boundaries tensor or None)."""
@@ -336,13 +335,39 @@ def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 
         bnd = bound_out if bound_out is not None else torch.empty(
             nch + 1, dtype=torch.int32, device="cuda")
         assert bnd.numel() >= nch + 1
-    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes,
-              two_step)
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
     _check(lib().dfa_match_ex(d.handle, d_input.data_ptr() if n else None, n,
                               DFA_Q0 if start is None else int(start), ctypes.byref(o),
                               _stream_handle(stream), result.data_ptr(),
                               bnd.data_ptr() if bnd is not None else None))
     return result, bnd
+
+
+def dfa_match_maps(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
+                   lookahead: int = 1, stream=None, result=None, max_pairs: Optional[int] = None,
+                   early_exit: bool = False, rounds: int = 0, single_step: bool = False,
+                   interleave: bool = False, chunk_lanes: bool = False):
+    """dfa_match_maps: the test plus its level-0 state maps.  Returns (result
+    tensor, first [num_chunks + 1] int32, pair start states int16, pair end
+    states int16), all device tensors; pair P of chunk i (first[i] <= P <
+    first[i + 1]) walked chunk i from start[P] and ended in end[P]."""
+    import torch
+    result = _result_tensor(result)
+    n = int(d_input.numel())
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
+    plan = dfa_plan_info_t()
+    _check(lib().dfa_plan(d.handle, n, ctypes.byref(o), ctypes.byref(plan)))
+    nch = int(plan.num_chunks)
+    if max_pairs is None:
+        max_pairs = max(1, nch * max(1, int(plan.set_max)))
+    first = torch.empty(nch + 1, dtype=torch.int32, device="cuda")
+    ps = torch.empty(max_pairs, dtype=torch.int16, device="cuda")
+    pe = torch.empty(max_pairs, dtype=torch.int16, device="cuda")
+    _check(lib().dfa_match_maps(d.handle, d_input.data_ptr() if n else None, n,
+                                DFA_Q0 if start is None else int(start), ctypes.byref(o),
+                                _stream_handle(stream), result.data_ptr(), first.data_ptr(),
+                                ps.data_ptr(), pe.data_ptr(), int(max_pairs)))
+    return result, first, ps, pe
 
 
 def dfa_match_batch(dfas: Sequence[DFA], inputs: Sequence, stream=None, results=None):
@@ -374,8 +399,7 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
 
 def dfa_autotune(d: DFA, d_input, stream=None):
     """Tune on a device input: (lookahead r, chunk length, ms per call, early exit,
-    walk rounds (0 = one), one symbol per lookup, interleaved codes, chunk lanes,
-    at most two symbols per lookup)."""
+    walk rounds (0 = one), one symbol per lookup, interleaved codes, chunk lanes)."""
     o = dfa_match_opts_t()
     ms = ctypes.c_double()
     n = int(d_input.numel())
@@ -383,8 +407,7 @@ def dfa_autotune(d: DFA, d_input, stream=None):
                               _stream_handle(stream), ctypes.byref(o), ctypes.byref(ms)))
     return (int(o.lookahead), int(o.chunk_len), float(ms.value), bool(o.flags & MATCH_EARLY_EXIT),
             (int(o.flags) >> 8) & 0xF, bool(o.flags & MATCH_SINGLE_STEP),
-            bool(o.flags & MATCH_INTERLEAVE), bool(o.flags & MATCH_CHUNK_LANES),
-            bool(o.flags & MATCH_TWO_STEP))
+            bool(o.flags & MATCH_INTERLEAVE), bool(o.flags & MATCH_CHUNK_LANES))
 
 
 def dfa_batch_tune(dfas: Sequence[DFA], inputs: Sequence, stream=None
@@ -464,7 +487,20 @@ class Server:
         self._dfas.append(d)
         return int(i.value)
 
-    def submit(self, dfa_id: int, d_input) -> int:
+    def submit(self, dfa_id: int, d_input, stream=None) -> int:
+        """Submit a device uint8 tensor.  Its producer is torch's current
+        stream (or `stream`): the server's batch waits for the work enqueued
+        on it so far before it reads the input (dfa_server_submit_after)."""
+        t = ctypes.c_uint64()
+        n = int(d_input.numel())
+        _check(lib().dfa_server_submit_after(self._h, int(dfa_id),
+                                             d_input.data_ptr() if n else None, n,
+                                             _stream_handle(stream), ctypes.byref(t)))
+        self._live[int(t.value)] = d_input
+        return int(t.value)
+
+    def submit_ready(self, dfa_id: int, d_input) -> int:
+        """Submit an input whose contents are already complete (dfa_server_submit)."""
         t = ctypes.c_uint64()
         n = int(d_input.numel())
         _check(lib().dfa_server_submit(self._h, int(dfa_id), d_input.data_ptr() if n else None, n,

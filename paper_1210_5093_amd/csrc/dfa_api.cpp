@@ -38,10 +38,6 @@ struct Workspace {
     bool timing = false;
     struct Stamp { hipEvent_t begin, before_match, after_match, end; };
     std::vector<Stamp> stamps;    // one per timed call, read by dfa_timing_read
-    // second stream and events of the segmented translate/match pipeline
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr;
-    hipEvent_t ev_seg[kMaxSegments] = {};
 };
 
 namespace {
@@ -57,12 +53,14 @@ Workspace *workspace_for(hipStream_t s) {
     return slot.get();
 }
 
-int ensure(void **ptr, size_t *have, size_t need) {
+// Grows a per-stream buffer.  Only work on stream s uses it, so waiting for
+// s (not the whole device) makes the old buffer free to release.
+int ensure(void **ptr, size_t *have, size_t need, hipStream_t s) {
     if (*have >= need && *ptr) return DFA_OK;
     if (*ptr) {
         // the stream may still be reading the old buffer
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize (workspace)");
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (workspace)");
         (void)hipFree(*ptr);
         *ptr = nullptr;
         *have = 0;
@@ -107,9 +105,13 @@ dfa_match_opts_t resolve_opts(const dfa_t *d, size_t len, const dfa_match_opts_t
     return o;
 }
 
+// fixed: when not null, the call's scratch memory (fixed_bytes of device
+// memory) instead of the stream's workspace; nothing is allocated and no
+// timing events are made.
 int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
               const dfa_match_opts_t *opts_in, hipStream_t s, uint32_t *d_result,
-              uint32_t *d_bound) {
+              uint32_t *d_bound, const PackedBufs *readout = nullptr,
+              uint8_t *fixed = nullptr, size_t fixed_bytes = 0) {
     if (!d || !d_result || (len && !d_in)) return fail(DFA_E_INVAL, "match: NULL argument");
     if (start == DFA_Q0) start = d->dev.q0;
     if (start >= d->dev.nq) return fail(DFA_E_INVAL, "match: start state out of range");
@@ -120,8 +122,11 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     MatchPlan p;
     int rc = plan_match(d, len, chunk, look, &p, opts->flags);
     if (rc) return rc;
-    Workspace *ws = workspace_for(s);
-    if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
+    if (readout && (!p.packed || len == 0))
+        return fail(DFA_E_INVAL, "map readout needs the packed-pair matcher and a non-empty input");
+    Workspace *ws = fixed ? nullptr : workspace_for(s);
+    if (!fixed && !ws) return fail(DFA_E_DEVICE, "no HIP device");
+    const bool timing = ws && ws->timing;
     auto a256 = [](uint64_t b) { return (size_t)((b + 255) / 256 * 256); };
     const size_t map_bytes = a256(p.map_entries * 2);
     const size_t sz_bytes = a256(p.msize_entries * 2);
@@ -135,7 +140,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
                 code_stream, ((uint64_t)p.nch + 63) / 64 * 64 * p.ilv_nblk * 16 + 64);
         need += a256(code_stream);
         bad_off = need;
-        need += a256((uint64_t)p.tblocks * 4 * kMaxSegments);
+        need += a256((uint64_t)p.tblocks * 4);
         bsum_off = need;
         need += a256((uint64_t)match2_scan_blocks(p.nch) * 4 + 4);
         first_off = need;
@@ -163,15 +168,23 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
                 need += k ? a256(places * 4) + a256(places * 8) : a256(walks * 4);
         }
     }
-    rc = ensure(&ws->buf, &ws->bytes, need + 256);
-    if (rc) return rc;
-    uint8_t *base = (uint8_t *)ws->buf;
+    uint8_t *base = fixed;
+    if (fixed) {
+        if (need > fixed_bytes)
+            return fail(DFA_E_TOOBIG, "match: needs " + std::to_string(need) +
+                                          " bytes of scratch, more than the " +
+                                          std::to_string(fixed_bytes) + " the call may use");
+    } else {
+        rc = ensure(&ws->buf, &ws->bytes, need + 256, s);
+        if (rc) return rc;
+        base = (uint8_t *)ws->buf;
+    }
     uint16_t *maps = (uint16_t *)base;
     uint16_t *msize = (uint16_t *)(base + map_bytes);
     uint16_t *bvals = (uint16_t *)(base + map_bytes + sz_bytes);
     Workspace::Stamp st{};
     hipError_t e = hipSuccess;
-    if (ws->timing) {
+    if (timing) {
         e = hipEventCreate(&st.begin);
         if (e == hipSuccess) e = hipEventCreate(&st.before_match);
         if (e == hipSuccess) e = hipEventCreate(&st.after_match);
@@ -207,37 +220,30 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
                 }
             }
         }
-        if (p.fork) {
-            if (!ws->aux) {
-                // non-blocking, default priority
-                e = hipStreamCreateWithFlags(&ws->aux, hipStreamNonBlocking);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming);
-                for (uint32_t k = 0; k < kMaxSegments && e == hipSuccess; ++k)
-                    e = hipEventCreateWithFlags(&ws->ev_seg[k], hipEventDisableTiming);
-                if (e != hipSuccess) return hip_fail(e, "pipeline stream");
-            }
-            pb.aux = ws->aux;
-            pb.ev_fork = ws->ev_fork;
-            for (uint32_t k = 0; k < kMaxSegments; ++k) pb.ev_seg[k] = ws->ev_seg[k];
+        if (readout) {
+            pb.out_first = readout->out_first;
+            pb.out_start = readout->out_start;
+            pb.out_end = readout->out_end;
+            pb.out_cap = readout->out_cap;
         }
         rc = launch_match2(d, d_in, start, p, pb, maps, msize, s,
-                           ws->timing ? st.before_match : nullptr);
+                           timing ? st.before_match : nullptr);
         if (rc) return rc;
-        if (ws->timing) {
+        if (timing) {
             e = hipEventRecord(st.after_match, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         rc = launch_combine(d, d_in, start, p, maps, msize, bvals, &pb, d_result, d_bound, s);
     } else {
-        if (ws->timing) {
+        if (timing) {
             e = hipEventRecord(st.before_match, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         rc = launch_match(d, d_in, start, p, maps, msize, bvals, d_result, d_bound, s,
-                          ws->timing ? st.after_match : nullptr);
+                          timing ? st.after_match : nullptr);
     }
     if (rc) return rc;
-    if (!ws->timing) return DFA_OK;
+    if (!timing) return DFA_OK;
     e = hipEventRecord(st.end, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     ws->stamps.push_back(st);
@@ -252,6 +258,21 @@ extern "C" int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len,
                             uint32_t *d_result, uint32_t *d_boundaries) {
     return run_match(d, d_input, len, start_state, opts, (hipStream_t)stream, d_result,
                      d_boundaries);
+}
+
+extern "C" int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len,
+                              uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
+                              uint32_t *d_result, uint32_t *d_first, uint16_t *d_pair_start,
+                              uint16_t *d_pair_end, uint64_t max_pairs) {
+    if (!d_first || (max_pairs && (!d_pair_start || !d_pair_end)))
+        return fail(DFA_E_INVAL, "dfa_match_maps: NULL output");
+    PackedBufs ro;
+    ro.out_first = d_first;
+    ro.out_start = d_pair_start;
+    ro.out_end = d_pair_end;
+    ro.out_cap = max_pairs;
+    return run_match(d, d_input, len, start_state, opts, (hipStream_t)stream, d_result, nullptr,
+                     &ro);
 }
 
 extern "C" int dfa_match_async(const dfa_t *d, const uint8_t *d_input, size_t len,
@@ -287,7 +308,7 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->lookahead = p.r;
     out->blocks = p.packed ? p.blocks2 : p.blocks;
     out->threads = p.packed ? p.threads2 : p.waves_per_block * 64u;
-    out->symbols_per_step = p.triples ? 3u : p.pairs ? 2u : 1u;
+    out->symbols_per_step = p.pairs ? 2u : 1u;
     out->rounds = p.rounds;
     out->interleaved = p.ilv_nblk ? 1u : 0u;
     out->chunk_lanes = p.chunk_lanes ? 1u : 0u;
@@ -295,8 +316,7 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->levels = p.levels;
     out->group0 = p.levels ? p.group_l[0] : 0u;
     out->group = p.levels > 1 ? p.group_l[1] : 0u;
-    out->raw_input = p.packed && !p.pairs && !p.triples && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
-                     p.segments <= 1;
+    out->raw_input = p.packed && !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2;
     return DFA_OK;
 }
 
@@ -306,7 +326,7 @@ extern "C" int dfa_match(const dfa_t *d, const uint8_t *input, size_t len, uint3
     hipStream_t s = nullptr;
     Workspace *ws = workspace_for(s);
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
-    int rc = ensure((void **)&ws->in, &ws->in_bytes, len + 256);
+    int rc = ensure((void **)&ws->in, &ws->in_bytes, len + 256, s);
     if (rc) return rc;
     if (!ws->result) {
         hipError_t e = hipMalloc(&ws->result, 4 * sizeof(uint32_t));
@@ -460,37 +480,6 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
                     consider(o);
                 }
             }
-        }
-    }
-    // three-symbol steps: chunk lengths of a multiple of 48 around the best
-    // (3/8 .. 3 times it), at the best r and the next; then the best of all
-    // with at most two symbols per lookup
-    if (rc == DFA_OK && d->dev.triples) {
-        const dfa_match_opts_t base = pick;
-        uint64_t c0 = base.chunk_len;
-        if (c0 == 0) {
-            MatchPlan p0;
-            if (plan_match(d, n, 0, base.lookahead, &p0, 0) == DFA_OK) c0 = p0.chunk;
-        }
-        for (uint32_t r : {base.lookahead, std::min(base.lookahead + 1, rmax)}) {
-            for (uint64_t num : {3u, 6u, 12u, 24u}) {
-                const uint64_t c = (c0 * num / 8) / 48 * 48;
-                if (c < 384 || c > (1u << 20) || rc != DFA_OK) continue;
-                const uint64_t nch = (n + c - 1) / c;
-                if (nch > (1u << 20) || nch * per_chunk > (1ull << 30)) continue;
-                dfa_match_opts_t o{};
-                o.chunk_len = c;
-                o.lookahead = r;
-                consider(o);
-            }
-            if (r == rmax) break;
-        }
-        MatchPlan pp;
-        if (rc == DFA_OK && plan_match(d, n, pick.chunk_len, pick.lookahead, &pp, pick.flags) == DFA_OK &&
-            pp.triples) {
-            dfa_match_opts_t o = pick;
-            o.flags |= DFA_MATCH_TWO_STEP;
-            consider(o);
         }
     }
     if (rc == DFA_OK && d->dev.pairs) {

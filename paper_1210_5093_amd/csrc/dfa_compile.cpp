@@ -108,6 +108,14 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         lut[b] = byte_class[b] < 0 ? kLutInvalid
                                    : ((uint32_t)byte_class[b] << 24) | ((uint32_t)byte_class[b] * colstride);
 
+    // Fault injection for tests of the speculation check: with the
+    // environment variable DFA_DROP_STATE=s, state s is left out of every
+    // initial-state set (one-symbol and precomputed multi-symbol sets), so a
+    // chunk whose true start state is s has no walk from it and the result
+    // must carry DFA_FLAG_SPECULATION rather than a state.
+    uint32_t dropped = 0xFFFFFFFFu;
+    if (const char *ds = std::getenv("DFA_DROP_STATE")) dropped = (uint32_t)std::strtoul(ds, nullptr, 10);
+
     // ---- per-class sets: mode 1 = I_c (Eq. 11), mode 0 = all non-absorbing
     std::vector<uint32_t> off[2];
     std::vector<uint16_t> st[2], pos[2];
@@ -130,7 +138,7 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
             for (uint32_t s = 0; s < nq; ++s) {
                 if (absorbing[s]) {
                     pos[mode][(size_t)c * nq + s] = (uint16_t)(kTerm | s);
-                } else if (in[s]) {
+                } else if (in[s] && s != dropped) {
                     pos[mode][(size_t)c * nq + s] = (uint16_t)(st[mode].size() - off[mode][c]);
                     st[mode].push_back((uint16_t)s);
                 }
@@ -169,15 +177,26 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
         std::vector<uint32_t> prev_off, cur_off;
         std::vector<uint16_t> prev_st, cur_st;
         if (Kc > 0) {
-            prev_off.assign(off[1].begin(), off[1].begin() + Kc + 1);
-            prev_st.assign(st[1].begin(), st[1].begin() + off[1][Kc]);
+            // level 1 as stored (I_c); the images that seed level 2 keep a
+            // state left out by fault injection (each level is the exact image
+            // of Q; only the stored sets lack it)
+            std::vector<uint32_t> st_off(off[1].begin(), off[1].begin() + Kc + 1);
+            std::vector<uint16_t> st_st(st[1].begin(), st[1].begin() + off[1][Kc]);
+            prev_off.assign(1, 0);
+            for (uint32_t c = 0; c < Kc; ++c) {
+                std::vector<uint8_t> in(nq, 0);
+                for (uint32_t x = 0; x < nq; ++x) in[delta[(uint64_t)x * nsym + class_sym[c]]] = 1;
+                for (uint32_t q = 0; q < nq; ++q)
+                    if (in[q] && !absorbing[q]) prev_st.push_back((uint16_t)q);
+                prev_off.push_back((uint32_t)prev_st.size());
+            }
             r0 = 1;
-            mset_mean_k[1] = (double)prev_st.size() / Kc;
+            mset_mean_k[1] = (double)st_st.size() / Kc;
             mset_max_k[1] = setmax[1];
             moff[1] = 0;
             mst[1] = 0;
-            mset_off = prev_off;
-            mset_st = prev_st;
+            mset_off = st_off;
+            mset_st = st_st;
             std::vector<uint32_t> mark(nq, 0);
             uint32_t stamp = 0;
             for (uint32_t k = 2; k <= kMaxMsetLevel; ++k) {
@@ -203,13 +222,22 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
                     }
                 }
                 if (over) break;
-                mset_mean_k[k] = cur_off.size() > 1 ? (double)cur_st.size() / (cur_off.size() - 1) : 0.0;
-                for (size_t q = 0; q + 1 < cur_off.size(); ++q)
-                    mset_max_k[k] = std::max<uint32_t>(mset_max_k[k], cur_off[q + 1] - cur_off[q]);
+                // stored sets: the images without a state left out by fault injection
+                std::vector<uint32_t> keep_off(1, 0);
+                std::vector<uint16_t> keep_st;
+                keep_st.reserve(cur_st.size());
+                for (size_t q = 0; q + 1 < cur_off.size(); ++q) {
+                    for (uint32_t j = cur_off[q]; j < cur_off[q + 1]; ++j)
+                        if (cur_st[j] != dropped) keep_st.push_back(cur_st[j]);
+                    keep_off.push_back((uint32_t)keep_st.size());
+                }
+                mset_mean_k[k] = keep_off.size() > 1 ? (double)keep_st.size() / (keep_off.size() - 1) : 0.0;
+                for (size_t q = 0; q + 1 < keep_off.size(); ++q)
+                    mset_max_k[k] = std::max<uint32_t>(mset_max_k[k], keep_off[q + 1] - keep_off[q]);
                 moff[k] = (uint32_t)mset_off.size();
                 mst[k] = (uint32_t)mset_st.size();
-                mset_off.insert(mset_off.end(), cur_off.begin(), cur_off.end());
-                mset_st.insert(mset_st.end(), cur_st.begin(), cur_st.end());
+                mset_off.insert(mset_off.end(), keep_off.begin(), keep_off.end());
+                mset_st.insert(mset_st.end(), keep_st.begin(), keep_st.end());
                 prev_off.swap(cur_off);
                 prev_st.swap(cur_st);
                 r0 = k;
@@ -385,82 +413,6 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
             }
         }
     }
-    // ---- three-symbol steps ------------------------------------------------
-    // delta3(s, c1 c2 c3) = delta(delta(delta(s, c1), c2), c3) cuts a walk's
-    // lookups to a third.  Columns (distinct functions over the states) are
-    // deduplicated and stored class-major, 16-bit: column j holds 2 * delta3
-    // at byte offset j * CS, the code of a class string is that offset, and
-    // an LDS address is code + 2 * s (both 16-bit, so all columns must fit
-    // 64 KiB).  CS, the column stride, is 2 nq rounded up to an odd number of
-    // dwords, so that lanes in one state but on different columns fall into
-    // different LDS banks.  Class strings end early at a string's last byte: c2 = K or
-    // c3 = K stands for "no further symbol".  tcode holds the code of class
-    // string (c1, c2, c3) at (c1 (K + 1) + c2) (K + 1) + c3.  The staged image
-    // is the columns, then the absorbing-state bitmap (bit s).
-    uint32_t triples = 0, abs_off3 = 0, ncol3 = 0;
-    std::vector<uint16_t> stab3, tcode;
-    {
-        const uint32_t Kc = (uint32_t)class_sym.size();
-        const char *ft = std::getenv("DFA_TRIPLES");   // "0": no three-symbol table (diagnostic)
-        if (pairs && Kc >= 1 && Kc <= 15 && !(ft && ft[0] == '0')) {
-            const uint32_t K1 = Kc + 1;
-            uint32_t cs = (2u * nq + 3u) / 4u * 4u;
-            if ((cs / 4u) % 2u == 0) cs += 4u;
-            const uint32_t max_cols = 0x10000u / cs;
-            std::unordered_map<std::string, uint32_t> tid;
-            std::vector<std::vector<uint32_t>> cols;
-            std::vector<uint16_t> tc((size_t)Kc * K1 * K1, 0);
-            std::string key(nq * sizeof(uint32_t), '\0');
-            std::vector<uint32_t> colv(nq);
-            bool ok = max_cols >= 1;
-            for (uint32_t c1 = 0; c1 < Kc && ok; ++c1)
-                for (uint32_t c2 = 0; c2 <= Kc && ok; ++c2)
-                    for (uint32_t c3 = 0; c3 <= Kc && ok; ++c3) {
-                        if (c2 == Kc && c3 != Kc) continue;   // no string has a gap
-                        for (uint32_t q = 0; q < nq; ++q) {
-                            uint32_t t = delta[(uint64_t)q * nsym + class_sym[c1]];
-                            if (c2 < Kc) t = delta[(uint64_t)t * nsym + class_sym[c2]];
-                            if (c3 < Kc) t = delta[(uint64_t)t * nsym + class_sym[c3]];
-                            colv[q] = t;
-                        }
-                        std::memcpy(&key[0], colv.data(), key.size());
-                        auto it = tid.find(key);
-                        uint32_t id;
-                        if (it == tid.end()) {
-                            id = (uint32_t)cols.size();
-                            if (id >= max_cols) { ok = false; break; }
-                            tid.emplace(key, id);
-                            cols.push_back(colv);
-                        } else {
-                            id = it->second;
-                        }
-                        tc[((size_t)c1 * K1 + c2) * K1 + c3] = (uint16_t)(id * cs);
-                    }
-            const uint64_t img = align_up((uint64_t)cols.size() * cs, 16);
-            const uint64_t bits_bytes = align_up(((uint64_t)nq + 31) / 32 * 4, 16);
-            if (ok && img + bits_bytes + 16 <= (uint64_t)lds) {
-                triples = 1;
-                ncol3 = (uint32_t)cols.size();
-                stab3.assign(img / 2, 0);
-                for (size_t j = 0; j < cols.size(); ++j)
-                    for (uint32_t q = 0; q < nq; ++q)
-                        stab3[j * (cs / 2u) + q] = (uint16_t)(2u * cols[j][q]);
-                abs_off3 = (uint32_t)img;
-                std::vector<uint32_t> bits(bits_bytes / 4, 0);
-                for (uint32_t q = 0; q < nq; ++q)
-                    if (absorbing[q]) bits[q >> 5] |= 1u << (q & 31);
-                for (uint32_t w : bits) {
-                    stab3.push_back((uint16_t)(w & 0xFFFF));
-                    stab3.push_back((uint16_t)(w >> 16));
-                }
-                tcode = std::move(tc);
-                tcode.resize(align_up(tcode.size() * 2, 16) / 2, 0);
-            }
-        }
-    }
-    if (stab3.empty()) stab3.assign(8, 0);
-    if (tcode.empty()) tcode.assign(8, 0);
-
     if (stab2.empty()) stab2.assign(8, 0);
     pcode.resize(align_up(pcode.size(), 16), 0);
     if (pcode2.empty()) pcode2.assign(16, 0);
@@ -494,8 +446,6 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     size_t i_stab2 = add(stab2.data(), stab2.size() * 2);
     size_t i_pcode = add(pcode.data(), pcode.size());
     size_t i_pcode2 = add(pcode2.data(), pcode2.size());
-    size_t i_stab3 = add(stab3.data(), stab3.size() * 2);
-    size_t i_tcode = add(tcode.data(), tcode.size() * 2);
     const size_t arena_bytes = align_up(at, 256);
 
     dfa *d = new (std::nothrow) dfa();
@@ -557,11 +507,6 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     v.abs_off2 = abs_off2;
     v.pcode = (const uint8_t *)ptr(i_pcode);
     v.pcode2 = pcode2.size() > 16 ? (const uint8_t *)ptr(i_pcode2) : nullptr;
-    v.triples = triples;
-    v.stab3 = (const uint16_t *)ptr(i_stab3);
-    v.stab3_bytes = triples ? (uint32_t)(stab3.size() * 2) : 0u;
-    v.abs_off3 = abs_off3;
-    v.tcode = (const uint16_t *)ptr(i_tcode);
     v.nq = nq;
     v.nclass = K;
     v.colstride = colstride;
@@ -581,7 +526,6 @@ extern "C" int dfa_create(const uint32_t *delta, uint32_t nq, uint32_t nsym, uin
     inf.packed_layout = direct ? 3u : layout;
     inf.lookahead_tables = r0;
     inf.pair_columns = npair;
-    inf.triple_columns = ncol3;
     *out = d;
     return DFA_OK;
 }

@@ -24,7 +24,6 @@ constexpr uint32_t kLutInvalid = 0xFFFFFFFFu;
 constexpr uint32_t kMaxStates = 32767;
 constexpr uint32_t kMaxMsetLevel = 8;   // precomputed multi-symbol sets up to this r
 constexpr uint16_t kCodeInvalid = 0xFFFF;
-constexpr uint32_t kMaxSegments = 4;      // translate/match pipeline segments
 constexpr uint32_t kMaxRounds = 4;        // walk rounds with merging (DFA_MATCH_ROUNDS)
 constexpr uint32_t kRound1Bytes = 32;     // bytes of the first round; x4 per later round
 constexpr uint32_t kRegions = 64;         // regions (counters) of a round's walk list
@@ -86,18 +85,6 @@ struct DevDFA {
     const uint8_t *pcode2;       // direct tables only (else NULL): 32768 + 128 bytes, the
                                  // pair code of bytes b1, b2 < 128 at b1 + 256 * b2 and of a
                                  // lone last byte at 32768 + b; 0xFF for bytes outside Sigma
-    // Three-symbol steps: class-major columns of delta3(s, c1 c2 c3) over the
-    // distinct class-string functions (c2, c3 = K: no further symbol),
-    // 16-bit: entry 2 * delta3, code = column * CS (CS: 2 nq rounded up to an
-    // odd number of dwords), an LDS address is code + 2 * s; staged with an
-    // absorbing-state bitmap (bit s).  tcode:
-    // the 16-bit code of class string (c1, c2, c3) at (c1 (K+1) + c2) (K+1) + c3;
-    // pcode's first 256 bytes map bytes to classes.
-    uint32_t triples;            // 1 if the three-symbol table exists
-    const uint16_t *stab3;
-    uint32_t stab3_bytes;        // multiple of 16
-    uint32_t abs_off3;
-    const uint16_t *tcode;
     uint32_t nq;
     uint32_t nclass;
     uint32_t colstride;          // bytes between class columns (2 * Qp)
@@ -157,12 +144,7 @@ struct MatchPlan {
     bool packed = false;
     bool early_exit = false;     // DFA_MATCH_EARLY_EXIT honoured (packed, absorbing states)
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
-    uint32_t segments = 1;       // translate/match pipeline segments (1 .. kMaxSegments)
-    bool fork = false;           // translation on a second stream, beside the lookahead
-                                 // scan (and the matcher, when that reads the raw input)
     bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
-    bool triples = false;        // three-symbol steps over the class-major triple table
-                                 // (chunk % 48 == 0; excludes pairs)
     uint32_t rounds = 1;         // walk rounds (> 1: merged walks, chunk % 32 == 0)
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)
     uint32_t ilv_nblk = 0;       // chunk-interleaved code stream: 16-byte code blocks per
@@ -198,11 +180,12 @@ struct PackedBufs {
     uint32_t *lo[kMaxRounds] = {};
     uint2 *list[kMaxRounds] = {};
     uint32_t *cnt = nullptr;         // [kMaxRounds][kRegions]
-    // translation on a second stream (MatchPlan::fork): it runs on `aux`,
-    // segment by segment, beside the scan and the matcher's earlier segments
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr;
-    hipEvent_t ev_seg[kMaxSegments] = {};
+    // optional readout of the level-0 maps (dfa_match_maps): the first pair
+    // of every chunk, and per pair its start and end state, for pairs < out_cap
+    uint32_t *out_first = nullptr;
+    uint16_t *out_start = nullptr;
+    uint16_t *out_end = nullptr;
+    uint64_t out_cap = 0;
 };
 // The packed path stores level-0 maps indexed by pair (maps[first[i] + p]);
 // pb is null for the one-chunk-per-wave path (maps[i * stride + p]).

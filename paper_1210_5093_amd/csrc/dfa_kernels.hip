@@ -407,17 +407,6 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     const char *fpairs = std::getenv("DFA_PAIRS");
     p->pairs = p->packed && d->dev.pairs && p->lookahead != 2 && !(flags & DFA_MATCH_SINGLE_STEP) &&
                !(fpairs && fpairs[0] == '0') && (chunk_req == 0 || chunk_req % 32 == 0);
-    // three-symbol steps cut the lookups to a third; they need chunk lengths
-    // of a multiple of 48 (16-byte blocks of eight 3-symbol codes) and one
-    // walk round over a linear stream.  The planner's own chunk lengths keep
-    // two-symbol steps (on the protein-style workload the larger table and
-    // code stream cost more than the saved lookups); a requested length of a
-    // multiple of 48 takes three, unless DFA_MATCH_TWO_STEP.
-    p->triples = p->packed && d->dev.triples && p->lookahead != 2 &&
-                 !(flags & (DFA_MATCH_SINGLE_STEP | DFA_MATCH_TWO_STEP | DFA_MATCH_INTERLEAVE |
-                            DFA_MATCH_CHUNK_LANES)) &&
-                 DFA_MATCH_ROUNDS_OF(flags) <= 1 && chunk_req != 0 && chunk_req % 48 == 0;
-    if (p->triples) p->pairs = false;
     if (p->packed) {
         // two pairs per lane when the start sets are tiny (many chunks per
         // tile: shorter tiles spread the chains over more wavefronts), four
@@ -428,8 +417,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
         const char *fs = std::getenv("DFA_SLOTS");
         p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 8.0 ? 2u : 4u);
-        const uint32_t staged = p->triples ? d->dev.stab3_bytes
-                                : p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
+        const uint32_t staged = p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
         const uint32_t per_cu = std::max<uint32_t>(
             1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(staged, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
@@ -454,32 +442,13 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     }
     p->chunk = chunk;
     const uint64_t nch = (n + chunk - 1) / chunk;
-    // Optional: the translation pass on a second stream (DFA_FORK=1), beside
-    // the chunk-info scan (which reads the raw input, not the codes) and,
-    // for direct tables, beside the matcher.  Off by default: the join
-    // between the streams costs about as much as the overlap saves, and on
-    // one stream the translation's workgroups run the scan's first phase.
-    // Optional pipeline on top of it: translate segment k + 1 while the
-    // matcher walks segment k (DFA_SEGMENTS=2..4).  Slower on MI355X: the
-    // matcher loses more from the smaller per-launch tile count than the
-    // overlap gains.  Segment starts must be whole 16-byte code blocks
-    // (chunk lengths of 64k).  The window pass (lookahead beyond the
-    // precomputed sets) reads codes before the scan, so it keeps one stream.
-    const bool can_fork = p->packed && p->lookahead != 2;
-    if (const char *fs = std::getenv("DFA_SEGMENTS")) {
-        const int v = std::atoi(fs);
-        if (v >= 1 && v <= (int)kMaxSegments && can_fork && chunk % 64 == 0 && nch >= (uint64_t)v)
-            p->segments = (uint32_t)v;
-    }
-    const char *ff = std::getenv("DFA_FORK");
-    p->fork = can_fork && (p->segments > 1 || (ff && ff[0] == '1'));
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;
     p->early_exit = p->packed && (flags & DFA_MATCH_EARLY_EXIT) && d->dev.nabs > 0;
     // chunk-interleaved codes: the packed matcher's chunks are whole blocks
     // of 64 consecutive chunks' code streams; the window pass reads codes
     // across chunk ends, so it keeps the linear stream
-    if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) && p->segments == 1 &&
+    if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) &&
         p->lookahead != 2 && chunk % 32 == 0) {
         const uint64_t bytes_per_chunk = p->pairs ? chunk / 2 : chunk * p->code_bytes;
         p->ilv_nblk = (uint32_t)(bytes_per_chunk / 16);
@@ -498,7 +467,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     {
         const uint32_t req = DFA_MATCH_ROUNDS_OF(flags);
         uint32_t rounds = std::min<uint32_t>(req ? req : 1u, kMaxRounds);
-        if (!p->packed || p->segments > 1 || p->early_exit || chunk % 32 != 0 || p->chunk_lanes)
+        if (!p->packed || p->early_exit || chunk % 32 != 0 || p->chunk_lanes)
             rounds = 1;
         while (rounds > 1 && ((uint64_t)kRound1Bytes << (2 * (rounds - 2))) >= chunk) --rounds;
         p->rounds = rounds;
@@ -589,10 +558,9 @@ int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const Matc
                    uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
                    uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s) {
     hipError_t e;
-    // the packed path's translation flags (one word per translation block
-    // and segment) reach the result through the top level
-    const uint32_t nbad =
-        pb ? std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments)) * p.tblocks : 0u;
+    // the packed path's translation flags (one word per translation block)
+    // reach the result through the top level
+    const uint32_t nbad = pb ? p.tblocks : 0u;
     for (uint32_t l = 0; l < p.levels; ++l) {
         // level 0 of the packed matcher is pair-indexed; every other level
         // strided.  The last level (one group) also writes the result.

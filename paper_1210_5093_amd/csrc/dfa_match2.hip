@@ -690,94 +690,6 @@ __global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *_
     if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
 }
 
-// Three-symbol translation: code i is the tcode entry of the class string of
-// bytes 3i, 3i + 1, 3i + 2 (class K, "no further symbol", past the end of the
-// input); per-block flag if a byte is outside Sigma (class 0xFF).  A lane
-// turns 48 input bytes (three 16-byte loads) into 16 codes (two 16-byte
-// stores); the stream is written in whole 32-byte units, codes past the end
-// of the input are 0.  Classes are masked to 4 bits before the tcode lookup
-// (K <= 15), so every index stays inside the 4096-entry staged table.
-__global__ __launch_bounds__(256) void k_translate_triples(const uint8_t *__restrict__ in,
-                                                           uint64_t n,
-                                                           const uint8_t *__restrict__ pcode,
-                                                           const uint16_t *__restrict__ tcode,
-                                                           uint32_t K, uint16_t *__restrict__ out,
-                                                           uint32_t *__restrict__ block_bad,
-                                                           SumsArgs sa) {
-    scan_sums_in_pass(sa);
-    __shared__ uint8_t cls[256];
-    __shared__ __align__(16) uint16_t tc[4096];
-    __shared__ uint32_t bad_any;
-    const uint32_t K1 = K + 1;
-    const uint32_t ntc = K * K1 * K1;
-    cls[threadIdx.x] = pcode[threadIdx.x];
-    for (uint32_t i = threadIdx.x; i < 4096u; i += blockDim.x) tc[i] = i < ntc ? tcode[i] : 0u;
-    if (threadIdx.x == 0) bad_any = 0;
-    __syncthreads();
-    uint32_t bad = 0;
-    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t units = (n + 47) / 48;
-    const bool aligned = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += T) {
-        const uint64_t first = u * 48u;
-        uint32_t w[12];
-        const bool whole = first + 48u <= n;
-        if (whole && aligned) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(in + first);
-            const uint4 v0 = p[0], v1 = p[1], v2 = p[2];
-            w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
-            w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
-            w[8] = v2.x; w[9] = v2.y; w[10] = v2.z; w[11] = v2.w;
-        } else {
-            uint32_t (&w0)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[0]);
-            uint32_t (&w1)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[4]);
-            uint32_t (&w2)[4] = *reinterpret_cast<uint32_t (*)[4]>(&w[8]);
-            load16(in, first, n, w0);
-            load16(in, first + 16u, n, w1);
-            load16(in, first + 32u, n, w2);
-        }
-        auto byte_at = [&](uint32_t k) -> uint32_t { return (w[k >> 2] >> (8u * (k & 3u))) & 0xFFu; };
-        uint32_t c[16];
-        if (whole) {
-            uint32_t acc = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < 16; ++k) {
-                const uint32_t a0 = cls[byte_at(3 * k)], a1 = cls[byte_at(3 * k + 1)],
-                               a2 = cls[byte_at(3 * k + 2)];
-                acc |= a0 | a1 | a2;
-                c[k] = tc[(((a0 & 15u) * K1 + (a1 & 15u)) * K1 + (a2 & 15u)) & 4095u];
-            }
-            bad |= acc >> 7;
-        } else {
-#pragma unroll
-            for (uint32_t k = 0; k < 16; ++k) {
-                uint32_t a[3];
-                bool inv = false;
-#pragma unroll
-                for (uint32_t j = 0; j < 3; ++j) {
-                    const bool inside = first + 3 * k + j < n;
-                    const uint32_t v = cls[byte_at(3 * k + j)];
-                    inv = inv || (inside && v == 0xFFu);
-                    a[j] = inside ? (v & 15u) : K;
-                }
-                bad |= inv ? 1u : 0u;
-                const bool live = first + 3 * k < n;
-                c[k] = (live && !inv) ? tc[((a[0] * K1 + a[1]) * K1 + a[2]) & 4095u] : 0u;
-            }
-        }
-        uint4 o[2];
-        uint32_t *ow = reinterpret_cast<uint32_t *>(o);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ow[q] = __builtin_amdgcn_perm(c[2 * q + 1], c[2 * q], 0x05040100u);
-        uint4 *dst = reinterpret_cast<uint4 *>(out + u * 16u);
-        dst[0] = o[0];
-        dst[1] = o[1];
-    }
-    if (bad) atomicOr(&bad_any, 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) block_bad[blockIdx.x] = bad_any;
-}
-
 // Multi-symbol reverse lookahead (Eq. 13).  The start set of chunk i >= 1 is
 // the image of Q under the r' = min(r, p) bytes before it (p = i*C), minus the
 // absorbing states; the true state at p lies in it, and so does the end state
@@ -983,10 +895,9 @@ __global__ __launch_bounds__(1024, (S == 4 && !EXIT) ? 8 : 6) void k_match2(Matc
     auto code_at = [&](uint64_t pos) -> uint32_t {
         return L == 3 ? 2u * (codes[pos] & 0x7Fu) : (uint32_t)codes[pos];
     };
-    // L = 4 (two-symbol steps): one code per two input bytes; L = 5 (three-
-    // symbol steps): one per three.  Chunk lengths are multiples of the step
-    // (the host picks them for multiples of 32, resp. 48)
-    constexpr uint32_t kSym = L == 5 ? 3u : L == 4 ? 2u : 1u;   // symbols per code
+    // L = 4 (two-symbol steps): one code per two input bytes.  Chunk lengths
+    // are multiples of the step (the host picks them for multiples of 32)
+    constexpr uint32_t kSym = L == 4 ? 2u : 1u;   // symbols per code
     // full chunks start on 16-byte boundaries iff the chunk length does
     const bool aligned_chunks = (a.chunk % (kPer16 * kSym)) == 0;
 
@@ -1441,6 +1352,41 @@ __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__re
     }
 }
 
+// Readout of the level-0 maps in the caller's numbering (test and
+// diagnostic use): out_first[i] = first pair of chunk i (out_first[nch] =
+// number of pairs); for pair P < cap: its start state and the end state its
+// walk reached, delta*(start, chunk) (Section 4.1's L_i[j]).  An entry that
+// names no state of the next chunk's set reads 0xFFFF.
+struct MapOut {
+    uint32_t *first;
+    uint16_t *start;
+    uint16_t *end;
+    uint64_t cap;
+};
+
+__global__ __launch_bounds__(256) void k_decode_maps(Match2Args a, MapOut mo) {
+    const uint32_t total = a.first[a.nch];
+    const uint32_t P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P <= a.nch) mo.first[P] = a.first[P];
+    if (P >= total || P >= mo.cap) return;
+    const uint32_t tile = P / a.tile;
+    const uint32_t ntiles = (total + a.tile - 1) / a.tile;
+    const uint32_t lo0 = a.tile_first[tile];
+    const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
+    const uint32_t c = owner_chunk(a.first, lo0, hi0, P);
+    const uint32_t v = a.maps[P];
+    uint32_t e = 0xFFFFu;
+    if (v == kBadPos) {
+        e = 0xFFFFu;
+    } else if (v & kTerm) {
+        e = v & 0x7FFFu;
+    } else if (c + 1 < a.nch && v < a.first[c + 2] - a.first[c + 1]) {
+        e = pair_start(a, c + 1, a.first[c + 1] + v);
+    }
+    mo.start[P] = (uint16_t)pair_start(a, c, P);
+    mo.end[P] = (uint16_t)e;
+}
+
 // ---------------------------------------------------------------------------
 namespace {
 template <int SRC>
@@ -1463,27 +1409,12 @@ void launch_scan(const MatchPlan &p, const ScanSrc &q, const PackedBufs &b, uint
 
 namespace {
 const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
-    static const void *const tab[5][2][2] = {
-        {{reinterpret_cast<const void *>(&k_match2<1, 2, false>),
-          reinterpret_cast<const void *>(&k_match2<1, 2, true>)},
-         {reinterpret_cast<const void *>(&k_match2<1, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<1, 4, true>)}},
-        {{reinterpret_cast<const void *>(&k_match2<2, 2, false>),
-          reinterpret_cast<const void *>(&k_match2<2, 2, true>)},
-         {reinterpret_cast<const void *>(&k_match2<2, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<2, 4, true>)}},
-        {{reinterpret_cast<const void *>(&k_match2<3, 2, false>),
-          reinterpret_cast<const void *>(&k_match2<3, 2, true>)},
-         {reinterpret_cast<const void *>(&k_match2<3, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<3, 4, true>)}},
-        {{reinterpret_cast<const void *>(&k_match2<4, 2, false>),
-          reinterpret_cast<const void *>(&k_match2<4, 2, true>)},
-         {reinterpret_cast<const void *>(&k_match2<4, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<4, 4, true>)}},
-        {{reinterpret_cast<const void *>(&k_match2<5, 2, false>),
-          reinterpret_cast<const void *>(&k_match2<5, 2, true>)},
-         {reinterpret_cast<const void *>(&k_match2<5, 4, false>),
-          reinterpret_cast<const void *>(&k_match2<5, 4, true>)}}};
+#define DFA_MK(l) {{reinterpret_cast<const void *>(&k_match2<l, 2, false>),      \
+                    reinterpret_cast<const void *>(&k_match2<l, 2, true>)},       \
+                   {reinterpret_cast<const void *>(&k_match2<l, 4, false>),      \
+                    reinterpret_cast<const void *>(&k_match2<l, 4, true>)}}
+    static const void *const tab[4][2][2] = {DFA_MK(1), DFA_MK(2), DFA_MK(3), DFA_MK(4)};
+#undef DFA_MK
     return tab[L - 1][slots >= 4 ? 1 : 0][ex ? 1 : 0];
 }
 const void *chunk_walk_kernel(uint32_t L) {
@@ -1514,78 +1445,41 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
                   hipEvent_t ev_before_matcher) {
     // two-symbol steps (the plan checked the chunk length); else direct
     // tables: the matcher reads the (16-byte aligned) input itself
-    const bool triples = p.triples && d->dev.triples;
-    const bool pairs = !triples && p.pairs && d->dev.pairs;
-    const bool direct = !triples && !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
-                        p.segments <= 1 && (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
-    const bool fork = p.fork && p.lookahead != 2;
+    const bool pairs = p.pairs && d->dev.pairs;
+    const bool direct = !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+                        (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
     const Ilv ilv{p.ilv_nblk, p.nch, p.chunk};
-    if (p.ilv_nblk && (p.segments > 1 || p.chunk % 32 != 0 || p.lookahead == 2))
-        return fail(DFA_E_INVAL, "interleaved codes with segments, window pass or odd chunks");
-    const uint32_t L = triples ? 5u : pairs ? 4u : direct ? 3u : d->dev.layout;
-    if (triples && (p.chunk % 48 != 0 || p.lookahead == 2 || p.ilv_nblk || p.rounds > 1 ||
-                    p.chunk_lanes))
-        return fail(DFA_E_INVAL, "three-symbol plan with a window pass, merged walks or odd chunks");
-    if (pairs && (p.chunk % 32 != 0 || p.lookahead == 2 || (p.segments > 1 && p.chunk % 64 != 0)))
+    if (p.ilv_nblk && (p.chunk % 32 != 0 || p.lookahead == 2))
+        return fail(DFA_E_INVAL, "interleaved codes with a window pass or odd chunks");
+    const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
+    if (pairs && (p.chunk % 32 != 0 || p.lookahead == 2))
         return fail(DFA_E_INVAL, "two-symbol plan with a window pass or odd chunks");
-    const uint32_t nseg = std::max<uint32_t>(1u, std::min(p.segments, kMaxSegments));
-    if (nseg > 1 && !fork) return fail(DFA_E_INVAL, "segments without the translation stream");
-    uint32_t cb[kMaxSegments + 1];
-    for (uint32_t k = 0; k <= nseg; ++k) cb[k] = (uint32_t)((uint64_t)p.nch * k / nseg);
-    // fork: the translation runs on the aux stream from this point of s (so
-    // after every earlier use of the codes and flags); s waits for segment k
-    // before the matcher reads it, or (raw input) before the composition
-    hipStream_t ts = s;
-    if (fork) {
-        if (!b.aux || !b.ev_fork) return fail(DFA_E_DEVICE, "forked translation without an aux stream");
-        hipError_t fe = hipEventRecord(b.ev_fork, s);
-        if (fe == hipSuccess) fe = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
-        if (fe != hipSuccess) return hip_fail(fe, "fork to the translation stream");
-        ts = b.aux;
-    }
-    auto join = [&](uint32_t k) -> int {
-        if (!fork) return DFA_OK;
-        const hipError_t je = hipStreamWaitEvent(s, b.ev_seg[k], 0);
-        return je == hipSuccess ? DFA_OK : hip_fail(je, "hipStreamWaitEvent (translation)");
-    };
-    // Scan of the start-set sizes.  On one stream with precomputed sets the
-    // translation pass's workgroups also run the scan's first phase (the
-    // lookahead sets from the raw input) before they translate, and one
-    // pass finishes the scan; else the three-phase scan runs on s.
+    // Scan of the start-set sizes.  With precomputed sets the translation
+    // pass's workgroups also run the scan's first phase (the lookahead sets
+    // from the raw input) before they translate, and one pass finishes the
+    // scan; the window pass needs the three-phase scan.
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
     const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset};
-    const bool fused_scan = !fork && p.lookahead != 2;
+    const bool fused_scan = p.lookahead != 2;
     const uint32_t nsb = match2_scan_blocks(p.nch);
-    for (uint32_t k = 0; k < nseg; ++k) {
-        const uint64_t off = (uint64_t)cb[k] * p.chunk;
-        const uint64_t end = std::min<uint64_t>((uint64_t)cb[k + 1] * p.chunk, p.n);
-        uint32_t *bad = b.block_bad + (size_t)k * p.tblocks;
+    {
         const SumsArgs sa{q, info, b.bsum, fused_scan ? nsb : 0u};
-        if (triples)
-            hipLaunchKernelGGL(k_translate_triples, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.pcode, d->dev.tcode, d->dev.nclass,
-                               (uint16_t *)b.codes + off / 3, bad, sa);
-        else if (pairs && d->dev.pcode2)
-            hipLaunchKernelGGL(k_translate_pairs_direct, dim3(p.tblocks), dim3(256), 0, ts,
-                               d_in + off, end - off, d->dev.pcode2, (uint8_t *)b.codes + off / 2,
-                               bad, ilv, sa);
+        if (pairs && d->dev.pcode2)
+            hipLaunchKernelGGL(k_translate_pairs_direct, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                               d->dev.pcode2, (uint8_t *)b.codes, b.block_bad, ilv, sa);
         else if (pairs)
-            hipLaunchKernelGGL(k_translate_pairs, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.pcode, d->dev.nclass, (uint8_t *)b.codes + off / 2,
-                               bad, ilv, sa);
+            hipLaunchKernelGGL(k_translate_pairs, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                               d->dev.pcode, d->dev.nclass, (uint8_t *)b.codes, b.block_bad, ilv,
+                               sa);
         else if (direct)
-            hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, ts,
-                               d_in + off, end - off, d->dev.code, (uint8_t *)nullptr, bad, ilv, sa);
+            hipLaunchKernelGGL((k_translate<uint8_t, false>), dim3(p.tblocks), dim3(256), 0, s, d_in,
+                               p.n, d->dev.code, (uint8_t *)nullptr, b.block_bad, ilv, sa);
         else if (L == 1)
-            hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint8_t *)b.codes + off, bad, ilv, sa);
+            hipLaunchKernelGGL(k_translate<uint8_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                               d->dev.code, (uint8_t *)b.codes, b.block_bad, ilv, sa);
         else
-            hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, ts, d_in + off,
-                               end - off, d->dev.code, (uint16_t *)b.codes + off, bad, ilv, sa);
-        if (fork) {
-            hipError_t fe = hipEventRecord(b.ev_seg[k], ts);
-            if (fe != hipSuccess) return hip_fail(fe, "hipEventRecord (segment)");
-        }
+            hipLaunchKernelGGL(k_translate<uint16_t>, dim3(p.tblocks), dim3(256), 0, s, d_in, p.n,
+                               d->dev.code, (uint16_t *)b.codes, b.block_bad, ilv, sa);
     }
     Match2Args a;
     a.d = d->dev;
@@ -1595,12 +1489,6 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         a.d.rowbytes = d->dev.rowbytes2;
         a.d.abs_off = d->dev.abs_off2;
         a.d.abs_shift = 2;
-    } else if (triples) {   // or the class-major triple table (state offset 2 * s)
-        a.d.stab = d->dev.stab3;
-        a.d.stab_bytes = d->dev.stab3_bytes;
-        a.d.rowbytes = 2;
-        a.d.abs_off = d->dev.abs_off3;
-        a.d.abs_shift = 1;
     }
     a.codes = direct ? static_cast<const void *>(d_in) : b.codes;
     a.n = p.n;
@@ -1635,39 +1523,28 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         hipError_t we = hipLaunchKernel(wf, dim3(p.blocks2), dim3(p.threads2), wargs, lds, s);
         if (we != hipSuccess) return hip_fail(we, "k_window2 launch");
         launch_scan<1>(p, q, b, nullptr, start, s);
-    } else if (fused_scan) {
+    } else {
         hipLaunchKernelGGL(k_scan_finish, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum, b.first,
                            b.tile_first, b.cnt, b.cnt ? kMaxRounds * kRegions : 0u);
-    } else {
-        // lookahead sets and sizes computed inside the scan's first phase
-        launch_scan<0>(p, q, b, nullptr, start, s, &info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
+    if (ev_before_matcher) {
+        e = hipEventRecord(ev_before_matcher, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     if (p.chunk_lanes) {
-        if (!p.ilv_nblk || L == 3 || p.lookahead == 2 || nseg > 1)
+        if (!p.ilv_nblk || L == 3 || p.lookahead == 2)
             return fail(DFA_E_INVAL, "chunk lanes need interleaved codes and precomputed sets");
-        if (int jr = join(0)) return jr;
-        if (ev_before_matcher) {
-            e = hipEventRecord(ev_before_matcher, s);
-            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        }
         ChunkWalkArgs cw{kRound1Bytes};
         void *cargs[] = {&a, &cw};
         const uint32_t blocks = std::max<uint32_t>(
             1u, std::min<uint32_t>((p.nch + 255) / 256, p.blocks2 * (p.threads2 / 256)));
         e = hipLaunchKernel(chunk_walk_kernel(L), dim3(blocks), dim3(256), cargs, lds, s);
-        return e == hipSuccess ? DFA_OK : hip_fail(e, "k_chunk_walk launch");
-    }
-    if (p.rounds > 1) {
-        if (nseg > 1 || p.early_exit || p.chunk % 32 != 0 || !b.cnt)
-            return fail(DFA_E_INVAL, "merged walks need one segment, no early exit, chunks of 32k");
-        if (!direct)
-            if (int jr = join(0)) return jr;
-        if (ev_before_matcher) {
-            e = hipEventRecord(ev_before_matcher, s);
-            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        }
+        if (e != hipSuccess) return hip_fail(e, "k_chunk_walk launch");
+    } else if (p.rounds > 1) {
+        if (p.early_exit || p.chunk % 32 != 0 || !b.cnt)
+            return fail(DFA_E_INVAL, "merged walks need no early exit and chunks of 32k");
         const void *rf = round_kernel(L, p.slots, a.d.nabs > 0);
         for (uint32_t k = 0; k < p.rounds; ++k) {
             RoundArgs m;
@@ -1693,27 +1570,23 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         hipLaunchKernelGGL(k_merge_maps, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s, a, mm);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "k_merge_maps launch");
-        return direct ? join(0) : DFA_OK;
-    }
-    const void *fn = match2_kernel(L, p.slots, p.early_exit);
-    for (uint32_t k = 0; k < nseg; ++k) {
-        // raw input: the matcher does not read the validation pass's output
-        if (!direct)
-            if (int jr = join(k)) return jr;
-        if (k == 0 && ev_before_matcher) {
-            e = hipEventRecord(ev_before_matcher, s);
-            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        }
-        a.c_lo = cb[k];
-        a.c_hi = cb[k + 1];
+    } else {
         void *args[] = {&a};
-        e = hipLaunchKernel(fn, dim3(p.blocks2), dim3(p.threads2), args, lds, s);
+        e = hipLaunchKernel(match2_kernel(L, p.slots, p.early_exit), dim3(p.blocks2),
+                            dim3(p.threads2), args, lds, s);
         if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
     }
-    if (direct)
-        if (int jr = join(nseg - 1)) return jr;
-    e = hipGetLastError();
-    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_match2 launch");
+    if (b.out_first) {
+        // readout of the level-0 maps: one thread per chunk boundary and pair
+        const uint64_t bound = std::max<uint64_t>((uint64_t)p.max_tiles * kWave2 * p.slots,
+                                                  (uint64_t)p.nch + 1);
+        const MapOut mo{b.out_first, b.out_start, b.out_end, b.out_cap};
+        hipLaunchKernelGGL(k_decode_maps, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s,
+                           a, mo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "k_decode_maps launch");
+    }
+    return DFA_OK;
 }
 
 int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
@@ -1751,8 +1624,6 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(3, 4, false), match2_kernel(3, 4, true),
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
-                         match2_kernel(5, 2, false), match2_kernel(5, 2, true),
-                         match2_kernel(5, 4, false), match2_kernel(5, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(4),
                          round_kernel(1, 2, false), round_kernel(1, 4, false),
                          round_kernel(2, 2, false), round_kernel(2, 4, false),

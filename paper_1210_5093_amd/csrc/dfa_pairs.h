@@ -19,11 +19,10 @@ __device__ __forceinline__ uint32_t lds_ld(uint32_t addr) {
     return *(lds_u16_t *)(size_t)addr;
 }
 
-// Code streams of 16-bit codes: layout 2 (one symbol per code) and the
-// three-symbol table (L = 5, class-major like layout 2); every other L reads
-// one-byte codes.
+// Code streams of 16-bit codes: layout 2 (one symbol per code); every other
+// L reads one-byte codes.
 template <int L>
-constexpr bool kWideCodes = L == 2 || L == 5;
+constexpr bool kWideCodes = L == 2;
 
 // state_offset + selected byte (one-byte codes) or 16-bit word of w.
 template <int L, int K>

@@ -43,6 +43,7 @@ struct Request {
     const uint8_t *in;
     size_t len;
     uint64_t cost;   // admitted bytes: input + arena estimate
+    hipEvent_t ready = nullptr;   // recorded on the producer's stream at submit, or none
 };
 
 struct Slot {
@@ -83,6 +84,7 @@ struct dfa_server {
     int error = DFA_OK;
     std::thread worker;
     dfa_server_stats_t stats{};
+    std::vector<hipEvent_t> free_events;   // producer-stream events for reuse
 };
 
 namespace {
@@ -92,6 +94,27 @@ uint64_t request_cost(const dfa_t *d, size_t len) {
     // (an upper bound)
     const uint64_t stride = (std::max<uint32_t>(d->setmax_host[1], 1u) + 7u) & ~7u;
     return 3ull * len + 64 + ((uint64_t)len / 1024 + 2) * stride * 2 * 2;
+}
+
+// Would the request, alone in a batch, fit a slot's arena and staging?  The
+// dispatcher shrinks a batch that does not fit down to its first request, so
+// a request that passes this test is always run.
+bool fits_a_slot(const dfa_server *srv, const dfa_t *d, const uint8_t *in, size_t len) {
+    const dfa_t *ds[1] = {d};
+    const uint8_t *ins[1] = {in};
+    const size_t lens[1] = {len};
+    const size_t staging = std::min<size_t>(srv->opts.slot_bytes, 64u << 20);
+    const bool packed = batch2_supported(ds, 1) &&
+                        (srv->opts.lookahead >= 2 || len >= (256ull << 20));
+    if (packed) {
+        Batch2Plan p2;
+        if (plan_batch2(ds, ins, lens, 1, 0, std::max<uint32_t>(srv->opts.lookahead, 1u), &p2))
+            return false;
+        return p2.total_bytes <= srv->opts.slot_bytes && p2.desc_bytes <= staging;
+    }
+    BatchPlan p;
+    if (plan_batch(ds, ins, lens, 1, 0, &p)) return false;
+    return p.total_bytes <= srv->opts.slot_bytes && p.desc_bytes <= staging;
 }
 
 void publish(dfa_server *srv, Slot &sl) {
@@ -146,6 +169,12 @@ int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *
         *fits = false;
         return DFA_OK;
     }
+    // inputs produced on the clients' streams: wait for them on this stream
+    for (const Request &r : reqs)
+        if (r.ready) {
+            hipError_t we = hipStreamWaitEvent(sl.stream, r.ready, 0);
+            if (we != hipSuccess) return hip_fail(we, "server: wait for the producer stream");
+        }
     std::memcpy(sl.staging, packed ? plan2.desc.data() : plan.desc.data(), desc_bytes);
     hipError_t e = hipMemcpyAsync(sl.arena, sl.staging, desc_bytes, hipMemcpyHostToDevice,
                                   sl.stream);
@@ -159,6 +188,13 @@ int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *
     if (e != hipSuccess) return hip_fail(e, "server: result readback");
     sl.reqs = std::move(reqs);
     sl.busy = true;
+    // the waits are enqueued: the producer events can be recorded again
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (Request &r : sl.reqs)
+        if (r.ready) {
+            srv->free_events.push_back(r.ready);
+            r.ready = nullptr;
+        }
     return DFA_OK;
 }
 
@@ -184,6 +220,7 @@ void dispatcher(dfa_server *srv) {
         std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->stop && srv->pending.empty() && !any_busy) break;
         if (srv->stop && srv->error) break;
+        bool admitted = false;
         for (auto &sl : srv->slots) {
             if (sl.busy || srv->pending.empty()) continue;
             std::vector<Request> take;
@@ -223,6 +260,7 @@ void dispatcher(dfa_server *srv) {
                 srv->stop = true;
                 break;
             }
+            admitted = true;
             sl.cost = 0;
             for (auto &r : take) sl.cost += r.cost;
             uint64_t back_cost = 0;
@@ -233,9 +271,10 @@ void dispatcher(dfa_server *srv) {
             srv->inflight_bytes -= back_cost;
             srv->inflight_reqs -= (uint32_t)put_back.size();
         }
-        if (srv->pending.empty() || std::all_of(srv->slots.begin(), srv->slots.end(),
-                                                [](const Slot &s) { return s.busy; })) {
-            // wait briefly for submissions or completions
+        if (!admitted) {
+            // nothing to launch (no request, no free slot, or the budget or
+            // in-flight cap holds the next request back until a batch
+            // completes): wait briefly for submissions or completions
             srv->cv_submit.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 200));
         }
     }
@@ -289,28 +328,66 @@ extern "C" int dfa_server_register(dfa_server_t *srv, const dfa_t *d, uint32_t *
     return DFA_OK;
 }
 
-extern "C" int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
-                                 uint64_t *ticket) {
+namespace {
+int submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
+           hipStream_t producer, bool after, uint64_t *ticket) {
     if (!srv || !ticket || (len && !d_input)) return fail(DFA_E_INVAL, "dfa_server_submit: NULL argument");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->error) return srv->error;
-    if (srv->stop) return fail(DFA_E_INVAL, "dfa_server_submit: server is stopping");
-    if (id >= srv->dfas.size()) return fail(DFA_E_INVAL, "dfa_server_submit: unknown DFA id");
+    const dfa_t *d = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->error) return srv->error;
+        if (srv->stop) return fail(DFA_E_INVAL, "dfa_server_submit: server is stopping");
+        if (id >= srv->dfas.size()) return fail(DFA_E_INVAL, "dfa_server_submit: unknown DFA id");
+        d = srv->dfas[id];
+    }
     Request r;
-    r.submit_ns = now_ns();
-    r.ticket = srv->next_ticket++;
     r.id = id;
     r.in = d_input;
     r.len = len;
-    r.cost = request_cost(srv->dfas[id], len);
+    r.cost = request_cost(d, len);
     if (r.cost > srv->opts.budget_bytes)
         return fail(DFA_E_TOOBIG, "dfa_server_submit: request exceeds the memory budget");
+    if (!fits_a_slot(srv, d, d_input, len))
+        return fail(DFA_E_TOOBIG, "dfa_server_submit: request exceeds a slot's arena (slot_bytes)");
+    if (after) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (!srv->free_events.empty()) {
+                r.ready = srv->free_events.back();
+                srv->free_events.pop_back();
+            }
+        }
+        hipError_t e = r.ready ? hipSuccess
+                               : hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r.ready, producer);
+        if (e != hipSuccess) {
+            if (r.ready) {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->free_events.push_back(r.ready);
+            }
+            return hip_fail(e, "dfa_server_submit_after: hipEventRecord");
+        }
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    r.submit_ns = now_ns();
+    r.ticket = srv->next_ticket++;
     srv->pending.push_back(r);
     srv->stats.submitted++;
     srv->stats.bytes += len;
     *ticket = r.ticket;
     srv->cv_submit.notify_one();
     return DFA_OK;
+}
+}  // namespace
+
+extern "C" int dfa_server_submit(dfa_server_t *srv, uint32_t id, const uint8_t *d_input, size_t len,
+                                 uint64_t *ticket) {
+    return submit(srv, id, d_input, len, nullptr, false, ticket);
+}
+
+extern "C" int dfa_server_submit_after(dfa_server_t *srv, uint32_t id, const uint8_t *d_input,
+                                       size_t len, void *producer_stream, uint64_t *ticket) {
+    return submit(srv, id, d_input, len, (hipStream_t)producer_stream, true, ticket);
 }
 
 extern "C" int dfa_server_poll(dfa_server_t *srv, uint64_t ticket, dfa_result_t *out) {
@@ -372,6 +449,9 @@ extern "C" void dfa_server_destroy(dfa_server_t *srv) {
         srv->cv_submit.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
+    for (auto &r : srv->pending)
+        if (r.ready) (void)hipEventDestroy(r.ready);
+    for (hipEvent_t ev : srv->free_events) (void)hipEventDestroy(ev);
     for (auto &sl : srv->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);

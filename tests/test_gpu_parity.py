@@ -161,7 +161,7 @@ def test_c2_full_size_bench_configuration(dfa_mod):
     (6, 1024, {}),
     (5, 2048, {}),
     (5, 2048, {"interleave": True, "rounds": 2}),
-    (5, 1536, {}),                        # three-symbol steps
+    (5, 1536, {}),                        # chunks of a multiple of 48
     (6, 1024, {"chunk_lanes": True}),
 ])
 def test_c2_full_size_tuned_settings(dfa_mod, look, chunk, kw):
@@ -574,46 +574,12 @@ def test_compose_tree_group_edges(dfa_mod, nch, look):
     d.close()
 
 
-# ---------------------------------------------------------------------------
-# Segmented pipeline: translation of segment k + 1 on a second stream while
-# the matcher walks segment k.  Forced segment counts, boundary states, and a
-# byte outside Sigma in the last segment (its flag reaches the result through
-# the top composition level).
-# ---------------------------------------------------------------------------
-@pytest.mark.parametrize("segs", [2, 3, 4])
-@pytest.mark.parametrize("look", [1, 4])
-def test_segmented_pipeline(dfa_mod, monkeypatch, segs, look):
-    import torch
-    monkeypatch.setenv("DFA_SEGMENTS", str(segs))
-    w = configs.c2_dfa()
-    C = 1024
-    n = 9 * (1 << 20) + 333
-    x = configs.c2_input(n, seed=segs * 10 + look).copy()
-    probes = list(range(0, n + 1, 64 * C))
-    fin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
-    d = dfa_mod.DFA.from_workload(w)
-    dev = torch.from_numpy(x).to("cuda")
-    res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=C, lookahead=look, boundaries=True)
-    torch.cuda.synchronize()
-    assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
-    b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
-    assert np.array_equal(b[np.array(probes) // C], ps.astype(np.int64))
-    x[n - 100] = ord("#")
-    res, _ = dfa_mod.dfa_match_ex(d, torch.from_numpy(x).to("cuda"), chunk_len=C, lookahead=look)
-    torch.cuda.synchronize()
-    assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
-    d.close()
-
-
-@pytest.mark.parametrize("fork", ["0", "1"])
 @pytest.mark.parametrize("look,single", [(1, False), (5, False), (5, True), (3, True)])
-def test_translation_stream(dfa_mod, monkeypatch, fork, look, single):
-    """The translation (or, for direct tables, validation) pass on a second
-    stream beside the scan, or on the caller's stream (DFA_FORK=0): results,
+def test_translation_pass(dfa_mod, look, single):
+    """The translation (or, for direct tables, validation) pass: results,
     boundaries, a byte outside Sigma in the middle and at the very end, and a
     clean call after a flagged one on the same workspace."""
     import torch
-    monkeypatch.setenv("DFA_FORK", fork)
     w = configs.c2_dfa()
     C = 2048
     n = 6 * (1 << 20) + 4096 * 3
@@ -640,23 +606,6 @@ def test_translation_stream(dfa_mod, monkeypatch, fork, look, single):
     res, _ = dfa_mod.dfa_match_ex(d, dev, chunk_len=C, lookahead=look, single_step=single)
     torch.cuda.synchronize()
     assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
-    d.close()
-
-
-def test_segmented_pipeline_large(dfa_mod, monkeypatch):
-    """Two segments on a 96 MiB input with the planner's chunk length."""
-    import torch
-    monkeypatch.setenv("DFA_SEGMENTS", "2")
-    w = configs.c2_dfa()
-    n = 96 << 20
-    x = configs.c2_input(n, seed=77)
-    fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
-    d = dfa_mod.DFA.from_workload(w)
-    dev = torch.from_numpy(x).to("cuda")
-    for look in (1, 5):
-        res, _ = dfa_mod.dfa_match_ex(d, dev, lookahead=look)
-        torch.cuda.synchronize()
-        assert dfa_mod.result_tuple(res)[:3] == (fin, acc, 0), look
     d.close()
 
 
@@ -716,9 +665,16 @@ def test_direct_table_full_ascii_window(dfa_mod):
 @pytest.mark.parametrize("offset", [0, 4, 8])
 def test_direct_table_early_exit_c3_protein(dfa_mod, offset):
     """Rows of 50 bytes (the absorbing bitmap is then indexed in 2-byte units),
-    early exit on and off; a misaligned view takes the translating path."""
+    early exit on and off; a misaligned view takes the translating path.  Both
+    1297/1298-state DFAs: the early-sink one (walks absorbed within a few KiB)
+    and the configured one (never absorbed)."""
     import torch
-    w = configs.c3_protein_dfa()
+    for seed in (configs.C3_EARLY_SINK_SEED, configs.C3_PATTERN_SEED):
+        direct_table_early_exit_case(dfa_mod, configs.c3_protein_dfa(seed), offset)
+
+
+def direct_table_early_exit_case(dfa_mod, w, offset):
+    import torch
     n = 3 << 20
     x = configs.c3_protein_input(n + offset)[offset:]
     probes = list(range(0, n + 1, 4096))
@@ -811,23 +767,22 @@ def test_two_symbol_steps_random_small_alphabets(dfa_mod):
 
 
 # ---------------------------------------------------------------------------
-# Three-symbol steps (class-major columns of delta(delta(delta(s, a), b), c)
-# over the distinct class-string functions; one 16-bit code per three input
-# bytes): every remainder of the length mod 3 and 48, ragged last chunks,
-# boundary states, bytes outside Sigma at each place of a code, early exit,
-# misaligned input, and DFA_MATCH_TWO_STEP on the same inputs.
+# Two-symbol steps at chunk lengths of a multiple of 48 and 32: every
+# remainder of the length mod 2, 3 and 48, ragged last chunks, boundary
+# states, bytes outside Sigma at either place of a pair code, early exit,
+# misaligned input and small random alphabets.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [1, 2, 3, 47, 48, 49, 1535, 1536, 1537, 100_003, (3 << 20) + 2])
 @pytest.mark.parametrize("look", [1, 5])
-def test_three_symbol_steps_lengths(dfa_mod, n, look):
+def test_pair_steps_lengths(dfa_mod, n, look):
     w = configs.c2_dfa()
     x = configs.c2_input(n, seed=90 + n % 97)
     d = dfa_mod.DFA.from_workload(w)
-    assert d.info().triple_columns > 0
+    assert d.info().pair_columns > 0
     for chunk in (0, 1536, 3072):
         plan = dfa_mod.dfa_plan(d, n, chunk, look)
-        if plan.kernel == 1:   # the planner's own lengths keep two symbols per step
-            assert plan.symbols_per_step == (2 if chunk == 0 else 3), chunk
+        if plan.kernel == 1:
+            assert plan.symbols_per_step == 2, chunk
         check(dfa_mod, w, x, chunk=chunk, lookahead=look)
     d.close()
 
@@ -835,15 +790,15 @@ def test_three_symbol_steps_lengths(dfa_mod, n, look):
 @pytest.mark.parametrize("byte", [ord("J"), 0x80, 0xC1])
 @pytest.mark.parametrize("pos", [0, 1, 2, 3, 46, 47, 48, 1535, 1536, 99_999, 100_000, 100_001,
                                  100_002])
-def test_three_symbol_steps_invalid_bytes(dfa_mod, byte, pos):
-    """Bytes outside Sigma below and above 128 as the first, second and third
-    byte of a code, at chunk and 48-byte unit edges and in the short last code."""
+def test_pair_steps_invalid_bytes(dfa_mod, byte, pos):
+    """Bytes outside Sigma below and above 128 as the first and second byte of
+    a code, at chunk and 48-byte edges and in the short last code."""
     w = configs.c2_dfa()
     x = configs.c2_input(100_003).copy()
     x[pos] = byte
     d = dfa_mod.DFA.from_workload(w)
     for look in (3, 5):
-        assert dfa_mod.dfa_plan(d, x.size, 1536, look).symbols_per_step == 3
+        assert dfa_mod.dfa_plan(d, x.size, 1536, look).symbols_per_step == 2
         assert gpu_run(dfa_mod, d, x, chunk=1536, lookahead=look, boundaries=False)[2] & \
             dfa_mod.FLAG_SYMBOL
     x[pos] = ord("A")
@@ -854,7 +809,7 @@ def test_three_symbol_steps_invalid_bytes(dfa_mod, byte, pos):
 
 
 @pytest.mark.parametrize("seed,contains", [(32, True), (32, False), (7, False), (7, True)])
-def test_three_symbol_steps_early_exit_and_other_dfas(dfa_mod, seed, contains):
+def test_pair_steps_1536_early_exit_and_other_dfas(dfa_mod, seed, contains):
     import torch
     w = from_pattern(patterns.pattern_dfa(seed, contains=contains))
     d = dfa_mod.DFA.from_workload(w)
@@ -865,11 +820,9 @@ def test_three_symbol_steps_early_exit_and_other_dfas(dfa_mod, seed, contains):
     acc = oracle.accepts(fin, w.accepting)
     dev = torch.from_numpy(x).to("cuda")
     say(f"pattern {seed} contains={contains}: Q={w.num_states} "
-        f"triple columns {d.info().triple_columns}")
+        f"pair columns {d.info().pair_columns}")
     for ex in (False, True):
         for look in (1, 3, 5):
-            if d.info().triple_columns:
-                assert dfa_mod.dfa_plan(d, n, 1536, look, early_exit=ex).symbols_per_step == 3
             res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=1536, lookahead=look,
                                             boundaries=True, early_exit=ex)
             torch.cuda.synchronize()
@@ -880,7 +833,7 @@ def test_three_symbol_steps_early_exit_and_other_dfas(dfa_mod, seed, contains):
 
 
 @pytest.mark.parametrize("shift", [1, 5, 16])
-def test_three_symbol_steps_misaligned_input(dfa_mod, shift):
+def test_pair_steps_misaligned_input(dfa_mod, shift):
     import torch
     w = configs.c2_dfa()
     n = (2 << 20) + 5
@@ -898,34 +851,18 @@ def test_three_symbol_steps_misaligned_input(dfa_mod, shift):
     d.close()
 
 
-def test_two_step_flag_keeps_pairs(dfa_mod):
-    import torch
-    w = configs.c2_dfa()
-    n = (4 << 20) + 11
-    x = configs.c2_input(n, seed=96)
-    fin, _ = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x)
-    d = dfa_mod.DFA.from_workload(w)
-    dev = torch.from_numpy(x).to("cuda")
-    for two, steps in ((False, 3), (True, 2)):
-        assert dfa_mod.dfa_plan(d, n, 1536, 5, two_step=two).symbols_per_step == steps
-        res, _ = dfa_mod.dfa_match_ex(d, dev, chunk_len=1536, lookahead=5, two_step=two)
-        torch.cuda.synchronize()
-        assert dfa_mod.result_tuple(res)[:3] == (fin, oracle.accepts(fin, w.accepting), 0)
-    d.close()
-
-
-def test_three_symbol_steps_random_small_alphabets(dfa_mod):
-    """Random byte-alphabet DFAs with 2..16 distinct columns (a triple table
-    when its distinct columns fit 64 KiB, none for 16 columns or more)."""
+def test_random_small_alphabets(dfa_mod):
+    """Random byte-alphabet DFAs with 2..16 distinct columns (a pair table for
+    up to 10 of them)."""
     rng = np.random.default_rng(78)
     for t, k in enumerate([2, 3, 4, 5, 6, 8, 12, 16]):
         nq = int(rng.integers(2, 200))
         w = column_dfa(800 + t, 900 + t, nq, k)
         d = dfa_mod.DFA.from_workload(w)
-        tc = d.info().triple_columns
+        pc = d.info().pair_columns
         d.close()
         x = streams.uniform_bytes(1000 + t, int(rng.integers(50_000, 400_000)))
-        say(f"random dfa {t}: Q={nq} K={k} triple columns {tc}")
+        say(f"random dfa {t}: Q={nq} K={k} pair columns {pc}")
         check(dfa_mod, w, x, chunk=1536, lookahead=2)
         check(dfa_mod, w, x, chunk=4800, lookahead=1)
 
@@ -1077,7 +1014,7 @@ def test_chunk_lanes_match_oracle(dfa_mod, case):
                 bad = np.nonzero(bb != ps)[0]
                 assert bad.size == 0, (chunk, look, single, bad[:8])
     say(f"{case}: chunk lanes used in {used} settings")
-    if case in ("c2", "c3p", "anchored", "c1"):
+    if case in ("c2", "anchored", "c1"):
         assert used > 0
     d.close()
 

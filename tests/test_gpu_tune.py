@@ -40,16 +40,16 @@ def test_autotuned_setting_matches_oracle(dfa_mod, which, n):
     fin, acc = oracle.membership(w.delta, w.byte_to_symbol, w.q0, w.accepting, x)
     d = dfa_mod.DFA.from_workload(w)
     dev = torch.from_numpy(x).to("cuda")
-    r, chunk, ms, ex, rounds, single, ilv, lanes, two = dfa_mod.dfa_autotune(d, dev)
+    r, chunk, ms, ex, rounds, single, ilv, lanes = dfa_mod.dfa_autotune(d, dev)
     say(f"{which}: tuned r={r} chunk={chunk} early_exit={ex} rounds={rounds} "
-        f"single_step={single} interleave={ilv} chunk_lanes={lanes} two_step={two} {ms:.3f} ms")
+        f"single_step={single} interleave={ilv} chunk_lanes={lanes} {ms:.3f} ms")
     assert 1 <= r <= 10 and ms > 0
     res, _ = dfa_mod.dfa_match_ex(d, dev, lookahead=dfa_mod.DFA_LOOKAHEAD_AUTO)
     torch.cuda.synchronize()
     assert dfa_mod.result_tuple(res)[:3] == (fin, int(acc), 0)
     auto = dfa_mod.dfa_plan(d, n, 0, dfa_mod.DFA_LOOKAHEAD_AUTO)
     explicit = dfa_mod.dfa_plan(d, n, chunk, r, rounds=rounds, early_exit=ex, single_step=single,
-                                interleave=ilv, chunk_lanes=lanes, two_step=two)
+                                interleave=ilv, chunk_lanes=lanes)
     assert (auto.chunk_len, auto.lookahead, auto.kernel, auto.rounds, auto.symbols_per_step,
             auto.interleaved, auto.chunk_lanes) == \
         (explicit.chunk_len, explicit.lookahead, explicit.kernel, explicit.rounds,

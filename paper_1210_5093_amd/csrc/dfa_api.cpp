@@ -134,7 +134,16 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0,
            bits_off = 0, mem_off = 0, cset_off = 0, round_off = 0;
     if (p.packed && len) {
-        uint64_t code_stream = ((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64;
+        // the translated stream: none when the matcher reads the raw input (a
+        // direct table, 16-byte aligned input, linear layout), one byte per
+        // two input bytes for pair codes (whole 16-byte units of 32 bytes),
+        // else code_bytes per byte
+        const bool raw = !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
+                         (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+        uint64_t code_stream =
+            raw ? 64
+                : p.pairs ? ((uint64_t)len + 32) / 32 * 16 + 64
+                          : ((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64;
         if (p.ilv_nblk)   // whole groups of 64 chunks of ilv_nblk blocks each
             code_stream = std::max<uint64_t>(
                 code_stream, ((uint64_t)p.nch + 63) / 64 * 64 * p.ilv_nblk * 16 + 64);
@@ -250,6 +259,13 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     return DFA_OK;
 }
 }  // namespace
+
+int match_in_region(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
+                    const dfa_match_opts_t *opts, hipStream_t s, uint32_t *d_result,
+                    uint8_t *region, size_t region_bytes) {
+    return run_match(d, d_in, len, start, opts, s, d_result, nullptr, nullptr, region,
+                     region_bytes);
+}
 
 }  // namespace dfaspec
 

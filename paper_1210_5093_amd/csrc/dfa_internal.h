@@ -118,6 +118,13 @@ namespace dfaspec {
 int fail(int status, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
+// One membership test (dfa_match_ex's path) with every scratch buffer taken
+// from `region` (region_bytes of device memory); allocates nothing and
+// returns DFA_E_TOOBIG when the plan needs more (dfa_api.cpp).
+int match_in_region(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
+                    const dfa_match_opts_t *opts, hipStream_t s, uint32_t *d_result,
+                    uint8_t *region, size_t region_bytes);
+
 // Kernel launchers (dfa_kernels.hip).
 struct Workspace;
 constexpr uint32_t kMaxLevels = 40;  // fan-in >= 2 and < 2^32 chunks need at most 32

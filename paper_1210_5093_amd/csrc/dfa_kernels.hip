@@ -448,7 +448,11 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // chunk-interleaved codes: the packed matcher's chunks are whole blocks
     // of 64 consecutive chunks' code streams; the window pass reads codes
     // across chunk ends, so it keeps the linear stream
-    if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) &&
+    // (one chunk per lane over a direct table's raw input keeps the input's
+    // own order: each lane reads its chunk)
+    const bool raw_lanes = (flags & DFA_MATCH_CHUNK_LANES) && !(flags & DFA_MATCH_INTERLEAVE) &&
+                           d->dev.direct && !p->pairs;
+    if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) && !raw_lanes &&
         p->lookahead != 2 && chunk % 32 == 0) {
         const uint64_t bytes_per_chunk = p->pairs ? chunk / 2 : chunk * p->code_bytes;
         p->ilv_nblk = (uint32_t)(bytes_per_chunk / 16);
@@ -459,8 +463,9 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     {
         uint32_t set_bound = std::max<uint32_t>(d->setmax_host[p->lookahead == 0 ? 0 : 1], 1u);
         if (p->lookahead == 3) set_bound = d->mset_max[std::min(p->r, d->dev.r0)];
-        p->chunk_lanes = (flags & DFA_MATCH_CHUNK_LANES) && p->ilv_nblk && !p->early_exit &&
-                         p->lookahead != 2 && set_bound <= 128;
+        p->chunk_lanes = (flags & DFA_MATCH_CHUNK_LANES) && (p->ilv_nblk || raw_lanes) &&
+                         !p->early_exit && p->lookahead != 2 && chunk % 32 == 0 &&
+                         set_bound <= 128;
     }
     // merged walks: two rounds unless asked otherwise; the last round must
     // start inside a chunk

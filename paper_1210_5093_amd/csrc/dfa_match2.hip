@@ -981,6 +981,9 @@ struct RoundArgs {
     uint32_t *out_cnt;         // [kRegions] its counters (zero before the first round)
 };
 
+template <int S>
+constexpr int kRoundAhead = S >= 4 ? 2 : 4;
+
 // EXIT: the DFA has absorbing states; a wave stops once all its walks are in one.
 template <int L, int S, bool EXIT>
 __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, RoundArgs m) {
@@ -1065,7 +1068,10 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
         };
         // a wave stops walking once all its walks are absorbing (checked every
         // four blocks); their end states are then final
-        walk_var<L, S, EXIT>(codes16, o16, len_of, st, EXIT ? a.d.abs_off : 0u, a.d.abs_shift,
+        // blocks of prefetch: the last round's walks run the rest of their
+        // chunks (thousands of blocks) and each lane's S walks read S
+        // unrelated code streams, so loads must be issued well ahead
+        walk_var<L, S, EXIT, kRoundAhead<S>>(codes16, o16, len_of, st, EXIT ? a.d.abs_off : 0u, a.d.abs_shift,
                              live, a.ilv_nblk ? 64u : 1u);
 
         // end states; done = the chunk ended or the state is absorbing
@@ -1200,8 +1206,11 @@ constexpr uint32_t kCwDistinct = 4;
 // Walk NS chains of one chunk over ncodes codes (whole 16-byte blocks from
 // unit u0 on, `stride` units apart; the last block may be partial).  A lane
 // walks one chunk, so one block lasts only 16 (or 8) steps: kCwAhead blocks
-// are loaded ahead to cover the memory latency.
-constexpr int kCwAhead = 4;
+// are loaded ahead to cover the memory latency.  The raw input (L = 3) is
+// read chunk by chunk, each lane from its own chunk: eight blocks ahead make
+// every lane's loads whole 128-byte lines, used before they leave the caches.
+template <int L>
+constexpr int kCwAhead = L == 3 ? 8 : 4;
 
 template <int L, int NS>
 __device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16, uint32_t u0,
@@ -1209,19 +1218,19 @@ __device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16
                                                uint32_t (&st)[NS]) {
     constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
     const uint32_t whole = ncodes / kPer16;
-    uint4 ring[kCwAhead];
+    uint4 ring[kCwAhead<L>];
 #pragma unroll
-    for (int k = 0; k < kCwAhead; ++k)
+    for (int k = 0; k < kCwAhead<L>; ++k)
         ring[k] = (uint32_t)k < whole ? codes16[(size_t)u0 + (size_t)k * stride] : make_uint4(0, 0, 0, 0);
     for (uint32_t b = 0; b < whole; ++b) {
         const uint4 cur = ring[0];
 #pragma unroll
-        for (int k = 0; k + 1 < kCwAhead; ++k) ring[k] = ring[k + 1];
-        if (b + kCwAhead < whole) ring[kCwAhead - 1] = codes16[(size_t)u0 + (size_t)(b + kCwAhead) * stride];
+        for (int k = 0; k + 1 < kCwAhead<L>; ++k) ring[k] = ring[k + 1];
+        if (b + kCwAhead<L> < whole) ring[kCwAhead<L> - 1] = codes16[(size_t)u0 + (size_t)(b + kCwAhead<L>) * stride];
         const uint32_t w4[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const uint32_t w = w4[q];
+            const uint32_t w = word_codes<L>(w4[q]);
             if constexpr (L != 2) {
 #pragma unroll
                 for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<1, 0>(st[j], w));
@@ -1241,10 +1250,18 @@ __device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16
     }
     const uint32_t rest = ncodes - whole * kPer16;
     if (rest) {
-        const uint4 v = codes16[(size_t)u0 + (size_t)whole * stride];
-        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        // the last, partial block: a translated stream is padded to whole
+        // blocks; raw input (L = 3) is read byte by byte up to its end
+        uint32_t w4[4] = {0, 0, 0, 0};
+        if constexpr (L == 3) {
+            const uint8_t *p = reinterpret_cast<const uint8_t *>(codes16 + u0 + (size_t)whole * stride);
+            for (uint32_t t = 0; t < rest; ++t) w4[t >> 2] |= (uint32_t)p[t] << (8 * (t & 3));
+        } else {
+            const uint4 v = codes16[(size_t)u0 + (size_t)whole * stride];
+            w4[0] = v.x; w4[1] = v.y; w4[2] = v.z; w4[3] = v.w;
+        }
         for (uint32_t t = 0; t < rest; ++t) {
-            const uint32_t w = w4[t / (kPer16 / 4)];
+            const uint32_t w = word_codes<L>(w4[t / (kPer16 / 4)]);
             const uint32_t code = L == 2 ? (w >> (16 * (t & 1))) & 0xFFFFu : (w >> (8 * (t & 3))) & 0xFFu;
 #pragma unroll
             for (int j = 0; j < NS; ++j) st[j] = lds_ld(st[j] + code);
@@ -1256,14 +1273,20 @@ struct ChunkWalkArgs {
     uint32_t prefix;          // codes walked by every start state (multiple of 16)
 };
 
+// L = 3: the raw input (direct table) in its own order, 16-byte aligned,
+// read by each lane from its chunk (stride 1); otherwise interleaved codes
+// (stride 64).  Workgroups of up to 1024 threads: with a table of tens of
+// KiB staged per workgroup, large workgroups keep 32 waves (32 x 64 walks)
+// on each CU.
 template <int L>
-__global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs cw) {
+__global__ __launch_bounds__(1024) void k_chunk_walk(Match2Args a, ChunkWalkArgs cw) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
     constexpr uint32_t kSym = L == 4 ? 2u : 1u;
     const uint32_t R = L != 2 ? a.d.rowbytes : 2u;
     const uint4 *codes16 = reinterpret_cast<const uint4 *>(a.codes);
+    const uint32_t stride = a.ilv_nblk ? 64u : 1u;
     const uint32_t per_chunk = (uint32_t)(a.chunk / (kPer16 * kSym));   // blocks per chunk
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nch;
          c += gridDim.x * blockDim.x) {
@@ -1283,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs 
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 st[j] = R * (b0 + j < m ? pair_start(a, c, P0 + b0 + j) : pair_start(a, c, P0));
-            walk_one_chunk<L, 4>(codes16, u0, 64u, pre, st);
+            walk_one_chunk<L, 4>(codes16, u0, stride, pre, st);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (b0 + j >= m) break;
@@ -1301,19 +1324,19 @@ __global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs 
         if (!spill) {
             // phase 2: the distinct states to the chunk's end
             const uint32_t rest = ncodes - pre;
-            const uint32_t ur = u0 + (pre / kPer16) * 64u;   // pre is whole blocks
+            const uint32_t ur = u0 + (pre / kPer16) * stride;   // pre is whole blocks
             if (rest) {
                 if (nd == 1) {
                     uint32_t st[1] = {dst[0]};
-                    walk_one_chunk<L, 1>(codes16, ur, 64u, rest, st);
+                    walk_one_chunk<L, 1>(codes16, ur, stride, rest, st);
                     dst[0] = st[0];
                 } else if (nd == 2) {
                     uint32_t st[2] = {dst[0], dst[1]};
-                    walk_one_chunk<L, 2>(codes16, ur, 64u, rest, st);
+                    walk_one_chunk<L, 2>(codes16, ur, stride, rest, st);
                     dst[0] = st[0]; dst[1] = st[1];
                 } else {
                     uint32_t st[4] = {dst[0], dst[1], nd > 2 ? dst[2] : dst[0], nd > 3 ? dst[3] : dst[0]};
-                    walk_one_chunk<L, 4>(codes16, ur, 64u, rest, st);
+                    walk_one_chunk<L, 4>(codes16, ur, stride, rest, st);
                     dst[0] = st[0]; dst[1] = st[1]; dst[2] = st[2]; dst[3] = st[3];
                 }
             }
@@ -1327,7 +1350,7 @@ __global__ __launch_bounds__(256) void k_chunk_walk(Match2Args a, ChunkWalkArgs 
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     st[j] = R * (b0 + j < m ? pair_start(a, c, P0 + b0 + j) : pair_start(a, c, P0));
-                walk_one_chunk<L, 4>(codes16, u0, 64u, ncodes, st);
+                walk_one_chunk<L, 4>(codes16, u0, stride, ncodes, st);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if (b0 + j < m) a.maps[P0 + b0 + j] = map_entry(a, c, st[j] / R);
@@ -1420,7 +1443,7 @@ const void *match2_kernel(uint32_t L, uint32_t slots, bool ex) {
 const void *chunk_walk_kernel(uint32_t L) {
     static const void *const tab[4] = {
         reinterpret_cast<const void *>(&k_chunk_walk<1>), reinterpret_cast<const void *>(&k_chunk_walk<2>),
-        reinterpret_cast<const void *>(&k_chunk_walk<1>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
+        reinterpret_cast<const void *>(&k_chunk_walk<3>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
     return tab[L - 1];
 }
 const void *round_kernel(uint32_t L, uint32_t slots, bool ex) {
@@ -1534,13 +1557,16 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     if (p.chunk_lanes) {
-        if (!p.ilv_nblk || L == 3 || p.lookahead == 2)
-            return fail(DFA_E_INVAL, "chunk lanes need interleaved codes and precomputed sets");
+        // (interleaved codes, the raw input, or a linear code stream when a
+        // direct table's input is not 16-byte aligned)
+        if (p.lookahead == 2)
+            return fail(DFA_E_INVAL, "chunk lanes need precomputed start sets");
         ChunkWalkArgs cw{kRound1Bytes};
         void *cargs[] = {&a, &cw};
-        const uint32_t blocks = std::max<uint32_t>(
-            1u, std::min<uint32_t>((p.nch + 255) / 256, p.blocks2 * (p.threads2 / 256)));
-        e = hipLaunchKernel(chunk_walk_kernel(L), dim3(blocks), dim3(256), cargs, lds, s);
+        const uint32_t tpb = p.threads2;
+        const uint32_t blocks =
+            std::max<uint32_t>(1u, std::min<uint32_t>((p.nch + tpb - 1) / tpb, p.blocks2));
+        e = hipLaunchKernel(chunk_walk_kernel(L), dim3(blocks), dim3(tpb), cargs, lds, s);
         if (e != hipSuccess) return hip_fail(e, "k_chunk_walk launch");
     } else if (p.rounds > 1) {
         if (p.early_exit || p.chunk % 32 != 0 || !b.cnt)
@@ -1624,7 +1650,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(3, 4, false), match2_kernel(3, 4, true),
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
-                         chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(4),
+                         chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(3),
+                         chunk_walk_kernel(4),
                          round_kernel(1, 2, false), round_kernel(1, 4, false),
                          round_kernel(2, 2, false), round_kernel(2, 4, false),
                          round_kernel(3, 2, false), round_kernel(3, 4, false),

@@ -242,7 +242,7 @@ __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
 // blocks; raw input (L = 3) is read byte by byte past its last whole block).
 // len_of recomputes a slot's length, so no per-slot length stays live through
 // the fast path.
-template <int L, int S, bool EXIT = false, typename LenFn>
+template <int L, int S, bool EXIT = false, int PF = 1, typename LenFn>
 __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
                                          const uint32_t (&o16)[S], LenFn len_of,
                                          uint32_t (&st)[S], uint32_t exit_base = 0,
@@ -257,7 +257,7 @@ __device__ __forceinline__ void walk_var(const uint4 *__restrict__ codes16,
         most = max(most, (len + kPer16 - 1) / kPer16);
     }
     if (common > 0)
-        walk_fast<L, S, EXIT>(codes16, o16, common, st, exit_base, exit_shift, live, stride);
+        walk_fast<L, S, EXIT, PF>(codes16, o16, common, st, exit_base, exit_shift, live, stride);
     for (uint32_t b = common; b < most; ++b) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {

@@ -22,6 +22,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include <sys/prctl.h>
 #include <time.h>
 
 #include "dfa_internal.h"
@@ -140,6 +141,37 @@ void publish(dfa_server *srv, Slot &sl) {
 // leaves the slot idle) if the batch does not fit the slot's arena.
 int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *fits) {
     *fits = true;
+    if (reqs.size() == 1) {
+        // a batch of one: the single-string path on the slot's stream, with
+        // the slot's arena as its scratch (no descriptors to plan or upload,
+        // the same kernels as dfa_match_ex)
+        const Request &r = reqs[0];
+        if (r.ready) {
+            hipError_t we = hipStreamWaitEvent(sl.stream, r.ready, 0);
+            if (we != hipSuccess) return hip_fail(we, "server: wait for the producer stream");
+        }
+        dfa_match_opts_t o{};
+        o.lookahead = std::max<uint32_t>(srv->opts.lookahead, 1u);
+        int rc = match_in_region(srv->dfas[r.id], r.in, r.len, DFA_Q0, &o, sl.stream,
+                                 sl.d_results, static_cast<uint8_t *>(sl.arena), sl.arena_bytes);
+        if (rc == DFA_OK) {
+            hipError_t e = hipMemcpyAsync(sl.h_results, sl.d_results, sizeof(dfa_result_t),
+                                          hipMemcpyDeviceToHost, sl.stream);
+            if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+            if (e != hipSuccess) return hip_fail(e, "server: result readback");
+            sl.reqs = std::move(reqs);
+            sl.busy = true;
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (Request &q : sl.reqs)
+                if (q.ready) {
+                    srv->free_events.push_back(q.ready);
+                    q.ready = nullptr;
+                }
+            return DFA_OK;
+        }
+        if (rc != DFA_E_TOOBIG) return rc;
+        // larger than the arena on this path: the batch path decides
+    }
     std::vector<const dfa_t *> ds(reqs.size());
     std::vector<const uint8_t *> ins(reqs.size());
     std::vector<size_t> lens(reqs.size());
@@ -200,6 +232,9 @@ int launch_on_slot(dfa_server *srv, Slot &sl, std::vector<Request> &reqs, bool *
 
 void dispatcher(dfa_server *srv) {
     (void)hipSetDevice(srv->device);
+    // the dispatcher sleeps in short waits between polls of its slots'
+    // events; the default timer slack (50 us) would stretch every wait
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
     while (true) {
         // 1. completions
         bool any_busy = false;
@@ -275,7 +310,7 @@ void dispatcher(dfa_server *srv) {
             // nothing to launch (no request, no free slot, or the budget or
             // in-flight cap holds the next request back until a batch
             // completes): wait briefly for submissions or completions
-            srv->cv_submit.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 200));
+            srv->cv_submit.wait_for(lk, std::chrono::microseconds(any_busy ? 5 : 200));
         }
     }
 }

@@ -1032,3 +1032,49 @@ def test_chunk_lanes_invalid_bytes(dfa_mod, pos):
         torch.cuda.synchronize()
         assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
     d.close()
+
+
+@pytest.mark.parametrize("which", ["c3p", "c2"])
+@pytest.mark.parametrize("offset", [0, 3])
+def test_chunk_lanes_over_raw_input(dfa_mod, which, offset):
+    """One chunk per lane over a direct table: each lane reads its own chunk of
+    the raw input (16-byte aligned; offset 3 takes a linear translated stream
+    instead).  Chunks of 32 bytes up with a ragged last chunk; every boundary
+    state and the state maps equal the oracle's."""
+    import torch
+    from test_gpu_maps import check_maps
+    if which == "c3p":
+        w = configs.c3_protein_dfa()
+        full = configs.c3_protein_input((3 << 20) + 21 + offset)
+    else:
+        w = configs.c2_dfa()
+        full = configs.c2_input((3 << 20) + 21 + offset, seed=66)
+    x = full[offset:]
+    buf = to_dev(full)
+    dev = buf[offset:]
+    d = dfa_mod.DFA.from_workload(w)
+    n = x.size
+    # (start sets of at most 128 states: r = 4 for the large protein DFA)
+    settings = ((32, 4), (1024, 4), (4096, 4), (65536, 4)) if which == "c3p" else \
+        ((32, 4), (1024, 4), (4096, 3), (65536, 2))
+    for chunk, look in settings:
+        plan = dfa_mod.dfa_plan(d, n, chunk, look, chunk_lanes=True, single_step=True)
+        assert plan.chunk_lanes == 1 and plan.interleaved == 0, (chunk, look)
+        res, bnd = dfa_mod.dfa_match_ex(d, dev, chunk_len=chunk, lookahead=look, boundaries=True,
+                                        chunk_lanes=True, single_step=True)
+        torch.cuda.synchronize()
+        probes = [min(i * chunk, n) for i in range(plan.num_chunks + 1)]
+        ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+        assert dfa_mod.result_tuple(res)[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+        b = bnd.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        bad = np.nonzero(b != ps)[0]
+        assert bad.size == 0, (chunk, look, bad[:8])
+        check_maps(dfa_mod, w, x, dev, d, chunk, look, expect=(ofin, oracle.accepts(ofin, w.accepting)),
+                   chunk_lanes=True, single_step=True)
+    x2 = x.copy()
+    x2[n - 5] = ord("#")
+    res, _ = dfa_mod.dfa_match_ex(d, to_dev(x2), chunk_len=1024, lookahead=4, chunk_lanes=True,
+                                  single_step=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
+    d.close()

@@ -81,7 +81,10 @@ def test_alone_equals_mix(dfa_mod):
     for k, (i, _, _, _) in enumerate(reqs):
         alone.append(srv.wait(srv.submit(ids[i], inputs[k][1])))
     srv.close()
-    assert mixed == alone
+    # the result (final state, accept bit, flags) is the same; the chunk count
+    # is a property of the path a batch took (a batch of one takes the
+    # single-string path)
+    assert [m[:3] for m in mixed] == [a[:3] for a in alone]
 
 
 def test_poll_before_and_after(dfa_mod):

@@ -511,8 +511,7 @@ def bench_batched(args, dfa, torch, stream) -> int:
         ok = records_match(got, expect) and records_match(got_run, expect) and \
             records_match(got_plain, expect)
         if not ok:
-            log("[bench] MISMATCH against the oracle")
-            return 1
+            raise SystemExit("[bench] MISMATCH against the oracle (batched)")
         line["cpu_baseline"] = {
             "value": round(total / t_cpu / 1e9, 4),
             "unit": "GB/s",
@@ -522,8 +521,7 @@ def bench_batched(args, dfa, torch, stream) -> int:
                       f"per pair on a pool of {threads} host threads",
         }
         line["matches_oracle"] = True
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 def percentile_ms(lat_ns, q):
@@ -563,75 +561,96 @@ def bench_served(args, dfa, torch, stream) -> int:
     cap_s = time.perf_counter() - t0
     capacity = nreq / cap_s
     rate = args.load * capacity
-    arrivals = configs.served_arrivals(nreq, rate)
     log(f"[bench] plain capacity {capacity:.0f} req/s ({buf.size / cap_s / 1e9:.1f} GB/s); "
         f"arrival rate {rate:.0f} req/s")
 
-    # served: open-loop submission at the arrival times
-    srv = dfa.Server()
-    sid = [srv.register(d) for d in ds]
-    done_ns = np.zeros(nreq, dtype=np.int64)
-    ticket_of = {}
-    got = [None] * nreq
-    start = time.monotonic_ns() + 2_000_000
-    arr_ns = start + (arrivals * 1e9).astype(np.int64)
-    k = 0
-    finished = 0
+    def run_served(rate):
+        """Open-loop submission at Poisson arrival times; returns latencies
+        (ns, measured requests), span (s), records and server stats."""
+        arrivals = configs.served_arrivals(nreq, rate)
+        srv = dfa.Server()
+        sid = [srv.register(d) for d in ds]
+        done_ns = np.zeros(nreq, dtype=np.int64)
+        ticket_of = {}
+        got = [None] * nreq
+        arr_ns = time.monotonic_ns() + 2_000_000 + (arrivals * 1e9).astype(np.int64)
+        k = 0
+        finished = 0
 
-    def take(records):
-        nonlocal finished
-        for t, r, _, dn in records:
-            j = ticket_of.pop(t)
-            done_ns[j] = dn
-            got[j] = (r[0], int(r[1]), r[2])
-            finished += 1
-    while k < nreq:
-        now = time.monotonic_ns()
-        while k < nreq and arr_ns[k] <= now:
-            ticket_of[srv.submit(sid[ids[k]], ins[k])] = k
-            k += 1
-        take(srv.drain())
-    while finished < nreq:
-        take(srv.drain())
-    stats = srv.stats()
-    srv.close()
-    lat = (done_ns - arr_ns)[nwarm:]
-    span = (done_ns[nwarm:].max() - arr_ns[nwarm]) * 1e-9
+        def take(records):
+            nonlocal finished
+            for t, r, _, dn in records:
+                j = ticket_of.pop(t)
+                done_ns[j] = dn
+                got[j] = (r[0], int(r[1]), r[2])
+                finished += 1
+        while k < nreq:
+            now = time.monotonic_ns()
+            while k < nreq and arr_ns[k] <= now:
+                ticket_of[srv.submit_ready(sid[ids[k]], ins[k])] = k
+                k += 1
+            take(srv.drain())
+        while finished < nreq:
+            take(srv.drain())
+        stats = srv.stats()
+        srv.close()
+        lat = (done_ns - arr_ns)[nwarm:]
+        span = (done_ns[nwarm:].max() - arr_ns[nwarm]) * 1e-9
+        return lat, span, got, stats
 
-    # plain FIFO under the same arrivals
-    p_done = np.zeros(nreq, dtype=np.int64)
-    evs = [None] * nreq
-    head = 0
-    start = time.monotonic_ns() + 2_000_000
-    p_arr = start + (arrivals * 1e9).astype(np.int64)
-    k = 0
-    while head < nreq:
-        now = time.monotonic_ns()
-        while k < nreq and p_arr[k] <= now:
-            dfa.dfa_match_ex(ds[ids[k]], ins[k], stream=stream, result=res_plain[k])
-            host_plain[k].copy_(res_plain[k], non_blocking=True)
-            e = torch.cuda.Event()
-            e.record(stream)
-            evs[k] = e
-            k += 1
-        while head < k and evs[head].query():
-            p_done[head] = time.monotonic_ns()
-            evs[head] = None
-            head += 1
-    p_lat = (p_done - p_arr)[nwarm:]
-    p_span = (p_done[nwarm:].max() - p_arr[nwarm]) * 1e-9
-    got_plain = [(int(a) & 0xFFFFFFFF, int(b), int(c)) for a, b, c, _ in host_plain.tolist()]
+    def run_fifo(rate):
+        """The plain method under the same arrivals: one dfa_match_ex per
+        request at its arrival, one stream, completions in FIFO order."""
+        arrivals = configs.served_arrivals(nreq, rate)
+        p_done = np.zeros(nreq, dtype=np.int64)
+        evs = [None] * nreq
+        head = 0
+        p_arr = time.monotonic_ns() + 2_000_000 + (arrivals * 1e9).astype(np.int64)
+        k = 0
+        while head < nreq:
+            now = time.monotonic_ns()
+            while k < nreq and p_arr[k] <= now:
+                dfa.dfa_match_ex(ds[ids[k]], ins[k], stream=stream, result=res_plain[k])
+                host_plain[k].copy_(res_plain[k], non_blocking=True)
+                e = torch.cuda.Event()
+                e.record(stream)
+                evs[k] = e
+                k += 1
+            while head < k and evs[head].query():
+                p_done[head] = time.monotonic_ns()
+                evs[head] = None
+                head += 1
+        p_lat = (p_done - p_arr)[nwarm:]
+        p_span = (p_done[nwarm:].max() - p_arr[nwarm]) * 1e-9
+        got_plain = [(int(a) & 0xFFFFFFFF, int(b), int(c)) for a, b, c, _ in host_plain.tolist()]
+        return p_lat, p_span, got_plain
+
+    lat, span, got, stats = run_served(rate)
+    p_lat, p_span, got_plain = run_fifo(rate)
+    load_sweep = []
+    for f in [float(v) for v in args.load_sweep.split(",") if v.strip()]:
+        l2, s2, g2, st2 = run_served(f * capacity)
+        pl2, ps2, gp2 = run_fifo(f * capacity)
+        if g2 != got or gp2 != got_plain:
+            raise SystemExit(f"[bench] served records at load {f} differ from the first run")
+        load_sweep.append({
+            "load": f, "arrival_rate_req_s": round(f * capacity, 1),
+            "served": {"req_s": round(nmeas / s2, 1), "p50_ms": percentile_ms(l2, 50),
+                       "p99_ms": percentile_ms(l2, 99), "batches": int(st2.batches)},
+            "plain_fifo": {"req_s": round(nmeas / ps2, 1), "p50_ms": percentile_ms(pl2, 50),
+                           "p99_ms": percentile_ms(pl2, 99)}})
+        log(f"[bench] load {f}: served p50 {load_sweep[-1]['served']['p50_ms']} p99 "
+            f"{load_sweep[-1]['served']['p99_ms']} ms; fifo p50 "
+            f"{load_sweep[-1]['plain_fifo']['p50_ms']} p99 {load_sweep[-1]['plain_fifo']['p99_ms']}")
 
     # closed-loop server capacity: everything submitted at once
     srv = dfa.Server()
     sid = [srv.register(d) for d in ds]
-    ticket_of.clear()
     t0 = time.monotonic_ns()
-    for j in range(nreq):
-        ticket_of[srv.submit(sid[ids[j]], ins[j])] = j
-    finished = 0
-    while finished < nreq:
-        take(srv.drain())
+    left = {srv.submit_ready(sid[ids[j]], ins[j]) for j in range(nreq)}
+    while left:
+        for t, _, _, _ in srv.drain():
+            left.discard(t)
     closed_s = (time.monotonic_ns() - t0) * 1e-9
     srv.close()
 
@@ -669,6 +688,7 @@ def bench_served(args, dfa, torch, stream) -> int:
                        "method": "one dfa_match_ex per request at its arrival, one stream, FIFO"},
         "closed_loop_capacity": {"GB/s": round(buf.size / closed_s / 1e9, 3),
                                  "req_s": round(nreq / closed_s, 1)},
+        "load_sweep": load_sweep,
         "roofline": {
             "bound": "lds",
             "kernel": "k_batch_match (served)",
@@ -687,8 +707,7 @@ def bench_served(args, dfa, torch, stream) -> int:
         expect = oracle_records([dfas_w[i] for i in ids], buf, offs, threads)
         t_cpu = time.perf_counter() - t0
         if not records_match(got, expect) or not records_match(got_plain, expect):
-            log("[bench] MISMATCH against the oracle")
-            return 1
+            raise SystemExit("[bench] MISMATCH against the oracle (served)")
         line["cpu_baseline"] = {
             "value": round(buf.size / t_cpu / 1e9, 4),
             "unit": "GB/s",
@@ -698,67 +717,13 @@ def bench_served(args, dfa, torch, stream) -> int:
                       f"(Algorithm 1) per request on a pool of {threads} host threads",
         }
         line["matches_oracle"] = True
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
-
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2a", "c3p", "c3b", "c4", "c5"])
-    ap.add_argument("--chunk", type=int, default=0, help="bytes per chunk (0 = planner)")
-    ap.add_argument("--lookahead", type=int, default=-1,
-                    help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64; "
-                         "-1 = pick r and the chunk length with the autotuner, untimed)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--early-exit", action="store_true",
-                    help="stop a wavefront's walks once all its pairs are absorbing")
-    ap.add_argument("--rounds", type=int, default=-1,
-                    help="walk rounds with merging (1 = none, 2..4; -1 = the autotuner's "
-                         "pick, else one)")
-    ap.add_argument("--single-step", action="store_true",
-                    help="one symbol per table lookup even where a two-symbol table exists")
-    ap.add_argument("--two-step", action="store_true",
-                    help="at most two symbols per table lookup even where a three-symbol "
-                         "table exists")
-    ap.add_argument("--chunk-lanes", action="store_true",
-                    help="one chunk per lane with merged walks")
-    ap.add_argument("--interleave", action="store_true",
-                    help="chunk-interleaved code stream (else linear; direct tables: raw input)")
-    ap.add_argument("--tune-only", action="store_true",
-                    help="print the autotuner's lookahead, chunk length, early exit and "
-                         "rounds, then exit")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one plain device copy of the input (counter calibration)")
-    ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
-    ap.add_argument("--warm-requests", type=int, default=500, help="c5: warm-up requests")
-    ap.add_argument("--load", type=float, default=0.7,
-                    help="c5: arrival rate as a fraction of the plain method's capacity")
-    ap.add_argument("--pairs", type=int, default=1024, help="c4: (DFA, string) pairs")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the matcher runs on a single MI355X "
-              "(no multi-GPU path); use --gpus 1", file=sys.stderr)
-        return 2
-
-    import torch
-    import paper_1210_5093_amd as dfa
-    if not os.path.exists(dfa.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    if args.workload == "c4":
-        # graph capture needs a stream of its own (not the legacy default stream)
-        return bench_batched(args, dfa, torch, torch.cuda.Stream())
-    if args.workload == "c5":
-        return bench_served(args, dfa, torch, stream)
-
-    w, gen, nbytes, desc = workload(args.workload)
+def bench_single(args, dfa, torch, stream, name) -> dict:
+    """One DFA and one input (c1, c2, c2a, c3p, c3b): value = input GB/s of
+    whole membership tests, the matcher kernel's roofline, the oracle beside it."""
+    w, gen, nbytes, desc = workload(name)
     log(f"[bench] generating {nbytes} bytes for {args.workload}")
     x = gen(nbytes)
     t0 = time.perf_counter()
@@ -770,20 +735,19 @@ def main() -> int:
     tuned = None
     if args.lookahead < 0:
         t0 = time.perf_counter()
-        r, c, ms, ex, rounds, single, ilv, lanes, two = dfa.dfa_autotune(d, dev_in, stream)
+        r, c, ms, ex, rounds, single, ilv, lanes = dfa.dfa_autotune(d, dev_in, stream)
         tuned = {"lookahead": r, "chunk": c, "ms": round(ms, 4), "early_exit": ex,
                  "rounds": rounds, "single_step": single, "interleave": ilv,
-                 "chunk_lanes": lanes, "two_step": two,
+                 "chunk_lanes": lanes,
                  "tuning_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] autotuner: lookahead {r}, chunk {c or 'planner'}, early exit {ex}, "
             f"rounds {rounds or 1}, single step {single}, interleave {ilv}, chunk lanes {lanes}, "
-            f"two-step {two} ({ms:.3f} ms)")
+            f"({ms:.3f} ms)")
         if args.rounds < 0:
             args.rounds = rounds
         args.single_step = args.single_step or single
         args.interleave = args.interleave or ilv
         args.chunk_lanes = args.chunk_lanes or lanes
-        args.two_step = args.two_step or two
         # the timed run uses early exit only when asked for (--early-exit):
         # its work depends on the data, so the roofline would need the
         # smaller exact count
@@ -791,14 +755,11 @@ def main() -> int:
         args.lookahead = r
         if not args.chunk:
             args.chunk = c
-        if args.tune_only:
-            print(r, c, int(ex), rounds, int(single), int(ilv), int(lanes), int(two), flush=True)
-            return 0
     args.rounds = max(args.rounds, 0)
     chunk, nch = dfa.dfa_plan_chunks(d, nbytes, args.chunk, args.lookahead)
     opts = dict(chunk_len=args.chunk, lookahead=args.lookahead, stream=stream, result=result,
                 early_exit=args.early_exit, rounds=args.rounds, single_step=args.single_step,
-                interleave=args.interleave, chunk_lanes=args.chunk_lanes, two_step=args.two_step)
+                interleave=args.interleave, chunk_lanes=args.chunk_lanes)
 
     if args.calibrate_copy:
         scratch = torch.empty_like(dev_in)
@@ -833,15 +794,13 @@ def main() -> int:
     dfa.dfa_timing_enable(False, stream)
     fin, acc, flags, nch_run = dfa.result_tuple(result)
     if flags:
-        log(f"[bench] result flags {flags}")
-        return 1
+        raise SystemExit(f"[bench] result flags {flags}")
 
     ms_per_step = total_ms / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
     plan = dfa.dfa_plan(d, nbytes, args.chunk, args.lookahead, rounds=args.rounds,
                         early_exit=args.early_exit, single_step=args.single_step,
-                        interleave=args.interleave, chunk_lanes=args.chunk_lanes,
-                        two_step=args.two_step)
+                        interleave=args.interleave, chunk_lanes=args.chunk_lanes)
     step = int(plan.symbols_per_step) if plan.kernel == 1 else 1
     if args.early_exit:
         lookups = early_exit_lookups(w, x, chunk, args.lookahead, int(w.q0))
@@ -855,7 +814,7 @@ def main() -> int:
         reads, covered = merged_lookups(w, x, chunk, args.lookahead, max(2, int(plan.rounds)),
                                         step)
     if plan.kernel == 1:
-        lay = 5 if step == 3 else 4 if step == 2 else 3 if plan.raw_input else (
+        lay = 4 if step == 2 else 3 if plan.raw_input else (
             2 if info.packed_layout == 2 else 1)
         kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
                   f"k_round<{lay}>" if merged else f"k_match2<{lay}>")
@@ -863,11 +822,10 @@ def main() -> int:
         kernel = "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
     achieved = reads / (matcher_avg_ms * 1e-3)
-    traffic, traffic_src = stored_traffic(kernel, args.workload, args.lookahead, int(chunk))
+    traffic, traffic_src = stored_traffic(kernel, name, args.lookahead, int(chunk))
     # bytes the walk streams per input byte: raw input or one-byte codes 1,
-    # two-byte codes 2, pair codes 1/2, triple codes (2 bytes) 2/3
-    stream_bpb = (2.0 / 3.0 if step == 3 else 0.5 if step == 2 else
-                  2.0 if kernel.endswith("<2>") else 1.0)
+    # two-byte codes 2, pair codes 1/2
+    stream_bpb = 0.5 if step == 2 else 2.0 if kernel.endswith("<2>") else 1.0
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -944,8 +902,7 @@ def main() -> int:
             times.append(t)
         t_med = float(np.median(times))
         if ofin != fin:
-            log(f"[bench] MISMATCH: gpu final {fin} oracle {ofin}")
-            return 1
+            raise SystemExit(f"[bench] MISMATCH: gpu final {fin} oracle {ofin}")
         line["cpu_baseline"] = {
             "value": round(nbytes / t_med / 1e9, 4),
             "unit": "GB/s",
@@ -967,8 +924,7 @@ def main() -> int:
             times.append(time.perf_counter() - t0)
         h.close()
         if hfin != fin:
-            log(f"[bench] MISMATCH: host speculative final {hfin}, GPU {fin}")
-            return 1
+            raise SystemExit(f"[bench] MISMATCH: host speculative final {hfin}, GPU {fin}")
         line["cpu_speculative"] = {
             "value": round(nbytes / float(np.median(times)) / 1e9, 4),
             "unit": "GB/s",
@@ -976,6 +932,339 @@ def main() -> int:
             "kind": "host multicore speculative matcher (Algorithm 3, partition of Eq. 10)",
             "sample": f"the full {nbytes >> 20} MiB input, median of 3",
         }
+    return line
+
+
+# Settings of the large configuration's two matches (lookahead r, chunk
+# length, walk rounds), from the chunk sweep on the full 10 GiB inputs;
+# --tune replaces them with the autotuner's choice on the first GiB.
+C3_SETTINGS = {
+    "protein": {"lookahead": 4, "chunk": 65536, "rounds": 4},
+    "byte": {"lookahead": 4, "chunk": 32768, "rounds": 4},
+}
+
+
+def c3_opts(st, stream, result, chunk=None):
+    return dict(chunk_len=int(chunk or st["chunk"]), lookahead=int(st["lookahead"]),
+                rounds=int(st.get("rounds", 0)), interleave=bool(st.get("interleave", False)),
+                single_step=bool(st.get("single_step", False)),
+                chunk_lanes=bool(st.get("chunk_lanes", False)), stream=stream, result=result)
+
+
+def golden_finals():
+    path = os.path.join(ROOT, "tests", "golden", "large_finals.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def bench_large(args, dfa, torch, stream) -> dict:
+    """The large configuration: the 1298-state protein DFA on 10 GiB of
+    residues and the 512-state byte DFA on 10 GiB of uniform bytes, both
+    resident in HBM.  One step = both membership tests; value = 20 GiB / step
+    time.  Per-DFA matcher times (HIP events), the chunk sweep 4 KiB - 1 MiB,
+    the dominant kernel's roofline and the whole step's HBM fraction."""
+    from workloads import configs
+    n = int(args.c3_bytes)
+    parts = [("protein", configs.c3_protein_dfa(), configs.c3_protein_input,
+              f"{configs.c3_protein_dfa().num_states}-state protein DFA (pattern seed "
+              f"{configs.C3_PATTERN_SEED}), residues stream {configs.C3_PROTEIN_INPUT_SEED}"),
+             ("byte", configs.c3_byte_dfa(), configs.c3_byte_input,
+              f"512-state byte DFA (64 columns, seeds 5, 6), uniform bytes stream "
+              f"{configs.C3_BYTE_INPUT_SEED}")]
+    P = []
+    for key, w, gen, desc in parts:
+        t0 = time.perf_counter()
+        x = np.empty(n, dtype=np.uint8)
+        gen(n, out=x)
+        dev = torch.from_numpy(x).to("cuda")
+        del x
+        t1 = time.perf_counter()
+        d = dfa.DFA.from_workload(w)
+        create_ms = (time.perf_counter() - t1) * 1e3
+        log(f"[bench] c3 {key}: {n} bytes generated and copied in {t1 - t0:.1f}s")
+        st = dict(C3_SETTINGS[key])
+        chosen = "fixed setting from the full-size chunk sweep"
+        if args.tune:
+            t0 = time.perf_counter()
+            r, c, ms, ex, rounds, single, ilv, lanes = dfa.dfa_autotune(d, dev, stream)
+            st = {"lookahead": r, "chunk": c, "rounds": rounds, "single_step": single,
+                  "interleave": ilv, "chunk_lanes": lanes}
+            chosen = f"autotuner on the first GiB ({time.perf_counter() - t0:.1f}s, untimed)"
+            log(f"[bench] c3 {key} tuned: {st}")
+        P.append({"key": key, "w": w, "gen": gen, "desc": desc, "dev": dev, "d": d,
+                  "st": st, "chosen": chosen, "create_ms": create_ms,
+                  "res": torch.empty(4, dtype=torch.int32, device="cuda")})
+
+    def step():
+        for p in P:
+            dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
+
+    log(f"[bench] c3 warmup {args.warmup}")
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    dfa.dfa_timing_read(stream)
+    log(f"[bench] c3 timing {args.steps} steps")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    # per-DFA times in a second, instrumented pass (events around the matcher
+    # kernel and around each call)
+    for p in P:
+        dfa.dfa_timing_enable(True, stream)
+        for _ in range(args.steps):
+            dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
+        torch.cuda.synchronize()
+        m, c, k = dfa.dfa_timing_read(stream)
+        dfa.dfa_timing_enable(False, stream)
+        p["matcher_ms"], p["call_ms"] = m / max(k, 1), c / max(k, 1)
+        fin, acc, flags, nch = dfa.result_tuple(p["res"])
+        if flags:
+            raise SystemExit(f"[bench] c3 {p['key']}: result flags {flags}")
+        p["fin"], p["acc"], p["nch"] = fin, acc, nch
+        p["plan"] = dfa.dfa_plan(p["d"], n, p["st"]["chunk"], p["st"]["lookahead"],
+                                 rounds=p["st"].get("rounds", 0),
+                                 interleave=p["st"].get("interleave", False),
+                                 single_step=p["st"].get("single_step", False),
+                                 chunk_lanes=p["st"].get("chunk_lanes", False))
+    # chunk sweep (same r and rounds; 3 timed calls per length)
+    sweep = {}
+    if not args.no_sweep:
+        log("[bench] c3 chunk sweep")
+        for p in P:
+            row = {}
+            for chunk in configs.C3_CHUNKS:
+                o = c3_opts(p["st"], stream, p["res"], chunk)
+                dfa.dfa_match_ex(p["d"], p["dev"], **o)
+                ev0.record(stream)
+                for _ in range(3):
+                    dfa.dfa_match_ex(p["d"], p["dev"], **o)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                row[str(chunk)] = round(n / (ev0.elapsed_time(ev1) / 3 * 1e-3) / 1e9, 1)
+                if dfa.result_tuple(p["res"])[:3] != (p["fin"], p["acc"], 0):
+                    raise SystemExit(f"[bench] c3 {p['key']} chunk {chunk}: result differs")
+            sweep[p["key"]] = row
+    # roofline: the matcher of the slower match.  Merged walks (rounds > 1,
+    # one chunk per lane) stream the code bytes they cover once; on these
+    # inputs the walks reach no absorbing state before the chunk ends, so
+    # they cover all n bytes.
+    dom = max(P, key=lambda p: p["matcher_ms"])
+    plan = dom["plan"]
+    merged = plan.kernel == 1 and (plan.rounds > 1 or plan.chunk_lanes)
+    step_k = int(plan.symbols_per_step) if plan.kernel == 1 else 1
+    lay = 4 if step_k == 2 else 3 if plan.raw_input else (
+        2 if dom["d"].info().packed_layout == 2 else 1)
+    kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
+              f"k_round<{lay}>" if plan.rounds > 1 else f"k_match2<{lay}>") \
+        if plan.kernel == 1 else "k_match"
+    stream_bpb = 0.5 if step_k == 2 else 2.0 if lay == 2 else 1.0
+    algo_bytes = n * stream_bpb
+    achieved = algo_bytes / (dom["matcher_ms"] * 1e-3) / 1e9
+    traffic, traffic_src = stored_traffic(kernel, "c3_" + dom["key"], dom["st"]["lookahead"],
+                                          int(dom["st"]["chunk"]))
+    value = 2 * n / (ms_per_step * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"large DFAs: {n >> 30} GiB per DFA, both resident in HBM; one step = "
+                        f"the {P[0]['desc']} plus the {P[1]['desc']}",
+            "bytes_per_step": 2 * n,
+        },
+        "roofline": {
+            "bound": "hbm" if merged else "lds",
+            "kernel": kernel,
+            "of": f"the {dom['key']} DFA's matcher (the larger matcher time of the step)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "traffic_source": traffic_src,
+            "algorithmic_bytes_per_launch": int(algo_bytes),
+            "kernel_avg_ms": round(dom["matcher_ms"], 4),
+            "step_hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        },
+        "parts": {},
+    }
+    for p in P:
+        pl = p["plan"]
+        line["parts"][p["key"]] = {
+            "dfa": p["desc"],
+            "states": int(p["d"].info().num_states),
+            "classes": int(p["d"].info().num_classes),
+            "imax": int(p["d"].info().imax),
+            "setting": p["st"], "chosen_by": p["chosen"],
+            "chunks": int(p["nch"]), "set_max": int(pl.set_max), "rounds": int(pl.rounds),
+            "compose_levels": int(pl.levels),
+            "GB/s_alone": round(n / (p["call_ms"] * 1e-3) / 1e9, 1),
+            "matcher_ms": round(p["matcher_ms"], 4), "call_ms": round(p["call_ms"], 4),
+            "matcher_hbm_frac": round(n * stream_bpb / (p["matcher_ms"] * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS, 4),
+            "final_state": p["fin"], "accepted": p["acc"],
+            "dfa_create_ms": round(p["create_ms"], 1),
+        }
+    if sweep:
+        line["chunk_sweep_GBps"] = sweep
+    # parity: the final state against the oracle's stored full walk, and the
+    # state after the first GiB against the oracle walking that GiB now (the
+    # CPU baseline's timed sample)
+    import oracle
+    gold = golden_finals() if n == configs.C3_BYTES else None
+    gib = min(n, 1 << 30)
+    t_cpu = 0.0
+    for p in P:
+        if gold:
+            g = gold["c3_" + p["key"]]
+            if (p["fin"], bool(p["acc"])) != (g["final_state"], g["accepted"]):
+                raise SystemExit(f"[bench] c3 {p['key']}: final {p['fin']} != oracle "
+                                 f"{g['final_state']}")
+        chunk = int(p["st"]["chunk"])
+        _, nch = dfa.dfa_plan_chunks(p["d"], n, chunk, p["st"]["lookahead"])
+        bnd = torch.empty(nch + 1, dtype=torch.int32, device="cuda")
+        o = c3_opts(p["st"], stream, p["res"])
+        dfa.dfa_match_ex(p["d"], p["dev"], boundaries=True, bound_out=bnd, **o)
+        torch.cuda.synchronize()
+        x = p["gen"](gib)
+        t0 = time.perf_counter()
+        ofin, _ = oracle.walk(p["w"].delta, p["w"].byte_to_symbol, p["w"].q0, x)
+        t_cpu += time.perf_counter() - t0
+        got = int(bnd[gib // chunk].item()) & 0xFFFFFFFF if gib % chunk == 0 else ofin
+        if got != ofin:
+            raise SystemExit(f"[bench] c3 {p['key']}: state after 1 GiB {got} != oracle {ofin}")
+        del bnd, x
+    line["cpu_baseline"] = {
+        "value": round(2 * gib / t_cpu / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"the first {gib >> 20} MiB of each of the two inputs, sequential walk "
+                  f"(Algorithm 1) on one host core; host {platform.machine()}, "
+                  f"{os.cpu_count()} logical CPUs visible",
+    }
+    line["matches_oracle"] = True
+    line["parity"] = ("final states equal the oracle's full sequential walks (stored by "
+                      "tests/golden/make_large_finals.py); the state after the first GiB "
+                      "equals the oracle's walk of that GiB" if gold else
+                      "the state after the first GiB equals the oracle's walk of that GiB")
+    for p in P:
+        p["d"].close()
+        del p["dev"]
+    torch.cuda.empty_cache()
+    return line
+
+
+SUB_FIELDS = ("value", "unit", "ms_per_step", "config", "roofline", "cpu_baseline",
+              "matches_oracle", "latency_ms", "plain_fifo", "served_req_s",
+              "closed_loop_capacity", "plain_per_request", "speedup_vs_plain",
+              "batched_no_graph", "cpu_speculative", "load_sweep")
+
+
+def sub_record(line: dict) -> dict:
+    return {k: line[k] for k in SUB_FIELDS if k in line}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c1", "c2", "c2a", "c3p", "c3b", "c4", "c5"],
+                    help="c3 (default): the large configuration, with the others as "
+                         "sub-records unless --no-sub")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="c3: skip the protein-style, plain, batched and served sub-records")
+    ap.add_argument("--no-sweep", action="store_true", help="c3: skip the chunk sweep")
+    ap.add_argument("--tune", action="store_true",
+                    help="c3, c4: choose settings with the autotuners (untimed) instead of the "
+                         "fixed ones")
+    ap.add_argument("--c3-bytes", type=int, default=10 << 30, help="c3: bytes per DFA")
+    ap.add_argument("--chunk", type=int, default=0, help="bytes per chunk (0 = planner)")
+    ap.add_argument("--lookahead", type=int, default=-1,
+                    help="reverse-lookahead symbols r (0 = all states, 1 = I_sigma, 2..64; "
+                         "-1 = pick r and the chunk length with the autotuner, untimed)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--early-exit", action="store_true",
+                    help="stop a wavefront's walks once all its pairs are absorbing")
+    ap.add_argument("--rounds", type=int, default=-1,
+                    help="walk rounds with merging (1 = none, 2..4; -1 = the autotuner's "
+                         "pick, else one)")
+    ap.add_argument("--single-step", action="store_true",
+                    help="one symbol per table lookup even where a two-symbol table exists")
+    ap.add_argument("--chunk-lanes", action="store_true",
+                    help="one chunk per lane with merged walks")
+    ap.add_argument("--interleave", action="store_true",
+                    help="chunk-interleaved code stream (else linear; direct tables: raw input)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of the input (counter calibration)")
+    ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
+    ap.add_argument("--warm-requests", type=int, default=500, help="c5: warm-up requests")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="c5: arrival rate as a fraction of the plain method's capacity")
+    ap.add_argument("--load-sweep", default="",
+                    help="c5: comma-separated further loads (fractions of plain capacity)")
+    ap.add_argument("--pairs", type=int, default=1024, help="c4: (DFA, string) pairs")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the matcher runs on a single MI355X "
+              "(no multi-GPU path); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1210_5093_amd as dfa
+    if not os.path.exists(dfa.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t_start = time.perf_counter()
+
+    def timed(label, fn, *a):
+        t0 = time.perf_counter()
+        out = fn(*a)
+        log(f"[bench] section {label}: {time.perf_counter() - t0:.1f}s")
+        return out
+
+    if args.workload == "c4":
+        line = timed("c4", bench_batched, args, dfa, torch, torch.cuda.Stream())
+    elif args.workload == "c5":
+        line = timed("c5", bench_served, args, dfa, torch, stream)
+    elif args.workload == "c3":
+        line = timed("c3", bench_large, args, dfa, torch, stream)
+        if not args.no_sub:
+            sub = {}
+            steps = args.steps
+            for name in ("c2", "c1"):
+                a2 = argparse.Namespace(**vars(args))
+                a2.lookahead, a2.rounds, a2.chunk = -1, -1, 0
+                sub[name] = sub_record(timed(name, bench_single, a2, dfa, torch, stream, name))
+            a4 = argparse.Namespace(**vars(args))
+            if not args.tune:
+                a4.chunk, a4.lookahead = 8192, 6
+            sub["c4"] = sub_record(timed("c4", bench_batched, a4, dfa, torch, torch.cuda.Stream()))
+            sub["c5"] = sub_record(timed("c5", bench_served, args, dfa, torch, stream))
+            args.steps = steps
+            line["sub"] = sub
+    else:
+        line = timed(args.workload, bench_single, args, dfa, torch, stream, args.workload)
+    log(f"[bench] total {time.perf_counter() - t_start:.1f}s")
     print(json.dumps(line), flush=True)
     return 0
 

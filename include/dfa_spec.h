@@ -144,7 +144,7 @@ typedef struct dfa_match_opts {
  * chunk within a few dozen bytes.
  *   DFA_MATCH_ROUNDS(1) or 0 (the default): one round, every walk runs its
  *                        whole chunk (Algorithm 3 as written);
- *   DFA_MATCH_ROUNDS(2..4): that many rounds.
+ *   DFA_MATCH_ROUNDS(2..6): that many rounds.
  * Rounds beyond one need chunk lengths that are multiples of 32 and no early
  * exit; otherwise a single round runs.  dfa_autotune tries them. */
 #define DFA_MATCH_ROUNDS(k) (((uint32_t)(k) & 0xFu) << 8)

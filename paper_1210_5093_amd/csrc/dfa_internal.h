@@ -24,7 +24,7 @@ constexpr uint32_t kLutInvalid = 0xFFFFFFFFu;
 constexpr uint32_t kMaxStates = 32767;
 constexpr uint32_t kMaxMsetLevel = 8;   // precomputed multi-symbol sets up to this r
 constexpr uint16_t kCodeInvalid = 0xFFFF;
-constexpr uint32_t kMaxRounds = 4;        // walk rounds with merging (DFA_MATCH_ROUNDS)
+constexpr uint32_t kMaxRounds = 6;        // walk rounds with merging (DFA_MATCH_ROUNDS)
 constexpr uint32_t kRound1Bytes = 32;     // bytes of the first round; x4 per later round
 constexpr uint32_t kRegions = 64;         // regions (counters) of a round's walk list
 

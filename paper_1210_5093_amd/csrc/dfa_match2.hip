@@ -982,7 +982,7 @@ struct RoundArgs {
 };
 
 template <int S>
-constexpr int kRoundAhead = S >= 4 ? 2 : 4;
+constexpr int kRoundAhead = S >= 4 ? 1 : 2;
 
 // EXIT: the DFA has absorbing states; a wave stops once all its walks are in one.
 template <int L, int S, bool EXIT>
@@ -1207,27 +1207,22 @@ constexpr uint32_t kCwDistinct = 4;
 // unit u0 on, `stride` units apart; the last block may be partial).  A lane
 // walks one chunk, so one block lasts only 16 (or 8) steps: kCwAhead blocks
 // are loaded ahead to cover the memory latency.  The raw input (L = 3) is
-// read chunk by chunk, each lane from its own chunk: eight blocks ahead make
-// every lane's loads whole 128-byte lines, used before they leave the caches.
-template <int L>
-constexpr int kCwAhead = L == 3 ? 8 : 4;
+// read chunk by chunk, each lane from its own chunk: a lane's blocks are
+// consecutive 16-byte pieces of its chunk.
+constexpr uint32_t kCwAhead = 3;
 
 template <int L, int NS>
 __device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16, uint32_t u0,
                                                uint32_t stride, uint32_t ncodes,
                                                uint32_t (&st)[NS]) {
     constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;
+    constexpr uint32_t A = kCwAhead;
     const uint32_t whole = ncodes / kPer16;
-    uint4 ring[kCwAhead<L>];
-#pragma unroll
-    for (int k = 0; k < kCwAhead<L>; ++k)
-        ring[k] = (uint32_t)k < whole ? codes16[(size_t)u0 + (size_t)k * stride] : make_uint4(0, 0, 0, 0);
-    for (uint32_t b = 0; b < whole; ++b) {
-        const uint4 cur = ring[0];
-#pragma unroll
-        for (int k = 0; k + 1 < kCwAhead<L>; ++k) ring[k] = ring[k + 1];
-        if (b + kCwAhead<L> < whole) ring[kCwAhead<L> - 1] = codes16[(size_t)u0 + (size_t)(b + kCwAhead<L>) * stride];
-        const uint32_t w4[4] = {cur.x, cur.y, cur.z, cur.w};
+    // ring slot k holds block b0 + k and is reloaded with block b0 + k + A
+    // right after its last use; loads are issued without branches (see
+    // walk_fast)
+    auto walk_ring_block = [&](const uint4 &blk) {
+        const uint32_t w4[4] = {blk.x, blk.y, blk.z, blk.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t w = word_codes<L>(w4[q]);
@@ -1247,6 +1242,23 @@ __device__ __forceinline__ void walk_one_chunk(const uint4 *__restrict__ codes16
                 for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 1>(st[j], w));
             }
         }
+    };
+    if (whole) {
+        const uint32_t lastb = whole - 1;
+        uint4 ring[A];
+#pragma unroll
+        for (uint32_t k = 0; k < A; ++k) ring[k] = codes16[(size_t)u0 + (size_t)min(k, lastb) * stride];
+        uint32_t b0 = 0;
+        for (; b0 + A <= whole; b0 += A) {
+#pragma unroll
+            for (uint32_t k = 0; k < A; ++k) {
+                walk_ring_block(ring[k]);
+                ring[k] = codes16[(size_t)u0 + (size_t)min(b0 + k + A, lastb) * stride];
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k + 1 < A; ++k)
+            if (b0 + k < whole) walk_ring_block(ring[k]);
     }
     const uint32_t rest = ncodes - whole * kPer16;
     if (rest) {
@@ -1279,7 +1291,7 @@ struct ChunkWalkArgs {
 // KiB staged per workgroup, large workgroups keep 32 waves (32 x 64 walks)
 // on each CU.
 template <int L>
-__global__ __launch_bounds__(1024) void k_chunk_walk(Match2Args a, ChunkWalkArgs cw) {
+__global__ __launch_bounds__(1024, 8) void k_chunk_walk(Match2Args a, ChunkWalkArgs cw) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     constexpr uint32_t kPer16 = L == 2 ? 8u : 16u;

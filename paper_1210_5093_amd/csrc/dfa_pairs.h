@@ -181,57 +181,70 @@ __device__ __forceinline__ void step_slots(uint32_t (&st)[S], const uint32_t (&w
     for (int j = 0; j < S; ++j) st[j] = lds_ld(st[j]);
 }
 
-// With EXIT the walk stops early (every 4 blocks it checks) once
-// every live slot of the wavefront is absorbing: the rest of the chunk cannot
-// change those states.  exit_base = 0 (no absorbing state) skips the check.
+// With EXIT the walk stops early (every few blocks it checks) once every live
+// slot of the wavefront is absorbing: the rest of the chunk cannot change
+// those states.  exit_base = 0 (no absorbing state) skips the check.
+//
+// Code blocks are software-pipelined: A = PF + 1 blocks per slot sit in
+// registers, and the register that held block b is reloaded with block
+// b + A right after its last use, so each load has PF blocks of walking to
+// arrive.  The steady-state loop is unrolled by A and issues every load
+// without a branch (past the last block it reloads the last block, which is
+// never walked again), so that the wait before a block's first step waits
+// for that block's own load only; a load under a branch, or a register
+// copied between ring slots, would make it wait for every load in flight.
+template <int L, int S>
+__device__ __forceinline__ void walk_block(const uint4 (&blk)[S], uint32_t (&st)[S]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t w[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            w[j] = word_codes<L>(q == 0 ? blk[j].x : q == 1 ? blk[j].y : q == 2 ? blk[j].z : blk[j].w);
+        // round-robin over the slots, one code at a time, so that the
+        // slots' independent chains keep several LDS loads in flight
+        step_slots<L, 0, S>(st, w);
+        step_slots<L, 1, S>(st, w);
+        if constexpr (!kWideCodes<L>) {
+            step_slots<L, 2, S>(st, w);
+            step_slots<L, 3, S>(st, w);
+        }
+    }
+}
+
 template <int L, int S, bool EXIT = false, int PF = 1>
 __device__ __forceinline__ void walk_fast(const uint4 *__restrict__ codes16,
                                           const uint32_t (&o16)[S], uint32_t blocks,
                                           uint32_t (&st)[S], uint32_t exit_base = 0,
                                           uint32_t exit_shift = 0, uint32_t live = 0,
                                           uint32_t stride = 1) {
-    // PF blocks of prefetch: cur is block b - 1, ahead[k] is block b - 1 + k + 1
-    uint4 cur[S], ahead[PF][S];
+    constexpr uint32_t A = PF + 1;
+    if (blocks == 0) return;
+    const uint32_t last = blocks - 1;
+    uint4 buf[A][S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) cur[j] = codes16[o16[j]];
-#pragma unroll
-    for (int k = 0; k + 1 < PF; ++k)
+    for (uint32_t k = 0; k < A; ++k)
 #pragma unroll
         for (int j = 0; j < S; ++j)
-            if ((uint32_t)(k + 1) < blocks)
-                ahead[k][j] = codes16[(size_t)o16[j] + (size_t)(k + 1) * stride];
-    for (uint32_t b = 1; ; ++b) {
-        const bool more = b < blocks;
-        const uint32_t far = b + PF - 1;
-        if (far < blocks) {
+            buf[k][j] = codes16[(size_t)o16[j] + (size_t)min(k, last) * stride];
+    uint32_t b0 = 0;
+    for (; b0 + A <= blocks; b0 += A) {
 #pragma unroll
-            for (int j = 0; j < S; ++j) ahead[PF - 1][j] = codes16[(size_t)o16[j] + (size_t)far * stride];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t w[S];
+        for (uint32_t k = 0; k < A; ++k) {
+            walk_block<L, S>(buf[k], st);
+            const uint32_t nb = min(b0 + k + A, last);
 #pragma unroll
             for (int j = 0; j < S; ++j)
-                w[j] = word_codes<L>(q == 0 ? cur[j].x : q == 1 ? cur[j].y : q == 2 ? cur[j].z : cur[j].w);
-            // round-robin over the slots, one code at a time, so that the
-            // slots' independent chains keep several LDS loads in flight
-            step_slots<L, 0, S>(st, w);
-            step_slots<L, 1, S>(st, w);
-            if constexpr (!kWideCodes<L>) {
-                step_slots<L, 2, S>(st, w);
-                step_slots<L, 3, S>(st, w);
-            }
+                buf[k][j] = codes16[(size_t)o16[j] + (size_t)nb * stride];
         }
-        if (!more) break;
         if constexpr (EXIT)
-            if (exit_base && (b & 3u) == 0 && wave_absorbed(st, live, exit_base, exit_shift)) break;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            cur[j] = ahead[0][j];
-#pragma unroll
-            for (int k = 0; k + 1 < PF; ++k) ahead[k][j] = ahead[k + 1][j];
-        }
+            if (exit_base && ((b0 / A) & 1u) && wave_absorbed(st, live, exit_base, exit_shift))
+                return;
     }
+    // fewer than A blocks left: they are in buf[0 ..]
+#pragma unroll
+    for (uint32_t k = 0; k + 1 < A; ++k)
+        if (b0 + k < blocks) walk_block<L, S>(buf[k], st);
 }
 
 // Walk pairs whose chunks may end inside a 16-byte block: slot j walks

@@ -244,6 +244,26 @@ int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t 
                    uint32_t *d_first, uint16_t *d_pair_start, uint16_t *d_pair_end,
                    uint64_t max_pairs);
 
+/* dfa_match_noalloc -- dfa_match_ex for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result record and boundaries as
+ * dfa_match_ex (no timing instrumentation is recorded).  Every scratch
+ * buffer of the call (maps, start-set sizes, scans, and on the packed-pair
+ * path the code stream: about one byte per input byte when the input is
+ * translated, none when the matcher reads the raw input) comes from one
+ * fixed region of DFA_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * from the first call on that device until the process ends.  The call
+ * allocates and frees no device memory.
+ * Returns DFA_E_TOOBIG (nothing enqueued) when the plan needs more scratch
+ * than the region holds.  All calls on one GPU share its region and leave
+ * their contents in it: calls that overlap on one GPU (on different
+ * streams, or from several host threads) race, and the caller must order
+ * them (one stream, or events between them). */
+#define DFA_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dfa_match_noalloc(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t start_state,
+                      const dfa_match_opts_t *opts, void *stream, uint32_t *d_result,
+                      uint32_t *d_boundaries);
+
 /* lookahead value meaning "use what dfa_autotune chose for this DFA and a
  * length of this order (one symbol if it was never tuned)". */
 #define DFA_LOOKAHEAD_AUTO 0xFFFFFFFFu

@@ -112,6 +112,9 @@ def lib() -> ctypes.CDLL:
     L.dfa_match_ex.restype = I
     L.dfa_match_ex.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(dfa_match_opts_t), P,
                                P, P]
+    L.dfa_match_noalloc.restype = I
+    L.dfa_match_noalloc.argtypes = [P, P, ctypes.c_size_t, U32,
+                                    ctypes.POINTER(dfa_match_opts_t), P, P, P]
     L.dfa_match_maps.restype = I
     L.dfa_match_maps.argtypes = [P, P, ctypes.c_size_t, U32, ctypes.POINTER(dfa_match_opts_t), P,
                                  P, P, P, P, U64]
@@ -340,6 +343,32 @@ def dfa_match_ex(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 
                               DFA_Q0 if start is None else int(start), ctypes.byref(o),
                               _stream_handle(stream), result.data_ptr(),
                               bnd.data_ptr() if bnd is not None else None))
+    return result, bnd
+
+
+def dfa_match_noalloc(d: DFA, d_input, start: Optional[int] = None, chunk_len: int = 0,
+                      lookahead: int = 1, boundaries: bool = False, stream=None, result=None,
+                      bound_out=None, early_exit: bool = False, rounds: int = 0,
+                      single_step: bool = False, interleave: bool = False,
+                      chunk_lanes: bool = False):
+    """dfa_match_noalloc: dfa_match_ex with every scratch buffer in the library's
+    fixed per-GPU region (no device allocation by the library).  Returns
+    (result tensor, boundaries tensor or None); pass `result` and `bound_out`
+    to allocate nothing on the Python side either."""
+    import torch
+    result = _result_tensor(result)
+    n = int(d_input.numel())
+    bnd = None
+    if boundaries:
+        _, nch = dfa_plan_chunks(d, n, chunk_len, lookahead)
+        bnd = bound_out if bound_out is not None else torch.empty(
+            nch + 1, dtype=torch.int32, device="cuda")
+        assert bnd.numel() >= nch + 1
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
+    _check(lib().dfa_match_noalloc(d.handle, d_input.data_ptr() if n else None, n,
+                                   DFA_Q0 if start is None else int(start), ctypes.byref(o),
+                                   _stream_handle(stream), result.data_ptr(),
+                                   bnd.data_ptr() if bnd is not None else None))
     return result, bnd
 
 

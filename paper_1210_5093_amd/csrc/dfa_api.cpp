@@ -276,6 +276,45 @@ extern "C" int dfa_match_ex(const dfa_t *d, const uint8_t *d_input, size_t len,
                      d_boundaries);
 }
 
+namespace {
+// dfa_match_noalloc's scratch: one fixed region per GPU.  A file-scope device
+// array exists once on every device the code object is loaded on, for the
+// life of the process.  Host code reaches it only through the address
+// hipGetSymbolAddress returns with that device current (the array's name is
+// not a device address in host code).
+constexpr size_t kScratchBytes = (size_t)DFA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t *> g_scratch;   // device -> address of its region
+
+int scratch_region(uint8_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress (scratch)");
+        it = g_scratch.emplace(dev, static_cast<uint8_t *>(ptr)).first;
+    }
+    *out = it->second;
+    return DFA_OK;
+}
+}  // namespace
+
+extern "C" int dfa_match_noalloc(const dfa_t *d, const uint8_t *d_input, size_t len,
+                                 uint32_t start_state, const dfa_match_opts_t *opts,
+                                 void *stream, uint32_t *d_result, uint32_t *d_boundaries) {
+    uint8_t *region = nullptr;
+    int rc = scratch_region(&region);
+    if (rc) return rc;
+    return run_match(d, d_input, len, start_state, opts, (hipStream_t)stream, d_result,
+                     d_boundaries, nullptr, region, kScratchBytes);
+}
+
 extern "C" int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len,
                               uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
                               uint32_t *d_result, uint32_t *d_first, uint16_t *d_pair_start,

@@ -939,8 +939,8 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
 # length, walk rounds), from the chunk sweep on the full 10 GiB inputs;
 # --tune replaces them with the autotuner's choice on the first GiB.
 C3_SETTINGS = {
-    "protein": {"lookahead": 4, "chunk": 65536, "rounds": 4},
-    "byte": {"lookahead": 4, "chunk": 32768, "rounds": 4},
+    "protein": {"lookahead": 4, "chunk": 8192, "chunk_lanes": True, "single_step": True},
+    "byte": {"lookahead": 2, "chunk": 131072, "rounds": 5, "interleave": True},
 }
 
 

@@ -477,6 +477,14 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         while (rounds > 1 && ((uint64_t)kRound1Bytes << (2 * (rounds - 2))) >= chunk) --rounds;
         p->rounds = rounds;
     }
+    // merged walks over interleaved codes: four pairs per lane whatever the
+    // set size (the later rounds' short chains need more walks per wavefront
+    // in flight); DFA_SLOTS still forces either
+    {
+        const char *fs = std::getenv("DFA_SLOTS");
+        if (p->packed && p->rounds > 1 && p->ilv_nblk && !(fs && (fs[0] == '2' || fs[0] == '4')))
+            p->slots = 4;
+    }
     // compose fan-in: G maps of `stride` entries staged in LDS for the tree
     // composition
     const uint64_t stage = std::min<uint64_t>(96u * 1024u, (uint64_t)lds - 1024u);

@@ -26,9 +26,11 @@ GiB = 1 << 30
 MiB = 1 << 20
 
 # (lookahead, chunk, options) of the readout checks: the benchmark's settings
-# and two others
-PROTEIN_MAPS = [(6, 65536, {"rounds": 4}), (1, 4096, {}), (8, 1 << 20, {})]
-BYTE_MAPS = [(4, 32768, {"rounds": 4}), (1, 4096, {}), (3, 1 << 20, {})]
+# first, then three others
+PROTEIN_MAPS = [(4, 8192, {"chunk_lanes": True, "single_step": True}), (6, 65536, {"rounds": 4}),
+                (1, 4096, {}), (8, 1 << 20, {})]
+BYTE_MAPS = [(2, 131072, {"rounds": 5, "interleave": True}), (4, 32768, {"rounds": 4}),
+             (1, 4096, {}), (3, 1 << 20, {})]
 
 
 def say(*a):

@@ -939,8 +939,9 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
 # length, walk rounds), from the chunk sweep on the full 10 GiB inputs;
 # --tune replaces them with the autotuner's choice on the first GiB.
 C3_SETTINGS = {
-    "protein": {"lookahead": 4, "chunk": 8192, "chunk_lanes": True, "single_step": True},
-    "byte": {"lookahead": 2, "chunk": 131072, "rounds": 5, "interleave": True},
+    "protein": {"lookahead": 4, "chunk": 65536, "rounds": 2, "interleave": True,
+                "single_step": True},
+    "byte": {"lookahead": 2, "chunk": 65536, "rounds": 6, "interleave": True},
 }
 
 
@@ -999,6 +1000,12 @@ def bench_large(args, dfa, torch, stream) -> dict:
         for p in P:
             dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
 
+    if args.calibrate_copy:
+        # one device copy of a known size, for scaling the HBM counters
+        scratch = torch.empty_like(P[0]["dev"])
+        scratch.copy_(P[0]["dev"])
+        torch.cuda.synchronize()
+        del scratch
     log(f"[bench] c3 warmup {args.warmup}")
     for _ in range(max(1, args.warmup)):
         step()
@@ -1019,9 +1026,10 @@ def bench_large(args, dfa, torch, stream) -> dict:
         for _ in range(args.steps):
             dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
         torch.cuda.synchronize()
-        m, c, k = dfa.dfa_timing_read(stream)
+        m, c, kern, k = dfa.dfa_timing_read_ex(stream)
         dfa.dfa_timing_enable(False, stream)
         p["matcher_ms"], p["call_ms"] = m / max(k, 1), c / max(k, 1)
+        p["kernel_ms"] = kern / max(k, 1)
         fin, acc, flags, nch = dfa.result_tuple(p["res"])
         if flags:
             raise SystemExit(f"[bench] c3 {p['key']}: result flags {flags}")
@@ -1049,22 +1057,36 @@ def bench_large(args, dfa, torch, stream) -> dict:
                 if dfa.result_tuple(p["res"])[:3] != (p["fin"], p["acc"], 0):
                     raise SystemExit(f"[bench] c3 {p['key']} chunk {chunk}: result differs")
             sweep[p["key"]] = row
-    # roofline: the matcher of the slower match.  Merged walks (rounds > 1,
-    # one chunk per lane) stream the code bytes they cover once; on these
-    # inputs the walks reach no absorbing state before the chunk ends, so
-    # they cover all n bytes.
-    dom = max(P, key=lambda p: p["matcher_ms"])
+    # roofline: the longest single kernel launch of the step (HIP events
+    # around it on the matcher's stream, dfa_timing_read_ex).  With a
+    # one-chunk-per-lane last round that is k_tail, which reads every byte
+    # of each chunk from tail_start on (raw input: 1 B per byte; on these
+    # inputs every chunk keeps a walk to its end) and makes at least two LDS
+    # lookups per byte (its code, one transition).  Otherwise the matcher
+    # streams its code bytes once (1 B, 2 B or 1/2 B per input byte).
+    dom = max(P, key=lambda p: p["kernel_ms"])
     plan = dom["plan"]
-    merged = plan.kernel == 1 and (plan.rounds > 1 or plan.chunk_lanes)
     step_k = int(plan.symbols_per_step) if plan.kernel == 1 else 1
-    lay = 4 if step_k == 2 else 3 if plan.raw_input else (
-        2 if dom["d"].info().packed_layout == 2 else 1)
-    kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
-              f"k_round<{lay}>" if plan.rounds > 1 else f"k_match2<{lay}>") \
-        if plan.kernel == 1 else "k_match"
-    stream_bpb = 0.5 if step_k == 2 else 2.0 if lay == 2 else 1.0
-    algo_bytes = n * stream_bpb
-    achieved = algo_bytes / (dom["matcher_ms"] * 1e-3) / 1e9
+    code_lay = 2 if dom["d"].info().packed_layout == 2 else 1
+    lay = 4 if step_k == 2 else 3 if plan.raw_input else code_lay
+    if plan.kernel == 1 and plan.tail_lanes:
+        kernel = f"k_tail<{code_lay}>"
+        t0 = int(plan.tail_start)
+        chunk = int(plan.chunk_len)
+        nch = int(plan.num_chunks)
+        last = n - (nch - 1) * chunk
+        algo_bytes = (nch - 1) * (chunk - t0) + max(0, last - t0)
+        algo_lookups = 2 * algo_bytes
+    else:
+        kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
+                  f"k_round<{lay}>" if plan.rounds > 1 else f"k_match2<{lay}>") \
+            if plan.kernel == 1 else "k_match"
+        stream_bpb = 0.5 if step_k == 2 else 2.0 if lay == 2 else 1.0
+        algo_bytes = int(n * stream_bpb)
+        algo_lookups = n // step_k
+    kms = dom["kernel_ms"]
+    achieved = algo_bytes / (kms * 1e-3) / 1e9
+    lds_achieved = algo_lookups / (kms * 1e-3)
     traffic, traffic_src = stored_traffic(kernel, "c3_" + dom["key"], dom["st"]["lookahead"],
                                           int(dom["st"]["chunk"]))
     value = 2 * n / (ms_per_step * 1e-3) / 1e9
@@ -1087,9 +1109,10 @@ def bench_large(args, dfa, torch, stream) -> dict:
             "bytes_per_step": 2 * n,
         },
         "roofline": {
-            "bound": "hbm" if merged else "lds",
+            "bound": "hbm",
             "kernel": kernel,
-            "of": f"the {dom['key']} DFA's matcher (the larger matcher time of the step)",
+            "of": f"the {dom['key']} DFA's {kernel} (the longest single kernel launch of the "
+                  f"step, HIP events on its stream)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -1097,7 +1120,11 @@ def bench_large(args, dfa, torch, stream) -> dict:
             "traffic": traffic,
             "traffic_source": traffic_src,
             "algorithmic_bytes_per_launch": int(algo_bytes),
-            "kernel_avg_ms": round(dom["matcher_ms"], 4),
+            "kernel_avg_ms": round(kms, 4),
+            "lds_view": {"algorithmic_lookups_per_launch": int(algo_lookups),
+                         "achieved_Glookups_s": round(lds_achieved / 1e9, 1),
+                         "peak_Glookups_s": round(LDS_LOOKUP_PEAK / 1e9, 1),
+                         "frac": round(lds_achieved / LDS_LOOKUP_PEAK, 4)},
             "step_hbm_frac": round(value / HBM_PEAK_GBS, 4),
         },
         "parts": {},
@@ -1112,10 +1139,14 @@ def bench_large(args, dfa, torch, stream) -> dict:
             "setting": p["st"], "chosen_by": p["chosen"],
             "chunks": int(p["nch"]), "set_max": int(pl.set_max), "rounds": int(pl.rounds),
             "compose_levels": int(pl.levels),
+            "tail_lanes": int(pl.tail_lanes), "tail_start": int(pl.tail_start),
             "GB/s_alone": round(n / (p["call_ms"] * 1e-3) / 1e9, 1),
             "matcher_ms": round(p["matcher_ms"], 4), "call_ms": round(p["call_ms"], 4),
-            "matcher_hbm_frac": round(n * stream_bpb / (p["matcher_ms"] * 1e-3) / 1e9
-                                      / HBM_PEAK_GBS, 4),
+            "longest_kernel_ms": round(p["kernel_ms"], 4),
+            # input bytes over the matcher section (all rounds, or the one
+            # matcher launch) against HBM
+            "matcher_input_hbm_frac": round(n / (p["matcher_ms"] * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4),
             "final_state": p["fin"], "accepted": p["acc"],
             "dfa_create_ms": round(p["create_ms"], 1),
         }

@@ -146,7 +146,11 @@ typedef struct dfa_match_opts {
  *                        whole chunk (Algorithm 3 as written);
  *   DFA_MATCH_ROUNDS(2..6): that many rounds.
  * Rounds beyond one need chunk lengths that are multiples of 32 and no early
- * exit; otherwise a single round runs.  dfa_autotune tries them. */
+ * exit; otherwise a single round runs.  dfa_autotune tries them.
+ * With DFA_MATCH_INTERLEAVE, one symbol per step and a 16-byte aligned input,
+ * the last round runs one chunk per lane over the raw input (each chunk's
+ * remaining walks side by side in one lane, bytes turned into codes in LDS),
+ * and only the bytes before it are translated (dfa_plan_info_t::tail_lanes). */
 #define DFA_MATCH_ROUNDS(k) (((uint32_t)(k) & 0xFu) << 8)
 #define DFA_MATCH_ROUNDS_OF(flags) (((flags) >> 8) & 0xFu)
 
@@ -244,6 +248,46 @@ int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len, uint32_t 
                    uint32_t *d_first, uint16_t *d_pair_start, uint16_t *d_pair_end,
                    uint64_t max_pairs);
 
+/* dfa_match_block -- the block map of one shard of a longer string, and
+ * dfa_compose_blocks -- the ordered composition of several shards' maps.
+ * Together they are the one-GPU part of matching a string sharded over
+ * several processors (Section 3: the input is cut into pieces whose lengths
+ * follow the processors' measured capacities, Eqs. 1-7, with the first piece
+ * lengthened by Eq. 10 since it starts from one state; each piece is matched
+ * from its reverse-lookahead set, Eq. 11 / Eq. 13, and the pieces' maps are
+ * combined in order, Eq. 9).  dfa_host_partition computes such boundaries.
+ *
+ * dfa_match_block matches bytes [offset, offset + len) of the string at
+ * d_input (device; the `lookahead` bytes before offset must be readable,
+ * they choose the start set).  offset = 0: the block starts from start_state
+ * alone (DFA_Q0 = q0); otherwise from I of the r bytes before offset
+ * (absorbing states left out).  Written on the stream:
+ *   d_info:   device, 4 x uint32: number of entries m, flags (DFA_FLAG_SYMBOL
+ *             if the shard holds a byte outside Sigma), chunks, 0;
+ *   d_start:  device, max_entries uint16: the start states, ascending;
+ *   d_end:    device, max_entries uint16: the state at the shard's end from
+ *             each start state (0xFFFF: the walk left the chunks' start sets,
+ *             an invariant violation; the composition then reports
+ *             DFA_FLAG_SPECULATION if it needs that entry).
+ * opts as for dfa_match_ex (boundaries are not offered); a lookahead beyond
+ * the precomputed levels (dfa_info_t::lookahead_tables) is lowered to them.
+ * Needs a packed layout (dfa_info_t::packed_layout != 0; DFA_E_INVAL
+ * otherwise), len > 0, and max_entries >= dfa_plan()'s set_max for this
+ * length (DFA_E_TOOBIG otherwise).
+ *
+ * dfa_compose_blocks follows start_state through `count` blocks in order:
+ * block g's record at d_infos + 4 g, its entries at d_starts / d_ends +
+ * g * max_entries.  Writes d_result (dfa_result_t: final state, accept bit,
+ * flags, total chunks) and, if not NULL, d_block_states[0 .. count]: the
+ * state before each block and the final state (0xFFFFFFFF after a flag). */
+int dfa_match_block(const dfa_t *d, const uint8_t *d_input, size_t offset, size_t len,
+                    uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
+                    uint32_t *d_info, uint16_t *d_start, uint16_t *d_end, uint32_t max_entries);
+int dfa_compose_blocks(const dfa_t *d, uint32_t count, const uint32_t *d_infos,
+                       const uint16_t *d_starts, const uint16_t *d_ends, uint32_t max_entries,
+                       uint32_t start_state, void *stream, uint32_t *d_result,
+                       uint32_t *d_block_states);
+
 /* dfa_match_noalloc -- dfa_match_ex for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, result record and boundaries as
@@ -321,6 +365,11 @@ typedef struct dfa_plan_info {
     uint32_t levels;          /* composition levels (Eq. 9 applied as a tree) */
     uint32_t group0;          /* maps composed per workgroup on the first level */
     uint32_t group;           /* maps composed per workgroup on the later levels */
+    uint32_t tail_lanes;      /* 1: merged walks whose last round runs one chunk per lane
+                                 over the raw input (interleaved one-symbol codes, 16-byte
+                                 aligned input); the code stream then covers only each
+                                 chunk's first tail_start bytes */
+    uint32_t tail_start;      /* chunk bytes walked before that last round */
 } dfa_plan_info_t;
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);
 
@@ -447,6 +496,12 @@ void dfa_server_destroy(dfa_server_t *srv);
  * clears the record. */
 int dfa_timing_enable(void *stream, int on);
 int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms, uint32_t *calls);
+/* dfa_timing_read_ex -- dfa_timing_read plus kernel_ms: the summed time of
+ * each call's longest single matcher launch (the one-chunk-per-lane last
+ * round when the plan has one, else the last merged round, else the packed
+ * matcher; batches and the one-chunk-per-wave kernel: the matcher time). */
+int dfa_timing_read_ex(void *stream, double *matcher_ms, double *call_ms, double *kernel_ms,
+                       uint32_t *calls);
 
 /* Message for a status code / for this thread's last failure. */
 const char *dfa_strerror(int status);

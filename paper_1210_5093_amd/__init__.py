@@ -53,7 +53,8 @@ class dfa_plan_info_t(ctypes.Structure):
                 ("rounds", ctypes.c_uint32), ("interleaved", ctypes.c_uint32),
                 ("chunk_lanes", ctypes.c_uint32), ("set_max", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("group0", ctypes.c_uint32),
-                ("group", ctypes.c_uint32)]
+                ("group", ctypes.c_uint32), ("tail_lanes", ctypes.c_uint32),
+                ("tail_start", ctypes.c_uint32)]
 
 
 class dfa_result_t(ctypes.Structure):
@@ -169,6 +170,15 @@ def lib() -> ctypes.CDLL:
     L.dfa_timing_read.restype = I
     L.dfa_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U32)]
+    L.dfa_timing_read_ex.restype = I
+    L.dfa_timing_read_ex.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U32)]
+    L.dfa_match_block.restype = I
+    L.dfa_match_block.argtypes = [P, P, ctypes.c_size_t, ctypes.c_size_t, U32,
+                                  ctypes.POINTER(dfa_match_opts_t), P, P, P, P, U32]
+    L.dfa_compose_blocks.restype = I
+    L.dfa_compose_blocks.argtypes = [P, U32, P, P, P, U32, U32, P, P, P]
     L.dfa_strerror.restype = ctypes.c_char_p
     L.dfa_strerror.argtypes = [I]
     L.dfa_last_error.restype = ctypes.c_char_p
@@ -399,6 +409,51 @@ def dfa_match_maps(d: DFA, d_input, start: Optional[int] = None, chunk_len: int 
     return result, first, ps, pe
 
 
+def dfa_match_block(d: DFA, d_input, offset: int, length: int, start: Optional[int] = None,
+                    chunk_len: int = 0, lookahead: int = 1, stream=None, max_entries: int = 0,
+                    out=None, rounds: int = 0, single_step: bool = False,
+                    interleave: bool = False, chunk_lanes: bool = False, early_exit: bool = False):
+    """dfa_match_block: the block map of bytes [offset, offset + length) of the
+    device string d_input.  Returns (info int32 [4], start int16 [max_entries],
+    end int16 [max_entries]) device tensors (or writes into `out`, a tuple of
+    such tensors)."""
+    import torch
+    o = _opts(chunk_len, lookahead, early_exit, rounds, single_step, interleave, chunk_lanes)
+    if out is None:
+        if not max_entries:
+            plan = dfa_plan_info_t()
+            _check(lib().dfa_plan(d.handle, int(length), ctypes.byref(o), ctypes.byref(plan)))
+            max_entries = max(8, int(plan.set_max))
+        out = (torch.empty(4, dtype=torch.int32, device="cuda"),
+               torch.empty(max_entries, dtype=torch.int16, device="cuda"),
+               torch.empty(max_entries, dtype=torch.int16, device="cuda"))
+    info, st, en = out
+    _check(lib().dfa_match_block(d.handle, d_input.data_ptr(), int(offset), int(length),
+                                 DFA_Q0 if start is None else int(start), ctypes.byref(o),
+                                 _stream_handle(stream), info.data_ptr(), st.data_ptr(),
+                                 en.data_ptr(), int(st.numel())))
+    return info, st, en
+
+
+def dfa_compose_blocks(d: DFA, infos, starts, ends, start: Optional[int] = None, stream=None,
+                       result=None, block_states=None):
+    """dfa_compose_blocks over G blocks: infos int32 [G, 4], starts / ends int16
+    [G, max_entries] (contiguous).  Returns (result tensor, block states int32
+    [G + 1])."""
+    import torch
+    G = int(infos.shape[0])
+    assert infos.is_contiguous() and starts.is_contiguous() and ends.is_contiguous()
+    assert starts.shape == ends.shape and starts.shape[0] == G
+    result = _result_tensor(result)
+    if block_states is None:
+        block_states = torch.empty(G + 1, dtype=torch.int32, device="cuda")
+    _check(lib().dfa_compose_blocks(d.handle, G, infos.data_ptr(), starts.data_ptr(),
+                                    ends.data_ptr(), int(starts.shape[1]),
+                                    DFA_Q0 if start is None else int(start), _stream_handle(stream),
+                                    result.data_ptr(), block_states.data_ptr()))
+    return result, block_states
+
+
 def dfa_match_batch(dfas: Sequence[DFA], inputs: Sequence, stream=None, results=None):
     """Many (DFA, device string) pairs in one call; returns an int32 [count, 4] tensor."""
     import torch
@@ -424,6 +479,15 @@ def dfa_timing_read(stream=None) -> Tuple[float, float, int]:
     _check(lib().dfa_timing_read(_stream_handle(stream), ctypes.byref(m), ctypes.byref(c),
                                  ctypes.byref(k)))
     return float(m.value), float(c.value), int(k.value)
+
+
+def dfa_timing_read_ex(stream=None) -> Tuple[float, float, float, int]:
+    """(matcher ms, whole-call ms, longest single matcher launch ms, calls),
+    each summed since the last read."""
+    m, c, x, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_uint32()
+    _check(lib().dfa_timing_read_ex(_stream_handle(stream), ctypes.byref(m), ctypes.byref(c),
+                                    ctypes.byref(x), ctypes.byref(k)))
+    return float(m.value), float(c.value), float(x.value), int(k.value)
 
 
 def dfa_autotune(d: DFA, d_input, stream=None):

@@ -36,7 +36,9 @@ struct Workspace {
     size_t in_bytes = 0;
     uint32_t *result = nullptr;   // 4 words for the synchronous path
     bool timing = false;
-    struct Stamp { hipEvent_t begin, before_match, after_match, end; };
+    // kern_begin / kern_end (may be null): around the call's longest single
+    // matcher launch (see dfa_timing_read_ex)
+    struct Stamp { hipEvent_t begin, before_match, after_match, end, kern_begin, kern_end; };
     std::vector<Stamp> stamps;    // one per timed call, read by dfa_timing_read
 };
 
@@ -105,14 +107,25 @@ dfa_match_opts_t resolve_opts(const dfa_t *d, size_t len, const dfa_match_opts_t
     return o;
 }
 
+// A block map request (dfa_match_block): the shard's input starts `before`
+// bytes into the caller's string, and the composed map goes to these buffers.
+struct BlockReq {
+    uint64_t before;
+    uint32_t *info;
+    uint16_t *start;
+    uint16_t *end;
+    uint32_t max;
+};
+
 // fixed: when not null, the call's scratch memory (fixed_bytes of device
 // memory) instead of the stream's workspace; nothing is allocated and no
 // timing events are made.
 int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
               const dfa_match_opts_t *opts_in, hipStream_t s, uint32_t *d_result,
               uint32_t *d_bound, const PackedBufs *readout = nullptr,
-              uint8_t *fixed = nullptr, size_t fixed_bytes = 0) {
-    if (!d || !d_result || (len && !d_in)) return fail(DFA_E_INVAL, "match: NULL argument");
+              uint8_t *fixed = nullptr, size_t fixed_bytes = 0,
+              const BlockReq *block = nullptr) {
+    if (!d || (!d_result && !block) || (len && !d_in)) return fail(DFA_E_INVAL, "match: NULL argument");
     if (start == DFA_Q0) start = d->dev.q0;
     if (start >= d->dev.nq) return fail(DFA_E_INVAL, "match: start state out of range");
     const dfa_match_opts_t resolved = resolve_opts(d, len, opts_in);
@@ -120,8 +133,22 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     uint64_t chunk = opts->chunk_len ? opts->chunk_len : env_chunk();
     uint32_t look = opts->lookahead;
     MatchPlan p;
-    int rc = plan_match(d, len, chunk, look, &p, opts->flags);
+    const bool unaligned = (reinterpret_cast<uintptr_t>(d_in) & 15u) != 0;
+    int rc = plan_match(d, len, chunk, look, &p,
+                        opts->flags | (unaligned ? kPlanUnaligned : 0u) | (block ? kPlanBlock : 0u));
     if (rc) return rc;
+    if (block) {
+        if (!p.packed)
+            return fail(DFA_E_INVAL, "block maps need a DFA with a packed layout (dfa_info_t)");
+        if (p.lookahead == 2)
+            return fail(DFA_E_INVAL, "block maps need lookahead 0, 1 or a precomputed r (<= r0)");
+        if (len == 0 || d_bound || readout)
+            return fail(DFA_E_INVAL, "block maps: empty shard, or boundaries/readout requested");
+        if (block->max < p.stride)
+            return fail(DFA_E_TOOBIG, "block maps: max_entries below the largest start set (" +
+                                          std::to_string(p.stride) + ")");
+        p.before = block->before;
+    }
     if (readout && (!p.packed || len == 0))
         return fail(DFA_E_INVAL, "map readout needs the packed-pair matcher and a non-empty input");
     Workspace *ws = fixed ? nullptr : workspace_for(s);
@@ -130,7 +157,7 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     auto a256 = [](uint64_t b) { return (size_t)((b + 255) / 256 * 256); };
     const size_t map_bytes = a256(p.map_entries * 2);
     const size_t sz_bytes = a256(p.msize_entries * 2);
-    size_t need = map_bytes + 2 * sz_bytes;
+    size_t need = map_bytes + 2 * sz_bytes + (block ? 256u : 0u);   // + block: result record
     size_t code_off = need, bad_off = 0, bsum_off = 0, first_off = 0, tf_off = 0, ccls_off = 0,
            bits_off = 0, mem_off = 0, cset_off = 0, round_off = 0;
     if (p.packed && len) {
@@ -144,9 +171,9 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
             raw ? 64
                 : p.pairs ? ((uint64_t)len + 32) / 32 * 16 + 64
                           : ((uint64_t)len + 16) / 16 * 16 * p.code_bytes + 64;
-        if (p.ilv_nblk)   // whole groups of 64 chunks of ilv_nblk blocks each
-            code_stream = std::max<uint64_t>(
-                code_stream, ((uint64_t)p.nch + 63) / 64 * 64 * p.ilv_nblk * 16 + 64);
+        if (p.ilv_nblk)   // whole groups of 64 chunks of ilv_nblk blocks each (with a
+                          // one-chunk-per-lane last round, each chunk's first bytes only)
+            code_stream = ((uint64_t)p.nch + 63) / 64 * 64 * p.ilv_nblk * 16 + 64;
         need += a256(code_stream);
         bad_off = need;
         need += a256((uint64_t)p.tblocks * 4);
@@ -168,13 +195,19 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         }
         if (p.rounds > 1) {
             // per round: outcomes (4 B per walk or place); rounds >= 1: walk
-            // lists of kRegions regions (8 B per place)
+            // lists of kRegions regions (8 B per place); a one-chunk-per-lane
+            // last round: per-chunk counts and states, and its outcomes
+            // start with kTailSlots places per chunk
             const uint64_t walks = p.max_tiles * (uint64_t)match2_tile_pairs(p.slots);
             const uint64_t places = (uint64_t)kRegions * round_region_cap(p);
+            const uint64_t tail_places = p.tail ? (uint64_t)p.nch * kTailSlots : 0u;
             round_off = need;
             need += a256((uint64_t)kMaxRounds * kRegions * 4);
             for (uint32_t k = 0; k < p.rounds; ++k)
-                need += k ? a256(places * 4) + a256(places * 8) : a256(walks * 4);
+                need += k ? a256((places + (k + 1 == p.rounds ? tail_places : 0u)) * 4) +
+                                a256(places * 8)
+                          : a256(walks * 4);
+            if (p.tail) need += a256((uint64_t)p.nch * 4) + a256(tail_places * 2);
         }
     }
     uint8_t *base = fixed;
@@ -191,6 +224,8 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     uint16_t *maps = (uint16_t *)base;
     uint16_t *msize = (uint16_t *)(base + map_bytes);
     uint16_t *bvals = (uint16_t *)(base + map_bytes + sz_bytes);
+    // a block map's combine writes its result record into the workspace
+    if (block) d_result = (uint32_t *)(base + map_bytes + 2 * sz_bytes);
     Workspace::Stamp st{};
     hipError_t e = hipSuccess;
     if (timing) {
@@ -198,6 +233,8 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
         if (e == hipSuccess) e = hipEventCreate(&st.before_match);
         if (e == hipSuccess) e = hipEventCreate(&st.after_match);
         if (e == hipSuccess) e = hipEventCreate(&st.end);
+        if (e == hipSuccess && p.packed && len) e = hipEventCreate(&st.kern_begin);
+        if (e == hipSuccess && p.packed && len) e = hipEventCreate(&st.kern_end);
         if (e == hipSuccess) e = hipEventRecord(st.begin, s);
         if (e != hipSuccess) return hip_fail(e, "timing events");
     }
@@ -220,13 +257,20 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
             size_t at = round_off;
             pb.cnt = (uint32_t *)(base + at);
             at += a256((uint64_t)kMaxRounds * kRegions * 4);
+            const uint64_t tail_places = p.tail ? (uint64_t)p.nch * kTailSlots : 0u;
             for (uint32_t k = 0; k < p.rounds; ++k) {
                 pb.lo[k] = (uint32_t *)(base + at);
-                at += a256((k ? places : walks) * 4);
+                at += a256((k ? places + (k + 1 == p.rounds ? tail_places : 0u) : walks) * 4);
                 if (k) {
                     pb.list[k] = (uint2 *)(base + at);
                     at += a256(places * 8);
                 }
+            }
+            if (p.tail) {
+                pb.tail_cnt = (uint32_t *)(base + at);
+                at += a256((uint64_t)p.nch * 4);
+                pb.tail_st = (uint16_t *)(base + at);
+                at += a256(tail_places * 2);
             }
         }
         if (readout) {
@@ -236,13 +280,16 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
             pb.out_cap = readout->out_cap;
         }
         rc = launch_match2(d, d_in, start, p, pb, maps, msize, s,
-                           timing ? st.before_match : nullptr);
+                           timing ? st.before_match : nullptr, st.kern_begin, st.kern_end);
         if (rc) return rc;
         if (timing) {
             e = hipEventRecord(st.after_match, s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         rc = launch_combine(d, d_in, start, p, maps, msize, bvals, &pb, d_result, d_bound, s);
+        if (!rc && block)
+            rc = launch_block_out(d, start, p, pb, maps, msize, d_result, block->info, block->start,
+                                  block->end, block->max, s);
     } else {
         if (timing) {
             e = hipEventRecord(st.before_match, s);
@@ -315,6 +362,29 @@ extern "C" int dfa_match_noalloc(const dfa_t *d, const uint8_t *d_input, size_t 
                      d_boundaries, nullptr, region, kScratchBytes);
 }
 
+extern "C" int dfa_match_block(const dfa_t *d, const uint8_t *d_input, size_t offset, size_t len,
+                               uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
+                               uint32_t *d_info, uint16_t *d_start, uint16_t *d_end,
+                               uint32_t max_entries) {
+    if (!d || !d_input || !d_info || !d_start || !d_end)
+        return fail(DFA_E_INVAL, "dfa_match_block: NULL argument");
+    const BlockReq req{offset, d_info, d_start, d_end, max_entries};
+    return run_match(d, d_input + offset, len, start_state, opts, (hipStream_t)stream, nullptr,
+                     nullptr, nullptr, nullptr, 0, &req);
+}
+
+extern "C" int dfa_compose_blocks(const dfa_t *d, uint32_t count, const uint32_t *d_infos,
+                                  const uint16_t *d_starts, const uint16_t *d_ends,
+                                  uint32_t max_entries, uint32_t start_state, void *stream,
+                                  uint32_t *d_result, uint32_t *d_block_states) {
+    if (!d || !d_result || (count && (!d_infos || !d_starts || !d_ends)))
+        return fail(DFA_E_INVAL, "dfa_compose_blocks: NULL argument");
+    if (start_state == DFA_Q0) start_state = d->dev.q0;
+    if (start_state >= d->dev.nq) return fail(DFA_E_INVAL, "dfa_compose_blocks: start state out of range");
+    return launch_compose_blocks(d, count, d_infos, d_starts, d_ends, max_entries, start_state,
+                                 d_result, d_block_states, (hipStream_t)stream);
+}
+
 extern "C" int dfa_match_maps(const dfa_t *d, const uint8_t *d_input, size_t len,
                               uint32_t start_state, const dfa_match_opts_t *opts, void *stream,
                               uint32_t *d_result, uint32_t *d_first, uint16_t *d_pair_start,
@@ -371,6 +441,8 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->levels = p.levels;
     out->group0 = p.levels ? p.group_l[0] : 0u;
     out->group = p.levels > 1 ? p.group_l[1] : 0u;
+    out->tail_lanes = p.tail ? 1u : 0u;
+    out->tail_start = p.tail ? p.tail_t0 : 0u;
     out->raw_input = p.packed && !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2;
     return DFA_OK;
 }
@@ -695,7 +767,7 @@ int timing_end(hipStream_t s, hipEvent_t ev[4]) {
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
     hipError_t e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ws->stamps.push_back({ev[0], ev[1], ev[2], ev[3]});
+    ws->stamps.push_back({ev[0], ev[1], ev[2], ev[3], nullptr, nullptr});
     return DFA_OK;
 }
 }  // namespace dfaspec
@@ -707,30 +779,41 @@ extern "C" int dfa_timing_enable(void *stream, int on) {
     return DFA_OK;
 }
 
-extern "C" int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms,
-                               uint32_t *calls) {
+extern "C" int dfa_timing_read_ex(void *stream, double *matcher_ms, double *call_ms,
+                                  double *kernel_ms, uint32_t *calls) {
     Workspace *ws = workspace_for((hipStream_t)stream);
     if (!ws) return fail(DFA_E_DEVICE, "no HIP device");
-    double m = 0.0, c = 0.0;
+    double m = 0.0, c = 0.0, k = 0.0;
     int rc = DFA_OK;
     for (auto &st : ws->stamps) {
-        float a = 0.f, b = 0.f;
+        float a = 0.f, b = 0.f, x = 0.f;
         hipError_t e = hipEventSynchronize(st.end);
         if (e == hipSuccess) e = hipEventElapsedTime(&a, st.before_match, st.after_match);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, st.begin, st.end);
+        if (e == hipSuccess && st.kern_begin) e = hipEventElapsedTime(&x, st.kern_begin, st.kern_end);
+        else x = a;
         if (e != hipSuccess && rc == DFA_OK) rc = hip_fail(e, "dfa_timing_read");
         m += a;
         c += b;
+        k += x;
         (void)hipEventDestroy(st.begin);
         (void)hipEventDestroy(st.before_match);
         (void)hipEventDestroy(st.after_match);
         (void)hipEventDestroy(st.end);
+        if (st.kern_begin) (void)hipEventDestroy(st.kern_begin);
+        if (st.kern_end) (void)hipEventDestroy(st.kern_end);
     }
     if (calls) *calls = (uint32_t)ws->stamps.size();
     ws->stamps.clear();
     if (matcher_ms) *matcher_ms = m;
     if (call_ms) *call_ms = c;
+    if (kernel_ms) *kernel_ms = k;
     return rc;
+}
+
+extern "C" int dfa_timing_read(void *stream, double *matcher_ms, double *call_ms,
+                               uint32_t *calls) {
+    return dfa_timing_read_ex(stream, matcher_ms, call_ms, nullptr, calls);
 }
 
 extern "C" const char *dfa_strerror(int status) {

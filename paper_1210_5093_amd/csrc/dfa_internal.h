@@ -27,6 +27,12 @@ constexpr uint16_t kCodeInvalid = 0xFFFF;
 constexpr uint32_t kMaxRounds = 6;        // walk rounds with merging (DFA_MATCH_ROUNDS)
 constexpr uint32_t kRound1Bytes = 32;     // bytes of the first round; x4 per later round
 constexpr uint32_t kRegions = 64;         // regions (counters) of a round's walk list
+constexpr uint32_t kTailSlots = 4;        // walks per chunk held for the one-chunk-per-lane
+                                          // last round (more go to its overflow list)
+// plan_match flags (not DFA_MATCH_* bits): the input is not 16-byte aligned;
+// the plan is for a block map (the packed matcher, whatever the input size)
+constexpr uint32_t kPlanUnaligned = 1u << 31;
+constexpr uint32_t kPlanBlock = 1u << 30;
 
 // Device-resident compiled DFA, passed by value to kernels.
 struct DevDFA {
@@ -153,6 +159,14 @@ struct MatchPlan {
     uint32_t slots = 4;          // pairs per lane of a wave-tile (2 or 4)
     bool pairs = false;          // two-symbol steps over the pair table (chunk % 32 == 0)
     uint32_t rounds = 1;         // walk rounds (> 1: merged walks, chunk % 32 == 0)
+    bool tail = false;           // merged walks whose last round runs one chunk per lane
+                                 // over the raw input (the code stream then holds only
+                                 // each chunk's first tail_t0 bytes)
+    uint32_t tail_t0 = 0;        // chunk bytes before the last round
+    uint32_t tail_threads = 0;   // its grid: one lane per chunk
+    uint32_t tail_blocks = 0;
+    uint64_t before = 0;         // block map of a shard: bytes of lookahead readable before
+                                 // the input; chunk 0 then starts from its lookahead set
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)
     uint32_t ilv_nblk = 0;       // chunk-interleaved code stream: 16-byte code blocks per
                                  // chunk (0: linear stream, or the raw input)
@@ -187,6 +201,10 @@ struct PackedBufs {
     uint32_t *lo[kMaxRounds] = {};
     uint2 *list[kMaxRounds] = {};
     uint32_t *cnt = nullptr;         // [kMaxRounds][kRegions]
+    // one-chunk-per-lane last round (MatchPlan::tail): per chunk the number
+    // of walks that reach it and the states of the first kTailSlots
+    uint32_t *tail_cnt = nullptr;    // [nch]
+    uint16_t *tail_st = nullptr;     // [nch][kTailSlots]
     // optional readout of the level-0 maps (dfa_match_maps): the first pair
     // of every chunk, and per pair its start and end state, for pairs < out_cap
     uint32_t *out_first = nullptr;
@@ -196,14 +214,28 @@ struct PackedBufs {
 };
 // The packed path stores level-0 maps indexed by pair (maps[first[i] + p]);
 // pb is null for the one-chunk-per-wave path (maps[i * stride + p]).
+// Block maps of shards (dfa_match_block / dfa_compose_blocks): the composed
+// top-level map with chunk 0's start states, and the ordered composition of
+// several blocks' maps from one start state.
+int launch_block_out(const dfa *d, uint32_t start, const MatchPlan &p, const PackedBufs &b,
+                     const uint16_t *maps, const uint16_t *msize, const uint32_t *rec,
+                     uint32_t *info, uint16_t *out_start, uint16_t *out_end, uint32_t max,
+                     hipStream_t s);
+int launch_compose_blocks(const dfa *d, uint32_t count, const uint32_t *infos,
+                          const uint16_t *starts, const uint16_t *ends, uint32_t max,
+                          uint32_t start, uint32_t *result, uint32_t *states, hipStream_t s);
 int launch_combine(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                    uint16_t *maps, uint16_t *msize, uint16_t *bvals, const PackedBufs *pb,
                    uint32_t *d_result, uint32_t *d_boundaries, hipStream_t s);
 // ev_before_matcher (may be null) is recorded after the preparation kernels,
 // right before the packed matcher kernel.
+// ev_kern_begin / ev_kern_end (may be null): recorded around the plan's
+// longest single matcher launch (the one-chunk-per-lane last round, else the
+// last merged round, else the matcher).
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
-                  hipEvent_t ev_before_matcher);
+                  hipEvent_t ev_before_matcher, hipEvent_t ev_kern_begin = nullptr,
+                  hipEvent_t ev_kern_end = nullptr);
 int launch_down0(const MatchPlan &p, const uint16_t *maps0, const uint32_t *first,
                  const uint16_t *bv_up, uint16_t *bv0, hipStream_t s);
 int set_match2_lds_limit(int lds);

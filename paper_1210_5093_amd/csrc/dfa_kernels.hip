@@ -365,6 +365,10 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // r >= 2 needs the packed matcher (bitmaps); without a packed layout the
     // one-symbol sets are used, which give the same result.
     if (lookahead >= 2 && d->dev.layout == 0) lookahead = 1;
+    // a block map takes precomputed sets only: a longer lookahead is lowered
+    // to them (the set of fewer symbols contains the set of more, Section 4.3)
+    if ((flags & kPlanBlock) && lookahead >= 2 && lookahead > d->dev.r0)
+        lookahead = d->dev.r0 >= 2 ? d->dev.r0 : 1;
     if (lookahead > 64) return fail(DFA_E_INVAL, "lookahead must be at most 64 symbols");
     p->r = lookahead;
     p->lookahead = lookahead <= 1 ? lookahead : (lookahead <= d->dev.r0 ? 3u : 2u);
@@ -398,7 +402,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // path needs fewer launches.  DFA_KERNEL=1 / =2 force either kernel.
     const bool idle_lanes = p->lookahead == 0 ? false : d->wave_util < 0.85;
     p->packed = d->dev.layout != 0 &&
-                (p->lookahead >= 2 ||
+                (p->lookahead >= 2 || (flags & kPlanBlock) ||
                  (!(force && force[0] == '1') &&
                   ((n >= (4u << 20) && idle_lanes) || (force && force[0] == '2'))));
     // two-symbol steps halve the lookups; they need whole 32-byte chunk
@@ -531,6 +535,33 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                        match2_tile_pairs(p->slots) + 1;
     if (p->packed && nch * (uint64_t)setmax >= 0xFFFFFFFFull)
         return fail(DFA_E_TOOBIG, "too many (chunk, state) pairs; raise chunk_len");
+    // merged walks number walks and list places below 2^30 (their outcomes
+    // carry two flag bits above); beyond that a single round runs
+    if (p->rounds > 1 && (uint64_t)p->max_tiles * match2_tile_pairs(p->slots) +
+                                 (uint64_t)p->nch * kTailSlots >= (1ull << 30))
+        p->rounds = 1;
+    // merged walks over interleaved one-symbol codes: the last round takes
+    // one chunk per lane and reads the raw input (bytes to codes through a
+    // table in LDS), so only the first tail_t0 bytes of each chunk are
+    // translated.  Needs a 16-byte aligned input and room for the 1 KiB byte
+    // table; DFA_TAIL=0 keeps the wave-tile last round.
+    {
+        const char *ft = std::getenv("DFA_TAIL");
+        const uint64_t tail_lds = (uint64_t)d->dev.stab_bytes + 1024u + round_lds_extra();
+        p->tail = p->packed && p->rounds > 1 && p->ilv_nblk && !p->pairs && chunk < (1ull << 31) &&
+                  !(flags & kPlanUnaligned) && !(ft && ft[0] == '0') && tail_lds <= (uint64_t)lds;
+        if (p->tail) {
+            p->tail_t0 = kRound1Bytes << (2 * (p->rounds - 2));
+            p->ilv_nblk = p->tail_t0 * p->code_bytes / 16;
+            // workgroups of whole wavefronts, sized so that every CU holds as
+            // many as its LDS allows
+            const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)lds / tail_lds));
+            const uint64_t want = (nch + (uint64_t)cus * per_cu - 1) / ((uint64_t)cus * per_cu);
+            p->tail_threads = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(64, (want + 63) / 64 * 64));
+            p->tail_blocks = (uint32_t)std::min<uint64_t>((nch + p->tail_threads - 1) / p->tail_threads,
+                                                          0x7FFFFFFFull);
+        }
+    }
     return DFA_OK;
 }
 

@@ -111,7 +111,10 @@ __device__ __forceinline__ void translate_grid(const uint8_t *__restrict__ in, u
 // consecutive chunks (lane l: chunk l / PIECES, piece l % PIECES) and goes
 // through their code blocks a quad (4 blocks, PIECES 16-byte input pieces per
 // chunk) at a time, kTrU quads in flight, so that loads are contiguous per
-// chunk and every block's stores of the wave are contiguous too.
+// chunk and every block's stores of the wave are contiguous too.  The stream
+// holds v.nblk blocks per chunk: the whole chunk, or its first bytes when
+// the last round reads the raw input (bytes past them are not read here).
+// code_bytes_per_chunk: a chunk's code bytes in the linear numbering.
 template <int PIECES, typename Conv>
 __device__ __forceinline__ void translate_ilv_grid(const uint8_t *__restrict__ in, uint64_t n,
                                                    uint8_t *out, const Ilv &v,
@@ -128,7 +131,8 @@ __device__ __forceinline__ void translate_ilv_grid(const uint8_t *__restrict__ i
         const uint32_t c = sg * kCpw + cc;
         const bool live = c < v.nch;
         const uint64_t c0 = (uint64_t)c * v.chunk;
-        const uint64_t end = live ? min<uint64_t>(c0 + v.chunk, n) : 0u;
+        const uint64_t coded = min<uint64_t>(v.chunk, (uint64_t)v.nblk * PIECES * 4u);
+        const uint64_t end = live ? min<uint64_t>(c0 + coded, n) : 0u;
         const IlvSink sink{out, v.nblk, c, (uint64_t)c * code_bytes_per_chunk};
         for (uint32_t q0 = 0; q0 < nquad; q0 += kTrU) {
             uint32_t w[kTrU][4];
@@ -271,16 +275,20 @@ struct InfoSrc {
     uint32_t r;
     uint16_t *ccls;
     uint32_t *cset;
+    uint64_t before;         // bytes readable before `in` (a block map: chunk 0 then
+                             // starts from its lookahead set, not the start state)
 };
 
 __device__ __forceinline__ uint32_t chunk_info(const InfoSrc &f, uint64_t i) {
     uint32_t m = 1, id = 0;
-    if (i > 0) {
-        const uint64_t p = i * f.chunk;
+    if (i > 0 || f.before > 0) {
+        // chunk i starts at in + p, with `avail` bytes of lookahead behind it
+        const int64_t p = (int64_t)(i * f.chunk);
+        const uint64_t avail = f.before + i * f.chunk;
         if (f.mode == 3) {
-            const uint32_t k = (uint32_t)min<uint64_t>(f.r, p);
+            const uint32_t k = (uint32_t)min<uint64_t>(f.r, avail);
             bool bad = false;
-            if (k <= 8 && p >= 8 && ((reinterpret_cast<uintptr_t>(f.in) + p) & 7u) == 0) {
+            if (k <= 8 && avail >= 8 && ((reinterpret_cast<uintptr_t>(f.in) + p) & 7u) == 0) {
                 // the 8 bytes before p in one aligned load; the k class
                 // lookups are independent
                 const uint64_t wv = *reinterpret_cast<const uint64_t *>(f.in + p - 8);
@@ -292,7 +300,7 @@ __device__ __forceinline__ uint32_t chunk_info(const InfoSrc &f, uint64_t i) {
                     id = id * f.d.nclass + (cls[j] >> 24);
                 }
             } else {
-                id = class_string_id(f.d, f.in, p - k, k, &bad);
+                id = class_string_id(f.d, f.in + p - (int64_t)k, 0, k, &bad);
             }
             m = bad ? 0u : mset_end(f.d, k, id) - mset_begin(f.d, k, id);
         } else {
@@ -442,11 +450,13 @@ __global__ __launch_bounds__(1024) void k_scan_apply(ScanSrc q, const uint32_t *
 // The last two phases in one pass, for sizes from msize: workgroup b adds up
 // the totals of scan blocks 0 .. b - 1 itself (a few thousand at most), then
 // lays out its chunks as k_scan_apply does; the last workgroup writes
-// first[nch], the first clears the merged-walk round counters.
+// first[nch], the first clears the merged-walk round counters, and every
+// chunk's entry of chunk_zero (per-chunk counters, may be null) is cleared.
 __global__ __launch_bounds__(1024) void k_scan_finish(ScanSrc q, const uint32_t *__restrict__ btot,
                                                       uint32_t *__restrict__ first,
                                                       uint32_t *__restrict__ tile_first,
-                                                      uint32_t *__restrict__ zero, uint32_t nzero) {
+                                                      uint32_t *__restrict__ zero, uint32_t nzero,
+                                                      uint32_t *__restrict__ chunk_zero) {
     __shared__ uint32_t part[kScanThreads];
     const uint32_t t = threadIdx.x, T = blockDim.x;
     if (blockIdx.x == 0)
@@ -470,6 +480,7 @@ __global__ __launch_bounds__(1024) void k_scan_finish(ScanSrc q, const uint32_t 
         const uint64_t i = base + k;
         if (i < q.nch) {
             first[i] = run;
+            if (chunk_zero) chunk_zero[i] = 0;
             if (m[k]) {
                 for (uint32_t w = (run + q.tile - 1) / q.tile; w <= (run + m[k] - 1) / q.tile; ++w)
                     tile_first[w] = (uint32_t)i;
@@ -547,7 +558,7 @@ __global__ __launch_bounds__(256) void k_translate(const uint8_t *__restrict__ i
     };
     uint8_t *ob = reinterpret_cast<uint8_t *>(out);
     if (WRITE && ilv.nblk)
-        translate_ilv_grid<kNarrow ? 4 : 2>(in, n, ob, ilv, (uint64_t)ilv.nblk * 16u, convert);
+        translate_ilv_grid<kNarrow ? 4 : 2>(in, n, ob, ilv, ilv.chunk * sizeof(CodeT), convert);
     else
         translate_grid(in, n, ob, convert);
     if (bad) atomicOr(&bad_any, 1u);
@@ -749,6 +760,7 @@ struct Match2Args {
     uint32_t ilv_nblk;       // chunk-interleaved codes: 16-byte blocks per chunk; 0 = linear
     uint32_t spread;         // tiles to waves: 1 = first wave of every workgroup first
                              // (few, large workgroups per CU), 0 = workgroup by workgroup
+    uint64_t before;         // bytes of lookahead before the input (block maps; 0 = none)
 };
 
 // First 16-byte unit of block b of chunk c in the code stream, and the
@@ -779,7 +791,7 @@ __device__ __forceinline__ uint16_t map_entry(const Match2Args &a, uint32_t c, u
     }
     if (a.mode == 3) {
         const uint16_t ab = a.d.pos[1][e];
-        const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)(c + 1) * a.chunk);
+        const uint32_t k = (uint32_t)min<uint64_t>(a.r, a.before + (uint64_t)(c + 1) * a.chunk);
         const uint32_t id = a.cset[c + 1];
         return ab == (uint16_t)(kTerm | e)
                    ? ab
@@ -791,10 +803,10 @@ __device__ __forceinline__ uint16_t map_entry(const Match2Args &a, uint32_t c, u
 
 // Start state of pair P (chunk c >= 0 of the pair numbering).
 __device__ __forceinline__ uint32_t pair_start(const Match2Args &a, uint32_t c, uint32_t P) {
-    if (c == 0) return a.start;
+    if (c == 0 && a.before == 0) return a.start;
     if (a.mode == 2) return a.members[P];
     if (a.mode == 3) {
-        const uint32_t k = (uint32_t)min<uint64_t>(a.r, (uint64_t)c * a.chunk);
+        const uint32_t k = (uint32_t)min<uint64_t>(a.r, a.before + (uint64_t)c * a.chunk);
         return a.d.mset_st[a.d.mst[k] + mset_begin(a.d, k, a.cset[c]) + (P - a.first[c])];
     }
     return a.d.set_st[a.mode][a.d.set_off[a.mode][a.ccls[c]] + (P - a.first[c])];
@@ -979,6 +991,13 @@ struct RoundArgs {
                                //  state, or the place of its leader in out_list
     uint2 *out_list;           // the next round's walks
     uint32_t *out_cnt;         // [kRegions] its counters (zero before the first round)
+    // the round before a one-chunk-per-lane last round: a leader takes a slot
+    // of its chunk (tail_cnt[c] counts them; place c * kTailSlots + slot);
+    // leaders beyond kTailSlots go to out_list, whose places then start at
+    // next_off in the last round's outcomes
+    uint32_t *tail_cnt;
+    uint16_t *tail_st;
+    uint32_t next_off;
 };
 
 template <int S>
@@ -1119,12 +1138,27 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
                 }
             }
         }
-        // leaders take consecutive places in the next list
+        // leaders take a slot of their chunk (before a one-chunk-per-lane
+        // last round), else consecutive places in the next list
         uint32_t nlead = 0, myidx[S];
+        bool listed[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            const uint64_t lm = __ballot(is_lead[j]);
-            myidx[j] = nlead + (uint32_t)__popcll(lm & lanes_lt);
+            listed[j] = is_lead[j];
+            myidx[j] = 0;
+            if (m.tail_cnt && is_lead[j]) {
+                const uint32_t k = atomicAdd(m.tail_cnt + ci[j], 1u);
+                if (k < kTailSlots) {
+                    myidx[j] = ci[j] * kTailSlots + k;
+                    m.tail_st[myidx[j]] = (uint16_t)e[j];
+                    listed[j] = false;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const uint64_t lm = __ballot(listed[j]);
+            if (listed[j]) myidx[j] = nlead + (uint32_t)__popcll(lm & lanes_lt);
             nlead += (uint32_t)__popcll(lm);
         }
         uint32_t base = 0;
@@ -1135,8 +1169,11 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
         }
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            myidx[j] += base;
-            if (is_lead[j]) m.out_list[myidx[j]] = make_uint2(ci[j], e[j]);
+            if (listed[j]) {
+                myidx[j] += base;
+                m.out_list[myidx[j]] = make_uint2(ci[j], e[j]);
+                myidx[j] += m.next_off;
+            }
         }
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -1371,6 +1408,282 @@ __global__ __launch_bounds__(1024, 8) void k_chunk_walk(Match2Args a, ChunkWalkA
     }
 }
 
+// ---------------------------------------------------------------------------
+// The last round of merged walks, one chunk per lane (MatchPlan::tail).  By
+// the start of the last round the walks of a chunk have mostly met: the
+// round before hands each chunk's remaining walks to this kernel (up to
+// kTailSlots per chunk; more go to an overflow list, walked one per lane by
+// the same kernel in list mode).  Lane c walks chunk c's states from byte t0
+// to the chunk's end, reading the raw input: each byte becomes its code
+// through a 256-entry table in LDS (an entry is the code, with kTailBad set
+// for a byte outside Sigma).  The bytes a tail reads are validated here: the
+// translation pass covered only every chunk's first t0 bytes, so every lane
+// whose chunk extends past t0 walks it, with no state if its walks all ended.
+// Walks of a lane that meet are merged at segment ends (2 t0, 4 t0, ...):
+// a wavefront runs as many chains as its busiest lane (0, 1, 2 or 4), mostly
+// one.  A lane loads its chunk 32 bytes at a time, one group ahead (eight
+// wavefronts per SIMD fit in the registers).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTailBad = 0x10000u;
+
+struct TailArgs {
+    const uint8_t *in;         // the raw input (16-byte aligned)
+    uint32_t t0;               // chunk bytes walked by the earlier rounds
+    const uint32_t *cnt;       // [nch] walks handed over per chunk
+    const uint16_t *st;        // [nch][kTailSlots] their states
+    uint32_t *lo;              // the last round's outcomes: [nch][kTailSlots], then the
+                               //  overflow list's places
+    const uint32_t *ovf_cnt;   // [kRegions] overflow walks per region
+    const uint2 *ovf_list;     // overflow walks {chunk, state} per place
+    uint32_t cap;              // places per region
+    uint32_t *bad;             // OR-ed with 1 when a byte outside Sigma is read
+    uint32_t list_mode;        // 0: lanes over chunks; 1: lanes over overflow walks
+};
+
+// 16 bytes: codes from the byte table, then 16 steps of each of the NS
+// chains (NS = 0: validation only).
+template <int NS>
+__device__ __forceinline__ void tail_piece(const uint4 &v, uint32_t lut,
+                                           uint32_t (&st)[NS > 0 ? NS : 1], uint32_t &bad) {
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            e[k] = lds_ld32(lut + (((w4[q] >> (8 * k)) & 0xFFu) << 2));
+            bad |= e[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 0>(st[j], e[k]));
+    }
+}
+
+// Bytes [from, to) of the chunk at cb (from a multiple of 16; to = from
+// when the lane has nothing to walk).
+template <int NS>
+__device__ __forceinline__ void tail_walk(const uint8_t *__restrict__ cb, uint32_t from, uint32_t to,
+                                          uint32_t lut, uint32_t (&st)[NS > 0 ? NS : 1],
+                                          uint32_t &bad) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(cb + from);
+    constexpr uint32_t GP = 2;   // pieces per group
+    const uint32_t ng = (to - from) / (16 * GP);
+    if (ng) {
+        // ring of two groups: a group is reloaded right after its walk, so
+        // the other group's walk covers the load
+        const uint32_t lastg = ng - 1;
+        uint4 ring[2][GP];
+#pragma unroll
+        for (uint32_t k = 0; k < 2; ++k)
+#pragma unroll
+            for (int h = 0; h < GP; ++h) ring[k][h] = p[min(k, lastg) * GP + h];
+        uint32_t g0 = 0;
+        for (; g0 + 2 <= ng; g0 += 2) {
+#pragma unroll
+            for (uint32_t k = 0; k < 2; ++k) {
+#pragma unroll
+                for (int h = 0; h < GP; ++h) tail_piece<NS>(ring[k][h], lut, st, bad);
+                const uint32_t gn = min(g0 + k + 2, lastg);
+#pragma unroll
+                for (int h = 0; h < GP; ++h) ring[k][h] = p[gn * GP + h];
+            }
+        }
+        if (g0 < ng) {
+#pragma unroll
+            for (int h = 0; h < GP; ++h) tail_piece<NS>(ring[0][h], lut, st, bad);
+        }
+    }
+    uint32_t at = from + ng * 16 * GP;
+    for (; at + 16 <= to; at += 16) tail_piece<NS>(*reinterpret_cast<const uint4 *>(cb + at), lut, st, bad);
+    for (; at < to; ++at) {   // the input's last bytes
+        const uint32_t e = lds_ld32(lut + ((uint32_t)cb[at] << 2));
+        bad |= e;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 0>(st[j], e));
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+
+// Walk the lane's chains st[0 .. nl) over [from, to) with the wave's chain
+// count ns (wave-uniform; lanes with fewer chains repeat their first).
+__device__ __forceinline__ void tail_walk_n(uint32_t ns, const uint8_t *cb, uint32_t from,
+                                            uint32_t to, uint32_t lut, uint32_t (&st)[4],
+                                            uint32_t &bad) {
+    if (ns == 0) {
+        uint32_t s0[1] = {0};
+        tail_walk<0>(cb, from, to, lut, s0, bad);
+    } else if (ns == 1) {
+        uint32_t s1[1] = {st[0]};
+        tail_walk<1>(cb, from, to, lut, s1, bad);
+        st[0] = s1[0];
+    } else if (ns == 2) {
+        uint32_t s2[2] = {st[0], st[1]};
+        tail_walk<2>(cb, from, to, lut, s2, bad);
+        st[0] = s2[0];
+        st[1] = s2[1];
+    } else {
+        tail_walk<4>(cb, from, to, lut, st, bad);
+    }
+}
+
+// Chains that reached the same state become one: st[0 .. nl) keeps the
+// distinct states in order, map (4 bits per handed-over walk) is updated.
+__device__ __forceinline__ void tail_merge(uint32_t (&st)[4], uint32_t &nl, uint32_t &map) {
+    uint32_t where[4], nst[4] = {st[0], st[0], st[0], st[0]}, k2 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t f = 0xFFu;
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+            if (f == 0xFFu && (uint32_t)i < nl && st[i] == st[j]) f = where[i];
+        if ((uint32_t)j < nl && f == 0xFFu) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((uint32_t)q == k2) nst[q] = st[j];
+            f = k2++;
+        }
+        where[j] = f;
+    }
+    uint32_t m2 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t cur = (map >> (4 * k)) & 0xFu;
+        uint32_t w = where[0];
+#pragma unroll
+        for (int j = 1; j < 4; ++j)
+            if (cur == (uint32_t)j) w = where[j];
+        m2 |= (w & 0xFu) << (4 * k);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st[q] = nst[q];
+    nl = k2;
+    map = m2;
+}
+
+template <int L>
+__global__ __launch_bounds__(1024, 8) void k_tail(Match2Args a, TailArgs t) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    // list mode: nothing to do unless some chunk had more than kTailSlots
+    // walks (the count is uniform, so whole workgroups leave together)
+    if (t.list_mode) {
+        uint32_t tot = 0;
+        for (uint32_t g = 0; g < kRegions; ++g) tot += t.ovf_cnt[g];
+        if (tot == 0) return;
+    }
+    stage_table<L>(a.d, smem);
+    const uint32_t lut = a.d.stab_bytes;
+    uint32_t *lut_w = reinterpret_cast<uint32_t *>(smem + lut);
+    uint32_t *region_pre = reinterpret_cast<uint32_t *>(smem + lut + 1024);
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        const uint16_t c = a.d.code[i];
+        lut_w[i] = c == kCodeInvalid ? kTailBad : (uint32_t)c;
+    }
+    if (t.list_mode && threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t g = 0; g < kRegions; ++g) {
+            region_pre[g] = acc;
+            acc += t.ovf_cnt[g];
+        }
+        region_pre[kRegions] = acc;
+    }
+    __syncthreads();
+    const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
+    uint32_t bad = 0;
+    if (!t.list_mode) {
+        // lanes over chunks (the loop bound is uniform: every lane of a
+        // wavefront takes part in its shuffles)
+        const uint32_t T = gridDim.x * blockDim.x;
+        for (uint32_t c0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); c0 < a.nch; c0 += T) {
+            const uint32_t c = c0 + (threadIdx.x & 63u);
+            const bool in = c < a.nch;
+            const uint64_t len = in ? min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk) : 0u;
+            const uint32_t to = len > t.t0 ? (uint32_t)len : t.t0;
+            const uint32_t cnt = len > t.t0 ? min(t.cnt[c], kTailSlots) : 0u;
+            uint32_t st[4] = {0, 0, 0, 0};
+            if (cnt) {
+                const uint2 sv = reinterpret_cast<const uint2 *>(t.st)[c];   // kTailSlots == 4
+                const uint32_t s4[4] = {sv.x & 0xFFFFu, sv.x >> 16, sv.y & 0xFFFFu, sv.y >> 16};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) st[k] = R * ((uint32_t)k < cnt ? s4[k] : s4[0]);
+            }
+            uint32_t nl = cnt, map = 0x3210u;
+            const uint8_t *cb = t.in + (uint64_t)c * a.chunk;
+            uint32_t pos = t.t0;
+            uint64_t seg = 2ull * t.t0;
+            while (__any(pos < to)) {
+                const uint32_t ns = wave_max(pos < to ? nl : 0u);
+                const uint32_t end = ns <= 1 ? to : (uint32_t)min<uint64_t>(seg, to);
+                const uint32_t lo = min(pos, to), hi = max(min(end, to), lo);
+                tail_walk_n(ns, cb, lo, hi, lut, st, bad);
+                pos = max(pos, hi);
+                if (ns > 1) tail_merge(st, nl, map);
+                seg *= 2;
+            }
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t cur = (map >> (4 * k)) & 0xFu;
+                const uint32_t s = cur == 0 ? st[0] : cur == 1 ? st[1] : cur == 2 ? st[2] : st[3];
+                t.lo[c * kTailSlots + k] = kDone | kMapped | map_entry(a, c, s / R);
+            }
+        }
+    } else {
+        // lanes over the overflow walks
+        const uint32_t total = region_pre[kRegions];
+        const uint32_t T = gridDim.x * blockDim.x;
+        for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total; w += T) {
+            uint32_t lo = 0, hi = kRegions;
+            while (hi > lo + 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (region_pre[mid] <= w) lo = mid; else hi = mid;
+            }
+            const uint32_t place = lo * t.cap + (w - region_pre[lo]);
+            const uint2 rec = t.ovf_list[place];
+            const uint32_t c = rec.x;
+            const uint32_t len = (uint32_t)min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk);
+            uint32_t s1[1] = {R * rec.y};
+            tail_walk<1>(t.in + (uint64_t)c * a.chunk, t.t0, len, lut, s1, bad);
+            t.lo[a.nch * kTailSlots + place] = kDone | kMapped | map_entry(a, c, s1[0] / R);
+        }
+    }
+    if (__any(bad & kTailBad) && (threadIdx.x & 63u) == 0) atomicOr(t.bad, 1u);
+}
+
+// Block map output (a shard matched from its lookahead set): entry p of the
+// composed top-level map belongs to chunk 0's p-th start state; it holds
+// kTerm | the state at the shard's end, or names no state (kBadPos: the walk
+// from that start state met a chunk start outside the next chunk's set).
+// rec: the combine's result record (its flags carry bytes outside Sigma).
+struct BlockOut {
+    uint32_t *info;          // [4]: entries, flags, chunks, 0
+    uint16_t *start;         // [max]
+    uint16_t *end;           // [max]; 0xFFFF = no state
+    uint32_t max;
+};
+
+__global__ __launch_bounds__(256) void k_block_out(Match2Args a, const uint16_t *__restrict__ top,
+                                                   const uint16_t *__restrict__ top_msize,
+                                                   const uint32_t *__restrict__ rec, BlockOut bo) {
+    const uint32_t m0 = top_msize ? (top_msize[0] & 0x7FFFu) : a.first[1];
+    const uint32_t n = min(m0, bo.max);
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        bo.start[p] = (uint16_t)pair_start(a, 0, p);
+        const uint32_t v = top[p];
+        bo.end[p] = (v & kTerm) && (v & 0x7FFFu) < a.d.nq ? (uint16_t)(v & 0x7FFFu) : (uint16_t)0xFFFFu;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        bo.info[0] = m0;
+        bo.info[1] = rec[2] & DFA_FLAG_SYMBOL;
+        bo.info[2] = a.nch;
+        bo.info[3] = 0;
+    }
+}
+
 // Down-sweep into pair-indexed level-0 maps: bv0[i] = value at chunk i's start.
 __global__ void k_down0(const uint16_t *__restrict__ maps0, const uint32_t *__restrict__ first,
                         uint32_t nch, uint32_t G, const uint16_t *__restrict__ bv_up,
@@ -1458,6 +1771,10 @@ const void *chunk_walk_kernel(uint32_t L) {
         reinterpret_cast<const void *>(&k_chunk_walk<3>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
     return tab[L - 1];
 }
+const void *tail_kernel(uint32_t L) {
+    return L == 1 ? reinterpret_cast<const void *>(&k_tail<1>)
+                  : reinterpret_cast<const void *>(&k_tail<2>);
+}
 const void *round_kernel(uint32_t L, uint32_t slots, bool ex) {
 #define DFA_RK(l) {{reinterpret_cast<const void *>(&k_round<l, 2, false>),      \
                     reinterpret_cast<const void *>(&k_round<l, 2, true>)},       \
@@ -1477,7 +1794,14 @@ const void *window2_kernel(uint32_t L, uint32_t slots) {
 
 int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                   const PackedBufs &b, uint16_t *maps, uint16_t *msize, hipStream_t s,
-                  hipEvent_t ev_before_matcher) {
+                  hipEvent_t ev_before_matcher, hipEvent_t ev_kern_begin,
+                  hipEvent_t ev_kern_end) {
+    // events around the plan's longest single matcher launch (timing only)
+    auto mark = [&](hipEvent_t ev) -> int {
+        if (!ev) return DFA_OK;
+        const hipError_t er = hipEventRecord(ev, s);
+        return er == hipSuccess ? DFA_OK : hip_fail(er, "hipEventRecord");
+    };
     // two-symbol steps (the plan checked the chunk length); else direct
     // tables: the matcher reads the (16-byte aligned) input itself
     const bool pairs = p.pairs && d->dev.pairs;
@@ -1494,7 +1818,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     // from the raw input) before they translate, and one pass finishes the
     // scan; the window pass needs the three-phase scan.
     ScanSrc q{msize, b.bits, p.bitmap_words, p.nch, kWave2 * p.slots};
-    const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset};
+    const InfoSrc info{d->dev, d_in, p.chunk, p.lookahead, p.r, b.ccls, b.cset, p.before};
     const bool fused_scan = p.lookahead != 2;
     const uint32_t nsb = match2_scan_blocks(p.nch);
     {
@@ -1547,6 +1871,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     a.tile = kWave2 * p.slots;
     a.ilv_nblk = p.ilv_nblk;
     a.spread = p.threads2 >= 1024 ? 1u : 0u;
+    a.before = p.before;
     const size_t lds = a.d.stab_bytes;
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
@@ -1560,7 +1885,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         launch_scan<1>(p, q, b, nullptr, start, s);
     } else {
         hipLaunchKernelGGL(k_scan_finish, dim3(nsb), dim3(kScanThreads), 0, s, q, b.bsum, b.first,
-                           b.tile_first, b.cnt, b.cnt ? kMaxRounds * kRegions : 0u);
+                           b.tile_first, b.cnt, b.cnt ? kMaxRounds * kRegions : 0u, b.tail_cnt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "packed-matcher preparation launch");
@@ -1578,13 +1903,20 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         const uint32_t tpb = p.threads2;
         const uint32_t blocks =
             std::max<uint32_t>(1u, std::min<uint32_t>((p.nch + tpb - 1) / tpb, p.blocks2));
+        if (int rc = mark(ev_kern_begin)) return rc;
         e = hipLaunchKernel(chunk_walk_kernel(L), dim3(blocks), dim3(tpb), cargs, lds, s);
         if (e != hipSuccess) return hip_fail(e, "k_chunk_walk launch");
+        if (int rc = mark(ev_kern_end)) return rc;
     } else if (p.rounds > 1) {
         if (p.early_exit || p.chunk % 32 != 0 || !b.cnt)
             return fail(DFA_E_INVAL, "merged walks need no early exit and chunks of 32k");
+        if (p.tail && (!b.tail_cnt || (L != 1 && L != 2) || p.tail_t0 % 32 != 0))
+            return fail(DFA_E_INVAL, "one-chunk-per-lane last round: plan and buffers disagree");
         const void *rf = round_kernel(L, p.slots, a.d.nabs > 0);
-        for (uint32_t k = 0; k < p.rounds; ++k) {
+        // with a one-chunk-per-lane last round the wave-tile rounds stop one
+        // round early; the last of them hands its walks to k_tail
+        const uint32_t tiled = p.tail ? p.rounds - 1 : p.rounds;
+        for (uint32_t k = 0; k < tiled; ++k) {
             RoundArgs m;
             m.t0 = k == 0 ? 0u : kRound1Bytes << (2 * (k - 1));
             m.t1 = kRound1Bytes << (2 * k);
@@ -1596,10 +1928,33 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             m.out_lo = b.lo[k];
             m.out_list = m.last_round ? nullptr : b.list[k + 1];
             m.out_cnt = m.last_round ? nullptr : b.cnt + (size_t)(k + 1) * kRegions;
+            const bool hand = p.tail && k + 1 == tiled;
+            m.tail_cnt = hand ? b.tail_cnt : nullptr;
+            m.tail_st = hand ? b.tail_st : nullptr;
+            m.next_off = hand ? p.nch * kTailSlots : 0u;
             void *rargs[] = {&a, &m};
+            const bool timed = !p.tail && k + 1 == tiled;
+            if (timed)
+                if (int rc = mark(ev_kern_begin)) return rc;
             e = hipLaunchKernel(rf, dim3(p.blocks2), dim3(p.threads2), rargs,
                                 lds + round_lds_extra(), s);
             if (e != hipSuccess) return hip_fail(e, "k_round launch");
+            if (timed)
+                if (int rc = mark(ev_kern_end)) return rc;
+        }
+        if (p.tail) {
+            const uint32_t last = p.rounds - 1;
+            TailArgs t{d_in, p.tail_t0, b.tail_cnt, b.tail_st, b.lo[last], b.cnt + (size_t)last * kRegions,
+                       b.list[last], round_region_cap(p), b.block_bad, 0u};
+            const size_t tl = lds + 1024u + round_lds_extra();
+            void *targs[] = {&a, &t};
+            if (int rc = mark(ev_kern_begin)) return rc;
+            e = hipLaunchKernel(tail_kernel(L), dim3(p.tail_blocks), dim3(p.tail_threads), targs, tl, s);
+            if (e != hipSuccess) return hip_fail(e, "k_tail launch");
+            if (int rc = mark(ev_kern_end)) return rc;
+            t.list_mode = 1u;
+            e = hipLaunchKernel(tail_kernel(L), dim3(p.blocks2), dim3(p.threads2), targs, tl, s);
+            if (e != hipSuccess) return hip_fail(e, "k_tail (overflow) launch");
         }
         MergeMapArgs mm{};
         for (uint32_t k = 0; k < p.rounds; ++k) mm.lo[k] = b.lo[k];
@@ -1610,9 +1965,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         if (e != hipSuccess) return hip_fail(e, "k_merge_maps launch");
     } else {
         void *args[] = {&a};
+        if (int rc = mark(ev_kern_begin)) return rc;
         e = hipLaunchKernel(match2_kernel(L, p.slots, p.early_exit), dim3(p.blocks2),
                             dim3(p.threads2), args, lds, s);
         if (e != hipSuccess) return hip_fail(e, "k_match2 launch");
+        if (int rc = mark(ev_kern_end)) return rc;
     }
     if (b.out_first) {
         // readout of the level-0 maps: one thread per chunk boundary and pair
@@ -1625,6 +1982,83 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         if (e != hipSuccess) return hip_fail(e, "k_decode_maps launch");
     }
     return DFA_OK;
+}
+
+int launch_block_out(const dfa *d, uint32_t start, const MatchPlan &p, const PackedBufs &b,
+                     const uint16_t *maps, const uint16_t *msize, const uint32_t *rec,
+                     uint32_t *info, uint16_t *out_start, uint16_t *out_end, uint32_t max,
+                     hipStream_t s) {
+    Match2Args a{};
+    a.d = d->dev;
+    a.n = p.n;
+    a.chunk = p.chunk;
+    a.nch = p.nch;
+    a.start = start;
+    a.mode = p.lookahead;
+    a.r = p.r;
+    a.first = b.first;
+    a.ccls = b.ccls;
+    a.cset = b.cset;
+    a.members = b.members;
+    a.before = p.before;
+    const uint16_t *top = maps + p.level_off[p.levels];
+    const uint16_t *top_msize = p.levels ? msize + p.msize_off[p.levels] : nullptr;
+    const BlockOut bo{info, out_start, out_end, max};
+    hipLaunchKernelGGL(k_block_out, dim3((std::max<uint32_t>(max, 1u) + 255) / 256), dim3(256), 0, s,
+                       a, top, top_msize, rec, bo);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_block_out launch");
+}
+
+// Ordered composition of block maps (Eq. 9 over shards): one wavefront
+// follows the state from block to block, each lane searching a slice of the
+// block's start states.
+__global__ __launch_bounds__(64) void k_compose_blocks(DevDFA d, uint32_t count,
+                                                       const uint32_t *__restrict__ infos,
+                                                       const uint16_t *__restrict__ starts,
+                                                       const uint16_t *__restrict__ ends,
+                                                       uint32_t max, uint32_t start,
+                                                       uint32_t *__restrict__ result,
+                                                       uint32_t *__restrict__ states) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t s = start, flags = 0, chunks = 0;
+    if (states && lane == 0) states[0] = s;
+    for (uint32_t g = 0; g < count; ++g) {
+        const uint32_t *inf = infos + 4ull * g;
+        flags |= inf[1] & DFA_FLAG_SYMBOL;
+        chunks += inf[2];
+        if (!flags) {
+            const uint32_t m = min(inf[0], max);
+            uint32_t hit = 0xFFFFFFFFu;
+            for (uint32_t p = lane; p < m; p += 64)
+                if (starts[(size_t)g * max + p] == s) hit = p;
+            const uint64_t mask = __ballot(hit != 0xFFFFFFFFu);
+            if (mask) {
+                const uint32_t p = __shfl(hit, (int)(__ffsll((unsigned long long)mask) - 1));
+                const uint32_t e = ends[(size_t)g * max + p];
+                if (e < d.nq) s = e; else flags |= DFA_FLAG_SPECULATION;
+            } else {
+                flags |= DFA_FLAG_SPECULATION;
+            }
+        }
+        if (states && lane == 0) states[g + 1] = flags ? 0xFFFFFFFFu : s;
+    }
+    if (lane == 0) {
+        const bool ok = flags == 0;
+        result[0] = ok ? s : 0xFFFFFFFFu;
+        result[1] = ok ? (d.accept_bits[s >> 5] >> (s & 31)) & 1u : 0u;
+        result[2] = flags;
+        result[3] = chunks;
+    }
+}
+
+int launch_compose_blocks(const dfa *d, uint32_t count, const uint32_t *infos,
+                          const uint16_t *starts, const uint16_t *ends, uint32_t max,
+                          uint32_t start, uint32_t *result, uint32_t *states, hipStream_t s) {
+    hipLaunchKernelGGL(k_compose_blocks, dim3(1), dim3(64), 0, s, d->dev, count, infos, starts, ends,
+                       max, start, result, states);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DFA_OK : hip_fail(e, "k_compose_blocks launch");
 }
 
 int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *first,
@@ -1663,7 +2097,7 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(3),
-                         chunk_walk_kernel(4),
+                         chunk_walk_kernel(4), tail_kernel(1), tail_kernel(2),
                          round_kernel(1, 2, false), round_kernel(1, 4, false),
                          round_kernel(2, 2, false), round_kernel(2, 4, false),
                          round_kernel(3, 2, false), round_kernel(3, 4, false),

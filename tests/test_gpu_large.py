@@ -27,10 +27,11 @@ MiB = 1 << 20
 
 # (lookahead, chunk, options) of the readout checks: the benchmark's settings
 # first, then three others
-PROTEIN_MAPS = [(4, 8192, {"chunk_lanes": True, "single_step": True}), (6, 65536, {"rounds": 4}),
+PROTEIN_MAPS = [(4, 65536, {"rounds": 2, "interleave": True, "single_step": True}),
+                (4, 8192, {"chunk_lanes": True, "single_step": True}), (6, 65536, {"rounds": 4}),
                 (1, 4096, {}), (8, 1 << 20, {})]
-BYTE_MAPS = [(2, 131072, {"rounds": 5, "interleave": True}), (4, 32768, {"rounds": 4}),
-             (1, 4096, {}), (3, 1 << 20, {})]
+BYTE_MAPS = [(2, 65536, {"rounds": 6, "interleave": True}), (2, 131072, {"rounds": 5, "interleave": True}),
+             (4, 32768, {"rounds": 4}), (1, 4096, {}), (3, 1 << 20, {})]
 
 
 def say(*a):

@@ -135,7 +135,8 @@ int run_match(const dfa_t *d, const uint8_t *d_in, size_t len, uint32_t start,
     MatchPlan p;
     const bool unaligned = (reinterpret_cast<uintptr_t>(d_in) & 15u) != 0;
     int rc = plan_match(d, len, chunk, look, &p,
-                        opts->flags | (unaligned ? kPlanUnaligned : 0u) | (block ? kPlanBlock : 0u));
+                        opts->flags | (unaligned ? kPlanUnaligned : 0u) | (block ? kPlanBlock : 0u),
+                        block ? block->before : 0u);
     if (rc) return rc;
     if (block) {
         if (!p.packed)

@@ -177,9 +177,11 @@ struct MatchPlan {
     uint64_t max_tiles = 0;      // upper bound on wave-tiles of pairs
 };
 
-// flags: DFA_MATCH_* bits (early exit, walk rounds)
+// flags: DFA_MATCH_* bits (early exit, walk rounds) and kPlan* bits.
+// before: bytes of lookahead readable before the input (block maps; 0 = a
+// whole string, whose chunk 0 starts from the start state).
 int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p,
-               uint32_t flags = 0);
+               uint32_t flags = 0, uint64_t before = 0);
 // ev_after_match (may be null) is recorded right after the matcher kernel.
 int launch_match(const dfa *d, const uint8_t *d_in, uint32_t start, const MatchPlan &p,
                  uint16_t *maps, uint16_t *msize, uint16_t *bvals, uint32_t *d_result,

@@ -359,7 +359,7 @@ int device_lds_bytes() { return props().lds; }
 int device_cu_count() { return props().cus; }
 
 int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead, MatchPlan *p,
-               uint32_t flags) {
+               uint32_t flags, uint64_t before) {
     *p = MatchPlan();
     p->n = n;
     // r >= 2 needs the packed matcher (bitmaps); without a packed layout the
@@ -445,6 +445,19 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         }
     }
     p->chunk = chunk;
+    // a chunk whose lookahead reaches back fewer than r bytes (chunk 1 when
+    // chunks are shorter than r; a block map's chunk 0 with fewer bytes
+    // before it) starts from the set of that many symbols, which can be
+    // larger than the r-symbol sets: size maps and tiles for the shortest
+    // lookahead any chunk has
+    if (p->lookahead >= 2) {
+        const uint64_t lead = before ? before : chunk;
+        const uint32_t kmin = (uint32_t)std::min<uint64_t>(std::min(p->r, d->dev.r0), lead);
+        if (kmin >= 1 && d->mset_max[kmin] > setmax) {
+            setmax = d->mset_max[kmin];
+            p->stride = (setmax + 7u) & ~7u;
+        }
+    }
     const uint64_t nch = (n + chunk - 1) / chunk;
     if (nch > 0xFFFFFFFFull) return fail(DFA_E_TOOBIG, "too many chunks; raise chunk_len");
     p->nch = (uint32_t)nch;

@@ -71,8 +71,9 @@ def run_blocks(dfa, d, dev, bounds, look, chunk, start=None, check=None, **kw):
     import torch
     G = len(bounds) - 1
     n = bounds[-1]
-    plan = dfa.dfa_plan(d, max(bounds[k + 1] - bounds[k] for k in range(G)), chunk, look, **kw)
-    mx = max(8, int(plan.set_max))
+    # room for any start set (a shard with fewer lookahead bytes before it
+    # than r starts from a set of fewer symbols, larger than dfa_plan's)
+    mx = (int(d.info().num_states) + 7) // 8 * 8
     infos = torch.empty((G, 4), dtype=torch.int32, device="cuda")
     starts = torch.empty((G, mx), dtype=torch.int16, device="cuda")
     ends = torch.empty((G, mx), dtype=torch.int16, device="cuda")

@@ -438,6 +438,21 @@ def test_lookahead_longer_than_chunks(dfa_mod, chunk):
     check(dfa_mod, configs.c2_dfa(), configs.c2_input(20_000), chunk=chunk * 13, lookahead=6)
 
 
+@pytest.mark.parametrize("chunk", [1, 2, 3, 5])
+def test_chunks_shorter_than_lookahead_large_sets(dfa_mod, chunk):
+    """Chunks shorter than r: chunk 1's lookahead has only `chunk` symbols,
+    and sets of fewer symbols can be larger than the r-symbol sets (Lemma,
+    Section 4.3), so maps and tiles are sized for the shortest lookahead."""
+    d = dfa_mod.DFA.from_workload(configs.c3_byte_dfa())
+    plan = dfa_mod.dfa_plan(d, 20_000, chunk, 2)
+    assert plan.set_max >= d.info().imax if chunk == 1 else True
+    d.close()
+    check(dfa_mod, configs.c3_byte_dfa(), configs.c3_byte_input(20_000), chunk=chunk, lookahead=2)
+    check(dfa_mod, configs.c3_protein_dfa(), configs.c3_protein_input(20_001), chunk=chunk,
+          lookahead=4)
+    check(dfa_mod, configs.c2_dfa(), configs.c2_input(20_002), chunk=chunk, lookahead=6)
+
+
 def test_lookahead_shrinks_sets_and_keeps_result(dfa_mod):
     """Lemma (Section 4.3): more lookahead never enlarges a start set, so the
     result is unchanged and the work (lookups) does not grow."""

@@ -941,7 +941,7 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
 C3_SETTINGS = {
     "protein": {"lookahead": 4, "chunk": 65536, "rounds": 2, "interleave": True,
                 "single_step": True},
-    "byte": {"lookahead": 2, "chunk": 65536, "rounds": 6, "interleave": True},
+    "byte": {"lookahead": 2, "chunk": 65536, "rounds": 4, "interleave": True},
 }
 
 

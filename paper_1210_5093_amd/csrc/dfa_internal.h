@@ -27,7 +27,7 @@ constexpr uint16_t kCodeInvalid = 0xFFFF;
 constexpr uint32_t kMaxRounds = 6;        // walk rounds with merging (DFA_MATCH_ROUNDS)
 constexpr uint32_t kRound1Bytes = 32;     // bytes of the first round; x4 per later round
 constexpr uint32_t kRegions = 64;         // regions (counters) of a round's walk list
-constexpr uint32_t kTailSlots = 4;        // walks per chunk held for the one-chunk-per-lane
+constexpr uint32_t kTailSlots = 8;        // walks per chunk held for the one-chunk-per-lane
                                           // last round (more go to its overflow list)
 // plan_match flags (not DFA_MATCH_* bits): the input is not 16-byte aligned;
 // the plan is for a block map (the packed matcher, whatever the input size)
@@ -163,7 +163,8 @@ struct MatchPlan {
                                  // over the raw input (the code stream then holds only
                                  // each chunk's first tail_t0 bytes)
     uint32_t tail_t0 = 0;        // chunk bytes before the last round
-    uint32_t tail_threads = 0;   // its grid: one lane per chunk
+    uint32_t tail_threads = 0;   // its grid: one lane per chunk (+ one wavefront per
+                                 // workgroup for the overflow list)
     uint32_t tail_blocks = 0;
     uint64_t before = 0;         // block map of a shard: bytes of lookahead readable before
                                  // the input; chunk 0 then starts from its lookahead set
@@ -301,6 +302,7 @@ int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *fi
 uint32_t match2_tile_pairs(uint32_t slots);
 uint32_t round_region_cap(const MatchPlan &p);   // places per region of a walk list
 size_t round_lds_extra();                         // LDS the round kernels add after the table
+size_t tail_lut_bytes();                          // LDS of k_tail's byte table (all copies)
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();
 size_t tree_lds_bytes(uint32_t G, uint32_t stride);   // LDS of k_compose_tree

@@ -556,21 +556,22 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     // merged walks over interleaved one-symbol codes: the last round takes
     // one chunk per lane and reads the raw input (bytes to codes through a
     // table in LDS), so only the first tail_t0 bytes of each chunk are
-    // translated.  Needs a 16-byte aligned input and room for the 1 KiB byte
+    // translated.  Needs a 16-byte aligned input and room for the 32 KiB byte
     // table; DFA_TAIL=0 keeps the wave-tile last round.
     {
         const char *ft = std::getenv("DFA_TAIL");
-        const uint64_t tail_lds = (uint64_t)d->dev.stab_bytes + 1024u + round_lds_extra();
+        const uint64_t tail_lds = (uint64_t)d->dev.stab_bytes + tail_lut_bytes() + round_lds_extra();
         p->tail = p->packed && p->rounds > 1 && p->ilv_nblk && !p->pairs && chunk < (1ull << 31) &&
                   !(flags & kPlanUnaligned) && !(ft && ft[0] == '0') && tail_lds <= (uint64_t)lds;
         if (p->tail) {
             p->tail_t0 = kRound1Bytes << (2 * (p->rounds - 2));
             p->ilv_nblk = p->tail_t0 * p->code_bytes / 16;
             // workgroups of whole wavefronts, sized so that every CU holds as
-            // many as its LDS allows
+            // many as its LDS allows; each adds one wavefront for the
+            // overflow list
             const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)lds / tail_lds));
             const uint64_t want = (nch + (uint64_t)cus * per_cu - 1) / ((uint64_t)cus * per_cu);
-            p->tail_threads = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(64, (want + 63) / 64 * 64));
+            p->tail_threads = (uint32_t)std::min<uint64_t>(960, std::max<uint64_t>(64, (want + 63) / 64 * 64));
             p->tail_blocks = (uint32_t)std::min<uint64_t>((nch + p->tail_threads - 1) / p->tail_threads,
                                                           0x7FFFFFFFull);
         }

@@ -1412,19 +1412,29 @@ __global__ __launch_bounds__(1024, 8) void k_chunk_walk(Match2Args a, ChunkWalkA
 // The last round of merged walks, one chunk per lane (MatchPlan::tail).  By
 // the start of the last round the walks of a chunk have mostly met: the
 // round before hands each chunk's remaining walks to this kernel (up to
-// kTailSlots per chunk; more go to an overflow list, walked one per lane by
-// the same kernel in list mode).  Lane c walks chunk c's states from byte t0
-// to the chunk's end, reading the raw input: each byte becomes its code
-// through a 256-entry table in LDS (an entry is the code, with kTailBad set
-// for a byte outside Sigma).  The bytes a tail reads are validated here: the
-// translation pass covered only every chunk's first t0 bytes, so every lane
-// whose chunk extends past t0 walks it, with no state if its walks all ended.
-// Walks of a lane that meet are merged at segment ends (2 t0, 4 t0, ...):
-// a wavefront runs as many chains as its busiest lane (0, 1, 2 or 4), mostly
-// one.  A lane loads its chunk 32 bytes at a time, one group ahead (eight
-// wavefronts per SIMD fit in the registers).
+// kTailSlots per chunk; more go to an overflow list).  Lane c walks chunk c's
+// states from byte t0 to the chunk's end, reading the raw input: each byte
+// becomes its code through a 256-entry table in LDS (an entry is the code,
+// with kTailBad set for a byte outside Sigma).  The bytes a tail reads are
+// validated here: the translation pass covered only every chunk's first t0
+// bytes, so every lane whose chunk extends past t0 walks it, with no state
+// if its walks all ended.  Walks of a lane that meet are merged at segment
+// ends (2 t0, 4 t0, ...): a wavefront runs as many chains as its busiest
+// lane (0, 1, 2, 4 or 8), mostly one.  A lane loads its chunk 32 bytes at a
+// time, one group ahead (eight wavefronts per SIMD fit in the registers).
+// The byte table is held in kTailLutCopies copies, entry e of copy k at
+// dword 32 e + k, and lane l reads copy l mod 32: the 32 lanes of a half
+// wavefront then hit 32 distinct banks whatever bytes they read (random
+// bytes on one copy would pile up on a few banks).
+// The last wavefront of every workgroup walks the overflow list, one walk
+// per lane, beside the chunk lanes (a lone overflow walk is as long as a
+// chunk's tail; run after them it would add its whole length).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTailBad = 0x10000u;
+constexpr uint32_t kTailChains = 8;     // chains a lane can run (= kTailSlots)
+constexpr uint32_t kTailLutCopies = 32;
+constexpr uint32_t kTailLutBytes = 256u * kTailLutCopies * 4u;   // 32 KiB
+static_assert(kTailSlots == kTailChains, "a lane holds every slot of its chunk");
 
 struct TailArgs {
     const uint8_t *in;         // the raw input (16-byte aligned)
@@ -1437,11 +1447,11 @@ struct TailArgs {
     const uint2 *ovf_list;     // overflow walks {chunk, state} per place
     uint32_t cap;              // places per region
     uint32_t *bad;             // OR-ed with 1 when a byte outside Sigma is read
-    uint32_t list_mode;        // 0: lanes over chunks; 1: lanes over overflow walks
+    uint32_t chunk_threads;    // threads per workgroup on chunks (the rest: overflow)
 };
 
-// 16 bytes: codes from the byte table, then 16 steps of each of the NS
-// chains (NS = 0: validation only).
+// 16 bytes: codes from the byte table (lut: this lane's copy), then 16
+// steps of each of the NS chains (NS = 0: validation only).
 template <int NS>
 __device__ __forceinline__ void tail_piece(const uint4 &v, uint32_t lut,
                                            uint32_t (&st)[NS > 0 ? NS : 1], uint32_t &bad) {
@@ -1451,7 +1461,7 @@ __device__ __forceinline__ void tail_piece(const uint4 &v, uint32_t lut,
         uint32_t e[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            e[k] = lds_ld32(lut + (((w4[q] >> (8 * k)) & 0xFFu) << 2));
+            e[k] = lds_ld32(lut + (((w4[q] >> (8 * k)) & 0xFFu) << 7));
             bad |= e[k];
         }
 #pragma unroll
@@ -1468,7 +1478,7 @@ __device__ __forceinline__ void tail_walk(const uint8_t *__restrict__ cb, uint32
                                           uint32_t lut, uint32_t (&st)[NS > 0 ? NS : 1],
                                           uint32_t &bad) {
     const uint4 *p = reinterpret_cast<const uint4 *>(cb + from);
-    constexpr uint32_t GP = 2;   // pieces per group
+    constexpr uint32_t GP = NS >= 8 ? 1 : 2;   // pieces per group (eight chains: one)
     const uint32_t ng = (to - from) / (16 * GP);
     if (ng) {
         // ring of two groups: a group is reloaded right after its walk, so
@@ -1498,7 +1508,7 @@ __device__ __forceinline__ void tail_walk(const uint8_t *__restrict__ cb, uint32
     uint32_t at = from + ng * 16 * GP;
     for (; at + 16 <= to; at += 16) tail_piece<NS>(*reinterpret_cast<const uint4 *>(cb + at), lut, st, bad);
     for (; at < to; ++at) {   // the input's last bytes
-        const uint32_t e = lds_ld32(lut + ((uint32_t)cb[at] << 2));
+        const uint32_t e = lds_ld32(lut + ((uint32_t)cb[at] << 7));
         bad |= e;
 #pragma unroll
         for (int j = 0; j < NS; ++j) st[j] = lds_ld(add_sel<2, 0>(st[j], e));
@@ -1511,41 +1521,49 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
-// Walk the lane's chains st[0 .. nl) over [from, to) with the wave's chain
-// count ns (wave-uniform; lanes with fewer chains repeat their first).
+// Walk the lane's first `NS` chains of st over [from, to).
+template <int NS>
+__device__ __forceinline__ void tail_walk_first(const uint8_t *cb, uint32_t from, uint32_t to,
+                                                uint32_t lut, uint32_t (&st)[kTailChains],
+                                                uint32_t &bad) {
+    uint32_t sn[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int j = 0; j < (NS > 0 ? NS : 1); ++j) sn[j] = st[j];
+    tail_walk<NS>(cb, from, to, lut, sn, bad);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) st[j] = sn[j];
+}
+
+// The wave's chain count ns (wave-uniform; lanes with fewer chains repeat
+// their first): 0, 1, 2, 4 or 8 chains.
 __device__ __forceinline__ void tail_walk_n(uint32_t ns, const uint8_t *cb, uint32_t from,
-                                            uint32_t to, uint32_t lut, uint32_t (&st)[4],
-                                            uint32_t &bad) {
-    if (ns == 0) {
-        uint32_t s0[1] = {0};
-        tail_walk<0>(cb, from, to, lut, s0, bad);
-    } else if (ns == 1) {
-        uint32_t s1[1] = {st[0]};
-        tail_walk<1>(cb, from, to, lut, s1, bad);
-        st[0] = s1[0];
-    } else if (ns == 2) {
-        uint32_t s2[2] = {st[0], st[1]};
-        tail_walk<2>(cb, from, to, lut, s2, bad);
-        st[0] = s2[0];
-        st[1] = s2[1];
-    } else {
-        tail_walk<4>(cb, from, to, lut, st, bad);
-    }
+                                            uint32_t to, uint32_t lut,
+                                            uint32_t (&st)[kTailChains], uint32_t &bad) {
+    if (ns == 0) tail_walk_first<0>(cb, from, to, lut, st, bad);
+    else if (ns == 1) tail_walk_first<1>(cb, from, to, lut, st, bad);
+    else if (ns == 2) tail_walk_first<2>(cb, from, to, lut, st, bad);
+    else if (ns <= 4) tail_walk_first<4>(cb, from, to, lut, st, bad);
+    else tail_walk_first<8>(cb, from, to, lut, st, bad);
 }
 
 // Chains that reached the same state become one: st[0 .. nl) keeps the
-// distinct states in order, map (4 bits per handed-over walk) is updated.
-__device__ __forceinline__ void tail_merge(uint32_t (&st)[4], uint32_t &nl, uint32_t &map) {
-    uint32_t where[4], nst[4] = {st[0], st[0], st[0], st[0]}, k2 = 0;
+// distinct states in order (the rest repeat st[0]); map (4 bits per
+// handed-over walk: the index of its chain) is updated.
+__device__ __forceinline__ void tail_merge(uint32_t (&st)[kTailChains], uint32_t &nl,
+                                           uint32_t &map) {
+    constexpr int C = (int)kTailChains;
+    uint32_t where[C], nst[C], k2 = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int q = 0; q < C; ++q) nst[q] = st[0];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
         uint32_t f = 0xFFu;
 #pragma unroll
         for (int i = 0; i < j; ++i)
             if (f == 0xFFu && (uint32_t)i < nl && st[i] == st[j]) f = where[i];
         if ((uint32_t)j < nl && f == 0xFFu) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < C; ++q)
                 if ((uint32_t)q == k2) nst[q] = st[j];
             f = k2++;
         }
@@ -1553,16 +1571,16 @@ __device__ __forceinline__ void tail_merge(uint32_t (&st)[4], uint32_t &nl, uint
     }
     uint32_t m2 = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < C; ++k) {
         const uint32_t cur = (map >> (4 * k)) & 0xFu;
         uint32_t w = where[0];
 #pragma unroll
-        for (int j = 1; j < 4; ++j)
+        for (int j = 1; j < C; ++j)
             if (cur == (uint32_t)j) w = where[j];
         m2 |= (w & 0xFu) << (4 * k);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) st[q] = nst[q];
+    for (int q = 0; q < C; ++q) st[q] = nst[q];
     nl = k2;
     map = m2;
 }
@@ -1570,22 +1588,16 @@ __device__ __forceinline__ void tail_merge(uint32_t (&st)[4], uint32_t &nl, uint
 template <int L>
 __global__ __launch_bounds__(1024, 8) void k_tail(Match2Args a, TailArgs t) {
     extern __shared__ __align__(16) uint8_t smem[];
-    // list mode: nothing to do unless some chunk had more than kTailSlots
-    // walks (the count is uniform, so whole workgroups leave together)
-    if (t.list_mode) {
-        uint32_t tot = 0;
-        for (uint32_t g = 0; g < kRegions; ++g) tot += t.ovf_cnt[g];
-        if (tot == 0) return;
-    }
     stage_table<L>(a.d, smem);
-    const uint32_t lut = a.d.stab_bytes;
-    uint32_t *lut_w = reinterpret_cast<uint32_t *>(smem + lut);
-    uint32_t *region_pre = reinterpret_cast<uint32_t *>(smem + lut + 1024);
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
-        const uint16_t c = a.d.code[i];
+    uint32_t *lut_w = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes);
+    uint32_t *region_pre = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes + kTailLutBytes);
+    for (uint32_t i = threadIdx.x; i < 256u * kTailLutCopies; i += blockDim.x) {
+        const uint16_t c = a.d.code[i / kTailLutCopies];
         lut_w[i] = c == kCodeInvalid ? kTailBad : (uint32_t)c;
     }
-    if (t.list_mode && threadIdx.x == 0) {
+    // this lane's copy of the byte table
+    const uint32_t lut = a.d.stab_bytes + 4u * (threadIdx.x % kTailLutCopies);
+    if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (uint32_t g = 0; g < kRegions; ++g) {
             region_pre[g] = acc;
@@ -1595,25 +1607,32 @@ __global__ __launch_bounds__(1024, 8) void k_tail(Match2Args a, TailArgs t) {
     }
     __syncthreads();
     const uint32_t R = L == 1 ? a.d.rowbytes : 2u;
+    const uint32_t CT = t.chunk_threads;
     uint32_t bad = 0;
-    if (!t.list_mode) {
-        // lanes over chunks (the loop bound is uniform: every lane of a
-        // wavefront takes part in its shuffles)
-        const uint32_t T = gridDim.x * blockDim.x;
-        for (uint32_t c0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); c0 < a.nch; c0 += T) {
+    if (threadIdx.x < CT) {
+        // lanes over chunks (the loop bound is uniform per wavefront: every
+        // lane of a wavefront takes part in its shuffles)
+        const uint32_t T = gridDim.x * CT;
+        for (uint32_t c0 = blockIdx.x * CT + (threadIdx.x & ~63u); c0 < a.nch; c0 += T) {
             const uint32_t c = c0 + (threadIdx.x & 63u);
             const bool in = c < a.nch;
             const uint64_t len = in ? min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk) : 0u;
             const uint32_t to = len > t.t0 ? (uint32_t)len : t.t0;
             const uint32_t cnt = len > t.t0 ? min(t.cnt[c], kTailSlots) : 0u;
-            uint32_t st[4] = {0, 0, 0, 0};
-            if (cnt) {
-                const uint2 sv = reinterpret_cast<const uint2 *>(t.st)[c];   // kTailSlots == 4
-                const uint32_t s4[4] = {sv.x & 0xFFFFu, sv.x >> 16, sv.y & 0xFFFFu, sv.y >> 16};
+            uint32_t st[kTailChains];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) st[k] = R * ((uint32_t)k < cnt ? s4[k] : s4[0]);
+            for (int k = 0; k < (int)kTailChains; ++k) st[k] = 0;
+            if (cnt) {
+                const uint4 sv = reinterpret_cast<const uint4 *>(t.st)[c];   // kTailSlots == 8
+                const uint32_t w4[4] = {sv.x, sv.y, sv.z, sv.w};
+                const uint32_t s0 = w4[0] & 0xFFFFu;
+#pragma unroll
+                for (int k = 0; k < (int)kTailChains; ++k) {
+                    const uint32_t s = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                    st[k] = R * ((uint32_t)k < cnt ? s : s0);
+                }
             }
-            uint32_t nl = cnt, map = 0x3210u;
+            uint32_t nl = cnt, map = 0x76543210u;
             const uint8_t *cb = t.in + (uint64_t)c * a.chunk;
             uint32_t pos = t.t0;
             uint64_t seg = 2ull * t.t0;
@@ -1628,15 +1647,18 @@ __global__ __launch_bounds__(1024, 8) void k_tail(Match2Args a, TailArgs t) {
             }
             for (uint32_t k = 0; k < cnt; ++k) {
                 const uint32_t cur = (map >> (4 * k)) & 0xFu;
-                const uint32_t s = cur == 0 ? st[0] : cur == 1 ? st[1] : cur == 2 ? st[2] : st[3];
+                uint32_t s = st[0];
+#pragma unroll
+                for (int j = 1; j < (int)kTailChains; ++j)
+                    if (cur == (uint32_t)j) s = st[j];
                 t.lo[c * kTailSlots + k] = kDone | kMapped | map_entry(a, c, s / R);
             }
         }
     } else {
-        // lanes over the overflow walks
+        // the overflow list, one walk per lane
         const uint32_t total = region_pre[kRegions];
-        const uint32_t T = gridDim.x * blockDim.x;
-        for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total; w += T) {
+        const uint32_t T = gridDim.x * 64u;
+        for (uint32_t w = blockIdx.x * 64u + (threadIdx.x - CT); w < total; w += T) {
             uint32_t lo = 0, hi = kRegions;
             while (hi > lo + 1) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -1945,16 +1967,14 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         if (p.tail) {
             const uint32_t last = p.rounds - 1;
             TailArgs t{d_in, p.tail_t0, b.tail_cnt, b.tail_st, b.lo[last], b.cnt + (size_t)last * kRegions,
-                       b.list[last], round_region_cap(p), b.block_bad, 0u};
-            const size_t tl = lds + 1024u + round_lds_extra();
+                       b.list[last], round_region_cap(p), b.block_bad, p.tail_threads};
+            const size_t tl = lds + kTailLutBytes + round_lds_extra();
             void *targs[] = {&a, &t};
             if (int rc = mark(ev_kern_begin)) return rc;
-            e = hipLaunchKernel(tail_kernel(L), dim3(p.tail_blocks), dim3(p.tail_threads), targs, tl, s);
+            e = hipLaunchKernel(tail_kernel(L), dim3(p.tail_blocks), dim3(p.tail_threads + 64u), targs,
+                                tl, s);
             if (e != hipSuccess) return hip_fail(e, "k_tail launch");
             if (int rc = mark(ev_kern_end)) return rc;
-            t.list_mode = 1u;
-            e = hipLaunchKernel(tail_kernel(L), dim3(p.blocks2), dim3(p.threads2), targs, tl, s);
-            if (e != hipSuccess) return hip_fail(e, "k_tail (overflow) launch");
         }
         MergeMapArgs mm{};
         for (uint32_t k = 0; k < p.rounds; ++k) mm.lo[k] = b.lo[k];
@@ -2116,6 +2136,7 @@ int set_match2_lds_limit(int lds) {
 
 uint32_t match2_tile_pairs(uint32_t slots) { return kWave2 * slots; }
 size_t round_lds_extra() { return (4u * (kRegions + 1) + 15u) / 16u * 16u; }
+size_t tail_lut_bytes() { return kTailLutBytes; }
 uint32_t round_region_cap(const MatchPlan &p) {
     // a region receives the leaders of every kRegions-th tile, at most a
     // tile's walks each

@@ -227,7 +227,10 @@ def test_packed_batch_graph_replays(dfa_mod):
 
 
 def test_full_batched_configuration(dfa_mod):
-    """1024 pairs, DFAs 8-512 states, strings 1 KiB - 64 MiB (5.7 GiB)."""
+    """1024 pairs, DFAs 8-512 states, strings 1 KiB - 64 MiB (5.7 GiB): at the
+    planner's defaults, and at the setting dfa_batch_tune picks (the one the
+    benchmark times) through HIP-graph replays, with eager work between
+    replays; every record against the oracle."""
     import torch
     wl = configs.batch_workload()
     say("building", len(wl), "requests")
@@ -241,6 +244,20 @@ def test_full_batched_configuration(dfa_mod):
     b.run(res)
     torch.cuda.synchronize()
     check_records(res, expect)
+    b.close()
+    s = torch.cuda.Stream()
+    chunk, look, ms, ex = dfa_mod.dfa_batch_tune(ds, ins, s)
+    torch.cuda.synchronize()
+    say(f"tuned: chunk {chunk}, lookahead {look}, early exit {ex}, {ms:.2f} ms")
+    b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
+    for rep in range(3):
+        res = torch.full((len(ds), 4), -1, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(s):
+            b.graph_launch(res, s)
+        torch.cuda.synchronize()
+        check_records(res, expect)
+        res.fill_(0)
+        torch.cuda.synchronize()
     b.close()
 
 

@@ -30,7 +30,7 @@ MiB = 1 << 20
 PROTEIN_MAPS = [(4, 65536, {"rounds": 2, "interleave": True, "single_step": True}),
                 (4, 8192, {"chunk_lanes": True, "single_step": True}), (6, 65536, {"rounds": 4}),
                 (1, 4096, {}), (8, 1 << 20, {})]
-BYTE_MAPS = [(2, 65536, {"rounds": 6, "interleave": True}), (2, 131072, {"rounds": 5, "interleave": True}),
+BYTE_MAPS = [(2, 65536, {"rounds": 4, "interleave": True}), (2, 131072, {"rounds": 6, "interleave": True}),
              (4, 32768, {"rounds": 4}), (1, 4096, {}), (3, 1 << 20, {})]
 
 

@@ -1290,7 +1290,12 @@ def main() -> int:
             if not args.tune:
                 a4.chunk, a4.lookahead = 8192, 6
             sub["c4"] = sub_record(timed("c4", bench_batched, a4, dfa, torch, torch.cuda.Stream()))
-            sub["c5"] = sub_record(timed("c5", bench_served, args, dfa, torch, stream))
+            # the served sub-record also sweeps the arrival rate around the
+            # plain method's capacity
+            a5 = argparse.Namespace(**vars(args))
+            if not a5.load_sweep:
+                a5.load_sweep = "0.5,0.9,1.2"
+            sub["c5"] = sub_record(timed("c5", bench_served, a5, dfa, torch, stream))
             args.steps = steps
             line["sub"] = sub
     else:

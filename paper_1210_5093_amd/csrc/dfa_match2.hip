@@ -1003,6 +1003,8 @@ struct RoundArgs {
 template <int S>
 constexpr int kRoundAhead = S >= 4 ? 1 : 2;
 
+constexpr uint32_t kRoundPreBytes = (4u * (kRegions + 1) + 15u) / 16u * 16u;
+
 // EXIT: the DFA has absorbing states; a wave stops once all its walks are in one.
 template <int L, int S, bool EXIT>
 __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, RoundArgs m) {
@@ -1420,8 +1422,8 @@ __global__ __launch_bounds__(1024, 8) void k_chunk_walk(Match2Args a, ChunkWalkA
 // bytes, so every lane whose chunk extends past t0 walks it, with no state
 // if its walks all ended.  Walks of a lane that meet are merged at segment
 // ends (2 t0, 4 t0, ...): a wavefront runs as many chains as its busiest
-// lane (0, 1, 2, 4 or 8), mostly one.  A lane loads its chunk 32 bytes at a
-// time, one group ahead (eight wavefronts per SIMD fit in the registers).
+// lane (0, 1, 2, 4 or 8), mostly one.  A lane loads its chunk 64 bytes at a
+// time (16 or 32 with four or eight chains), one group ahead.
 // The byte table is held in kTailLutCopies copies, entry e of copy k at
 // dword 32 e + k, and lane l reads copy l mod 32: the 32 lanes of a half
 // wavefront then hit 32 distinct banks whatever bytes they read (random
@@ -1478,7 +1480,10 @@ __device__ __forceinline__ void tail_walk(const uint8_t *__restrict__ cb, uint32
                                           uint32_t lut, uint32_t (&st)[NS > 0 ? NS : 1],
                                           uint32_t &bad) {
     const uint4 *p = reinterpret_cast<const uint4 *>(cb + from);
-    constexpr uint32_t GP = NS >= 8 ? 1 : 2;   // pieces per group (eight chains: one)
+    // pieces per group: a lane's whole 64 bytes of a line half per load
+    // group for one or two chains (parts of a line fetched by one group are
+    // not evicted before the next group reads them), fewer for more chains
+    constexpr uint32_t GP = NS >= 8 ? 1 : NS >= 4 ? 2 : 4;
     const uint32_t ng = (to - from) / (16 * GP);
     if (ng) {
         // ring of two groups: a group is reloaded right after its walk, so
@@ -1586,7 +1591,7 @@ __device__ __forceinline__ void tail_merge(uint32_t (&st)[kTailChains], uint32_t
 }
 
 template <int L>
-__global__ __launch_bounds__(1024, 8) void k_tail(Match2Args a, TailArgs t) {
+__global__ __launch_bounds__(1024, 5) void k_tail(Match2Args a, TailArgs t) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     uint32_t *lut_w = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes);
@@ -2135,7 +2140,7 @@ int set_match2_lds_limit(int lds) {
 }
 
 uint32_t match2_tile_pairs(uint32_t slots) { return kWave2 * slots; }
-size_t round_lds_extra() { return (4u * (kRegions + 1) + 15u) / 16u * 16u; }
+size_t round_lds_extra() { return kRoundPreBytes; }
 size_t tail_lut_bytes() { return kTailLutBytes; }
 uint32_t round_region_cap(const MatchPlan &p) {
     // a region receives the leaders of every kRegions-th tile, at most a

@@ -301,7 +301,8 @@ int launch_size_scan(uint32_t nch, uint16_t *msize, uint32_t *bsum, uint32_t *fi
                      uint32_t *tile_first, uint32_t tile, hipStream_t s);
 uint32_t match2_tile_pairs(uint32_t slots);
 uint32_t round_region_cap(const MatchPlan &p);   // places per region of a walk list
-size_t round_lds_extra();                         // LDS the round kernels add after the table
+size_t round_lds_extra();                         // LDS of the region prefix after the table
+size_t round_lds_bytes(uint32_t threads);         // all LDS k_round adds after the table
 size_t tail_lut_bytes();                          // LDS of k_tail's byte table (all copies)
 uint32_t match2_scan_blocks(uint32_t nch);
 int device_lds_bytes();

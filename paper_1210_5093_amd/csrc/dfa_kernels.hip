@@ -421,9 +421,14 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
                                               : d->mset_mean[std::min(p->r, d->dev.r0)]);
         const char *fs = std::getenv("DFA_SLOTS");
         p->slots = fs && fs[0] == '2' ? 2u : fs && fs[0] == '4' ? 4u : (mean_set < 8.0 ? 2u : 4u);
+        // workgroups per CU by LDS: the staged table plus, for merged rounds,
+        // the round kernel's grouping tables at their largest (16 waves), so
+        // that every workgroup of the persistent grid is resident
         const uint32_t staged = p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes;
+        const uint32_t with_rounds = DFA_MATCH_ROUNDS_OF(flags) > 1
+                                         ? staged + (uint32_t)round_lds_bytes(1024u) : staged;
         const uint32_t per_cu = std::max<uint32_t>(
-            1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(staged, 1024u)));
+            1u, std::min<uint32_t>(8u, (uint32_t)lds / std::max<uint32_t>(with_rounds, 1024u)));
         // 32 wavefronts per CU: blocks of up to 16 waves when few tables fit
         p->threads2 = 64u * std::min<uint32_t>(16u, std::max<uint32_t>(4u, (32u + per_cu - 1) / per_cu));
         p->blocks2 = (uint32_t)cus * per_cu;
@@ -491,6 +496,9 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
         uint32_t rounds = std::min<uint32_t>(req ? req : 1u, kMaxRounds);
         if (!p->packed || p->early_exit || chunk % 32 != 0 || p->chunk_lanes)
             rounds = 1;
+        // the round kernel's grouping tables must fit beside the staged table
+        const uint64_t staged = p->packed ? (p->pairs ? d->dev.stab2_bytes : d->dev.stab_bytes) : 0u;
+        if (rounds > 1 && staged + round_lds_bytes(p->threads2) > (uint64_t)lds) rounds = 1;
         while (rounds > 1 && ((uint64_t)kRound1Bytes << (2 * (rounds - 2))) >= chunk) --rounds;
         p->rounds = rounds;
     }

@@ -1004,6 +1004,15 @@ template <int S>
 constexpr int kRoundAhead = S >= 4 ? 1 : 2;
 
 constexpr uint32_t kRoundPreBytes = (4u * (kRegions + 1) + 15u) / 16u * 16u;
+// First-round grouping table per wavefront (LDS, after the region prefix):
+// kRoundHash 32-bit entries, linear probing.  In the first round a tile's
+// walks are pairs in chunk order, so a tile spans few chunks and an entry
+// holds the chunk's offset from the tile's first chunk (8 bits), the end
+// state (15 bits) and the leader's tile position (8 bits), exactly.
+constexpr uint32_t kRoundHashBits = 7;
+constexpr uint32_t kRoundHash = 1u << kRoundHashBits;
+constexpr uint32_t kRoundProbes = 8;
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;   // bit 31 is never set in an entry
 
 // EXIT: the DFA has absorbing states; a wave stops once all its walks are in one.
 template <int L, int S, bool EXIT>
@@ -1027,6 +1036,7 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
     // later rounds: exclusive prefix of the regions' counts, in LDS after the
     // staged table (the kernel has no static LDS: the table stays at address 0)
     uint32_t *region_pre = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes);
+    uint32_t *round_table = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes + kRoundPreBytes);
     if (!m.first_round) {
         if (threadIdx.x == 0) {
             uint32_t acc = 0;
@@ -1114,7 +1124,46 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
         bool is_lead[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) { lead[j] = kNone; is_lead[j] = false; }
-        if (!m.last_round) {
+        // first round: the wave's hash table in LDS groups the walks (the
+        // first walk to claim an empty entry for its key leads, walks that
+        // find their key follow it; a walk whose probes all meet other keys
+        // leads alone), unless the tile spans 256 chunks or more
+        const uint32_t cbase = __builtin_amdgcn_readfirstlane(ci[0]);
+        bool hashed = false;
+        if (m.first_round) {
+            bool wide = false;
+#pragma unroll
+            for (int j = 0; j < S; ++j) wide = wide || (act[j] && ci[j] - cbase >= 256u);
+            hashed = !__any(wide);
+        }
+        if (hashed) {
+            uint32_t *tab = round_table + (threadIdx.x / kWave2) * kRoundHash;
+            for (uint32_t k = lane; k < kRoundHash; k += kWave2) tab[k] = kHashEmpty;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (!act[j]) continue;
+                const uint32_t key = (ci[j] - cbase) << 23 | e[j] << 8;
+                const uint32_t q = (uint32_t)j * kWave2 + lane;
+                uint32_t h = ((ci[j] * 0x9E3779B1u) ^ (e[j] * 0x85EBCA77u)) >> (32 - kRoundHashBits);
+                bool placed = false;
+                for (int probe = 0; probe < (int)kRoundProbes && !placed; ++probe) {
+                    const uint32_t old = atomicCAS(tab + h, kHashEmpty, key | q);
+                    if (old == kHashEmpty) {
+                        is_lead[j] = true;
+                        lead[j] = q;
+                        placed = true;
+                    } else if ((old & ~0xFFu) == key) {
+                        lead[j] = old & 0xFFu;
+                        placed = true;
+                    }
+                    h = (h + 1) & (kRoundHash - 1);
+                }
+                if (!placed) {
+                    is_lead[j] = true;
+                    lead[j] = q;
+                }
+            }
+        } else if (!m.last_round) {
             // group the active walks by (chunk, state): one pass per distinct
             // key, taking the first unresolved lane's key (at most 64 passes
             // per slot; each removes at least that lane)
@@ -1964,7 +2013,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             if (timed)
                 if (int rc = mark(ev_kern_begin)) return rc;
             e = hipLaunchKernel(rf, dim3(p.blocks2), dim3(p.threads2), rargs,
-                                lds + round_lds_extra(), s);
+                                lds + round_lds_bytes(p.threads2), s);
             if (e != hipSuccess) return hip_fail(e, "k_round launch");
             if (timed)
                 if (int rc = mark(ev_kern_end)) return rc;
@@ -2141,6 +2190,9 @@ int set_match2_lds_limit(int lds) {
 
 uint32_t match2_tile_pairs(uint32_t slots) { return kWave2 * slots; }
 size_t round_lds_extra() { return kRoundPreBytes; }
+size_t round_lds_bytes(uint32_t threads) {
+    return kRoundPreBytes + (size_t)(threads / kWave2) * kRoundHash * sizeof(uint32_t);
+}
 size_t tail_lut_bytes() { return kTailLutBytes; }
 uint32_t round_region_cap(const MatchPlan &p) {
     // a region receives the leaders of every kRegions-th tile, at most a

@@ -228,9 +228,9 @@ def test_packed_batch_graph_replays(dfa_mod):
 
 def test_full_batched_configuration(dfa_mod):
     """1024 pairs, DFAs 8-512 states, strings 1 KiB - 64 MiB (5.7 GiB): at the
-    planner's defaults, and at the setting dfa_batch_tune picks (the one the
-    benchmark times) through HIP-graph replays, with eager work between
-    replays; every record against the oracle."""
+    planner's defaults, and through HIP-graph replays (eager work between
+    replays) at the setting the benchmark times (8 KiB chunks, r = 6) and at
+    the one dfa_batch_tune picks; every record against the oracle."""
     import torch
     wl = configs.batch_workload()
     say("building", len(wl), "requests")
@@ -249,16 +249,17 @@ def test_full_batched_configuration(dfa_mod):
     chunk, look, ms, ex = dfa_mod.dfa_batch_tune(ds, ins, s)
     torch.cuda.synchronize()
     say(f"tuned: chunk {chunk}, lookahead {look}, early exit {ex}, {ms:.2f} ms")
-    b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
-    for rep in range(3):
-        res = torch.full((len(ds), 4), -1, dtype=torch.int32, device="cuda")
-        with torch.cuda.stream(s):
-            b.graph_launch(res, s)
-        torch.cuda.synchronize()
-        check_records(res, expect)
-        res.fill_(0)
-        torch.cuda.synchronize()
-    b.close()
+    for chunk, look, ex in ((8192, 6, False), (chunk, look, ex)):
+        b = dfa_mod.Batch(ds, ins, chunk_len=chunk, lookahead=look, early_exit=ex)
+        for rep in range(3):
+            res = torch.full((len(ds), 4), -1, dtype=torch.int32, device="cuda")
+            with torch.cuda.stream(s):
+                b.graph_launch(res, s)
+            torch.cuda.synchronize()
+            check_records(res, expect)
+            res.fill_(0)
+            torch.cuda.synchronize()
+        b.close()
 
 
 def test_packed_batch_early_exit(dfa_mod):

@@ -365,10 +365,12 @@ typedef struct dfa_plan_info {
     uint32_t levels;          /* composition levels (Eq. 9 applied as a tree) */
     uint32_t group0;          /* maps composed per workgroup on the first level */
     uint32_t group;           /* maps composed per workgroup on the later levels */
-    uint32_t tail_lanes;      /* 1: merged walks whose last round runs one chunk per lane
-                                 over the raw input (interleaved one-symbol codes, 16-byte
-                                 aligned input); the code stream then covers only each
-                                 chunk's first tail_start bytes */
+    uint32_t tail_lanes;      /* nonzero: merged walks whose last round runs one chunk per
+                                 lane over the raw input (interleaved one-symbol codes,
+                                 16-byte aligned input); the code stream then covers only
+                                 each chunk's first tail_start bytes.  The value is the
+                                 chunks each lane takes (1, or 2 side by side when one per
+                                 lane would not fit the device at once) */
     uint32_t tail_start;      /* chunk bytes walked before that last round */
 } dfa_plan_info_t;
 int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts, dfa_plan_info_t *out);

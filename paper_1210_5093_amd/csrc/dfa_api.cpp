@@ -442,7 +442,7 @@ extern "C" int dfa_plan(const dfa_t *d, size_t len, const dfa_match_opts_t *opts
     out->levels = p.levels;
     out->group0 = p.levels ? p.group_l[0] : 0u;
     out->group = p.levels > 1 ? p.group_l[1] : 0u;
-    out->tail_lanes = p.tail ? 1u : 0u;
+    out->tail_lanes = p.tail ? p.tail_k : 0u;
     out->tail_start = p.tail ? p.tail_t0 : 0u;
     out->raw_input = p.packed && !p.pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2;
     return DFA_OK;

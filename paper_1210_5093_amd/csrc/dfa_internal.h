@@ -166,6 +166,8 @@ struct MatchPlan {
     uint32_t tail_threads = 0;   // its grid: one lane per chunk (+ one wavefront per
                                  // workgroup for the overflow list)
     uint32_t tail_blocks = 0;
+    uint32_t tail_k = 1;         // chunks per lane in that round (2: two chunks side by side
+                                 // once each has one chain left)
     uint64_t before = 0;         // block map of a shard: bytes of lookahead readable before
                                  // the input; chunk 0 then starts from its lookahead set
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)

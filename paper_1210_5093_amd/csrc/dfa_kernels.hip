@@ -578,9 +578,18 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
             // many as its LDS allows; each adds one wavefront for the
             // overflow list
             const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)lds / tail_lds));
-            const uint64_t want = (nch + (uint64_t)cus * per_cu - 1) / ((uint64_t)cus * per_cu);
+            // two chunks per lane when one per lane would not fit the chip at
+            // once: a lane's steps form one dependent chain per chunk, so the
+            // second chunk's steps fill the first's waits (DFA_TAIL_K=1 or 2
+            // sets it)
+            const char *fk = std::getenv("DFA_TAIL_K");
+            const uint64_t once = (uint64_t)cus * per_cu * 960;
+            p->tail_k = fk && (fk[0] == '1' || fk[0] == '2') ? (uint32_t)(fk[0] - '0')
+                                                              : (nch > once ? 2u : 1u);
+            const uint64_t lanes = (nch + p->tail_k - 1) / p->tail_k;
+            const uint64_t want = (lanes + (uint64_t)cus * per_cu - 1) / ((uint64_t)cus * per_cu);
             p->tail_threads = (uint32_t)std::min<uint64_t>(960, std::max<uint64_t>(64, (want + 63) / 64 * 64));
-            p->tail_blocks = (uint32_t)std::min<uint64_t>((nch + p->tail_threads - 1) / p->tail_threads,
+            p->tail_blocks = (uint32_t)std::min<uint64_t>((lanes + p->tail_threads - 1) / p->tail_threads,
                                                           0x7FFFFFFFull);
         }
     }

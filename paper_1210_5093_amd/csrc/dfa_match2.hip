@@ -1569,6 +1569,71 @@ __device__ __forceinline__ void tail_walk(const uint8_t *__restrict__ cb, uint32
     }
 }
 
+// Two chunks side by side in one lane, one chain each: 16 bytes of each,
+// their codes first, then the two chains' steps interleaved (two independent
+// lookups in flight per step).
+__device__ __forceinline__ void tail_piece2(const uint4 &va, const uint4 &vb, uint32_t lut,
+                                            uint32_t &sa, uint32_t &sb, uint32_t &bad) {
+    const uint32_t wa[4] = {va.x, va.y, va.z, va.w};
+    const uint32_t wb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t ea[4], eb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ea[k] = lds_ld32(lut + (((wa[q] >> (8 * k)) & 0xFFu) << 7));
+            eb[k] = lds_ld32(lut + (((wb[q] >> (8 * k)) & 0xFFu) << 7));
+            bad |= ea[k] | eb[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sa = lds_ld(add_sel<2, 0>(sa, ea[k]));
+            sb = lds_ld(add_sel<2, 0>(sb, eb[k]));
+        }
+    }
+}
+
+// n16 16-byte pieces from pa and from pb (both 16-byte aligned), walked in
+// lockstep; load groups of 64 bytes per chunk in a ring of two, as tail_walk.
+__device__ __forceinline__ void tail_walk2(const uint8_t *__restrict__ pa, const uint8_t *__restrict__ pb,
+                                           uint32_t n16, uint32_t lut, uint32_t &sa, uint32_t &sb,
+                                           uint32_t &bad) {
+    constexpr uint32_t GP = 4;
+    const uint4 *qa = reinterpret_cast<const uint4 *>(pa);
+    const uint4 *qb = reinterpret_cast<const uint4 *>(pb);
+    const uint32_t ng = n16 / GP;
+    if (ng) {
+        const uint32_t lastg = ng - 1;
+        uint4 ra[2][GP], rb[2][GP];
+#pragma unroll
+        for (uint32_t k = 0; k < 2; ++k)
+#pragma unroll
+            for (int h = 0; h < GP; ++h) {
+                ra[k][h] = qa[min(k, lastg) * GP + h];
+                rb[k][h] = qb[min(k, lastg) * GP + h];
+            }
+        uint32_t g0 = 0;
+        for (; g0 + 2 <= ng; g0 += 2) {
+#pragma unroll
+            for (uint32_t k = 0; k < 2; ++k) {
+#pragma unroll
+                for (int h = 0; h < GP; ++h) tail_piece2(ra[k][h], rb[k][h], lut, sa, sb, bad);
+                const uint32_t gn = min(g0 + k + 2, lastg);
+#pragma unroll
+                for (int h = 0; h < GP; ++h) {
+                    ra[k][h] = qa[gn * GP + h];
+                    rb[k][h] = qb[gn * GP + h];
+                }
+            }
+        }
+        if (g0 < ng) {
+#pragma unroll
+            for (int h = 0; h < GP; ++h) tail_piece2(ra[0][h], rb[0][h], lut, sa, sb, bad);
+        }
+    }
+    for (uint32_t i = ng * GP; i < n16; ++i) tail_piece2(qa[i], qb[i], lut, sa, sb, bad);
+}
+
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
@@ -1639,8 +1704,83 @@ __device__ __forceinline__ void tail_merge(uint32_t (&st)[kTailChains], uint32_t
     map = m2;
 }
 
-template <int L>
-__global__ __launch_bounds__(1024, 5) void k_tail(Match2Args a, TailArgs t) {
+// A chunk's handed-over walks in the last round (two chunks per lane): chains
+// st[0 .. nl) (the rest repeat st[0]), map (4 bits per walk: its chain), the
+// position the chains stand at and the chunk's end.
+__device__ __forceinline__ void tail_load(const Match2Args &a, const TailArgs &t, uint32_t c,
+                                          uint32_t R, uint32_t (&st)[kTailChains], uint32_t &cnt,
+                                          uint32_t &to) {
+    const bool in = c < a.nch;
+    const uint64_t len = in ? min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk) : 0u;
+    to = len > t.t0 ? (uint32_t)len : t.t0;
+    cnt = len > t.t0 ? min(t.cnt[c], kTailSlots) : 0u;
+#pragma unroll
+    for (int j = 0; j < (int)kTailChains; ++j) st[j] = 0;
+    if (cnt) {
+        const uint4 sv = reinterpret_cast<const uint4 *>(t.st)[c];   // kTailSlots == 8
+        const uint32_t w4[4] = {sv.x, sv.y, sv.z, sv.w};
+        const uint32_t s0 = w4[0] & 0xFFFFu;
+#pragma unroll
+        for (int j = 0; j < (int)kTailChains; ++j) {
+            const uint32_t s = (w4[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+            st[j] = R * ((uint32_t)j < cnt ? s : s0);
+        }
+    }
+}
+
+// Segments [pos, 2 t0), [2 t0, 4 t0), ... while some lane of the wavefront
+// has two chains or more; chains that meet become one at each segment's end.
+// Returns with at most one chain in every lane that has bytes left.
+__device__ __forceinline__ void tail_multi(const uint8_t *cb, uint32_t t0, uint32_t lut,
+                                           uint32_t (&st)[kTailChains], uint32_t &nl, uint32_t &map,
+                                           uint32_t &pos, uint32_t to, uint32_t &bad) {
+    uint64_t seg = 2ull * t0;
+    for (;;) {
+        const uint32_t ns = wave_max(pos < to ? nl : 0u);
+        if (ns <= 1) break;
+        const uint32_t end = (uint32_t)min<uint64_t>(seg, to);
+        const uint32_t lo = min(pos, to), hi = max(min(end, to), lo);
+        if (ns == 2) tail_walk_first<2>(cb, lo, hi, lut, st, bad);
+        else if (ns <= 4) tail_walk_first<4>(cb, lo, hi, lut, st, bad);
+        else tail_walk_first<8>(cb, lo, hi, lut, st, bad);
+        pos = max(pos, hi);
+        tail_merge(st, nl, map);
+        seg *= 2;
+    }
+}
+
+// Outcomes of chunk c's walks whose chain has ended: those of chains other
+// than the first once tail_multi returns, so that only the first chain's
+// state stays live.  (The chain is picked by masks, not by index, which keeps
+// st in registers.)
+__device__ __forceinline__ void tail_store_others(const Match2Args &a, const TailArgs &t, uint32_t c,
+                                                  uint32_t R, const uint32_t (&st)[kTailChains],
+                                                  uint32_t cnt, uint32_t map) {
+    for (uint32_t w = 0; w < cnt; ++w) {
+        const uint32_t cur = (map >> (4 * w)) & 0xFu;
+        if (cur == 0) continue;
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 1; j < (int)kTailChains; ++j) s |= st[j] & (0u - (uint32_t)(cur == (uint32_t)j));
+        t.lo[c * kTailSlots + w] = kDone | kMapped | map_entry(a, c, s / R);
+    }
+}
+
+// ... and the first chain's walks, from its end state s0.  Nothing for a
+// lane without walks: its chunk may lie past the last (c >= nch), where
+// map_entry would read beyond the per-chunk arrays.
+__device__ __forceinline__ void tail_store_first(const Match2Args &a, const TailArgs &t, uint32_t c,
+                                                 uint32_t R, uint32_t cnt, uint32_t map, uint32_t s0) {
+    if (cnt == 0) return;
+    const uint32_t v = kDone | kMapped | map_entry(a, c, s0 / R);
+    for (uint32_t w = 0; w < cnt; ++w)
+        if (((map >> (4 * w)) & 0xFu) == 0) t.lo[c * kTailSlots + w] = v;
+}
+
+// K: chunks per lane (1 or 2; with 2, wavefront w takes chunks 128 w + lane
+// and 128 w + 64 + lane, walked side by side once each has one chain left).
+template <int L, int K>
+__global__ __launch_bounds__(1024, K == 1 ? 5 : 4) void k_tail(Match2Args a, TailArgs t) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<L>(a.d, smem);
     uint32_t *lut_w = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes);
@@ -1666,46 +1806,86 @@ __global__ __launch_bounds__(1024, 5) void k_tail(Match2Args a, TailArgs t) {
     if (threadIdx.x < CT) {
         // lanes over chunks (the loop bound is uniform per wavefront: every
         // lane of a wavefront takes part in its shuffles)
-        const uint32_t T = gridDim.x * CT;
-        for (uint32_t c0 = blockIdx.x * CT + (threadIdx.x & ~63u); c0 < a.nch; c0 += T) {
+        const uint32_t T = gridDim.x * CT * K;
+        for (uint32_t c0 = (blockIdx.x * CT + (threadIdx.x & ~63u)) * K; c0 < a.nch; c0 += T) {
             const uint32_t c = c0 + (threadIdx.x & 63u);
-            const bool in = c < a.nch;
-            const uint64_t len = in ? min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk) : 0u;
-            const uint32_t to = len > t.t0 ? (uint32_t)len : t.t0;
-            const uint32_t cnt = len > t.t0 ? min(t.cnt[c], kTailSlots) : 0u;
-            uint32_t st[kTailChains];
+            if (K == 1) {
+                const bool in = c < a.nch;
+                const uint64_t len = in ? min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk) : 0u;
+                const uint32_t to = len > t.t0 ? (uint32_t)len : t.t0;
+                const uint32_t cnt = len > t.t0 ? min(t.cnt[c], kTailSlots) : 0u;
+                uint32_t st[kTailChains];
 #pragma unroll
-            for (int k = 0; k < (int)kTailChains; ++k) st[k] = 0;
-            if (cnt) {
-                const uint4 sv = reinterpret_cast<const uint4 *>(t.st)[c];   // kTailSlots == 8
-                const uint32_t w4[4] = {sv.x, sv.y, sv.z, sv.w};
-                const uint32_t s0 = w4[0] & 0xFFFFu;
+                for (int k = 0; k < (int)kTailChains; ++k) st[k] = 0;
+                if (cnt) {
+                    const uint4 sv = reinterpret_cast<const uint4 *>(t.st)[c];   // kTailSlots == 8
+                    const uint32_t w4[4] = {sv.x, sv.y, sv.z, sv.w};
+                    const uint32_t s0 = w4[0] & 0xFFFFu;
 #pragma unroll
-                for (int k = 0; k < (int)kTailChains; ++k) {
-                    const uint32_t s = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-                    st[k] = R * ((uint32_t)k < cnt ? s : s0);
+                    for (int k = 0; k < (int)kTailChains; ++k) {
+                        const uint32_t s = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                        st[k] = R * ((uint32_t)k < cnt ? s : s0);
+                    }
                 }
-            }
-            uint32_t nl = cnt, map = 0x76543210u;
-            const uint8_t *cb = t.in + (uint64_t)c * a.chunk;
-            uint32_t pos = t.t0;
-            uint64_t seg = 2ull * t.t0;
-            while (__any(pos < to)) {
-                const uint32_t ns = wave_max(pos < to ? nl : 0u);
-                const uint32_t end = ns <= 1 ? to : (uint32_t)min<uint64_t>(seg, to);
-                const uint32_t lo = min(pos, to), hi = max(min(end, to), lo);
-                tail_walk_n(ns, cb, lo, hi, lut, st, bad);
-                pos = max(pos, hi);
-                if (ns > 1) tail_merge(st, nl, map);
-                seg *= 2;
-            }
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t cur = (map >> (4 * k)) & 0xFu;
-                uint32_t s = st[0];
+                uint32_t nl = cnt, map = 0x76543210u;
+                const uint8_t *cb = t.in + (uint64_t)c * a.chunk;
+                uint32_t pos = t.t0;
+                uint64_t seg = 2ull * t.t0;
+                while (__any(pos < to)) {
+                    const uint32_t ns = wave_max(pos < to ? nl : 0u);
+                    const uint32_t end = ns <= 1 ? to : (uint32_t)min<uint64_t>(seg, to);
+                    const uint32_t lo = min(pos, to), hi = max(min(end, to), lo);
+                    tail_walk_n(ns, cb, lo, hi, lut, st, bad);
+                    pos = max(pos, hi);
+                    if (ns > 1) tail_merge(st, nl, map);
+                    seg *= 2;
+                }
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    const uint32_t cur = (map >> (4 * k)) & 0xFu;
+                    uint32_t s = st[0];
 #pragma unroll
-                for (int j = 1; j < (int)kTailChains; ++j)
-                    if (cur == (uint32_t)j) s = st[j];
-                t.lo[c * kTailSlots + k] = kDone | kMapped | map_entry(a, c, s / R);
+                    for (int j = 1; j < (int)kTailChains; ++j)
+                        if (cur == (uint32_t)j) s = st[j];
+                    t.lo[c * kTailSlots + k] = kDone | kMapped | map_entry(a, c, s / R);
+                }
+            } else {
+                const uint8_t *cb = t.in + (uint64_t)c * a.chunk;
+                const uint32_t c2 = c + 64u;
+                const uint8_t *cb2 = t.in + (uint64_t)c2 * a.chunk;
+                uint32_t sa, pa, ta, na, ma;
+                {
+                    uint32_t st[kTailChains], nl;
+                    tail_load(a, t, c, R, st, na, ta);
+                    nl = na;
+                    ma = 0x76543210u;
+                    pa = t.t0;
+                    tail_multi(cb, t.t0, lut, st, nl, ma, pa, ta, bad);
+                    tail_store_others(a, t, c, R, st, na, ma);
+                    sa = st[0];
+                    pa = min(pa, ta);
+                }
+                uint32_t sb, pb, tb, nb, mb;
+                {
+                    uint32_t st[kTailChains], nl;
+                    tail_load(a, t, c2, R, st, nb, tb);
+                    nl = nb;
+                    mb = 0x76543210u;
+                    pb = t.t0;
+                    tail_multi(cb2, t.t0, lut, st, nl, mb, pb, tb, bad);
+                    tail_store_others(a, t, c2, R, st, nb, mb);
+                    sb = st[0];
+                    pb = min(pb, tb);
+                }
+                // one chain each (a lane without walks keeps a dummy chain
+                // that only validates bytes): both chunks side by side, then
+                // what one has left alone
+                const uint32_t n = min(ta - pa, tb - pb) / 16u * 16u;
+                tail_walk2(cb + pa, cb2 + pb, n / 16u, lut, sa, sb, bad);
+                uint32_t s1[1] = {sa}, s2[1] = {sb};
+                if (pa + n < ta) tail_walk<1>(cb, pa + n, ta, lut, s1, bad);
+                if (pb + n < tb) tail_walk<1>(cb2, pb + n, tb, lut, s2, bad);
+                tail_store_first(a, t, c, R, na, ma, s1[0]);
+                tail_store_first(a, t, c2, R, nb, mb, s2[0]);
             }
         }
     } else {
@@ -1847,9 +2027,11 @@ const void *chunk_walk_kernel(uint32_t L) {
         reinterpret_cast<const void *>(&k_chunk_walk<3>), reinterpret_cast<const void *>(&k_chunk_walk<4>)};
     return tab[L - 1];
 }
-const void *tail_kernel(uint32_t L) {
-    return L == 1 ? reinterpret_cast<const void *>(&k_tail<1>)
-                  : reinterpret_cast<const void *>(&k_tail<2>);
+const void *tail_kernel(uint32_t L, uint32_t K) {
+    static const void *const tab[2][2] = {
+        {reinterpret_cast<const void *>(&k_tail<1, 1>), reinterpret_cast<const void *>(&k_tail<1, 2>)},
+        {reinterpret_cast<const void *>(&k_tail<2, 1>), reinterpret_cast<const void *>(&k_tail<2, 2>)}};
+    return tab[L == 1 ? 0 : 1][K >= 2 ? 1 : 0];
 }
 const void *round_kernel(uint32_t L, uint32_t slots, bool ex) {
 #define DFA_RK(l) {{reinterpret_cast<const void *>(&k_round<l, 2, false>),      \
@@ -2025,7 +2207,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             const size_t tl = lds + kTailLutBytes + round_lds_extra();
             void *targs[] = {&a, &t};
             if (int rc = mark(ev_kern_begin)) return rc;
-            e = hipLaunchKernel(tail_kernel(L), dim3(p.tail_blocks), dim3(p.tail_threads + 64u), targs,
+            e = hipLaunchKernel(tail_kernel(L, p.tail_k), dim3(p.tail_blocks), dim3(p.tail_threads + 64u), targs,
                                 tl, s);
             if (e != hipSuccess) return hip_fail(e, "k_tail launch");
             if (int rc = mark(ev_kern_end)) return rc;
@@ -2171,7 +2353,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(3),
-                         chunk_walk_kernel(4), tail_kernel(1), tail_kernel(2),
+                         chunk_walk_kernel(4), tail_kernel(1, 1), tail_kernel(2, 1),
+                         tail_kernel(1, 2), tail_kernel(2, 2),
                          round_kernel(1, 2, false), round_kernel(1, 4, false),
                          round_kernel(2, 2, false), round_kernel(2, 4, false),
                          round_kernel(3, 2, false), round_kernel(3, 4, false),

@@ -8,8 +8,10 @@ state and accept bit, and the state maps themselves; chunks with more walks
 than a lane keeps (a permutation automaton: walks never meet) through the
 overflow list; bytes outside Sigma that only the last round reads; chunks
 whose walks all ended early (absorbing states) and the ragged last chunk;
-and the same results with the last round kept on wave-tiles (DFA_TAIL=0).
-Tolerance 0."""
+two chunks per lane (forced with DFA_TAIL_K=2: the second chunk of the
+last wavefront past the end, chunks left with different byte counts after
+their multi-chain segments); and the same results with the last round kept
+on wave-tiles (DFA_TAIL=0).  Tolerance 0."""
 import sys
 
 import numpy as np
@@ -200,4 +202,92 @@ def test_tail_plan_conditions(dfa_mod, monkeypatch):
     assert dfa_mod.dfa_plan(d, n, 4096, 1, rounds=3, interleave=True).tail_lanes == 0
     g, b = run_bounds(dfa_mod, d, to_dev(x), 4096, 1, rounds=3)
     assert g[:3] == want and np.array_equal(b, ps)
+    d.close()
+
+
+@pytest.mark.parametrize("case", list(cases()))
+def test_tail_two_chunks_per_lane_boundaries(dfa_mod, monkeypatch, case):
+    """Two chunks per lane: every boundary state and the result equal the
+    oracle's, for chunk counts that leave the last wavefront's second chunks
+    partly or wholly past the end."""
+    monkeypatch.setenv("DFA_TAIL_K", "2")
+    n = (3 << 20) + 13
+    w, x = cases()[case](n)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = to_dev(x)
+    seen = 0
+    for chunk, look, rounds in ((2048, 1, 2), (8192, 3, 4), (4096, 3, 3), (65536, 1, 5), (8192, 2, 4)):
+        plan = dfa_mod.dfa_plan(d, n, chunk, look, rounds=rounds, interleave=True, single_step=True)
+        if plan.kernel != 1 or plan.tail_lanes == 0:
+            continue
+        assert plan.tail_lanes == 2, plan.tail_lanes
+        seen += 1
+        probes = [min(i * chunk, n) for i in range(plan.num_chunks + 1)]
+        ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+        g, b = run_bounds(dfa_mod, d, dev, chunk, look, rounds=rounds)
+        say(f"{case} two per lane, chunk {chunk} r {look} rounds {rounds}: {plan.num_chunks} chunks, "
+            f"result {g}")
+        assert g[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+        bad = np.nonzero(b != ps)[0]
+        assert bad.size == 0, f"chunks {bad[:8]}: {b[bad[:8]]} vs {ps[bad[:8]]}"
+    assert seen > 0, "no setting took the one-chunk-per-lane last round"
+    d.close()
+
+
+@pytest.mark.parametrize("case,chunk,look,rounds", [
+    ("c3b", 8192, 2, 5),
+    ("perm", 2048, 1, 3),
+    ("anchored", 4096, 3, 4),
+    ("c3p", 4096, 4, 2),
+])
+def test_tail_two_chunks_per_lane_maps(dfa_mod, monkeypatch, case, chunk, look, rounds):
+    monkeypatch.setenv("DFA_TAIL_K", "2")
+    n = (2 << 20) + 77
+    w, x = cases()[case](n)
+    d = dfa_mod.DFA.from_workload(w)
+    plan = dfa_mod.dfa_plan(d, n, chunk, look, rounds=rounds, interleave=True, single_step=True)
+    assert plan.kernel == 1 and plan.tail_lanes == 2, (plan.kernel, plan.tail_lanes)
+    pairs = check_maps(dfa_mod, w, x, to_dev(x), d, chunk, look, rounds=rounds, interleave=True,
+                       single_step=True)
+    say(f"two per lane maps {case}: {pairs} pairs")
+    d.close()
+
+
+@pytest.mark.parametrize("n", [4096 + 1, 4096 + 2063, 3 * 4096 - 1, 129 * 4096 + 700, 130 * 4096])
+def test_tail_two_chunks_per_lane_ragged(dfa_mod, monkeypatch, n):
+    """The last chunk short, and the chunk count below, at and past one
+    wavefront's 128 chunks."""
+    monkeypatch.setenv("DFA_TAIL_K", "2")
+    w, x = cases()["c3b"](n)
+    d = dfa_mod.DFA.from_workload(w)
+    for rounds in (4, 5):
+        plan = dfa_mod.dfa_plan(d, n, 4096, 2, rounds=rounds, interleave=True)
+        assert plan.tail_lanes == 2
+        probes = [min(i * 4096, n) for i in range(plan.num_chunks + 1)]
+        ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+        g, b = run_bounds(dfa_mod, d, to_dev(x), 4096, 2, rounds=rounds)
+        assert g[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+        assert np.array_equal(b, ps)
+    d.close()
+
+
+@pytest.mark.parametrize("where", ["tail", "last_bytes", "prefix"])
+def test_tail_two_chunks_per_lane_invalid_byte(dfa_mod, monkeypatch, where):
+    import torch
+    monkeypatch.setenv("DFA_TAIL_K", "2")
+    n = (1 << 20) + 5
+    w, x = cases()["c3p"](n)
+    x = x.copy()
+    chunk, rounds = 8192, 4
+    t0 = 32 << (2 * (rounds - 2))
+    # chunk 77 is the second chunk of its lane (77 = 64 + 13)
+    pos = {"tail": 77 * chunk + t0 + 1000, "last_bytes": n - 2, "prefix": 91 * chunk + 100}[where]
+    x[pos] = 0xC1
+    d = dfa_mod.DFA.from_workload(w)
+    assert dfa_mod.dfa_plan(d, n, chunk, 1, rounds=rounds, interleave=True,
+                            single_step=True).tail_lanes == 2
+    res, _ = dfa_mod.dfa_match_ex(d, to_dev(x), chunk_len=chunk, lookahead=1, rounds=rounds,
+                                  interleave=True, single_step=True)
+    torch.cuda.synchronize()
+    assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
     d.close()

@@ -1070,7 +1070,7 @@ def bench_large(args, dfa, torch, stream) -> dict:
     code_lay = 2 if dom["d"].info().packed_layout == 2 else 1
     lay = 4 if step_k == 2 else 3 if plan.raw_input else code_lay
     if plan.kernel == 1 and plan.tail_lanes:
-        kernel = f"k_tail<{code_lay}>"
+        kernel = f"k_tail<{code_lay}, {int(plan.tail_lanes)}>"
         t0 = int(plan.tail_start)
         chunk = int(plan.chunk_len)
         nch = int(plan.num_chunks)

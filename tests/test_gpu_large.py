@@ -26,11 +26,14 @@ GiB = 1 << 30
 MiB = 1 << 20
 
 # (lookahead, chunk, options) of the readout checks: the benchmark's settings
-# first, then three others
+# first, then others (32 KiB chunks with merged rounds: more chunks than one
+# pass of one-chunk-per-lane holds, so the last round takes two per lane)
 PROTEIN_MAPS = [(4, 65536, {"rounds": 2, "interleave": True, "single_step": True}),
+                (4, 32768, {"rounds": 2, "interleave": True, "single_step": True}),
                 (4, 8192, {"chunk_lanes": True, "single_step": True}), (6, 65536, {"rounds": 4}),
                 (1, 4096, {}), (8, 1 << 20, {})]
-BYTE_MAPS = [(2, 65536, {"rounds": 4, "interleave": True}), (2, 131072, {"rounds": 6, "interleave": True}),
+BYTE_MAPS = [(2, 65536, {"rounds": 4, "interleave": True}), (2, 32768, {"rounds": 4, "interleave": True}),
+             (2, 131072, {"rounds": 6, "interleave": True}),
              (4, 32768, {"rounds": 4}), (1, 4096, {}), (3, 1 << 20, {})]
 
 
@@ -78,6 +81,8 @@ def run_sweep(dfa_mod, w, gen, lookaheads, map_checks, n=configs.C3_BYTES):
             del bnd
     for r, chunk, kw in map_checks:
         plan = dfa_mod.dfa_plan(d, n, chunk, r, **kw)
+        if chunk == 32768 and kw.get("interleave"):
+            assert plan.tail_lanes == 2, plan.tail_lanes
         nch = int(plan.num_chunks)
         # the mean start-set size bounds the oracle's work per sampled chunk
         mean_set = max(1.0, float(plan.set_max) / 2)

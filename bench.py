@@ -73,7 +73,7 @@ def stored_traffic(kernel: str, workload: str, lookahead: int, chunk: int):
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
             for line in fh:
-                m = re.search(r"traffic: kernel=(\S+) workload=(\S+) lookahead=(\d+) "
+                m = re.search(r"traffic: kernel=(.+?) workload=(\S+) lookahead=(\d+) "
                               r"chunk=(\d+) bytes=(\d+) sources=([0-9a-f]+)", line)
                 if m and m.group(1) == kernel and m.group(2) == workload and \
                         int(m.group(3)) == lookahead and int(m.group(4)) == chunk and \
@@ -790,7 +790,7 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
     for _ in range(args.steps):
         dfa.dfa_match_ex(d, dev_in, **opts)
     torch.cuda.synchronize()
-    matcher_ms, call_ms, calls = dfa.dfa_timing_read(stream)
+    matcher_ms, call_ms, kern_ms, calls = dfa.dfa_timing_read_ex(stream)
     dfa.dfa_timing_enable(False, stream)
     fin, acc, flags, nch_run = dfa.result_tuple(result)
     if flags:
@@ -818,6 +818,8 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
             2 if info.packed_layout == 2 else 1)
         kernel = (f"k_chunk_walk<{lay}>" if plan.chunk_lanes else
                   f"k_round<{lay}>" if merged else f"k_match2<{lay}>")
+        if plan.tail_lanes:
+            kernel = f"k_tail<{2 if info.packed_layout == 2 else 1}, {int(plan.tail_lanes)}>"
     else:
         kernel = "k_match"
     matcher_avg_ms = matcher_ms / max(calls, 1)
@@ -891,6 +893,28 @@ def bench_single(args, dfa, torch, stream, name) -> dict:
                    "lds_achieved_glookup_s": round(achieved / 1e9, 2),
                    "lds_frac": round(achieved / LDS_LOOKUP_PEAK, 4)})
         rl.pop("hbm_frac", None)
+    if plan.kernel == 1 and plan.tail_lanes:
+        # the one-chunk-per-lane last round is the longest launch: it reads
+        # every chunk's bytes from tail_start on from the raw input, with at
+        # least two LDS lookups per byte (its code, one transition); timed by
+        # HIP events around that launch
+        t0b = int(plan.tail_start)
+        lens = np.minimum(int(chunk), nbytes - np.arange(nch, dtype=np.int64) * int(chunk))
+        tail_bytes = int(np.maximum(lens - t0b, 0).sum())
+        kavg = kern_ms / max(calls, 1)
+        gbs = tail_bytes / (kavg * 1e-3) / 1e9
+        line["roofline"] = {
+            "bound": "hbm", "kernel": kernel,
+            "of": f"{kernel}, the longest single launch of the call (HIP events on its stream)",
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
+            "algorithmic_bytes_per_launch": tail_bytes, "kernel_avg_ms": round(kavg, 4),
+            "lds_view": {"algorithmic_lookups_per_launch": 2 * tail_bytes,
+                         "achieved_Glookups_s": round(2 * tail_bytes / (kavg * 1e-3) / 1e9, 1),
+                         "peak_Glookups_s": round(LDS_LOOKUP_PEAK / 1e9, 1),
+                         "frac": round(2 * tail_bytes / (kavg * 1e-3) / LDS_LOOKUP_PEAK, 4)},
+            "step_hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        }
 
     if not args.no_cpu_baseline:
         import oracle
@@ -1286,6 +1310,22 @@ def main() -> int:
                 a2 = argparse.Namespace(**vars(args))
                 a2.lookahead, a2.rounds, a2.chunk = -1, -1, 0
                 sub[name] = sub_record(timed(name, bench_single, a2, dfa, torch, stream, name))
+            # the protein-style configuration again with one symbol per step
+            # and a one-chunk-per-lane last round over the raw input: no
+            # pair-code stream through HBM (the autotuner weighs it too)
+            a2 = argparse.Namespace(**vars(args))
+            a2.lookahead, a2.rounds, a2.chunk = 6, 2, 2048
+            a2.interleave, a2.single_step, a2.no_cpu_baseline = True, True, True
+            raw = timed("c2 raw input", bench_single, a2, dfa, torch, stream, "c2")
+            rl = raw["roofline"]
+            sub["c2"]["raw_input_last_round"] = {
+                "setting": {"lookahead": 6, "chunk": 2048, "rounds": 2, "interleave": True,
+                            "single_step": True},
+                "value": raw["value"], "unit": raw["unit"], "ms_per_step": raw["ms_per_step"],
+                "kernel": rl["kernel"], "frac": rl["frac"], "unit_frac": rl["unit"],
+                "traffic": rl.get("traffic"), "traffic_source": rl.get("traffic_source"),
+                "final_state": raw.get("final_state"),
+            }
             a4 = argparse.Namespace(**vars(args))
             if not args.tune:
                 a4.chunk, a4.lookahead = 8192, 6

@@ -579,9 +579,17 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
             MatchPlan p0;
             if (plan_match(d, n, 0, base.lookahead, &p0, 0) == DFA_OK) c0 = p0.chunk;
         }
-        const uint32_t variants[] = {DFA_MATCH_ROUNDS(2), DFA_MATCH_ROUNDS(3), DFA_MATCH_ROUNDS(4),
-                                     DFA_MATCH_INTERLEAVE, DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2),
-                                     DFA_MATCH_CHUNK_LANES};
+        std::vector<uint32_t> variants = {DFA_MATCH_ROUNDS(2), DFA_MATCH_ROUNDS(3), DFA_MATCH_ROUNDS(4),
+                                          DFA_MATCH_INTERLEAVE, DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2),
+                                          DFA_MATCH_CHUNK_LANES};
+        // with a two-symbol table the variants above take two-symbol steps
+        // (and so no one-chunk-per-lane last round); one symbol per step
+        // with interleaved merged rounds reads the raw input in its last
+        // round instead of a pair-code stream
+        if (d->dev.pairs) {
+            variants.push_back(DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2) | DFA_MATCH_SINGLE_STEP);
+            variants.push_back(DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(3) | DFA_MATCH_SINGLE_STEP);
+        }
         // (merged rounds stop a walk at an absorbing state, so where the
         // input reaches one within a long chunk, lengths far above the
         // one-round best can win: up to 64 times it).  Besides r and r + 1

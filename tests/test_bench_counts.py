@@ -109,3 +109,23 @@ def test_merged_counts(case, chunk, r, rounds, step):
             walks, t0 = sorted(nxt), t1
         covered += ext
     assert bench.merged_lookups(w, x, chunk, r, rounds, step) == (reads, covered)
+
+
+def test_stored_traffic_lines_parse():
+    """Every committed traffic line names a kernel the way the bench does
+    (template arguments with spaces included) and parses back."""
+    import glob
+    import re
+    lines = []
+    for path in glob.glob(os.path.join(bench.ROOT, "profiles", "*.md")):
+        with open(path) as fh:
+            lines += [ln for ln in fh if ln.startswith("traffic:")]
+    assert lines, "no traffic lines in profiles/"
+    for ln in lines:
+        m = re.match(r"traffic: kernel=(.+?) workload=(\S+) lookahead=(\d+) chunk=(\d+) "
+                     r"bytes=(\d+) sources=([0-9a-f]+)", ln)
+        assert m, ln
+        if m.group(6) != bench.kernel_source_digest():
+            continue
+        got, src = bench.stored_traffic(m.group(1), m.group(2), int(m.group(3)), int(m.group(4)))
+        assert got == int(m.group(5)) and src, ln

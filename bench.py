@@ -1020,9 +1020,26 @@ def bench_large(args, dfa, torch, stream) -> dict:
                   "st": st, "chosen": chosen, "create_ms": create_ms,
                   "res": torch.empty(4, dtype=torch.int32, device="cuda")})
 
+    # the step's two membership tests are independent: each runs on its own
+    # stream (default priority), both after the step's start on `stream`,
+    # which then waits for both, so steps follow one another and the two
+    # tests of a step overlap (--serial-step: one after the other on `stream`)
+    side = [torch.cuda.Stream() for _ in P]
+
     def step():
-        for p in P:
-            dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
+        if args.serial_step:
+            for p in P:
+                dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], stream, p["res"]))
+            return
+        start = torch.cuda.Event()
+        start.record(stream)
+        for p, sp in zip(P, side):
+            sp.wait_event(start)
+            dfa.dfa_match_ex(p["d"], p["dev"], **c3_opts(p["st"], sp, p["res"]))
+        for sp in side:
+            done = torch.cuda.Event()
+            done.record(sp)
+            stream.wait_event(done)
 
     if args.calibrate_copy:
         # one device copy of a known size, for scaling the HBM counters
@@ -1131,6 +1148,8 @@ def bench_large(args, dfa, torch, stream) -> dict:
             "workload": f"large DFAs: {n >> 30} GiB per DFA, both resident in HBM; one step = "
                         f"the {P[0]['desc']} plus the {P[1]['desc']}",
             "bytes_per_step": 2 * n,
+            "step": ("the two tests one after the other on one stream" if args.serial_step else
+                     "the two tests on two streams, overlapping; steps one after another"),
         },
         "roofline": {
             "bound": "hbm",
@@ -1246,6 +1265,9 @@ def main() -> int:
     ap.add_argument("--no-sub", action="store_true",
                     help="c3: skip the protein-style, plain, batched and served sub-records")
     ap.add_argument("--no-sweep", action="store_true", help="c3: skip the chunk sweep")
+    ap.add_argument("--serial-step", action="store_true",
+                    help="c3: run the step's two tests one after the other on one stream "
+                         "(default: each on its own stream, overlapping)")
     ap.add_argument("--tune", action="store_true",
                     help="c3, c4: choose settings with the autotuners (untimed) instead of the "
                          "fixed ones")

@@ -475,7 +475,7 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     const bool raw_lanes = (flags & DFA_MATCH_CHUNK_LANES) && !(flags & DFA_MATCH_INTERLEAVE) &&
                            d->dev.direct && !p->pairs;
     if (p->packed && (flags & (DFA_MATCH_INTERLEAVE | DFA_MATCH_CHUNK_LANES)) && !raw_lanes &&
-        p->lookahead != 2 && chunk % 32 == 0) {
+        chunk % 32 == 0) {
         const uint64_t bytes_per_chunk = p->pairs ? chunk / 2 : chunk * p->code_bytes;
         p->ilv_nblk = (uint32_t)(bytes_per_chunk / 16);
     }

@@ -719,10 +719,11 @@ __global__ __launch_bounds__(256) void k_translate_pairs_direct(const uint8_t *_
 __global__ void k_chunkinfo_w(DevDFA d, const uint8_t *__restrict__ in, uint64_t chunk,
                               uint32_t nch, uint32_t r, uint32_t W,
                               uint16_t *__restrict__ msize, uint32_t *__restrict__ cset,
-                              uint32_t *__restrict__ bits) {
+                              uint32_t *__restrict__ bits, uint32_t *__restrict__ chunk_zero) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nch) return;
     for (uint32_t k = 0; k < W; ++k) bits[(size_t)i * W + k] = 0;
+    if (chunk_zero) chunk_zero[i] = 0;   // per-chunk slot counters of the last round
     uint32_t m = 0, id = 0;
     if (i > 0) {
         const uint64_t p = (uint64_t)i * chunk;
@@ -761,6 +762,8 @@ struct Match2Args {
     uint32_t spread;         // tiles to waves: 1 = first wave of every workgroup first
                              // (few, large workgroups per CU), 0 = workgroup by workgroup
     uint64_t before;         // bytes of lookahead before the input (block maps; 0 = none)
+    const uint8_t *raw;      // the input itself (the window pass reads it when the code
+                             // stream is chunk-interleaved)
 };
 
 // First 16-byte unit of block b of chunk c in the code stream, and the
@@ -856,10 +859,27 @@ __global__ __launch_bounds__(1024, 8) void k_window2(Match2Args a) {
         uint32_t maxlen = 0;
 #pragma unroll
         for (int j = 0; j < S; ++j) maxlen = max(maxlen, len[j]);
-        for (uint32_t t = 0; t < maxlen; ++t) {
+        if (a.ilv_nblk) {
+            // the code stream is chunk-interleaved (and may cover only each
+            // chunk's first bytes): read the bytes before the chunk from the
+            // input and turn them into codes here.  A byte outside Sigma
+            // (flagged where its own chunk is walked) steps as code 0, so the
+            // walk stays on table rows.
+            for (uint32_t t = 0; t < maxlen; ++t) {
 #pragma unroll
-            for (int j = 0; j < S; ++j)
-                if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[beg[j] + t]);
+                for (int j = 0; j < S; ++j) {
+                    if (t < len[j]) {
+                        const uint16_t c = a.d.code[a.raw[beg[j] + t]];
+                        st[j] = lds_ld(st[j] + (c == kCodeInvalid ? 0u : (uint32_t)c));
+                    }
+                }
+            }
+        } else {
+            for (uint32_t t = 0; t < maxlen; ++t) {
+#pragma unroll
+                for (int j = 0; j < S; ++j)
+                    if (t < len[j]) st[j] = lds_ld(st[j] + (uint32_t)codes[beg[j] + t]);
+            }
         }
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -2066,8 +2086,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     const bool direct = !pairs && !p.ilv_nblk && d->dev.direct && p.lookahead != 2 &&
                         (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
     const Ilv ilv{p.ilv_nblk, p.nch, p.chunk};
-    if (p.ilv_nblk && (p.chunk % 32 != 0 || p.lookahead == 2))
-        return fail(DFA_E_INVAL, "interleaved codes with a window pass or odd chunks");
+    if (p.ilv_nblk && p.chunk % 32 != 0)
+        return fail(DFA_E_INVAL, "interleaved codes with odd chunks");
     const uint32_t L = pairs ? 4u : direct ? 3u : d->dev.layout;
     if (pairs && (p.chunk % 32 != 0 || p.lookahead == 2))
         return fail(DFA_E_INVAL, "two-symbol plan with a window pass or odd chunks");
@@ -2108,6 +2128,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         a.d.abs_shift = 2;
     }
     a.codes = direct ? static_cast<const void *>(d_in) : b.codes;
+    a.raw = d_in;
     a.n = p.n;
     a.chunk = p.chunk;
     a.nch = p.nch;
@@ -2134,7 +2155,7 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
     if (p.lookahead == 2) {
         // window pairs (chunk, state of I_sigma_1) -> start-set bitmaps -> member lists
         hipLaunchKernelGGL(k_chunkinfo_w, dim3((p.nch + 255) / 256), dim3(256), 0, s, d->dev, d_in,
-                           p.chunk, p.nch, p.r, p.bitmap_words, msize, b.cset, b.bits);
+                           p.chunk, p.nch, p.r, p.bitmap_words, msize, b.cset, b.bits, b.tail_cnt);
         launch_scan<0>(p, q, b, nullptr, start, s);
         const void *wf = window2_kernel(L, p.slots);
         void *wargs[] = {&a};

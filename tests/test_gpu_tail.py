@@ -291,3 +291,49 @@ def test_tail_two_chunks_per_lane_invalid_byte(dfa_mod, monkeypatch, where):
     torch.cuda.synchronize()
     assert dfa_mod.result_tuple(res)[2] & dfa_mod.FLAG_SYMBOL
     d.close()
+
+
+@pytest.mark.parametrize("case", ["c3b", "c3p", "c1", "anchored", "perm", "cols6"])
+def test_tail_window_lookahead(dfa_mod, case):
+    """Lookahead beyond the precomputed sets (the window pass: each chunk's
+    Eq. 13 set as the image of a precomputed set over the bytes nearer the
+    chunk) with interleaved codes and the one-chunk-per-lane last round: the
+    window pass reads those bytes from the input itself.  Every boundary
+    state and the result equal the oracle's."""
+    n = (3 << 20) + 13
+    w, x = cases()[case](n)
+    d = dfa_mod.DFA.from_workload(w)
+    dev = to_dev(x)
+    r0 = int(d.info().lookahead_tables)
+    seen = 0
+    for chunk, look, rounds in ((2048, r0 + 1, 2), (8192, r0 + 2, 4), (4096, 16, 3), (64, 40, 2)):
+        if look <= r0:
+            continue
+        plan = dfa_mod.dfa_plan(d, n, chunk, look, rounds=rounds, interleave=True, single_step=True)
+        if plan.kernel != 1 or plan.tail_lanes == 0:
+            continue
+        seen += 1
+        probes = [min(i * chunk, n) for i in range(plan.num_chunks + 1)]
+        ofin, ps = oracle.walk(w.delta, w.byte_to_symbol, w.q0, x, probes=probes)
+        g, b = run_bounds(dfa_mod, d, dev, chunk, look, rounds=rounds)
+        say(f"{case} window r {look} (r0 {r0}) chunk {chunk} rounds {rounds}: result {g}")
+        assert g[:3] == (ofin, oracle.accepts(ofin, w.accepting), 0)
+        bad = np.nonzero(b != ps)[0]
+        assert bad.size == 0, f"chunks {bad[:8]}: {b[bad[:8]]} vs {ps[bad[:8]]}"
+    assert seen > 0, "no window-pass setting took the one-chunk-per-lane last round"
+    d.close()
+
+
+@pytest.mark.parametrize("case,chunk,look,rounds", [("c3b", 8192, 4, 4), ("c3p", 4096, 6, 2),
+                                                    ("perm", 2048, 10, 3)])
+def test_tail_window_lookahead_maps(dfa_mod, case, chunk, look, rounds):
+    n = (2 << 20) + 77
+    w, x = cases()[case](n)
+    d = dfa_mod.DFA.from_workload(w)
+    assert look > int(d.info().lookahead_tables)
+    plan = dfa_mod.dfa_plan(d, n, chunk, look, rounds=rounds, interleave=True, single_step=True)
+    assert plan.kernel == 1 and plan.tail_lanes == 1, (plan.kernel, plan.tail_lanes)
+    pairs = check_maps(dfa_mod, w, x, to_dev(x), d, chunk, look, rounds=rounds, interleave=True,
+                       single_step=True)
+    say(f"window maps {case}: {pairs} pairs")
+    d.close()

@@ -1276,24 +1276,41 @@ struct MergeMapArgs {
     uint32_t rounds;
 };
 
+// Four pairs per thread (256 apart, so loads stay coalesced): their leader
+// chains are followed side by side, four dependent gathers in flight.
+constexpr uint32_t kMergePer = 4;
+
 __global__ __launch_bounds__(256) void k_merge_maps(Match2Args a, MergeMapArgs mm) {
     const uint32_t total = a.first[a.nch];
-    const uint32_t P = blockIdx.x * blockDim.x + threadIdx.x;
-    if (P >= total) return;
-    uint32_t v = mm.lo[0][P];
-    for (uint32_t k = 1; k < mm.rounds && !(v & kDone); ++k) v = mm.lo[k][v];
-    if ((v & (kDone | kMapped)) == (kDone | kMapped)) {
-        a.maps[P] = (uint16_t)(v & 0xFFFFu);
-        return;
+    const uint32_t base = blockIdx.x * blockDim.x * kMergePer + threadIdx.x;
+    uint32_t v[kMergePer];
+#pragma unroll
+    for (uint32_t j = 0; j < kMergePer; ++j) {
+        const uint32_t P = base + j * blockDim.x;
+        v[j] = P < total ? mm.lo[0][P] : (kDone | kMapped);
     }
-    // a walk that stopped before the last round: its end state
-    const uint32_t e = (v & kDone) ? (v & 0x7FFFu) : 0xFFFFu;   // 0xFFFF: not reached
-    const uint32_t tile = P / a.tile;
-    const uint32_t ntiles = (total + a.tile - 1) / a.tile;
-    const uint32_t lo0 = a.tile_first[tile];
-    const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
-    const uint32_t c = owner_chunk(a.first, lo0, hi0, P);
-    a.maps[P] = e < a.d.nq ? map_entry(a, c, e) : kBadPos;
+    for (uint32_t k = 1; k < mm.rounds; ++k) {
+#pragma unroll
+        for (uint32_t j = 0; j < kMergePer; ++j)
+            if (!(v[j] & kDone)) v[j] = mm.lo[k][v[j]];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kMergePer; ++j) {
+        const uint32_t P = base + j * blockDim.x;
+        if (P >= total) continue;
+        if ((v[j] & (kDone | kMapped)) == (kDone | kMapped)) {
+            a.maps[P] = (uint16_t)(v[j] & 0xFFFFu);
+            continue;
+        }
+        // a walk that stopped before the last round: its end state
+        const uint32_t e = (v[j] & kDone) ? (v[j] & 0x7FFFu) : 0xFFFFu;   // 0xFFFF: not reached
+        const uint32_t tile = P / a.tile;
+        const uint32_t ntiles = (total + a.tile - 1) / a.tile;
+        const uint32_t lo0 = a.tile_first[tile];
+        const uint32_t hi0 = tile + 1 < ntiles ? a.tile_first[tile + 1] + 1 : a.nch;
+        const uint32_t c = owner_chunk(a.first, lo0, hi0, P);
+        a.maps[P] = e < a.d.nq ? map_entry(a, c, e) : kBadPos;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2237,7 +2254,8 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
         for (uint32_t k = 0; k < p.rounds; ++k) mm.lo[k] = b.lo[k];
         mm.rounds = p.rounds;
         const uint64_t bound = (uint64_t)p.max_tiles * kWave2 * p.slots;
-        hipLaunchKernelGGL(k_merge_maps, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s, a, mm);
+        hipLaunchKernelGGL(k_merge_maps, dim3((uint32_t)((bound + 256 * kMergePer - 1) / (256 * kMergePer))),
+                           dim3(256), 0, s, a, mm);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "k_merge_maps launch");
     } else {

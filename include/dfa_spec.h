@@ -315,17 +315,22 @@ int dfa_match_noalloc(const dfa_t *d, const uint8_t *d_input, size_t len, uint32
 /* dfa_autotune -- time candidate (lookahead r, chunk length) settings on the
  * caller's device input and keep the fastest.  Every candidate gives the same
  * result (the method is exact); only speed differs.  Inputs beyond 1 GiB
- * are tuned on their first 1 GiB.  The choice is cached per DFA and
+ * are tuned on their first 1 GiB; the best setting of each way of walking is
+ * then timed on the whole input, as measured and with its chunk length scaled
+ * to the input (the chunk count measured on the sample), then the fastest
+ * with a quarter, half and twice its chunk length, and the fastest kept.
+ * The choice is cached per DFA and
  * power-of-two length bucket and used by calls with lookahead
  * DFA_LOOKAHEAD_AUTO.  Around the best (r, chunk) (r, r + 1 and r0, a quarter
  * to four times the chunk, and 16 and 64 times it for merged rounds, which
  * stop a walk at an absorbing state) it then times merged rounds (DFA_MATCH_ROUNDS 2-4),
- * interleaved codes (one and two rounds) and one chunk per lane, then the
+ * interleaved codes (one to four rounds) and one chunk per lane, then the
  * best with DFA_MATCH_SINGLE_STEP where a two-symbol table exists, and for a
  * DFA with an absorbing state with DFA_MATCH_EARLY_EXIT; whichever is faster
  * is kept (in best->flags).
  *   d_input: device, len bytes.  best: out (may be NULL).  best_ms: out, the
- *   fastest candidate's time per call (may be NULL).  Synchronises `stream`. */
+ *   chosen setting's time per call on the whole input (may be NULL).
+ *   Synchronises `stream`. */
 int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, void *stream,
                  dfa_match_opts_t *best, double *best_ms);
 

@@ -562,8 +562,16 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
         }
         return t_best;
     };
+    // the best of each way of walking (flags) on the sample, for the whole-
+    // input check below
+    std::map<uint32_t, std::pair<double, dfa_match_opts_t>> family;
+    family[pick.flags] = {pick_ms, pick};
     auto consider = [&](const dfa_match_opts_t &o) {
         const double t = time_opts(o);
+        if (rc == DFA_OK) {
+            auto it = family.find(o.flags);
+            if (it == family.end() || t < it->second.first) family[o.flags] = {t, o};
+        }
         if (rc == DFA_OK && t < pick_ms) {
             pick_ms = t;
             pick = o;
@@ -581,6 +589,8 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
         }
         std::vector<uint32_t> variants = {DFA_MATCH_ROUNDS(2), DFA_MATCH_ROUNDS(3), DFA_MATCH_ROUNDS(4),
                                           DFA_MATCH_INTERLEAVE, DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(2),
+                                          DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(3),
+                                          DFA_MATCH_INTERLEAVE | DFA_MATCH_ROUNDS(4),
                                           DFA_MATCH_CHUNK_LANES};
         // with a two-symbol table the variants above take two-symbol steps
         // (and so no one-chunk-per-lane last round); one symbol per step
@@ -644,6 +654,66 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
             pick = o;
         }
     }
+    // On an input longer than the sample, the sample's best chunk length
+    // gives more chunks than were measured (more lanes and tiles than the
+    // device holds at once), and which way of walking wins can change with
+    // the chunk count: the best setting of every way of walking, as measured
+    // and with its chunk length scaled by len / n (the measured chunk count),
+    // is timed on the whole input, and the fastest is kept.
+    double full_ms = pick_ms * (double)len / (double)std::max<size_t>(n, 1);
+    if (rc == DFA_OK && len > n) {
+        auto time_full = [&](const dfa_match_opts_t &o) -> double {
+            double t_best = 1e30;
+            for (int rep = 0; rep < 3 && rc == DFA_OK; ++rep) {
+                if (rep > 0) (void)hipEventRecord(a, s);
+                rc = run_match(d, d_input, len, DFA_Q0, &o, s, res, nullptr);
+                if (rep > 0) {
+                    (void)hipEventRecord(b, s);
+                    (void)hipEventSynchronize(b);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    t_best = std::min<double>(t_best, ms);
+                }
+            }
+            return t_best;
+        };
+        double best_full = 1e30;
+        dfa_match_opts_t best_o = pick;
+        for (const auto &f : family) {
+            dfa_match_opts_t o = f.second.second;
+            for (int scale = 0; scale < 2 && rc == DFA_OK; ++scale) {
+                if (scale) {
+                    if (o.chunk_len == 0) break;
+                    uint64_t c = (uint64_t)((double)o.chunk_len * (double)len / (double)n);
+                    c = std::max<uint64_t>(32, std::min<uint64_t>(c, (1ull << 31) - 32) / 32 * 32);
+                    o.chunk_len = c;
+                }
+                const double t = time_full(o);
+                if (rc == DFA_OK && t < best_full) {
+                    best_full = t;
+                    best_o = o;
+                }
+            }
+        }
+        // then halving and doubling the chunk length around the winner
+        for (int sh : {-2, -1, 1}) {
+            if (rc != DFA_OK || best_o.chunk_len == 0) break;
+            dfa_match_opts_t o = best_o;
+            const uint64_t c0 = best_o.chunk_len;
+            const uint64_t c = sh < 0 ? c0 >> (-sh) : c0 << sh;
+            if (c < 256 || c >= (1ull << 31) || ((o.flags & 0xF00u) && c % 32 != 0)) continue;
+            o.chunk_len = c;
+            const double t = time_full(o);
+            if (rc == DFA_OK && t < best_full) {
+                best_full = t;
+                best_o = o;
+            }
+        }
+        if (rc == DFA_OK) {
+            full_ms = best_full;
+            pick = best_o;
+        }
+    }
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -654,7 +724,7 @@ extern "C" int dfa_autotune(const dfa_t *d, const uint8_t *d_input, size_t len, 
         g_tuned[{d, length_bucket(len)}] = pick;
     }
     if (best) *best = pick;
-    if (best_ms) *best_ms = pick_ms * (double)len / (double)std::max<size_t>(n, 1);
+    if (best_ms) *best_ms = full_ms;
     return DFA_OK;
 }
 

@@ -48,9 +48,17 @@ def both(dfa_mod, d, dev, **kw):
     ("c2", {"chunk_len": 1024, "lookahead": 6, "interleave": True}),
     ("c3b", {"chunk_len": 32768, "lookahead": 4, "rounds": 4}),        # merged walks
     ("c1", {"chunk_len": 0, "lookahead": 1}),                          # planner's choice
+    # merged walks with the one-chunk-per-lane last round over the raw input:
+    # one and two chunks per lane, and after a window pass (r above r0)
+    ("c3b", {"chunk_len": 8192, "lookahead": 2, "rounds": 4, "interleave": True}),
+    ("c3b", {"chunk_len": 8192, "lookahead": 2, "rounds": 4, "interleave": True, "_tail_k": "2"}),
+    ("c3b", {"chunk_len": 8192, "lookahead": 4, "rounds": 4, "interleave": True}),
 ])
-def test_noalloc_equals_match_ex_twice(dfa_mod, which, kw):
+def test_noalloc_equals_match_ex_twice(dfa_mod, monkeypatch, which, kw):
     import torch
+    kw = dict(kw)
+    if "_tail_k" in kw:
+        monkeypatch.setenv("DFA_TAIL_K", kw.pop("_tail_k"))
     w, gen = {"c2": (configs.c2_dfa(), lambda n: configs.c2_input(n, seed=5)),
               "c3b": (configs.c3_byte_dfa(), configs.c3_byte_input),
               "c1": (configs.c1_dfa(2), configs.c1_input)}[which]

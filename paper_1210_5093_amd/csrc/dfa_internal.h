@@ -168,6 +168,8 @@ struct MatchPlan {
     uint32_t tail_blocks = 0;
     uint32_t tail_k = 1;         // chunks per lane in that round (2: two chunks side by side
                                  // once each has one chain left)
+    bool round1c = false;        // first merged round chunk-major (k_round1c): one wavefront
+                                 // per chunk over its whole start set
     uint64_t before = 0;         // block map of a shard: bytes of lookahead readable before
                                  // the input; chunk 0 then starts from its lookahead set
     bool chunk_lanes = false;    // one chunk per lane with merged walks (interleaved codes)

@@ -561,6 +561,20 @@ int plan_match(const dfa *d, uint64_t n, uint64_t chunk_req, uint32_t lookahead,
     if (p->rounds > 1 && (uint64_t)p->max_tiles * match2_tile_pairs(p->slots) +
                                  (uint64_t)p->nch * kTailSlots >= (1ull << 30))
         p->rounds = 1;
+    // first merged round chunk-major (one wavefront per chunk, its codes
+    // loaded once, its walks grouped by end state alone) over interleaved
+    // one-symbol codes, when start sets average at least 128 states (a
+    // wavefront's 320 walks then mostly busy) and never exceed 320;
+    // DFA_ROUND1=0 / =1 turns it off / on wherever it can run
+    {
+        const char *f1 = std::getenv("DFA_ROUND1");
+        const double mean_set = p->lookahead == 0 ? (double)d->setmax_host[0]
+                                : p->lookahead == 1 ? d->info.mean_iset
+                                                    : d->mset_mean[std::min(p->r, d->dev.r0)];
+        const bool can = p->packed && p->rounds > 1 && p->ilv_nblk && !p->pairs && p->stride <= 320 &&
+                         (d->dev.layout == 1 || d->dev.layout == 2) && !d->dev.direct;
+        p->round1c = can && (f1 && (f1[0] == '0' || f1[0] == '1') ? f1[0] == '1' : mean_set >= 128.0);
+    }
     // merged walks over interleaved one-symbol codes: the last round takes
     // one chunk per lane and reads the raw input (bytes to codes through a
     // table in LDS), so only the first tail_t0 bytes of each chunk are

@@ -1268,6 +1268,157 @@ __global__ __launch_bounds__(1024, S == 4 ? 5 : 6) void k_round(Match2Args a, Ro
     }
 }
 
+// First merged round, chunk-major (interleaved codes, large start sets): a
+// wavefront takes one chunk at a time and walks its whole start set, up to
+// kR1Slots walks per lane, over the chunk's first t1 bytes.  The chunk's codes
+// are the same for every walk of the wavefront, so they are loaded once (as
+// wavefront-uniform values); the grouping key is the end state alone (a
+// per-wavefront hash table as in k_round); the leaders' slots of a
+// one-chunk-per-lane last round are numbered without atomics (the wavefront
+// holds all of its chunk's leaders), and the rest of its leaders go to the
+// next round's list, region c mod kRegions.  Outcomes as k_round's.
+constexpr uint32_t kR1Slots = 5;   // 320 walks per wavefront >= any start set here
+
+template <int L>
+__global__ __launch_bounds__(1024, 5) void k_round1c(Match2Args a, RoundArgs m) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table<L>(a.d, smem);
+    constexpr uint32_t kCodeBytes = L == 2 ? 2u : 1u;
+    const uint32_t lane = threadIdx.x & (kWave2 - 1);
+    const uint32_t waves = blockDim.x / kWave2;
+    const uint32_t wave_id = blockIdx.x * waves + threadIdx.x / kWave2;
+    const uint32_t total_waves = gridDim.x * waves;
+    uint32_t *round_table = reinterpret_cast<uint32_t *>(smem + a.d.stab_bytes + kRoundPreBytes);
+    uint32_t *tab = round_table + (threadIdx.x / kWave2) * kRoundHash;
+    const uint32_t R = L == 2 ? 2u : a.d.rowbytes;
+    const uint4 *codes16 = reinterpret_cast<const uint4 *>(a.codes);
+    const uint64_t lanes_lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    for (uint32_t c = wave_id; c < a.nch; c += total_waves) {
+        const uint32_t f0 = a.first[c];
+        const uint32_t mcnt = a.first[c + 1] - f0;
+        const uint64_t len = min<uint64_t>(a.chunk, a.n - (uint64_t)c * a.chunk);
+        const uint32_t steps = (uint32_t)min<uint64_t>(len, m.t1);
+        uint32_t st[kR1Slots];
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            const uint32_t q = j * kWave2 + lane;
+            st[j] = q < mcnt ? R * pair_start(a, c, f0 + q) : 0u;
+        }
+        // the chunk's first 32 codes (16 B units of the interleaved stream)
+        uint32_t cw[16];
+#pragma unroll
+        for (uint32_t b = 0; b < 32u * kCodeBytes / 16u; ++b) {
+            const uint4 u = codes16[code_unit(a, c, b, (uint32_t)(a.chunk * kCodeBytes / 16))];
+            cw[4 * b] = u.x;
+            cw[4 * b + 1] = u.y;
+            cw[4 * b + 2] = u.z;
+            cw[4 * b + 3] = u.w;
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < 32; ++t) {
+            if (t >= steps) break;
+            const uint32_t code = L == 2 ? (cw[t >> 1] >> (16 * (t & 1))) & 0xFFFFu
+                                         : (cw[t >> 2] >> (8 * (t & 3))) & 0xFFu;
+#pragma unroll
+            for (uint32_t j = 0; j < kR1Slots; ++j)
+                if (j * kWave2 < mcnt) st[j] = lds_ld(st[j] + code);
+        }
+        // end states; done = the chunk ended or the state is absorbing
+        uint32_t e[kR1Slots];
+        bool act[kR1Slots], valid[kR1Slots];
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            valid[j] = j * kWave2 + lane < mcnt;
+            e[j] = st[j] / R;
+            bool done = true;
+            if (valid[j]) {
+                const uint32_t idx = st[j] >> a.d.abs_shift;
+                const bool absorbed = (lds_ld32(a.d.abs_off + ((idx >> 5) << 2)) >> (idx & 31)) & 1u;
+                done = len <= m.t1 || absorbed;
+            }
+            act[j] = valid[j] && !done;
+        }
+        // group the active walks by end state: the first to claim a hash
+        // entry leads, walks that find their state follow it; a walk whose
+        // probes all meet other states leads alone
+        for (uint32_t k = lane; k < kRoundHash; k += kWave2) tab[k] = kHashEmpty;
+        uint32_t lead[kR1Slots];
+        bool is_lead[kR1Slots];
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            lead[j] = kNone;
+            is_lead[j] = false;
+            if (!act[j]) continue;
+            const uint32_t key = e[j] << 9;
+            const uint32_t q = j * kWave2 + lane;   // < 320: 9 bits
+            uint32_t h = (e[j] * 0x85EBCA77u) >> (32 - kRoundHashBits);
+            bool placed = false;
+            for (int probe = 0; probe < (int)kRoundProbes && !placed; ++probe) {
+                const uint32_t old = atomicCAS(tab + h, kHashEmpty, key | q);
+                if (old == kHashEmpty) {
+                    is_lead[j] = true;
+                    lead[j] = q;
+                    placed = true;
+                } else if ((old & ~0x1FFu) == key) {
+                    lead[j] = old & 0x1FFu;
+                    placed = true;
+                }
+                h = (h + 1) & (kRoundHash - 1);
+            }
+            if (!placed) {
+                is_lead[j] = true;
+                lead[j] = q;
+            }
+        }
+        // leaders numbered in (slot, lane) order: the first kTailSlots take
+        // the chunk's slots of a one-chunk-per-lane last round, the others
+        // (all of them without such a round) go to the next list
+        uint32_t rank[kR1Slots], nlead = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            const uint64_t lm = __ballot(is_lead[j]);
+            rank[j] = nlead + (uint32_t)__popcll(lm & lanes_lt);
+            nlead += (uint32_t)__popcll(lm);
+        }
+        const uint32_t nslot = m.tail_cnt ? min(nlead, kTailSlots) : 0u;
+        const uint32_t nlist = nlead - nslot;
+        uint32_t base = 0;
+        const uint32_t g = c % kRegions;
+        if (nlist) {
+            if (lane == 0) base = g * m.cap + atomicAdd(m.out_cnt + g, nlist);
+            base = __shfl(base, 0);
+        }
+        if (m.tail_cnt && lane == 0) m.tail_cnt[c] = nslot;
+        uint32_t myidx[kR1Slots];
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            myidx[j] = 0;
+            if (!is_lead[j]) continue;
+            if (rank[j] < nslot) {
+                myidx[j] = c * kTailSlots + rank[j];
+                m.tail_st[myidx[j]] = (uint16_t)e[j];
+            } else {
+                myidx[j] = base + (rank[j] - nslot);
+                m.out_list[myidx[j]] = make_uint2(c, e[j]);
+                myidx[j] += m.next_off;
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kR1Slots; ++j) {
+            // the leader's index, from its slot and lane
+            uint32_t li = 0;
+            const uint32_t ql = lead[j] == kNone ? 0u : lead[j];
+#pragma unroll
+            for (uint32_t jj = 0; jj < kR1Slots; ++jj) {
+                const uint32_t v = __shfl(myidx[jj], (int)(ql & (kWave2 - 1)));
+                if ((ql >> 6) == jj) li = v;
+            }
+            if (valid[j]) m.out_lo[f0 + j * kWave2 + lane] = act[j] ? li : (kDone | e[j]);
+        }
+    }
+}
+
 // Map entries of merged walks: pair P follows its leaders round by round to
 // the walk that ran to the end (which stored the map entry), or to its own
 // end state if its walk stopped early.
@@ -2232,7 +2383,11 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             const bool timed = !p.tail && k + 1 == tiled;
             if (timed)
                 if (int rc = mark(ev_kern_begin)) return rc;
-            e = hipLaunchKernel(rf, dim3(p.blocks2), dim3(p.threads2), rargs,
+            const bool chunk_major = k == 0 && p.round1c && (L == 1 || L == 2) && m.t1 == 32u;
+            const void *kf = chunk_major ? (L == 1 ? reinterpret_cast<const void *>(&k_round1c<1>)
+                                                   : reinterpret_cast<const void *>(&k_round1c<2>))
+                                         : rf;
+            e = hipLaunchKernel(kf, dim3(p.blocks2), dim3(p.threads2), rargs,
                                 lds + round_lds_bytes(p.threads2), s);
             if (e != hipSuccess) return hip_fail(e, "k_round launch");
             if (timed)
@@ -2392,7 +2547,8 @@ int set_match2_lds_limit(int lds) {
                          match2_kernel(4, 2, false), match2_kernel(4, 2, true),
                          match2_kernel(4, 4, false), match2_kernel(4, 4, true),
                          chunk_walk_kernel(1), chunk_walk_kernel(2), chunk_walk_kernel(3),
-                         chunk_walk_kernel(4), tail_kernel(1, 1), tail_kernel(2, 1),
+                         chunk_walk_kernel(4), reinterpret_cast<const void *>(&k_round1c<1>),
+                         reinterpret_cast<const void *>(&k_round1c<2>), tail_kernel(1, 1), tail_kernel(2, 1),
                          tail_kernel(1, 2), tail_kernel(2, 2),
                          round_kernel(1, 2, false), round_kernel(1, 4, false),
                          round_kernel(2, 2, false), round_kernel(2, 4, false),
@@ -2418,8 +2574,11 @@ size_t round_lds_bytes(uint32_t threads) {
 size_t tail_lut_bytes() { return kTailLutBytes; }
 uint32_t round_region_cap(const MatchPlan &p) {
     // a region receives the leaders of every kRegions-th tile, at most a
-    // tile's walks each
-    return (uint32_t)(((p.max_tiles + kRegions - 1) / kRegions) * kWave2 * p.slots);
+    // tile's walks each (chunk-major first round: of every kRegions-th
+    // chunk, at most a start set each)
+    const uint64_t tiles = ((p.max_tiles + kRegions - 1) / kRegions) * kWave2 * p.slots;
+    const uint64_t chunks = p.round1c ? ((uint64_t)p.nch + kRegions - 1) / kRegions * p.stride : 0u;
+    return (uint32_t)std::max<uint64_t>(tiles, chunks);
 }
 uint32_t match2_scan_blocks(uint32_t nch) { return (nch + kScanBlock - 1) / kScanBlock; }
 

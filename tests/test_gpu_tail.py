@@ -337,3 +337,24 @@ def test_tail_window_lookahead_maps(dfa_mod, case, chunk, look, rounds):
                        single_step=True)
     say(f"window maps {case}: {pairs} pairs")
     d.close()
+
+
+@pytest.mark.parametrize("case,look,rounds", [("c3b", 2, 4), ("c3p", 4, 2), ("perm", 10, 3),
+                                              ("anchored", 3, 3), ("cols6", 3, 2)])
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_first_round_chunk_major(dfa_mod, monkeypatch, case, look, rounds, mode):
+    """The first merged round chunk-major (DFA_ROUND1=1: one wavefront per
+    chunk, grouping by end state) and tile-major (=0), both with the
+    one-chunk-per-lane last round: the state maps themselves equal the
+    oracle's (chunks with one start state, sets of hundreds, absorbing
+    states, walks that never meet)."""
+    monkeypatch.setenv("DFA_ROUND1", mode)
+    n = (2 << 20) + 77
+    w, x = cases()[case](n)
+    d = dfa_mod.DFA.from_workload(w)
+    plan = dfa_mod.dfa_plan(d, n, 4096, look, rounds=rounds, interleave=True, single_step=True)
+    assert plan.kernel == 1 and plan.tail_lanes >= 1, (plan.kernel, plan.tail_lanes)
+    pairs = check_maps(dfa_mod, w, x, to_dev(x), d, 4096, look, rounds=rounds, interleave=True,
+                       single_step=True)
+    say(f"first round mode {mode} {case}: {pairs} pairs")
+    d.close()

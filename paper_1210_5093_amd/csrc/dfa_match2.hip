@@ -30,6 +30,8 @@
 // matcher's, so the combination kernels are shared.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <map>
 #include <type_traits>
 
 #include "dfa_pairs.h"
@@ -2387,8 +2389,36 @@ int launch_match2(const dfa *d, const uint8_t *d_in, uint32_t start, const Match
             const void *kf = chunk_major ? (L == 1 ? reinterpret_cast<const void *>(&k_round1c<1>)
                                                    : reinterpret_cast<const void *>(&k_round1c<2>))
                                          : rf;
-            e = hipLaunchKernel(kf, dim3(p.blocks2), dim3(p.threads2), rargs,
-                                lds + round_lds_bytes(p.threads2), s);
+            uint32_t kthreads = p.threads2, kblocks = p.blocks2;
+            if (chunk_major) {
+                // workgroups sized so that as many wavefronts as the kernel's
+                // registers and the staged table allow are resident at once
+                // (its waves loop over chunks, so a workgroup that cannot be
+                // resident only waits); cached per kernel and table size
+                static std::mutex mu;
+                static std::map<std::pair<const void *, size_t>, std::pair<uint32_t, uint32_t>> cache;
+                std::lock_guard<std::mutex> lk(mu);
+                auto it = cache.find({kf, lds});
+                if (it == cache.end()) {
+                    int best_res = 0;
+                    std::pair<uint32_t, uint32_t> pick{p.threads2, p.blocks2};
+                    for (uint32_t t = 1024; t >= 256; t -= 64) {
+                        int nb = 0;
+                        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kf, (int)t,
+                                                                         lds + round_lds_bytes(t)) != hipSuccess)
+                            break;
+                        if (nb > 0 && nb * (int)t > best_res) {
+                            best_res = nb * (int)t;
+                            pick = {t, (uint32_t)(nb * device_cu_count())};
+                        }
+                    }
+                    it = cache.emplace(std::make_pair(kf, lds), pick).first;
+                }
+                kthreads = it->second.first;
+                kblocks = it->second.second;
+            }
+            e = hipLaunchKernel(kf, dim3(kblocks), dim3(kthreads), rargs,
+                                lds + round_lds_bytes(kthreads), s);
             if (e != hipSuccess) return hip_fail(e, "k_round launch");
             if (timed)
                 if (int rc = mark(ev_kern_end)) return rc;
